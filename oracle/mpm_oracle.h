@@ -1,0 +1,146 @@
+/*
+ * mpm_oracle.h -- plain FP64 CPU implementation of one explicit material
+ * point method (MPM) time step on a uniform 8-node hexahedral mesh.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the independent checker of the
+ * GPU library: only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it.  It shares no code, header, table or helper
+ * with the GPU path.
+ *
+ * What it follows (Kumar et al., "Scalable and modular material point method
+ * for large-scale simulations", arXiv:1909.13380):
+ *   - Introduction: state lives on material points; nodal values are reset
+ *     every step; particle quantities are mapped to the nodes and the nodal
+ *     solution is interpolated back with the same mapping functions.
+ *   - Code overview: Node holds mass, momentum, velocity, acceleration and
+ *     force; velocity constraints live at nodes and survive the reset; a cell
+ *     and its nodes are active iff the cell holds a material point; Material
+ *     returns the updated stress for a strain increment; the explicit
+ *     algorithms are update-stress-first (USF) and update-stress-last (USL);
+ *     shape functions are linear or GIMP.
+ *   - Data structures: 6-component Voigt stress.
+ * The paper prints no MPM equations.  The steps are the textbook explicit MPM
+ * (Sulsky, Chen & Schreyer 1994; USF/USL orderings of Bardenhagen 2002 and
+ * Buzzi et al. 2008), uGIMP weights (Bardenhagen & Kober 2004) and the
+ * Drucker-Prager return map of de Souza Neto, Peric & Owen (2008).
+ *
+ * Conventions: tension positive; Voigt order xx, yy, zz, xy, yz, xz;
+ * engineering shear in strain increments, tensor shear in stress.
+ * Particle arrays are row-major: x[3*p+a], v[3*p+a], sig[6*p+k].
+ * Everything is double precision; particles and nodes are visited in index
+ * order by a single thread.
+ */
+#ifndef MPM_ORACLE_H
+#define MPM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    OM_OK = 0,
+    OM_E_ARG = -1,
+    OM_E_NOMEM = -2,
+    OM_E_OUT_OF_MESH = -4,
+    OM_E_NONFINITE = -5
+};
+enum { OM_LINEAR_ELASTIC = 0, OM_DRUCKER_PRAGER = 1 };
+enum { OM_DP_OUTER = 0, OM_DP_INNER = 1, OM_DP_PLANE_STRAIN = 2 };
+enum { OM_FREE = 0, OM_FIXED = 1, OM_SLIP = 2 };
+enum { OM_USF = 0, OM_USL = 1 };
+enum { OM_SHAPE_LINEAR = 0, OM_SHAPE_GIMP = 1 };
+enum { OM_FLIP = 0, OM_PIC = 1 };
+
+/* Uniform mesh: n[a] cells per axis, node (i,j,k) at origin + h*(i,j,k). */
+typedef struct {
+    int32_t n[3];
+    int32_t pad_;
+    double origin[3];
+    double h;
+} om_mesh;
+
+typedef struct {
+    int32_t model;   /* OM_LINEAR_ELASTIC or OM_DRUCKER_PRAGER */
+    int32_t dp_cone; /* OM_DP_OUTER / INNER / PLANE_STRAIN */
+    double rho, E, nu;
+    double phi, psi, c; /* friction angle, dilation angle (radians), cohesion */
+} om_material;
+
+/* Face rules for faces -x,+x,-y,+y,-z,+z plus optional per-node constraints
+ * (node id in this library's node numbering, axis 0..2, prescribed velocity). */
+typedef struct {
+    int32_t face[6];
+    int32_t pad_;
+    int64_t n_extra;
+    const int64_t *node;
+    const int32_t *axis;
+    const double *value;
+} om_bc;
+
+typedef struct {
+    int32_t algo;            /* OM_USF or OM_USL */
+    int32_t shape;           /* OM_SHAPE_LINEAR or OM_SHAPE_GIMP */
+    int32_t velocity_update; /* OM_FLIP or OM_PIC */
+    int32_t pad_;
+    double gravity[3];
+    double dt;
+    double mass_eps_rel;     /* nodes with m <= mass_eps_rel * mean(m_p) are void */
+} om_scheme;
+
+/* Caller-owned nodal workspace, sized by om_num_nodes / om_num_cells.
+ * After om_step it holds the step's nodal mass m, momentum p, velocity v
+ * (after constraints), force f, acceleration a and updated velocity vn,
+ * each vector field row-major [3*I+a], and the particle count per cell. */
+typedef struct {
+    double *m, *p, *v, *f, *a, *vn;
+    uint32_t *cell_count;
+} om_grid;
+
+/* Node numbering: linear shape functions use nodes 0..n[a]; GIMP adds one
+ * ghost layer, nodes -1..n[a]+1.  Id = (i+g) + N0*((j+g) + N1*(k+g)) with
+ * g the ghost width and N0, N1 the node counts along x and y. */
+int64_t om_num_nodes(const om_mesh *mesh, int32_t shape);
+int64_t om_num_cells(const om_mesh *mesh);
+int64_t om_node_id(const om_mesh *mesh, int32_t shape, int64_t i, int64_t j, int64_t k);
+
+/* Cell of each particle: c_a = floor((x_a - o_a)/h), id = cx + nx*(cy + ny*cz).
+ * Returns OM_E_OUT_OF_MESH if any particle lies outside [o, o + n h). */
+int om_locate(const om_mesh *mesh, int64_t n, const double *x, int64_t *cell);
+
+/* Shape functions of one particle.  Writes node ids, weights and
+ * x-gradients of every node in the particle's support (8 or 27) and returns
+ * that count, or a negative error code. */
+int om_shape(const om_mesh *mesh, int32_t shape, const double x[3],
+             int64_t *node, double *N, double *dN /* [3*k+a] */);
+
+/* One-dimensional uGIMP weight and derivative for node offset r = x_p - X_I,
+ * cell size h and particle half-length l: out[0] = S, out[1] = dS/dr. */
+void om_gimp_1d(double r, double h, double l, double out[2]);
+
+/* Drucker-Prager coefficients for the chosen cone: out = {eta, xi, eta_bar}. */
+void om_dp_coefficients(const om_material *mat, double out[3]);
+
+/* Stress update for one strain increment (Voigt, engineering shear).
+ * Returns 0 if the step was elastic, 1 for a return to the cone, 2 for a
+ * return to the apex. */
+int om_constitutive(const om_material *mat, const double deps[6], double sig[6]);
+
+/* One time step (algo in scheme) for n particles, updated in place.
+ * mass is constant.  Returns OM_OK or an error code. */
+int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
+            const om_scheme *scheme, int64_t n, double *x, double *v,
+            double *sig, double *vol, const double *mass, om_grid *grid);
+
+/* nsteps calls of om_step; stops at the first error. */
+int om_run(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
+           const om_scheme *scheme, int64_t n, double *x, double *v,
+           double *sig, double *vol, const double *mass, om_grid *grid,
+           int64_t nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif
