@@ -1,0 +1,178 @@
+"""Throughput of the explicit MPM step on one MI355X.
+
+Workload (default): the granular column collapse -- a Drucker-Prager block of
+64x32x128 cells (2,097,152 particles, 8 per cell, jittered) on a 256x128x160
+mesh of 0.01 m cells, frictionless walls, dt = 2e-5 s, FP32 particle state
+with FP64 positions and nodal mass.  One "step" is one full update-stress-
+first time step (reorder check, nodal clear, P2G, stress + force, G2P) of all
+particles.  Inputs are resident in device memory before timing starts.
+
+Prints one JSON line: particle-updates/s over the K timed steps, the
+dominant kernel's achieved bandwidth against the HBM peak (HIP events on the
+library's stream around every launch in the timed region), and the FP64
+oracle timed on a bounded sample on the host CPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-updates/s (FP32 batched vs plain) at stated error; p50/p99 scene latency"
+
+
+def kernel_bytes(kernel: str, n_particles: int, n_nodes: int) -> int:
+    """Algorithmic HBM bytes of one launch: every particle field the stage
+    needs read once and written once, every touched node's fields once.
+    Particle: x 24 B (FP64), v 12, sigma 24, vol 4, mass 4, key 4.
+    Node: mass 8 B (FP64), momentum 12, force 12."""
+    per_particle = {
+        "p2g": 24 + 12 + 4 + 4,                        # read x, v, mass, key
+        "stress": (24 + 4 + 4 + 4 + 24) + (24 + 4),    # read x, key, mass, vol, sigma; write sigma, vol
+        "g2p": (24 + 12 + 4) + (24 + 12 + 4),          # read x, v, key; write x, v, key
+        "p2g_usl": 24 + 12 + 4 + 4 + 24 + 4,
+        "g2p_usl": (24 + 12 + 4 + 24 + 4) + (24 + 12 + 4 + 24 + 4),
+    }
+    per_node = {"p2g": 20, "stress": 20 + 12, "g2p": 32, "p2g_usl": 32, "g2p_usl": 32}
+    return per_particle.get(kernel, 0) * n_particles + per_node.get(kernel, 0) * n_nodes
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("mpmx_kernels.hip", "mpmx_api.hip", "mpmx_dev.h"):
+        with open(os.path.join(ROOT, "paper_1909_13380_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    entry = data.get(workload, {}).get(kernel)
+    if not entry or entry.get("source_hash") != source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def make_workload(name: str):
+    from paper_1909_13380_amd import scenes
+    if name == "column":
+        return scenes.c2(), "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear"
+    if name == "column_gimp":
+        sc = scenes.c2()
+        sc["scheme"]["shape"] = scenes.SHAPE_GIMP
+        return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, GIMP"
+    if name == "c1":
+        return scenes.c1(), "elastic block, 4,096 particles, 16^3 mesh, linear"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(sc: dict, steps: int) -> dict:
+    import oracle
+    grid = oracle.Grid(sc["mesh"], sc["scheme"]["shape"])
+    oracle.run(sc, 1, grid=grid)          # first touch of the nodal arrays
+    t0 = time.perf_counter()
+    oracle.run(sc, steps, grid=grid)
+    dt = time.perf_counter() - t0
+    n = len(sc["x"])
+    return {"value": n * steps / dt, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} steps of the same scene ({n} particles), FP64, one thread",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="column")
+    ap.add_argument("--sort", default="on_demand", choices=["on_demand", "always"])
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel HIP event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        raise SystemExit(2)
+
+    import torch
+    from paper_1909_13380_amd import mpmx
+
+    sc, desc = make_workload(args.workload)
+    n = len(sc["x"])
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    ctx = mpmx.Context(0, stream=stream.cuda_stream)
+    policy = mpmx.SORT_ALWAYS if args.sort == "always" else mpmx.SORT_ON_DEMAND
+    s = ctx.create_scene(sc, precision=mpmx.FP32, sort_policy=policy)
+    print(f"# scene created: {desc}", file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    nodes = s.nodes()
+    n_nodes = int(np.count_nonzero(nodes["m"]))
+    if not args.no_profile:
+        ctx.profile(True)
+        ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read() if not args.no_profile else {}
+    ctx.profile(False)
+    st = s.stats()
+    if st["error_bits"]:
+        raise SystemExit(f"scene stopped with error bits {st['error_bits']}")
+    elapsed = t1 - t0
+    value = n * args.steps / elapsed
+    out = {"metric": METRIC, "value": value, "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": desc, "particles": n, "mesh": list(sc["mesh"]["n"]), "dt": sc["scheme"]["dt"],
+                      "precision": "fp32 state, fp64 positions and nodal mass", "sort_policy": args.sort,
+                      "reorders_in_run": st["n_sorts"], "work_items": st["n_items"], "touched_nodes": n_nodes}}
+    if prof:
+        kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1), "total_ms": v[1]}
+                   for k, v in prof.items()}
+        dom = max((k for k in kernels if k in ("p2g", "stress", "g2p", "p2g_usl", "g2p_usl")),
+                  key=lambda k: kernels[k]["total_ms"])
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        nbytes = kernel_bytes(dom, n, n_nodes)
+        achieved = nbytes / avg_s / 1e9
+        traffic = measured_traffic(dom, args.workload)
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "algorithmic_bytes_per_launch": nbytes}
+        out["kernels"] = kernels
+        step_bytes = sum(kernel_bytes(k, n, n_nodes) for k in ("p2g", "stress", "g2p"))
+        out["step_algorithmic_GBs"] = step_bytes / (elapsed / args.steps) / 1e9
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on the host", file=sys.stderr, flush=True)
+        cb = cpu_baseline(sc, args.cpu_steps)
+        cb["cores"] = 1
+        out["cpu_baseline"] = cb
+    s.destroy()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

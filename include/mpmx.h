@@ -1,0 +1,244 @@
+/*
+ * mpmx.h -- C ABI of the MI355X (gfx950) explicit material point method step.
+ *
+ * The calls follow the paper's statement of the problem (Kumar et al.,
+ * "Scalable and modular material point method for large-scale simulations",
+ * arXiv:1909.13380):
+ *   - a background mesh of nodes and cells (code overview: Mesh, Node, Cell;
+ *     here a uniform grid of 8-node hexahedra),
+ *   - material points carrying position, velocity, stress and volume
+ *     (introduction: points carry the state; nodal values are reset every
+ *     step),
+ *   - a material that returns the stress for a strain increment (code
+ *     overview: Material; linear elastic or Drucker-Prager),
+ *   - velocity constraints held at nodes (code overview; isoparametric-mesh
+ *     section: boundary conditions are applied at the nodes),
+ *   - an explicit algorithm, update-stress-first or update-stress-last, and
+ *     linear or GIMP shape functions (code overview),
+ *   - a time step and a step count (benchmark section: 1000 explicit USF
+ *     steps);
+ * in, and the updated particle state out.
+ *
+ * Every entry point returns MPMX_OK (0) or a negative MPMX_E_* code; the
+ * context keeps a message for the last failure (mpmx_last_error).  A context
+ * is used by one host thread at a time.  Work is queued on the context's HIP
+ * stream; calls that return data to the caller synchronise that stream.
+ *
+ * Ownership: every const input is copied before the call returns and stays
+ * the caller's.  Scene state lives in device memory owned by the library
+ * until mpmx_scene_destroy.  Outputs go to caller-allocated buffers; the
+ * library never frees caller memory.  A pointer flagged MPMX_MEM_DEVICE must
+ * be device memory of the context's GPU.
+ *
+ * Conventions: SI units; tension positive; Voigt stress order xx, yy, zz,
+ * xy, yz, xz; particle arrays are row-major (n x 3, n x 6); cells are
+ * half-open [o + h c, o + h (c + 1)) and numbered c_x + n_x (c_y + n_y c_z);
+ * nodes (i, j, k) sit at o + h (i, j, k), numbered
+ * (i + g) + N_x ((j + g) + N_y (k + g)) with g = 0 for linear and g = 1 for
+ * GIMP shape functions (one ghost layer) and N_a = n_a + 1 + 2 g.
+ */
+#ifndef MPMX_H
+#define MPMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPMX_VERSION 1
+
+/* ------------------------------------------------------------ codes ---- */
+enum {
+    MPMX_OK = 0,
+    MPMX_E_INVALID_ARG = -1, /* bad pointer, size, enum or descriptor */
+    MPMX_E_OOM = -2,         /* device or host allocation failed */
+    MPMX_E_BUDGET = -3,      /* the scene can never fit the server budget */
+    MPMX_E_OUT_OF_MESH = -4, /* a particle left the mesh; the scene stops */
+    MPMX_E_NONFINITE = -5,   /* a non-finite position, velocity or stress */
+    MPMX_E_HIP = -6,         /* a HIP runtime call failed */
+    MPMX_E_AGAIN = -7,       /* request queued, or nothing to report yet */
+    MPMX_E_NOT_FOUND = -8,   /* unknown scene, request or server id */
+    MPMX_E_STATE = -9        /* call not valid in the object's state */
+};
+
+enum { MPMX_LINEAR_ELASTIC = 0, MPMX_DRUCKER_PRAGER = 1 };
+/* Drucker-Prager cone matched to Mohr-Coulomb: through the triaxial
+ * compression meridian (outer), the extension meridian (inner), or the
+ * plane-strain match. */
+enum { MPMX_DP_OUTER = 0, MPMX_DP_INNER = 1, MPMX_DP_PLANE_STRAIN = 2 };
+enum { MPMX_BC_FREE = 0, MPMX_BC_FIXED = 1, MPMX_BC_SLIP = 2 };
+enum { MPMX_USF = 0, MPMX_USL = 1 };
+enum { MPMX_SHAPE_LINEAR = 0, MPMX_SHAPE_GIMP = 1 };
+enum { MPMX_FLIP = 0, MPMX_PIC = 1 };
+enum { MPMX_FP32 = 0, MPMX_FP64 = 1 };
+/* Particle reordering: keep particles grouped by 4x4x4-cell brick,
+ * re-sorting when a particle has moved more than one cell outside the
+ * brick of its work item (ON_DEMAND), or re-sort after every step (ALWAYS). */
+enum { MPMX_SORT_ON_DEMAND = 0, MPMX_SORT_ALWAYS = 1 };
+enum { MPMX_MEM_HOST = 0, MPMX_MEM_DEVICE = 1 };
+
+/* Scene error bits reported by mpmx_scene_stats. */
+enum { MPMX_ERRBIT_OUT_OF_MESH = 1u, MPMX_ERRBIT_NONFINITE = 2u };
+
+/* --------------------------------------------------------- descriptors -- */
+/* Each descriptor starts with its own size in bytes (sizeof), so that later
+ * versions can grow it; a size smaller than this version's is rejected. */
+
+typedef struct {
+    uint32_t size;
+    int32_t n[3];       /* cells per axis, each >= 1 */
+    double origin[3];   /* position of node (0,0,0) */
+    double h;           /* cell edge length, > 0 */
+} mpmx_mesh;
+
+typedef struct {
+    uint32_t size;
+    int32_t model;      /* MPMX_LINEAR_ELASTIC or MPMX_DRUCKER_PRAGER */
+    int32_t dp_cone;    /* MPMX_DP_* (Drucker-Prager only) */
+    int32_t pad_;
+    double rho, E, nu;  /* density, Young's modulus, Poisson ratio (-1 < nu < 0.5) */
+    double phi, psi, c; /* friction and dilation angles (radians), cohesion */
+} mpmx_material;
+
+/* Velocity constraints: face rules for faces -x,+x,-y,+y,-z,+z (a node with
+ * index i_b <= 0 lies on face -b, i_b >= n_b on face +b, ghost nodes
+ * included; FIXED constrains all components to 0, SLIP the normal one), then
+ * n_extra per-node constraints (node id, axis 0..2, prescribed velocity) that
+ * take precedence.  Constrained components get the prescribed velocity and
+ * zero acceleration. */
+typedef struct {
+    uint32_t size;
+    int32_t face[6];
+    int64_t n_extra;
+    const int64_t *node;
+    const int32_t *axis;
+    const double *value;
+} mpmx_bc;
+
+typedef struct {
+    uint32_t size;
+    int32_t algo;            /* MPMX_USF or MPMX_USL */
+    int32_t shape;           /* MPMX_SHAPE_LINEAR or MPMX_SHAPE_GIMP */
+    int32_t velocity_update; /* MPMX_FLIP or MPMX_PIC */
+    int32_t precision;       /* MPMX_FP32 (x and nodal mass FP64) or MPMX_FP64 */
+    int32_t sort_policy;     /* MPMX_SORT_* */
+    double gravity[3];
+    double dt;               /* > 0 */
+    double mass_eps_rel;     /* nodes with m <= mass_eps_rel * mean(m_p) are void */
+} mpmx_scheme;
+
+/* Particle input: n rows; x, v (n x 3), stress (n x 6, NULL = zero), vol and
+ * mass (n).  All double; in FP32 scenes v, stress, vol and mass are rounded
+ * to float.  mem says where the arrays live. */
+typedef struct {
+    uint32_t size;
+    int32_t mem;
+    int64_t n;
+    const double *x, *v, *stress, *vol, *mass;
+} mpmx_particles;
+
+/* Particle output in the original input order: any pointer may be NULL to
+ * skip that field; cell receives the linear cell id of each particle. */
+typedef struct {
+    uint32_t size;
+    int32_t mem;
+    double *x, *v, *stress, *vol;
+    int32_t *cell;
+} mpmx_particles_out;
+
+typedef struct {
+    uint32_t size;
+    int64_t n_particles;
+    int64_t steps_done;     /* steps completed (queued work included after a sync) */
+    int64_t n_sorts;        /* particle reorders performed */
+    int64_t n_items;        /* current work items (brick chunks) */
+    int64_t active_cells;   /* cells holding at least one particle */
+    uint32_t error_bits;    /* MPMX_ERRBIT_* */
+    uint32_t pad_;
+    uint64_t device_bytes;  /* device memory held by the scene */
+} mpmx_stats;
+
+typedef struct mpmx_ctx mpmx_ctx;
+
+/* ------------------------------------------------------------ context -- */
+
+/* Library version (MPMX_VERSION). */
+int mpmx_version(void);
+
+/* Create a context on HIP device `device`.  stream: a hipStream_t to queue
+ * work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a
+ * stream the context creates and owns.  Fails with MPMX_E_HIP if the device
+ * is not a usable GPU. */
+int mpmx_create(mpmx_ctx **out, int device, void *stream);
+
+/* Destroy a context, its scenes and servers; waits for queued work. */
+void mpmx_destroy(mpmx_ctx *ctx);
+
+/* Message of the last failed call on ctx (valid until the next call). */
+const char *mpmx_last_error(const mpmx_ctx *ctx);
+
+/* Per-kernel timing with HIP events on the context stream.  enable != 0
+ * records an event pair around every kernel launch from now on;
+ * mpmx_profile_read synchronises and returns, for up to `cap` kernels, the
+ * kernel name, launch count and summed milliseconds; *n gets the number of
+ * kernels seen.  mpmx_profile_reset clears the totals. */
+int mpmx_profile_enable(mpmx_ctx *ctx, int enable);
+int mpmx_profile_reset(mpmx_ctx *ctx);
+int mpmx_profile_read(mpmx_ctx *ctx, int cap, const char **names, int64_t *launches,
+                      double *ms, int *n);
+
+/* ------------------------------------------------------------- scenes -- */
+
+/* Device bytes a scene of this mesh, scheme and particle count would hold
+ * (used for admission).  Pure: touches no device. */
+int mpmx_scene_bytes(const mpmx_mesh *mesh, const mpmx_scheme *scheme, int64_t n_particles,
+                     uint64_t *bytes);
+
+/* Create a scene: validate and copy the descriptors, upload the particles,
+ * bin them into cells.  *scene receives an id > 0.  A particle outside the
+ * mesh or a non-finite input fails with MPMX_E_OUT_OF_MESH /
+ * MPMX_E_NONFINITE and creates nothing. */
+int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat,
+                      const mpmx_bc *bc, const mpmx_scheme *scheme,
+                      const mpmx_particles *particles, uint64_t *scene);
+
+/* Queue nsteps (>= 0) time steps.  Asynchronous; a particle leaving the
+ * mesh or a non-finite value stops the scene at the step where it happened
+ * and is reported by mpmx_scene_stats / mpmx_scene_read. */
+int mpmx_scene_step(mpmx_ctx *ctx, uint64_t scene, int64_t nsteps);
+
+/* Copy the particle state, in the original particle order, to the caller's
+ * buffers (synchronises).  Returns MPMX_E_OUT_OF_MESH / MPMX_E_NONFINITE
+ * (after copying) if the scene has stopped on that error. */
+int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out);
+
+/* Particles per cell (n_x n_y n_z uint32 in linear cell order) for the
+ * current positions, to host or device memory (synchronises). */
+int mpmx_scene_cell_counts(mpmx_ctx *ctx, uint64_t scene, uint32_t *counts, int32_t mem);
+
+/* Nodal mass (nn), momentum and force (nn x 3) accumulated by the last step,
+ * before constraints, to host buffers (synchronises); nn as in the header
+ * comment.  Any pointer may be NULL. */
+int mpmx_scene_nodes(mpmx_ctx *ctx, uint64_t scene, double *mass, double *momentum, double *force);
+
+/* Counters and error bits of a scene (synchronises). */
+int mpmx_scene_stats(mpmx_ctx *ctx, uint64_t scene, mpmx_stats *out);
+
+/* Free a scene (waits for its queued work). */
+int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene);
+
+/* ------------------------------------------------------------- batches -- */
+
+/* Advance n scenes together, scene i by nsteps[i] steps: every stage is one
+ * launch over the flattened (scene, work item) list of all scenes still
+ * stepping.  Scenes must share shape function and precision.  Asynchronous.
+ * Results equal running each scene alone up to the order of floating-point
+ * sums. */
+int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,980 @@
+// mpmx_api.hip -- host runtime of libmpmx: contexts, scenes, batches and the
+// C ABI declared in include/mpmx.h.
+//
+// A scene owns its device buffers (layout in mpmx_dev.h).  Every step
+// is a fixed sequence of launches over a BatchDev (one scene, or many):
+//   clear -> sort_count -> sort_bricks -> sort_scan -> sort_cells ->
+//   sort_scatter -> step_control -> p2g -> stress -> g2p         (USF)
+//   clear -> sort ... -> step_control -> p2g_usl -> g2p_usl      (USL)
+// The sort kernels do nothing unless the scene flagged a reorder; all
+// counts the kernels need live in device memory, so the host never waits on
+// the GPU between steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mpmx.h"
+#include "mpmx_dev.h"
+#include "mpmx_launch.h"
+
+using namespace mpmx;
+
+namespace {
+
+constexpr int kParticleBlock = 256;
+
+struct ProfEvent {
+    const char *name;
+    hipEvent_t a, b;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfEvent> pending;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+};
+
+struct Batch {
+    std::vector<uint64_t> ids;
+    SceneDev **d_scenes = nullptr;
+    int64_t *d_poffs = nullptr, *d_boffs = nullptr, *d_nsteps = nullptr;
+    uint32_t *d_ioffs = nullptr;
+    BatchDev bd{};
+    int prec = 0, shape = 0, algo = 0;
+    void release()
+    {
+        if (d_scenes) (void)hipFree(d_scenes);
+        if (d_poffs) (void)hipFree(d_poffs);
+        if (d_boffs) (void)hipFree(d_boffs);
+        if (d_nsteps) (void)hipFree(d_nsteps);
+        if (d_ioffs) (void)hipFree(d_ioffs);
+        d_scenes = nullptr;
+        d_poffs = d_boffs = d_nsteps = nullptr;
+        d_ioffs = nullptr;
+    }
+};
+
+struct Scene {
+    uint64_t id = 0;
+    SceneDev h{};
+    SceneDev *d = nullptr;
+    std::vector<void *> allocs;
+    uint64_t bytes = 0;
+    int prec = 0, shape = 0, algo = 0;
+    Batch single;
+};
+
+}  // namespace
+
+struct mpmx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int num_cu = 256;
+    std::string err;
+    uint64_t next_id = 1;
+    std::map<uint64_t, std::unique_ptr<Scene>> scenes;
+    Batch cached_batch;
+    Profiler prof;
+};
+
+namespace {
+
+int fail(mpmx_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), MPMX_E_HIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                               \
+    } while (0)
+
+int flush_profile(mpmx_ctx *ctx)
+{
+    if (ctx->prof.pending.empty())
+        return MPMX_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &pe : ctx->prof.pending) {
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, pe.a, pe.b));
+        auto &t = ctx->prof.totals[pe.name];
+        t.first += 1;
+        t.second += ms;
+        ctx->prof.pool.push_back(pe.a);
+        ctx->prof.pool.push_back(pe.b);
+    }
+    ctx->prof.pending.clear();
+    return MPMX_OK;
+}
+
+hipEvent_t pool_event(mpmx_ctx *ctx)
+{
+    if (ctx->prof.pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+    hipEvent_t e = ctx->prof.pool.back();
+    ctx->prof.pool.pop_back();
+    return e;
+}
+
+int launch(mpmx_ctx *ctx, const char *name, const void *fn, dim3 grid, dim3 block, void **args)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->prof.on) {
+        if (ctx->prof.pending.size() > 8192) {
+            int rc = flush_profile(ctx);
+            if (rc)
+                return rc;
+        }
+        a = pool_event(ctx);
+        b = pool_event(ctx);
+        if (a)
+            HIPCHK(ctx, hipEventRecord(a, ctx->stream));
+    }
+    HIPCHK(ctx, hipLaunchKernel(fn, grid, block, args, 0, ctx->stream));
+    if (ctx->prof.on && a && b) {
+        HIPCHK(ctx, hipEventRecord(b, ctx->stream));
+        ctx->prof.pending.push_back({name, a, b});
+    }
+    return MPMX_OK;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+dim3 particle_grid(int64_t n, int cap = 8192)
+{
+    int64_t g = ceil_div(std::max<int64_t>(n, 1), kParticleBlock);
+    return dim3((unsigned)std::min<int64_t>(g, cap));
+}
+
+// --- sizes -------------------------------------------------------------
+
+struct Sizes {
+    int64_t nb[3], nbricks, nkeys, nn, N[3], max_items, ncells;
+    int ghost;
+    size_t real;
+};
+
+Sizes sizes_of(const mpmx_mesh *m, int shape, int prec, int64_t np)
+{
+    Sizes s{};
+    s.ghost = shape == MPMX_SHAPE_GIMP ? 1 : 0;
+    s.real = prec == MPMX_FP64 ? 8 : 4;
+    s.ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        s.nb[a] = ceil_div(m->n[a], kBrick);
+        s.N[a] = m->n[a] + 1 + 2 * s.ghost;
+        s.ncells *= m->n[a];
+    }
+    s.nbricks = s.nb[0] * s.nb[1] * s.nb[2];
+    s.nkeys = s.nbricks * kBrickCells;
+    s.nn = s.N[0] * s.N[1] * s.N[2];
+    s.max_items = ceil_div(np, kChunk) + std::min<int64_t>(np, s.nbricks) + 1;
+    return s;
+}
+
+uint64_t align_up(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+
+// Device bytes of a scene; the allocation below follows the same list.
+uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc)
+{
+    uint64_t b = 0;
+    const uint64_t R = s.real;
+    for (int buf = 0; buf < 2; ++buf) {
+        b += align_up(3 * 8 * (uint64_t)np) + align_up(3 * R * np) + align_up(6 * R * np) + align_up(R * np) +
+             align_up(R * np) + align_up(4 * (uint64_t)np) + align_up(4 * (uint64_t)np);
+    }
+    b += align_up(8 * (uint64_t)s.nn) + 2 * align_up(3 * R * s.nn);
+    b += 2 * align_up(4 * (uint64_t)s.nkeys) + align_up(4 * (uint64_t)np);
+    b += 2 * align_up(4 * (uint64_t)s.nbricks) + 2 * align_up(4 * (uint64_t)(s.nbricks + 1));
+    b += align_up(sizeof(Item) * (uint64_t)s.max_items) + align_up(sizeof(Tile) * (uint64_t)s.max_items);
+    b += align_up(4 * CTL_WORDS) + align_up(sizeof(SceneDev));
+    if (extra_bc)
+        b += align_up((uint64_t)s.nn) + align_up(24 * (uint64_t)s.nn);
+    return b;
+}
+
+int validate(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat, const mpmx_bc *bc,
+             const mpmx_scheme *sch)
+{
+    if (!mesh || mesh->size < sizeof(mpmx_mesh))
+        return fail(ctx, MPMX_E_INVALID_ARG, "mesh descriptor missing or too small");
+    for (int a = 0; a < 3; ++a)
+        if (mesh->n[a] < 1 || mesh->n[a] > (1 << 20) || !std::isfinite(mesh->origin[a]))
+            return fail(ctx, MPMX_E_INVALID_ARG, "mesh: n[%d]=%d / origin invalid", a, mesh->n[a]);
+    if (!(mesh->h > 0.0) || !std::isfinite(mesh->h))
+        return fail(ctx, MPMX_E_INVALID_ARG, "mesh: h must be positive and finite");
+    if (mat) {
+        if (mat->size < sizeof(mpmx_material))
+            return fail(ctx, MPMX_E_INVALID_ARG, "material descriptor too small");
+        if (mat->model != MPMX_LINEAR_ELASTIC && mat->model != MPMX_DRUCKER_PRAGER)
+            return fail(ctx, MPMX_E_INVALID_ARG, "material: unknown model %d", mat->model);
+        if (!(mat->E > 0.0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->rho > 0.0))
+            return fail(ctx, MPMX_E_INVALID_ARG, "material: need E > 0, -1 < nu < 0.5, rho > 0");
+        if (mat->model == MPMX_DRUCKER_PRAGER) {
+            if (mat->dp_cone < 0 || mat->dp_cone > 2)
+                return fail(ctx, MPMX_E_INVALID_ARG, "material: unknown cone %d", mat->dp_cone);
+            if (!(mat->phi >= 0.0 && mat->phi < M_PI / 2) || !(mat->psi >= 0.0 && mat->psi <= mat->phi) ||
+                !(mat->c >= 0.0))
+                return fail(ctx, MPMX_E_INVALID_ARG, "material: need 0 <= psi <= phi < pi/2, c >= 0");
+        }
+    }
+    if (bc) {
+        if (bc->size < sizeof(mpmx_bc))
+            return fail(ctx, MPMX_E_INVALID_ARG, "bc descriptor too small");
+        for (int f = 0; f < 6; ++f)
+            if (bc->face[f] < 0 || bc->face[f] > 2)
+                return fail(ctx, MPMX_E_INVALID_ARG, "bc: face %d rule %d unknown", f, bc->face[f]);
+        if (bc->n_extra < 0 || (bc->n_extra > 0 && (!bc->node || !bc->axis || !bc->value)))
+            return fail(ctx, MPMX_E_INVALID_ARG, "bc: bad per-node constraint list");
+    }
+    if (!sch || sch->size < sizeof(mpmx_scheme))
+        return fail(ctx, MPMX_E_INVALID_ARG, "scheme descriptor missing or too small");
+    if ((sch->algo != MPMX_USF && sch->algo != MPMX_USL) ||
+        (sch->shape != MPMX_SHAPE_LINEAR && sch->shape != MPMX_SHAPE_GIMP) ||
+        (sch->velocity_update != MPMX_FLIP && sch->velocity_update != MPMX_PIC) ||
+        (sch->precision != MPMX_FP32 && sch->precision != MPMX_FP64) ||
+        (sch->sort_policy != MPMX_SORT_ON_DEMAND && sch->sort_policy != MPMX_SORT_ALWAYS))
+        return fail(ctx, MPMX_E_INVALID_ARG, "scheme: unknown algo/shape/velocity_update/precision/sort_policy");
+    if (!(sch->dt > 0.0) || !std::isfinite(sch->dt) || !(sch->mass_eps_rel >= 0.0))
+        return fail(ctx, MPMX_E_INVALID_ARG, "scheme: need dt > 0 and mass_eps_rel >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(sch->gravity[a]))
+            return fail(ctx, MPMX_E_INVALID_ARG, "scheme: gravity not finite");
+    return MPMX_OK;
+}
+
+void dp_constants(const mpmx_material *m, double &eta, double &xi, double &etab)
+{
+    // Mohr-Coulomb matched cones (outer: compression meridian; inner:
+    // extension meridian; plane strain).
+    auto coef = [&](double ang, double &e, double &x) {
+        const double s = std::sin(ang), c = std::cos(ang), t = std::tan(ang), r3 = std::sqrt(3.0);
+        if (m->dp_cone == MPMX_DP_INNER) {
+            e = 6.0 * s / (r3 * (3.0 + s));
+            x = 6.0 * c / (r3 * (3.0 + s));
+        } else if (m->dp_cone == MPMX_DP_PLANE_STRAIN) {
+            const double d = std::sqrt(9.0 + 12.0 * t * t);
+            e = 3.0 * t / d;
+            x = 3.0 / d;
+        } else {
+            e = 6.0 * s / (r3 * (3.0 - s));
+            x = 6.0 * c / (r3 * (3.0 - s));
+        }
+    };
+    double xb;
+    coef(m->phi, eta, xi);
+    coef(m->psi, etab, xb);
+}
+
+Scene *find(mpmx_ctx *ctx, uint64_t id)
+{
+    auto it = ctx->scenes.find(id);
+    return it == ctx->scenes.end() ? nullptr : it->second.get();
+}
+
+void free_scene(Scene *s)
+{
+    s->single.release();
+    for (void *p : s->allocs)
+        (void)hipFree(p);
+    s->allocs.clear();
+}
+
+int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
+{
+    b.release();
+    const int n = (int)list.size();
+    std::vector<SceneDev *> ptrs(n);
+    std::vector<int64_t> po(n + 1, 0), bo(n + 1, 0);
+    int64_t maxit = 0;
+    for (int i = 0; i < n; ++i) {
+        ptrs[i] = list[i]->d;
+        po[i + 1] = po[i] + list[i]->h.np;
+        bo[i + 1] = bo[i] + list[i]->h.nbricks;
+        maxit += list[i]->h.max_items;
+    }
+    HIPCHK(ctx, hipMalloc(&b.d_scenes, sizeof(SceneDev *) * std::max(n, 1)));
+    HIPCHK(ctx, hipMalloc(&b.d_poffs, sizeof(int64_t) * (n + 1)));
+    HIPCHK(ctx, hipMalloc(&b.d_boffs, sizeof(int64_t) * (n + 1)));
+    HIPCHK(ctx, hipMalloc(&b.d_nsteps, sizeof(int64_t) * std::max(n, 1)));
+    HIPCHK(ctx, hipMalloc(&b.d_ioffs, sizeof(uint32_t) * (n + 1)));
+    HIPCHK(ctx, hipMemcpy(b.d_scenes, ptrs.data(), sizeof(SceneDev *) * n, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(b.d_poffs, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(b.d_boffs, bo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(b.d_ioffs, 0, sizeof(uint32_t) * (n + 1)));
+    b.bd.scenes = b.d_scenes;
+    b.bd.poffs = b.d_poffs;
+    b.bd.boffs = b.d_boffs;
+    b.bd.ioffs = b.d_ioffs;
+    b.bd.nscenes = n;
+    b.bd.total_particles = po[n];
+    b.bd.total_bricks = bo[n];
+    b.bd.max_items = maxit;
+    b.ids.clear();
+    for (auto *s : list)
+        b.ids.push_back(s->id);
+    if (n) {
+        b.prec = list[0]->prec;
+        b.shape = list[0]->shape;
+        b.algo = list[0]->algo;
+    }
+    return MPMX_OK;
+}
+
+// Queue `steps` steps of every scene of b (scene i: nsteps[i], or `uniform`
+// for all when nsteps is null).
+int run_steps(mpmx_ctx *ctx, Batch &b, const int64_t *nsteps, int64_t uniform)
+{
+    const int n = b.bd.nscenes;
+    if (n == 0)
+        return MPMX_OK;
+    std::vector<int64_t> ns(n);
+    int64_t smax = 0;
+    for (int i = 0; i < n; ++i) {
+        ns[i] = nsteps ? nsteps[i] : uniform;
+        smax = std::max(smax, ns[i]);
+    }
+    if (smax <= 0)
+        return MPMX_OK;
+    HIPCHK(ctx, hipMemcpyAsync(b.d_nsteps, ns.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, ctx->stream));
+    const KernelSet &K = kernel_set(b.prec, b.shape);
+    const CommonKernels &C = common_kernels();
+    BatchDev bd = b.bd;
+    int mode0 = 0, mode1 = 1;
+    const int64_t *dns = b.d_nsteps;
+    void *a_bd[] = {&bd};
+    void *a_rem[] = {&bd, &dns};
+    void *a_ctl0[] = {&bd, &mode0};
+    void *a_ctl1[] = {&bd, &mode1};
+    int rc;
+    if ((rc = launch(ctx, "set_remaining", C.set_remaining, dim3(ceil_div(n, 256)), dim3(256), a_rem)))
+        return rc;
+    if ((rc = launch(ctx, "step_control", C.step_control, dim3(1), dim3(1024), a_ctl0)))
+        return rc;
+    const dim3 pg = particle_grid(bd.total_particles);
+    const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), 16384));
+    const dim3 ig((unsigned)std::max<int64_t>(1, std::min<int64_t>(bd.max_items, 8 * ctx->num_cu)));
+    for (int64_t s = 0; s < smax; ++s) {
+        if ((rc = launch(ctx, "clear", K.clear, ig, dim3(kBlock), a_bd)))
+            return rc;
+        if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)))
+            return rc;
+        if ((rc = launch(ctx, "sort_bricks", C.sort_bricks, bg, dim3(256), a_bd)))
+            return rc;
+        if ((rc = launch(ctx, "sort_scan", C.sort_scan, dim3(std::min(n, 1024)), dim3(1024), a_bd)))
+            return rc;
+        if ((rc = launch(ctx, "sort_cells", C.sort_cells, bg, dim3(256), a_bd)))
+            return rc;
+        if ((rc = launch(ctx, "sort_scatter", K.scatter, pg, dim3(kParticleBlock), a_bd)))
+            return rc;
+        if ((rc = launch(ctx, "step_control", C.step_control, dim3(1), dim3(1024), a_ctl1)))
+            return rc;
+        if (b.algo == MPMX_USF) {
+            if ((rc = launch(ctx, "p2g", K.p2g, ig, dim3(kBlock), a_bd)))
+                return rc;
+            if ((rc = launch(ctx, "stress", K.stress, ig, dim3(kBlock), a_bd)))
+                return rc;
+            if ((rc = launch(ctx, "g2p", K.g2p, ig, dim3(kBlock), a_bd)))
+                return rc;
+        } else {
+            if ((rc = launch(ctx, "p2g_usl", K.p2g_usl, ig, dim3(kBlock), a_bd)))
+                return rc;
+            if ((rc = launch(ctx, "g2p_usl", K.g2p_usl, ig, dim3(kBlock), a_bd)))
+                return rc;
+        }
+    }
+    return MPMX_OK;
+}
+
+int read_ctl(mpmx_ctx *ctx, Scene *s, uint32_t *ctl)
+{
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(ctl, s->h.ctl, sizeof(uint32_t) * CTL_WORDS, hipMemcpyDeviceToHost));
+    return MPMX_OK;
+}
+
+int err_code(uint32_t bits)
+{
+    if (bits & ERR_OUT_OF_MESH)
+        return MPMX_E_OUT_OF_MESH;
+    if (bits & ERR_NONFINITE)
+        return MPMX_E_NONFINITE;
+    if (bits)
+        return MPMX_E_STATE;
+    return MPMX_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ==
+
+extern "C" {
+
+int mpmx_version(void) { return MPMX_VERSION; }
+
+int mpmx_create(mpmx_ctx **out, int device, void *stream)
+{
+    if (!out)
+        return MPMX_E_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return MPMX_E_HIP;
+    if (hipSetDevice(device) != hipSuccess)
+        return MPMX_E_HIP;
+    auto *ctx = new (std::nothrow) mpmx_ctx();
+    if (!ctx)
+        return MPMX_E_OOM;
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->num_cu = prop.multiProcessorCount;
+    if (stream) {
+        ctx->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return MPMX_E_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    *out = ctx;
+    return MPMX_OK;
+}
+
+void mpmx_destroy(mpmx_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->scenes)
+        free_scene(kv.second.get());
+    ctx->scenes.clear();
+    ctx->cached_batch.release();
+    for (auto &pe : ctx->prof.pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    for (auto e : ctx->prof.pool)
+        (void)hipEventDestroy(e);
+    if (ctx->own_stream)
+        (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *mpmx_last_error(const mpmx_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int mpmx_profile_enable(mpmx_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    if (!enable) {
+        int rc = flush_profile(ctx);
+        if (rc)
+            return rc;
+    }
+    ctx->prof.on = enable != 0;
+    return MPMX_OK;
+}
+
+int mpmx_profile_reset(mpmx_ctx *ctx)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    int rc = flush_profile(ctx);
+    if (rc)
+        return rc;
+    ctx->prof.totals.clear();
+    return MPMX_OK;
+}
+
+int mpmx_profile_read(mpmx_ctx *ctx, int cap, const char **names, int64_t *launches, double *ms, int *n)
+{
+    if (!ctx || !n || cap < 0)
+        return MPMX_E_INVALID_ARG;
+    int rc = flush_profile(ctx);
+    if (rc)
+        return rc;
+    int i = 0;
+    for (auto &kv : ctx->prof.totals) {
+        if (i < cap) {
+            if (names)
+                names[i] = kv.first.c_str();
+            if (launches)
+                launches[i] = kv.second.first;
+            if (ms)
+                ms[i] = kv.second.second;
+        }
+        ++i;
+    }
+    *n = i;
+    return MPMX_OK;
+}
+
+int mpmx_scene_bytes(const mpmx_mesh *mesh, const mpmx_scheme *scheme, int64_t n_particles, uint64_t *bytes)
+{
+    if (!bytes || n_particles < 0)
+        return MPMX_E_INVALID_ARG;
+    int rc = validate(nullptr, mesh, nullptr, nullptr, scheme);
+    if (rc)
+        return rc;
+    Sizes s = sizes_of(mesh, scheme->shape, scheme->precision, n_particles);
+    *bytes = scene_bytes(s, n_particles, false);
+    return MPMX_OK;
+}
+
+int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat, const mpmx_bc *bc,
+                      const mpmx_scheme *sch, const mpmx_particles *parts, uint64_t *scene_out)
+{
+    if (!ctx || !scene_out)
+        return MPMX_E_INVALID_ARG;
+    ctx->err.clear();
+    *scene_out = 0;
+    if (!mat || !bc)
+        return fail(ctx, MPMX_E_INVALID_ARG, "material and bc descriptors are required");
+    int rc = validate(ctx, mesh, mat, bc, sch);
+    if (rc)
+        return rc;
+    if (!parts || parts->size < sizeof(mpmx_particles) || parts->n < 0 ||
+        (parts->mem != MPMX_MEM_HOST && parts->mem != MPMX_MEM_DEVICE))
+        return fail(ctx, MPMX_E_INVALID_ARG, "particles descriptor invalid");
+    const int64_t np = parts->n;
+    if (np > 0 && (!parts->x || !parts->v || !parts->vol || !parts->mass))
+        return fail(ctx, MPMX_E_INVALID_ARG, "particles: x, v, vol and mass are required");
+    if (np >= (int64_t)1 << 31)
+        return fail(ctx, MPMX_E_INVALID_ARG, "particles: at most 2^31 - 1 per scene");
+    const Sizes sz = sizes_of(mesh, sch->shape, sch->precision, np);
+    if (sz.nkeys >= (int64_t)1 << 32)
+        return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys");
+    const bool extra = bc->n_extra > 0;
+    for (int64_t e = 0; e < bc->n_extra; ++e)
+        if (bc->node[e] < 0 || bc->node[e] >= sz.nn || bc->axis[e] < 0 || bc->axis[e] > 2 ||
+            !std::isfinite(bc->value[e]))
+            return fail(ctx, MPMX_E_INVALID_ARG, "bc: constraint %lld names node %lld axis %d", (long long)e,
+                        (long long)bc->node[e], bc->axis[e]);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+
+    auto sc = std::make_unique<Scene>();
+    Scene *s = sc.get();
+    s->prec = sch->precision;
+    s->shape = sch->shape;
+    s->algo = sch->algo;
+    SceneDev &h = s->h;
+    auto dalloc = [&](uint64_t bytes, bool zero) -> void * {
+        if (bytes == 0)
+            return nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, align_up(bytes)) != hipSuccess)
+            return nullptr;
+        s->allocs.push_back(p);
+        s->bytes += align_up(bytes);
+        if (zero && hipMemset(p, 0, align_up(bytes)) != hipSuccess)
+            return nullptr;
+        return p;
+    };
+    bool ok = true;
+    auto need = [&](void *p, uint64_t bytes) {
+        if (bytes && !p)
+            ok = false;
+        return p;
+    };
+    const uint64_t R = sz.real;
+    for (int b = 0; b < 2; ++b) {
+        h.x[b] = (double *)need(dalloc(3 * 8 * (uint64_t)np, false), np);
+        h.v[b] = need(dalloc(3 * R * np, false), np);
+        h.sig[b] = need(dalloc(6 * R * np, false), np);
+        h.vol[b] = need(dalloc(R * np, false), np);
+        h.mass[b] = need(dalloc(R * np, false), np);
+        h.key[b] = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
+        h.pid[b] = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
+    }
+    h.nm = (double *)need(dalloc(8 * (uint64_t)sz.nn, true), 1);
+    h.np_ = need(dalloc(3 * R * sz.nn, true), 1);
+    h.nf = need(dalloc(3 * R * sz.nn, true), 1);
+    h.cnt = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nkeys, true), 1);
+    h.cstart = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nkeys, false), 1);
+    h.rank = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
+    h.bcnt = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nbricks, true), 1);
+    h.bitem = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nbricks, true), 1);
+    h.bstart = (uint32_t *)need(dalloc(4 * (uint64_t)(sz.nbricks + 1), true), 1);
+    h.istart = (uint32_t *)need(dalloc(4 * (uint64_t)(sz.nbricks + 1), true), 1);
+    h.items = (Item *)need(dalloc(sizeof(Item) * (uint64_t)sz.max_items, true), 1);
+    h.tiles = (Tile *)need(dalloc(sizeof(Tile) * (uint64_t)sz.max_items, true), 1);
+    h.ctl = (uint32_t *)need(dalloc(4 * CTL_WORDS, true), 1);
+    s->d = (SceneDev *)need(dalloc(sizeof(SceneDev), false), 1);
+    if (extra) {
+        std::vector<uint8_t> mask(sz.nn, 0);
+        std::vector<double> val(3 * sz.nn, 0.0);
+        for (int64_t e = 0; e < bc->n_extra; ++e) {
+            mask[bc->node[e]] |= (uint8_t)(1u << bc->axis[e]);
+            val[3 * bc->node[e] + bc->axis[e]] = bc->value[e];
+        }
+        void *dm = need(dalloc(sz.nn, false), 1);
+        void *dv = need(dalloc(24 * (uint64_t)sz.nn, false), 1);
+        if (ok) {
+            HIPCHK(ctx, hipMemcpy(dm, mask.data(), sz.nn, hipMemcpyHostToDevice));
+            HIPCHK(ctx, hipMemcpy(dv, val.data(), 24 * sz.nn, hipMemcpyHostToDevice));
+        }
+        h.bc_mask = (const uint8_t *)dm;
+        h.bc_val = (const double *)dv;
+    }
+    if (!ok) {
+        free_scene(s);
+        return fail(ctx, MPMX_E_OOM, "device allocation of %llu bytes failed",
+                    (unsigned long long)scene_bytes(sz, np, extra));
+    }
+
+    for (int a = 0; a < 3; ++a) {
+        h.origin[a] = mesh->origin[a];
+        h.n[a] = mesh->n[a];
+        h.nb[a] = (int)sz.nb[a];
+        h.N[a] = (int)sz.N[a];
+        h.g[a] = sch->gravity[a];
+    }
+    h.h = mesh->h;
+    h.ghost = sz.ghost;
+    h.nn = sz.nn;
+    h.nkeys = sz.nkeys;
+    h.nbricks = sz.nbricks;
+    h.np = np;
+    h.max_items = sz.max_items;
+    h.model = mat->model;
+    h.sort_always = sch->sort_policy == MPMX_SORT_ALWAYS;
+    const double E = mat->E, nu = mat->nu;
+    h.G = E / (2.0 * (1.0 + nu));
+    h.K = E / (3.0 * (1.0 - 2.0 * nu));
+    h.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    if (mat->model == MPMX_DRUCKER_PRAGER) {
+        double eta, xi, etab;
+        dp_constants(mat, eta, xi, etab);
+        h.eta = eta;
+        h.xic = xi * mat->c;
+        h.etab = etab;
+        h.has_apex = eta > 0.0;
+        h.apex_p = eta > 0.0 ? xi * mat->c / eta : 0.0;
+    }
+    h.algo = sch->algo;
+    h.shape = sch->shape;
+    h.vel_update = sch->velocity_update;
+    h.prec = sch->precision;
+    h.dt = sch->dt;
+    uint32_t fb = 0;
+    for (int f = 0; f < 6; ++f)
+        fb |= (uint32_t)bc->face[f] << (2 * f);
+    h.face_bits = fb;
+
+    // particles: host inputs are staged through device memory
+    const double *dx = parts->x, *dv = parts->v, *dsig = parts->stress, *dvol = parts->vol, *dmass = parts->mass;
+    std::vector<void *> staging;
+    if (np > 0 && parts->mem == MPMX_MEM_HOST) {
+        double mean = 0.0;
+        for (int64_t p = 0; p < np; ++p)
+            mean += parts->mass[p];
+        h.eps_m = sch->mass_eps_rel * (mean / (double)np);
+        auto up = [&](const double *src, size_t count) -> const double * {
+            if (!src)
+                return nullptr;
+            void *p = nullptr;
+            if (hipMalloc(&p, count * 8) != hipSuccess)
+                return (const double *)(ok = false, nullptr);
+            staging.push_back(p);
+            if (hipMemcpy(p, src, count * 8, hipMemcpyHostToDevice) != hipSuccess)
+                ok = false;
+            return (const double *)p;
+        };
+        dx = up(parts->x, 3 * np);
+        dv = up(parts->v, 3 * np);
+        dsig = up(parts->stress, 6 * np);
+        dvol = up(parts->vol, np);
+        dmass = up(parts->mass, np);
+    } else if (np > 0) {
+        std::vector<double> m(np);
+        if (hipMemcpy(m.data(), parts->mass, 8 * np, hipMemcpyDeviceToHost) != hipSuccess)
+            ok = false;
+        double mean = 0.0;
+        for (int64_t p = 0; p < np; ++p)
+            mean += m[p];
+        h.eps_m = sch->mass_eps_rel * (mean / (double)np);
+    }
+    uint32_t ctl[CTL_WORDS] = {0};
+    ctl[CTL_NEED_SORT] = 1;
+    if (ok && hipMemcpy(h.ctl, ctl, sizeof ctl, hipMemcpyHostToDevice) != hipSuccess)
+        ok = false;
+    if (ok && hipMemcpy(s->d, &h, sizeof(SceneDev), hipMemcpyHostToDevice) != hipSuccess)
+        ok = false;
+    if (ok && np > 0) {
+        const KernelSet &K = kernel_set(s->prec, s->shape);
+        SceneDev *d = s->d;
+        void *args[] = {&d, &dx, &dv, &dsig, &dvol, &dmass};
+        if (hipLaunchKernel(K.load, particle_grid(np), dim3(kParticleBlock), args, 0, ctx->stream) != hipSuccess)
+            ok = false;
+    }
+    if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        ok = false;
+    for (void *p : staging)
+        (void)hipFree(p);
+    if (!ok) {
+        free_scene(s);
+        return fail(ctx, MPMX_E_HIP, "scene upload failed");
+    }
+    if (hipMemcpy(ctl, h.ctl, sizeof ctl, hipMemcpyDeviceToHost) != hipSuccess) {
+        free_scene(s);
+        return fail(ctx, MPMX_E_HIP, "scene status read failed");
+    }
+    if (ctl[CTL_ERR]) {
+        free_scene(s);
+        return fail(ctx, err_code(ctl[CTL_ERR]), "input particle outside the mesh or not finite (bits %u)",
+                    ctl[CTL_ERR]);
+    }
+    std::vector<Scene *> one{s};
+    rc = build_batch(ctx, s->single, one);
+    if (rc) {
+        free_scene(s);
+        return rc;
+    }
+    s->id = ctx->next_id++;
+    *scene_out = s->id;
+    ctx->scenes[s->id] = std::move(sc);
+    return MPMX_OK;
+}
+
+int mpmx_scene_step(mpmx_ctx *ctx, uint64_t scene, int64_t nsteps)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    Scene *s = find(ctx, scene);
+    if (!s)
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
+    if (nsteps < 0)
+        return fail(ctx, MPMX_E_INVALID_ARG, "nsteps must be >= 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return run_steps(ctx, s->single, nullptr, nsteps);
+}
+
+int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n)
+{
+    if (!ctx || n < 0 || (n > 0 && (!scenes || !nsteps)))
+        return MPMX_E_INVALID_ARG;
+    if (n == 0)
+        return MPMX_OK;
+    std::vector<Scene *> list;
+    std::vector<uint64_t> ids(scenes, scenes + n);
+    for (int i = 0; i < n; ++i) {
+        Scene *s = find(ctx, scenes[i]);
+        if (!s)
+            return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scenes[i]);
+        if (nsteps[i] < 0)
+            return fail(ctx, MPMX_E_INVALID_ARG, "nsteps[%d] < 0", i);
+        if (std::find(list.begin(), list.end(), s) != list.end())
+            return fail(ctx, MPMX_E_INVALID_ARG, "scene %llu listed twice", (unsigned long long)scenes[i]);
+        if (!list.empty() && (s->prec != list[0]->prec || s->shape != list[0]->shape || s->algo != list[0]->algo))
+            return fail(ctx, MPMX_E_INVALID_ARG, "batched scenes must share precision, shape and algorithm");
+        list.push_back(s);
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (ctx->cached_batch.ids != ids) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        int rc = build_batch(ctx, ctx->cached_batch, list);
+        if (rc)
+            return rc;
+    }
+    return run_steps(ctx, ctx->cached_batch, nsteps, 0);
+}
+
+int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out)
+{
+    if (!ctx || !out || out->size < sizeof(mpmx_particles_out) ||
+        (out->mem != MPMX_MEM_HOST && out->mem != MPMX_MEM_DEVICE))
+        return MPMX_E_INVALID_ARG;
+    Scene *s = find(ctx, scene);
+    if (!s)
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t np = s->h.np;
+    if (np > 0) {
+        double *x = out->x, *v = out->v, *sg = out->stress, *vol = out->vol;
+        int32_t *cell = out->cell;
+        std::vector<void *> tmp;
+        auto dev = [&](void *host, size_t bytes) -> void * {
+            if (!host || out->mem == MPMX_MEM_DEVICE)
+                return host;
+            void *p = nullptr;
+            if (hipMalloc(&p, bytes) != hipSuccess)
+                return nullptr;
+            tmp.push_back(p);
+            return p;
+        };
+        double *dx = (double *)dev(x, 24 * np), *dv = (double *)dev(v, 24 * np);
+        double *ds = (double *)dev(sg, 48 * np), *dvo = (double *)dev(vol, 8 * np);
+        int32_t *dc = (int32_t *)dev(cell, 4 * np);
+        bool ok = (!x || dx) && (!v || dv) && (!sg || ds) && (!vol || dvo) && (!cell || dc);
+        const KernelSet &K = kernel_set(s->prec, s->shape);
+        SceneDev *d = s->d;
+        void *args[] = {&d, &dx, &dv, &ds, &dvo, &dc};
+        if (ok && hipLaunchKernel(K.read_out, particle_grid(np), dim3(kParticleBlock), args, 0, ctx->stream) !=
+                      hipSuccess)
+            ok = false;
+        if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
+            ok = false;
+        if (ok && out->mem == MPMX_MEM_HOST) {
+            if (x && hipMemcpy(x, dx, 24 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+            if (v && hipMemcpy(v, dv, 24 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+            if (sg && hipMemcpy(sg, ds, 48 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+            if (vol && hipMemcpy(vol, dvo, 8 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+            if (cell && hipMemcpy(cell, dc, 4 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        }
+        for (void *p : tmp)
+            (void)hipFree(p);
+        if (!ok)
+            return fail(ctx, MPMX_E_HIP, "particle read failed");
+    }
+    uint32_t ctl[CTL_WORDS];
+    int rc = read_ctl(ctx, s, ctl);
+    if (rc)
+        return rc;
+    if (ctl[CTL_ERR])
+        return fail(ctx, err_code(ctl[CTL_ERR]), "scene stopped on error bits %u", ctl[CTL_ERR]);
+    return MPMX_OK;
+}
+
+int mpmx_scene_cell_counts(mpmx_ctx *ctx, uint64_t scene, uint32_t *counts, int32_t mem)
+{
+    if (!ctx || !counts || (mem != MPMX_MEM_HOST && mem != MPMX_MEM_DEVICE))
+        return MPMX_E_INVALID_ARG;
+    Scene *s = find(ctx, scene);
+    if (!s)
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t nc = (int64_t)s->h.n[0] * s->h.n[1] * s->h.n[2];
+    uint32_t *d = counts;
+    if (mem == MPMX_MEM_HOST)
+        HIPCHK(ctx, hipMalloc(&d, 4 * nc));
+    HIPCHK(ctx, hipMemsetAsync(d, 0, 4 * nc, ctx->stream));
+    SceneDev *sd = s->d;
+    void *args[] = {&sd, &d};
+    hipError_t e = hipSuccess;
+    if (s->h.np > 0)
+        e = hipLaunchKernel(common_kernels().cell_counts, particle_grid(s->h.np), dim3(kParticleBlock), args, 0,
+                            ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && mem == MPMX_MEM_HOST)
+        e = hipMemcpy(counts, d, 4 * nc, hipMemcpyDeviceToHost);
+    if (mem == MPMX_MEM_HOST)
+        (void)hipFree(d);
+    if (e != hipSuccess)
+        return fail(ctx, MPMX_E_HIP, "cell counts: %s", hipGetErrorString(e));
+    return MPMX_OK;
+}
+
+int mpmx_scene_nodes(mpmx_ctx *ctx, uint64_t scene, double *mass, double *momentum, double *force)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    Scene *s = find(ctx, scene);
+    if (!s)
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int64_t nn = s->h.nn;
+    double *dm = nullptr, *dp = nullptr, *df = nullptr;
+    if (mass)
+        HIPCHK(ctx, hipMalloc(&dm, 8 * nn));
+    if (momentum)
+        HIPCHK(ctx, hipMalloc(&dp, 24 * nn));
+    if (force)
+        HIPCHK(ctx, hipMalloc(&df, 24 * nn));
+    SceneDev *sd = s->d;
+    void *args[] = {&sd, &dm, &dp, &df};
+    hipError_t e = hipLaunchKernel(kernel_set(s->prec, s->shape).nodes_out, particle_grid(nn), dim3(kParticleBlock),
+                                   args, 0, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && mass)
+        e = hipMemcpy(mass, dm, 8 * nn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && momentum)
+        e = hipMemcpy(momentum, dp, 24 * nn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && force)
+        e = hipMemcpy(force, df, 24 * nn, hipMemcpyDeviceToHost);
+    if (dm) (void)hipFree(dm);
+    if (dp) (void)hipFree(dp);
+    if (df) (void)hipFree(df);
+    if (e != hipSuccess)
+        return fail(ctx, MPMX_E_HIP, "node read: %s", hipGetErrorString(e));
+    return MPMX_OK;
+}
+
+int mpmx_scene_stats(mpmx_ctx *ctx, uint64_t scene, mpmx_stats *out)
+{
+    if (!ctx || !out || out->size < sizeof(mpmx_stats))
+        return MPMX_E_INVALID_ARG;
+    Scene *s = find(ctx, scene);
+    if (!s)
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    uint32_t ctl[CTL_WORDS];
+    int rc = read_ctl(ctx, s, ctl);
+    if (rc)
+        return rc;
+    const int64_t nc = (int64_t)s->h.n[0] * s->h.n[1] * s->h.n[2];
+    std::vector<uint32_t> counts(nc);
+    rc = mpmx_scene_cell_counts(ctx, scene, counts.data(), MPMX_MEM_HOST);
+    if (rc)
+        return rc;
+    int64_t active = 0;
+    for (uint32_t c : counts)
+        active += c > 0;
+    out->n_particles = s->h.np;
+    out->steps_done = ctl[CTL_STEPS];
+    out->n_sorts = ctl[CTL_N_SORTS];
+    out->n_items = ctl[CTL_N_ITEMS];
+    out->active_cells = active;
+    out->error_bits = ctl[CTL_ERR];
+    out->device_bytes = s->bytes;
+    return MPMX_OK;
+}
+
+int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    auto it = ctx->scenes.find(scene);
+    if (it == ctx->scenes.end())
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (std::find(ctx->cached_batch.ids.begin(), ctx->cached_batch.ids.end(), scene) != ctx->cached_batch.ids.end()) {
+        ctx->cached_batch.release();
+        ctx->cached_batch.ids.clear();
+    }
+    free_scene(it->second.get());
+    ctx->scenes.erase(it);
+    return MPMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""The C ABI library without a GPU: it loads, exports every function that
+include/mpmx.h declares, its descriptor layouts agree with what a C compiler
+makes of the header, and the pure sizing call works.  No compute runs."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mpmx():
+    from paper_1909_13380_amd import mpmx
+    return mpmx
+
+
+def test_library_exports_every_declared_function(mpmx):
+    names = mpmx.declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(mpmx.LIBPATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert mpmx.version() == 1
+
+
+def test_descriptor_layouts_match_the_c_header(mpmx, tmp_path):
+    structs = {"mpmx_mesh": mpmx.Mesh, "mpmx_material": mpmx.Material, "mpmx_bc": mpmx.Bc,
+               "mpmx_scheme": mpmx.Scheme, "mpmx_particles": mpmx.Particles,
+               "mpmx_particles_out": mpmx.ParticlesOut, "mpmx_stats": mpmx.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpmx.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            if field != "pad_":
+                lines.append(f'printf("{cname}.{field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True)
+               .stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            if field != "pad_":
+                assert int(got[f"{cname}.{field}"]) == getattr(py, field).offset, f"{cname}.{field}"
+
+
+def test_scene_bytes_is_pure_and_grows_with_size(mpmx):
+    from paper_1909_13380_amd import scenes
+    sc = scenes.c1()
+    b32 = mpmx.scene_bytes(sc, mpmx.FP32)
+    b64 = mpmx.scene_bytes(sc, mpmx.FP64)
+    assert 0 < b32 < b64
+    assert mpmx.scene_bytes(sc, mpmx.FP32, n_particles=2 * len(sc["x"])) > b32
+    # particles dominate at the large column: ~150 B per particle plus nodes
+    col = {"mesh": {"n": (256, 128, 160), "origin": (0, 0, 0), "h": 0.01}, "scheme": scenes.scheme(2e-5)}
+    b = mpmx.scene_bytes(col, mpmx.FP32, n_particles=2_097_152)
+    assert 400e6 < b < 700e6
+
+
+def test_invalid_descriptors_are_rejected(mpmx):
+    from paper_1909_13380_amd import scenes
+    sc = scenes.c1()
+    bad = dict(sc, mesh={"n": (0, 4, 4), "origin": (0, 0, 0), "h": 0.1})
+    with pytest.raises(mpmx.MpmxError) as e:
+        mpmx.scene_bytes(bad)
+    assert e.value.code == mpmx.E_INVALID_ARG
+    bad = dict(sc, scheme=dict(sc["scheme"], dt=-1.0))
+    with pytest.raises(mpmx.MpmxError):
+        mpmx.scene_bytes(bad)
+    with pytest.raises(mpmx.MpmxError):
+        mpmx.scene_bytes(sc, n_particles=-5)
+
+
+def test_context_creation_fails_cleanly_without_a_gpu(mpmx):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(mpmx.MpmxError) as e:
+        mpmx.Context(0)
+    assert e.value.code == mpmx.E_HIP

@@ -1,0 +1,346 @@
+"""GPU parity: the HIP library, called through its C ABI, against the FP64
+oracle on the same seeded inputs.
+
+Bars (relative L2 over all particles and components): displacement
+u = x_N - x_0 within 1e-4 and stress within 1e-3 for FP32 scenes; FP64
+scenes agree to rounding (the order of atomic sums differs), within 1e-9.
+Particles per cell (active cells) are compared bit for bit: exactly on
+identical positions, and after several steps up to particles lying within
+1e-6 h of a cell face (whose positions differ in the last bits).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_13380_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+U_TOL, S_TOL = 1e-4, 1e-3
+
+
+@pytest.fixture(scope="module")
+def mp():
+    from paper_1909_13380_amd import mpmx
+    return mpmx
+
+
+@pytest.fixture(scope="module")
+def ctx(mp):
+    c = mp.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def check_state(name, got, ref, x0, u_tol, s_tol, v_tol=None):
+    eu = rel(got["x"] - x0, ref["x"] - x0)
+    es = rel(got["stress"], ref["stress"])
+    ev = rel(got["v"], ref["v"])
+    evol = rel(got["vol"], ref["vol"])
+    print(f"[{name}] err_u={eu:.3e} err_sigma={es:.3e} err_v={ev:.3e} err_vol={evol:.3e}", flush=True)
+    assert eu <= u_tol, (name, "displacement", eu)
+    assert es <= s_tol, (name, "stress", es)
+    assert ev <= (v_tol if v_tol is not None else u_tol), (name, "velocity", ev)
+    assert evol <= s_tol, (name, "volume", evol)
+
+
+def near_face(mesh, x, tol_frac=1e-6):
+    t = (x - np.asarray(mesh["origin"])) / mesh["h"]
+    return np.any(np.abs(t - np.round(t)) < tol_frac, axis=1)
+
+
+def check_histograms(sc, got_counts, x_gpu, x_ref):
+    ref_counts = oracle.cell_counts(sc["mesh"], x_ref)
+    if np.array_equal(got_counts, ref_counts):
+        return 0
+    cg = oracle.locate(sc["mesh"], x_gpu)
+    cr = oracle.locate(sc["mesh"], x_ref)
+    differ = cg != cr
+    assert np.all(near_face(sc["mesh"], x_ref[differ])), "cell mismatch away from faces"
+    np.testing.assert_array_equal(got_counts, np.bincount(cg, minlength=len(ref_counts)))
+    return int(differ.sum())
+
+
+def block(shape=0, material=None, algo=0, seed=21, n_cells=(9, 7, 6), **kw):
+    sc = scenes.random_block(n_cells=n_cells, mesh_cells=(14, 11, 9), h=0.05, shape=shape, seed=seed,
+                             material=material, stress_scale=kw.pop("stress_scale", 3e3), **kw)
+    sc["scheme"]["algo"] = algo
+    return sc
+
+
+MATERIALS = {"le": scenes.elastic(), "dp": scenes.drucker_prager(), "dpc": scenes.drucker_prager(psi_deg=10, c=2e3)}
+
+
+# ------------------------------------------------------------- binning --
+
+@pytest.mark.parametrize("which", ["c1", "column_small", "ragged"])
+def test_binning_is_bit_exact_on_identical_positions(ctx, mp, which):
+    if which == "c1":
+        sc = scenes.c1()
+    elif which == "column_small":
+        sc = scenes.c5(subsample=True, shape=scenes.SHAPE_LINEAR)
+    else:
+        sc = block()
+        # particles exactly on interior cell faces (dyadic h and origin)
+        sc = dict(sc, mesh=dict(sc["mesh"], h=0.0625))
+        sc["x"] = scenes.block_positions((2, 2, 0), (10, 8, 6), 0.0625, layout="centre")
+        sc["x"][::7, 0] = np.floor(sc["x"][::7, 0] / 0.0625) * 0.0625
+        n = len(sc["x"])
+        sc.update(v=np.zeros((n, 3)), vol=np.full(n, 1e-4), mass=np.full(n, 0.18), stress=np.zeros((n, 6)))
+    s = ctx.create_scene(sc)
+    got = s.cell_counts()
+    ref = oracle.cell_counts(sc["mesh"], sc["x"])
+    np.testing.assert_array_equal(got, ref)
+    cells = s.read()["cell"]
+    np.testing.assert_array_equal(cells, oracle.locate(sc["mesh"], sc["x"]))
+    assert s.stats()["active_cells"] == int((ref > 0).sum())
+    s.destroy()
+
+
+# ------------------------------------------------------------ one step --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("mat", ["le", "dp", "dpc"])
+def test_one_step_nodes_and_particles_match_oracle(ctx, mp, prec, shape, algo, mat):
+    sc = block(shape=shape, material=MATERIALS[mat], algo=algo)
+    if mat != "le":
+        # pre-stress in compression so the return map is exercised on both branches
+        sc["stress"][:, :3] -= 2e3
+        sc["stress"] = sc["stress"].astype(np.float32).astype(np.float64)
+    p = mp.FP64 if prec == "fp64" else mp.FP32
+    s = ctx.create_scene(sc, precision=p)
+    s.step(1)
+    got = s.read()
+    nodes = s.nodes()
+    ref = oracle.run(sc, 1)
+    g = ref["grid"]
+    tol = 1e-9 if prec == "fp64" else 2e-5
+    name = f"{prec}/{'gimp' if shape else 'linear'}/{'usl' if algo else 'usf'}/{mat}"
+    for k, a, b in (("m", nodes["m"], g.m), ("p", nodes["p"], g.p), ("f", nodes["f"], g.f)):
+        e = rel(a, b)
+        print(f"[{name}] nodal {k}: {e:.3e}", flush=True)
+        assert e <= tol, (name, k, e)
+    check_state(name, got, ref, sc["x"], tol, tol, tol)
+    s.destroy()
+
+
+def test_bricks_split_into_several_items(ctx, mp):
+    """64 particles per cell: 4096 per brick, eight 512-particle work items."""
+    h = 0.05
+    x = scenes.block_positions((2, 2, 0), (10, 9, 6), h, layout="centre")
+    off = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)]) * (h / 4) - h / 8
+    x = (x[:, None, :] + off[None]).reshape(-1, 3)
+    rng = np.random.default_rng(3)
+    sc = scenes.make_scene("dense", {"n": (12, 11, 8), "origin": (0, 0, 0), "h": h}, scenes.drucker_prager(),
+                           scenes.walls(), scenes.scheme(1e-5), x, rng.uniform(-0.2, 0.2, x.shape), 3)
+    sc["vol"] = sc["vol"] / 8
+    sc["mass"] = sc["mass"] / 8
+    s = ctx.create_scene(sc, precision=mp.FP64)
+    s.step(3)
+    got = s.read()
+    # work items: ceil(particles of the brick / 512) per 4x4x4-cell brick
+    c = np.floor(sc["x"] / h).astype(int)
+    bricks = c // 4
+    _, per_brick = np.unique(bricks[:, 0] + 100 * (bricks[:, 1] + 100 * bricks[:, 2]), return_counts=True)
+    assert per_brick.max() == 4096
+    assert s.stats()["n_items"] == int(np.sum((per_brick + 511) // 512))
+    ref = oracle.run(sc, 3)
+    check_state("dense", got, ref, sc["x"], 1e-9, 1e-9, 1e-9)
+    s.destroy()
+
+
+# --------------------------------------------------------- closed forms --
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_free_fall_on_gpu(ctx, mp, shape):
+    sc = scenes.free_body(v0=(0.3, -0.2, 0.1), shape=shape)
+    sc["scheme"]["mass_eps_rel"] = 0.0
+    v0 = sc["v"][0]
+    g = np.array(scenes.GRAVITY)
+    dt = sc["scheme"]["dt"]
+    n = 40
+    for prec, tol in ((mp.FP64, 1e-11), (mp.FP32, 2e-6)):
+        s = ctx.create_scene(sc, precision=prec)
+        s.step(n)
+        got = s.read()
+        vref = v0 + n * g * dt
+        uref = n * dt * v0 + g * dt * dt * n * (n + 1) / 2
+        assert rel(got["v"], np.broadcast_to(vref, got["v"].shape)) < tol
+        assert rel(got["x"] - sc["x"], np.broadcast_to(uref, sc["x"].shape)) < tol
+        # FP32: rounding noise of the ideally zero stress, amplified at the
+        # near-void nodes of the GIMP support (0.01 Pa scale)
+        assert np.abs(got["stress"]).max() < (1e-8 if prec == mp.FP64 else 0.2)
+        s.destroy()
+
+
+def test_transfers_conserve_mass_momentum_and_weight(ctx, mp):
+    sc = block(stress_scale=5e3)
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(1)
+    nd = s.nodes()
+    M = sc["mass"].sum()
+    assert abs(nd["m"].sum() / M - 1) < 1e-6           # FP32 weights, FP64 accumulation
+    P = (sc["mass"][:, None] * sc["v"]).sum(axis=0)
+    assert np.abs(nd["p"].sum(axis=0) - P).max() < 1e-5 * (sc["mass"][:, None] * np.abs(sc["v"])).sum()
+    assert np.abs(nd["f"].sum(axis=0) - M * np.array(scenes.GRAVITY)).max() < 1e-5 * np.abs(nd["f"]).sum()
+    s.destroy()
+
+
+# ----------------------------------------------------------- configs ----
+
+def test_c1_full_run_within_bars(ctx, mp):
+    sc = scenes.c1()
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(sc["nsteps"])
+    got = s.read()
+    ref = oracle.run(sc, sc["nsteps"])
+    check_state("c1/fp32/200", got, ref, sc["x"], U_TOL, S_TOL, 1e-3)
+    check_histograms(sc, s.cell_counts(), got["x"], ref["x"])
+    s.destroy()
+    s = ctx.create_scene(sc, precision=mp.FP64)
+    s.step(sc["nsteps"])
+    got = s.read()
+    check_state("c1/fp64/200", got, ref, sc["x"], 1e-9, 1e-9, 1e-9)
+    s.destroy()
+
+
+def test_column_full_size_first_steps(ctx, mp):
+    """The 2.1M-particle Drucker-Prager column in the benchmark's launch
+    configuration (FP32, on-demand reordering): identical binning of the
+    input, then 2 steps against the oracle."""
+    sc = scenes.c2()
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    np.testing.assert_array_equal(s.cell_counts(), oracle.cell_counts(sc["mesh"], sc["x"]))
+    s.step(2)
+    got = s.read()
+    ref = oracle.run(sc, 2)
+    check_state("column/fp32/2", got, ref, sc["x"], U_TOL, S_TOL, 1e-3)
+    check_histograms(sc, s.cell_counts(), got["x"], ref["x"])
+    s.destroy()
+
+
+@pytest.mark.parametrize("shape", [1, 0])
+def test_column_subsample_steps(ctx, mp, shape):
+    """The 1/64 subsample of the 25M-particle column (393,216 particles,
+    64x32x24 block on a 128x64x32 mesh), GIMP and linear, 10 steps."""
+    sc = scenes.c5(subsample=True, shape=shape)
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(10)
+    got = s.read()
+    ref = oracle.run(sc, 10)
+    check_state(f"column_sub/{'gimp' if shape else 'linear'}/10", got, ref, sc["x"], U_TOL, S_TOL, 1e-3)
+    check_histograms(sc, s.cell_counts(), got["x"], ref["x"])
+    s.destroy()
+
+
+# ------------------------------------------------------------- runtime --
+
+def test_sort_policies_and_step_chunking_agree(ctx, mp):
+    sc = block(material=MATERIALS["dp"], vel=8.0, seed=5, n_cells=(6, 5, 4))
+    sc["scheme"]["dt"] = 2e-4   # fast particles: reorders along the way
+    runs = []
+    for policy, chunks in ((mp.SORT_ON_DEMAND, [30]), (mp.SORT_ALWAYS, [30]), (mp.SORT_ON_DEMAND, [7, 1, 22])):
+        s = ctx.create_scene(sc, precision=mp.FP64, sort_policy=policy)
+        for c in chunks:
+            s.step(c)
+        runs.append((s.read(), s.stats()))
+        s.destroy()
+    assert runs[1][1]["n_sorts"] == 30
+    assert runs[0][1]["n_sorts"] >= 1
+    for (r, _) in runs[1:]:
+        check_state("policy", r, runs[0][0], sc["x"], 1e-9, 1e-9, 1e-9)
+    ref = oracle.run(sc, 30)
+    check_state("policy/oracle", runs[0][0], ref, sc["x"], 1e-9, 1e-9, 1e-9)
+
+
+def test_batch_equals_alone(ctx, mp):
+    scs = [block(material=MATERIALS["dp"], seed=31), scenes.c1(),
+           block(material=MATERIALS["le"], seed=32, n_cells=(3, 3, 2)), block(material=MATERIALS["dpc"], seed=33)]
+    nsteps = [12, 20, 5, 0]
+    alone = []
+    for sc, k in zip(scs, nsteps):
+        s = ctx.create_scene(sc, precision=mp.FP32)
+        s.step(k)
+        alone.append(s.read())
+        s.destroy()
+    batch = [ctx.create_scene(sc, precision=mp.FP32) for sc in scs]
+    ctx.batch_step(batch, nsteps)
+    for sc, b, a, k in zip(scs, batch, alone, nsteps):
+        got = b.read()
+        assert b.stats()["steps_done"] == k
+        check_state(f"batch/{sc['name']}", got, a, sc["x"], 1e-5, 1e-5, 1e-5)
+        b.destroy()
+
+
+def test_out_of_mesh_stops_the_scene(ctx, mp):
+    sc = block(seed=40)
+    sc["v"][:, 2] = 300.0               # the block rises out of the open top within ~25 steps
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(60)
+    st = s.stats()
+    assert st["error_bits"] & mp.ERRBIT_OUT_OF_MESH
+    assert 0 < st["steps_done"] < 60
+    with pytest.raises(mp.MpmxError) as e:
+        s.read()
+    assert e.value.code == mp.E_OUT_OF_MESH
+    s.destroy()
+    bad = dict(sc, x=sc["x"].copy())
+    bad["x"][0, 2] = -1.0
+    with pytest.raises(mp.MpmxError) as e:
+        ctx.create_scene(bad)
+    assert e.value.code == mp.E_OUT_OF_MESH
+
+
+def test_empty_scene_and_zero_steps(ctx, mp):
+    sc = block()
+    for k in ("x", "v", "vol", "mass", "stress"):
+        sc[k] = sc[k][:0]
+    s = ctx.create_scene(sc)
+    s.step(5)
+    assert s.read()["x"].shape == (0, 3)
+    assert s.stats()["active_cells"] == 0
+    s.destroy()
+    sc = block()
+    s = ctx.create_scene(sc)
+    s.step(0)
+    np.testing.assert_array_equal(s.read()["x"], sc["x"])
+    s.destroy()
+
+
+def test_per_node_constraints(ctx, mp):
+    sc = block(seed=41)
+    mesh = sc["mesh"]
+    ids = [oracle.node_id(mesh, 0, 5, 5, 3), oracle.node_id(mesh, 0, 6, 5, 3), oracle.node_id(mesh, 0, 5, 4, 2)]
+    sc["bc"] = {"face": sc["bc"]["face"], "extra": (ids, [0, 2, 1], [0.05, -0.1, 0.0])}
+    s = ctx.create_scene(sc, precision=mp.FP64)
+    s.step(4)
+    got = s.read()
+    ref = oracle.run(sc, 4)
+    check_state("extra_bc", got, ref, sc["x"], 1e-9, 1e-9, 1e-9)
+    s.destroy()
+
+
+def test_device_resident_inputs_and_outputs(ctx, mp):
+    import torch
+    sc = block(seed=42)
+    dev = {k: torch.tensor(np.asarray(sc[k]), dtype=torch.float64, device="cuda") for k in
+           ("x", "v", "stress", "vol", "mass")}
+    s = ctx.create_scene(sc, precision=mp.FP32, state=dev)
+    s.step(3)
+    n = len(sc["x"])
+    out = {"x": torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+           "stress": torch.empty((n, 6), dtype=torch.float64, device="cuda")}
+    s.read(device_out=out)
+    host = s.read()
+    np.testing.assert_array_equal(out["x"].cpu().numpy(), host["x"])
+    np.testing.assert_array_equal(out["stress"].cpu().numpy(), host["stress"])
+    ref = oracle.run(sc, 3)
+    check_state("device_io", host, ref, sc["x"], 2e-5, 2e-5, 2e-5)
+    s.destroy()
