@@ -3,12 +3,13 @@
 //
 // A scene owns its device buffers (layout in mpmx_dev.h).  Every step
 // is a fixed sequence of launches over a BatchDev (one scene, or many):
-//   clear -> sort_count -> sort_bricks -> sort_scan -> sort_cells ->
-//   sort_scatter -> step_control -> p2g -> stress -> g2p         (USF)
-//   clear -> sort ... -> step_control -> p2g_usl -> g2p_usl      (USL)
-// The sort kernels do nothing unless the scene flagged a reorder; all
-// counts the kernels need live in device memory, so the host never waits on
-// the GPU between steps.
+//   sort_count -> sort_bricks -> sort_cells -> sort_perm -> sort_move (its
+//   last workgroup runs the step control) -> stress -> g2p_p2g      (USF)
+//   sort ... -> p2g_usl -> g2p_usl                                  (USL)
+// plus one p2g at the start of a USF call for scenes whose node buffer is
+// not yet filled.  The sort kernels return at once unless a scene flagged a
+// reorder; all counts the kernels need live in device memory, so the host
+// never waits on the GPU between steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,19 +48,18 @@ struct Batch {
     std::vector<uint64_t> ids;
     SceneDev **d_scenes = nullptr;
     int64_t *d_poffs = nullptr, *d_boffs = nullptr, *d_nsteps = nullptr;
-    uint32_t *d_ioffs = nullptr;
+    uint32_t *d_ioffs = nullptr, *d_coffs = nullptr, *d_flags = nullptr;
     BatchDev bd{};
     int prec = 0, shape = 0, algo = 0;
     void release()
     {
-        if (d_scenes) (void)hipFree(d_scenes);
-        if (d_poffs) (void)hipFree(d_poffs);
-        if (d_boffs) (void)hipFree(d_boffs);
-        if (d_nsteps) (void)hipFree(d_nsteps);
-        if (d_ioffs) (void)hipFree(d_ioffs);
+        for (void *p : {(void *)d_scenes, (void *)d_poffs, (void *)d_boffs, (void *)d_nsteps, (void *)d_ioffs,
+                        (void *)d_coffs, (void *)d_flags})
+            if (p)
+                (void)hipFree(p);
         d_scenes = nullptr;
         d_poffs = d_boffs = d_nsteps = nullptr;
-        d_ioffs = nullptr;
+        d_ioffs = d_coffs = d_flags = nullptr;
     }
 };
 
@@ -208,10 +208,10 @@ uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc)
         b += align_up(3 * 8 * (uint64_t)np) + align_up(3 * R * np) + align_up(6 * R * np) + align_up(R * np) +
              align_up(R * np) + align_up(4 * (uint64_t)np) + align_up(4 * (uint64_t)np);
     }
-    b += align_up(8 * (uint64_t)s.nn) + 2 * align_up(3 * R * s.nn);
-    b += 2 * align_up(4 * (uint64_t)s.nkeys) + align_up(4 * (uint64_t)np);
+    b += 2 * (align_up(8 * (uint64_t)s.nn) + 2 * align_up(3 * R * s.nn));
+    b += 2 * align_up(4 * (uint64_t)s.nkeys) + 2 * align_up(4 * (uint64_t)np);
     b += 2 * align_up(4 * (uint64_t)s.nbricks) + 2 * align_up(4 * (uint64_t)(s.nbricks + 1));
-    b += align_up(sizeof(Item) * (uint64_t)s.max_items) + align_up(sizeof(Tile) * (uint64_t)s.max_items);
+    b += align_up(sizeof(Item) * (uint64_t)s.max_items) + 3 * align_up(sizeof(Tile) * (uint64_t)s.max_items);
     b += align_up(4 * CTL_WORDS) + align_up(sizeof(SceneDev));
     if (extra_bc)
         b += align_up((uint64_t)s.nn) + align_up(24 * (uint64_t)s.nn);
@@ -224,8 +224,9 @@ int validate(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat, con
     if (!mesh || mesh->size < sizeof(mpmx_mesh))
         return fail(ctx, MPMX_E_INVALID_ARG, "mesh descriptor missing or too small");
     for (int a = 0; a < 3; ++a)
-        if (mesh->n[a] < 1 || mesh->n[a] > (1 << 20) || !std::isfinite(mesh->origin[a]))
-            return fail(ctx, MPMX_E_INVALID_ARG, "mesh: n[%d]=%d / origin invalid", a, mesh->n[a]);
+        if (mesh->n[a] < 1 || mesh->n[a] > kMaxCells[a] || !std::isfinite(mesh->origin[a]))
+            return fail(ctx, MPMX_E_INVALID_ARG, "mesh: n[%d]=%d outside 1..%d or origin not finite", a, mesh->n[a],
+                        kMaxCells[a]);
     if (!(mesh->h > 0.0) || !std::isfinite(mesh->h))
         return fail(ctx, MPMX_E_INVALID_ARG, "mesh: h must be positive and finite");
     if (mat) {
@@ -323,6 +324,11 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     HIPCHK(ctx, hipMalloc(&b.d_boffs, sizeof(int64_t) * (n + 1)));
     HIPCHK(ctx, hipMalloc(&b.d_nsteps, sizeof(int64_t) * std::max(n, 1)));
     HIPCHK(ctx, hipMalloc(&b.d_ioffs, sizeof(uint32_t) * (n + 1)));
+    HIPCHK(ctx, hipMalloc(&b.d_coffs, sizeof(uint32_t) * (n + 1)));
+
+    HIPCHK(ctx, hipMalloc(&b.d_flags, sizeof(uint32_t) * BF_WORDS));
+    HIPCHK(ctx, hipMemset(b.d_coffs, 0, sizeof(uint32_t) * (n + 1)));
+    HIPCHK(ctx, hipMemset(b.d_flags, 0, sizeof(uint32_t) * BF_WORDS));
     HIPCHK(ctx, hipMemcpy(b.d_scenes, ptrs.data(), sizeof(SceneDev *) * n, hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(b.d_poffs, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(b.d_boffs, bo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
@@ -331,6 +337,9 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     b.bd.poffs = b.d_poffs;
     b.bd.boffs = b.d_boffs;
     b.bd.ioffs = b.d_ioffs;
+    b.bd.coffs = b.d_coffs;
+
+    b.bd.flags = b.d_flags;
     b.bd.nscenes = n;
     b.bd.total_particles = po[n];
     b.bd.total_bricks = bo[n];
@@ -365,46 +374,40 @@ int run_steps(mpmx_ctx *ctx, Batch &b, const int64_t *nsteps, int64_t uniform)
     const KernelSet &K = kernel_set(b.prec, b.shape);
     const CommonKernels &C = common_kernels();
     BatchDev bd = b.bd;
-    int mode0 = 0, mode1 = 1;
     const int64_t *dns = b.d_nsteps;
     void *a_bd[] = {&bd};
-    void *a_rem[] = {&bd, &dns};
-    void *a_ctl0[] = {&bd, &mode0};
-    void *a_ctl1[] = {&bd, &mode1};
+    void *a_begin[] = {&bd, &dns};
     int rc;
-    if ((rc = launch(ctx, "set_remaining", C.set_remaining, dim3(ceil_div(n, 256)), dim3(256), a_rem)))
+    if ((rc = launch(ctx, "begin", C.begin, dim3(1), dim3(1024), a_begin)))
         return rc;
-    if ((rc = launch(ctx, "step_control", C.step_control, dim3(1), dim3(1024), a_ctl0)))
-        return rc;
-    const dim3 pg = particle_grid(bd.total_particles);
-    const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), 16384));
-    const dim3 ig((unsigned)std::max<int64_t>(1, std::min<int64_t>(bd.max_items, 8 * ctx->num_cu)));
+    // sort kernels stride over their range with one block per CU: they
+    // return at once on steps that need no reorder
+    const dim3 pg = particle_grid(bd.total_particles, ctx->num_cu);
+    const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), ctx->num_cu));
+    const dim3 ig((unsigned)std::max<int64_t>(1, std::min<int64_t>(bd.max_items, 16 * ctx->num_cu)));
+    const dim3 it(kItemThreads);
     for (int64_t s = 0; s < smax; ++s) {
-        if ((rc = launch(ctx, "clear", K.clear, ig, dim3(kBlock), a_bd)))
-            return rc;
         if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)))
             return rc;
         if ((rc = launch(ctx, "sort_bricks", C.sort_bricks, bg, dim3(256), a_bd)))
             return rc;
-        if ((rc = launch(ctx, "sort_scan", C.sort_scan, dim3(std::min(n, 1024)), dim3(1024), a_bd)))
-            return rc;
         if ((rc = launch(ctx, "sort_cells", C.sort_cells, bg, dim3(256), a_bd)))
             return rc;
-        if ((rc = launch(ctx, "sort_scatter", K.scatter, pg, dim3(kParticleBlock), a_bd)))
+        if ((rc = launch(ctx, "sort_perm", C.sort_perm, pg, dim3(kParticleBlock), a_bd)))
             return rc;
-        if ((rc = launch(ctx, "step_control", C.step_control, dim3(1), dim3(1024), a_ctl1)))
+        if ((rc = launch(ctx, "sort_move", K.move, bg, dim3(256), a_bd)))
             return rc;
         if (b.algo == MPMX_USF) {
-            if ((rc = launch(ctx, "p2g", K.p2g, ig, dim3(kBlock), a_bd)))
+            if (s == 0 && (rc = launch(ctx, "p2g", K.p2g, ig, it, a_bd)))
                 return rc;
-            if ((rc = launch(ctx, "stress", K.stress, ig, dim3(kBlock), a_bd)))
+            if ((rc = launch(ctx, "stress", K.stress, ig, it, a_bd)))
                 return rc;
-            if ((rc = launch(ctx, "g2p", K.g2p, ig, dim3(kBlock), a_bd)))
+            if ((rc = launch(ctx, "g2p_p2g", K.g2p_p2g, ig, it, a_bd)))
                 return rc;
         } else {
-            if ((rc = launch(ctx, "p2g_usl", K.p2g_usl, ig, dim3(kBlock), a_bd)))
+            if ((rc = launch(ctx, "p2g_usl", K.p2g_usl, ig, it, a_bd)))
                 return rc;
-            if ((rc = launch(ctx, "g2p_usl", K.g2p_usl, ig, dim3(kBlock), a_bd)))
+            if ((rc = launch(ctx, "g2p_usl", K.g2p_usl, ig, it, a_bd)))
                 return rc;
         }
     }
@@ -570,8 +573,8 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     if (np >= (int64_t)1 << 31)
         return fail(ctx, MPMX_E_INVALID_ARG, "particles: at most 2^31 - 1 per scene");
     const Sizes sz = sizes_of(mesh, sch->shape, sch->precision, np);
-    if (sz.nkeys >= (int64_t)1 << 32)
-        return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys");
+    if (sz.nkeys >= (int64_t)1 << 32 || sz.nn >= kMaxIndex)
+        return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys and node indices");
     const bool extra = bc->n_extra > 0;
     for (int64_t e = 0; e < bc->n_extra; ++e)
         if (bc->node[e] < 0 || bc->node[e] >= sz.nn || bc->axis[e] < 0 || bc->axis[e] > 2 ||
@@ -611,21 +614,26 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         h.sig[b] = need(dalloc(6 * R * np, false), np);
         h.vol[b] = need(dalloc(R * np, false), np);
         h.mass[b] = need(dalloc(R * np, false), np);
-        h.key[b] = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
+        h.cell[b] = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
         h.pid[b] = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
     }
-    h.nm = (double *)need(dalloc(8 * (uint64_t)sz.nn, true), 1);
-    h.np_ = need(dalloc(3 * R * sz.nn, true), 1);
-    h.nf = need(dalloc(3 * R * sz.nn, true), 1);
+    for (int b = 0; b < 2; ++b) {
+        h.nm[b] = (double *)need(dalloc(8 * (uint64_t)sz.nn, true), 1);
+        h.np_[b] = need(dalloc(3 * R * sz.nn, true), 1);
+        h.nf[b] = need(dalloc(3 * R * sz.nn, true), 1);
+    }
     h.cnt = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nkeys, true), 1);
     h.cstart = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nkeys, false), 1);
     h.rank = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
+    h.perm = (uint32_t *)need(dalloc(4 * (uint64_t)np, false), np);
     h.bcnt = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nbricks, true), 1);
     h.bitem = (uint32_t *)need(dalloc(4 * (uint64_t)sz.nbricks, true), 1);
     h.bstart = (uint32_t *)need(dalloc(4 * (uint64_t)(sz.nbricks + 1), true), 1);
     h.istart = (uint32_t *)need(dalloc(4 * (uint64_t)(sz.nbricks + 1), true), 1);
     h.items = (Item *)need(dalloc(sizeof(Item) * (uint64_t)sz.max_items, true), 1);
-    h.tiles = (Tile *)need(dalloc(sizeof(Tile) * (uint64_t)sz.max_items, true), 1);
+    h.tiles[0] = (Tile *)need(dalloc(sizeof(Tile) * (uint64_t)sz.max_items, true), 1);
+    h.tiles[1] = (Tile *)need(dalloc(sizeof(Tile) * (uint64_t)sz.max_items, true), 1);
+    h.tstep = (Tile *)need(dalloc(sizeof(Tile) * (uint64_t)sz.max_items, true), 1);
     h.ctl = (uint32_t *)need(dalloc(4 * CTL_WORDS, true), 1);
     s->d = (SceneDev *)need(dalloc(sizeof(SceneDev), false), 1);
     if (extra) {
@@ -658,6 +666,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         h.g[a] = sch->gravity[a];
     }
     h.h = mesh->h;
+    h.inv_h = 1.0 / mesh->h;
     h.ghost = sz.ghost;
     h.nn = sz.nn;
     h.nkeys = sz.nkeys;

@@ -2,17 +2,20 @@
 // the host runtime of libmpmx.
 //
 // Layout in HBM (per scene):
-//   particles, structure of arrays, double-buffered for reordering:
-//     x[3][n] f64 | v[3][n] R | sig[6][n] R | vol[n] R | mass[n] R | key[n] u32 | pid[n] u32
-//   nodes, dense over the (ghost-padded) node grid:
+//   particles, structure of arrays, two buffers (a reorder moves between them):
+//     x[3][n] f64 | v[3][n] R | sig[6][n] R | vol[n] R | mass[n] R | cell[n] u32 | pid[n] u32
+//   nodes, dense over the (ghost-padded) node grid, two buffers (one step
+//   fills one while the other still holds the previous step):
 //     m[nn] f64 | p[3][nn] R | f[3][nn] R      (R = float or double)
-//   sort scratch: cnt[nkeys] u32, cstart[nkeys] u32, rank[n] u32,
+//   sort scratch: cnt[nkeys] u32, cstart[nkeys] u32, rank[n] u32, perm[n] u32,
 //     bcnt/bitem[nbricks] u32, bstart/istart[nbricks+1] u32
-//   work list: items[max_items], tiles[max_items]
-// Cells are grouped in bricks of 4x4x4; a particle's key is
-//   brick_id * 64 + local cell index, brick_id = bx + nbx (by + nby bz),
-// so sorting by key groups a brick's particles together and orders them by
-// cell inside it.
+//   work list: items[max_items]; node boxes tiles[2][max_items], tstep[max_items]
+// A particle's cell is stored packed: cx | cy << 11 | cz << 22.  Cells are
+// grouped in bricks of 4x4x4; the sort key is brick_id * 64 + local cell
+// index, brick_id = bx + nbx (by + nby bz).  A reorder groups each brick's
+// particles together and, inside the brick, stores them level-major: the
+// first particle of every occupied cell, then the second of every cell
+// holding two or more, and so on.
 #pragma once
 
 #include <stdint.h>
@@ -22,8 +25,10 @@ namespace mpmx {
 constexpr int kBrick = 4;                 // cells per brick edge
 constexpr int kBrickCells = 64;           // cells per brick
 constexpr int kChunk = 512;               // max particles per work item
-constexpr int kBlock = 256;               // threads per work-item workgroup
-constexpr int kMaxTileNodes = 729;        // 9^3: GIMP tile with one cell of drift
+constexpr int kBlock = 256;               // threads per workgroup of the sort and control kernels
+constexpr int kItemThreads = 128;         // threads per work-item workgroup
+constexpr int kMaxCells[3] = {2047, 2047, 1023};   // packed-cell limits
+constexpr int64_t kMaxIndex = (int64_t)1 << 31;     // particle and node indices are 32-bit
 
 enum Ctl : int {
     CTL_CUR = 0,        // which particle buffer is current (0/1)
@@ -34,6 +39,11 @@ enum Ctl : int {
     CTL_STEPS = 5,      // completed steps
     CTL_REMAIN = 6,     // steps still to run in the current call
     CTL_ACTIVE = 7,     // the scene takes part in the step being run
+    CTL_NBUF = 8,       // node buffer of the current (or last completed) step
+    CTL_READY = 9,      // the other node buffer already holds the next step's P2G
+    CTL_HAVE_P2G = 10,  // node buffer CTL_NBUF holds this step's P2G
+    CTL_ACC0 = 11,      // items whose tiles[b] cover node buffer b's data (b = 0, 1)
+    CTL_ACC1 = 12,
     CTL_WORDS = 16
 };
 
@@ -48,20 +58,18 @@ struct Item {
     uint32_t pad;
 };
 
-// Node box touched by an item: lo (node index per axis, ghost-relative
-// indexing i.e. may be -1) and extent per axis.  Written by the first
-// scatter of a step, read by the later stages and by the next step's clear.
+// Box of nodes: lo per axis (ghost nodes have index -1) and extent.
 struct Tile {
     int lo[3];
     int dim[3];
-    int fits;   // extent fits the LDS tile
+    int fits;   // extent fits the shape's LDS tile size
     int pad;
 };
 
 struct SceneDev {
     // mesh
     double origin[3];
-    double h;
+    double h, inv_h;
     int n[3];        // cells
     int nb[3];       // bricks
     int N[3];        // nodes per axis incl. ghosts
@@ -92,18 +100,26 @@ struct SceneDev {
     void *sig[2];
     void *vol[2];
     void *mass[2];
-    uint32_t *key[2];
+    uint32_t *cell[2];
     uint32_t *pid[2];
-    // nodes
-    double *nm;
-    void *np_;   // momentum p[3][nn]
-    void *nf;    // force f[3][nn]
+    // nodes (two buffers)
+    double *nm[2];
+    void *np_[2];   // momentum p[3][nn]
+    void *nf[2];    // force f[3][nn]
     // sort scratch
-    uint32_t *cnt, *cstart, *rank;
+    uint32_t *cnt, *cstart, *rank, *perm;
     uint32_t *bcnt, *bitem, *bstart, *istart;
     Item *items;
-    Tile *tiles;
+    Tile *tiles[2];  // per node buffer: boxes its data was accumulated over
+    Tile *tstep;     // per item: node box of its particles in the current step
     uint32_t *ctl;
+};
+
+enum BatchFlag : int {
+    BF_ANY_SORT = 0,      // some scene of the batch reorders this step
+    BF_TICKET_BRICKS = 1, // finished-block counters (the last block runs the
+    BF_TICKET_MOVE = 2,   // single-workgroup tail of the kernel)
+    BF_WORDS = 4
 };
 
 // A launch over several scenes: work is flattened over scenes in order.
@@ -111,7 +127,9 @@ struct BatchDev {
     const SceneDev *const *scenes;  // device array of device pointers
     const int64_t *poffs;           // particle offsets [nscenes+1] (static)
     const int64_t *boffs;           // brick offsets [nscenes+1] (static)
-    uint32_t *ioffs;                // item offsets [nscenes+1] (device-written)
+    uint32_t *ioffs;                // this step's item offsets [nscenes+1]
+    uint32_t *coffs;                // offsets of the boxes to clear [nscenes+1]
+    uint32_t *flags;                // BF_*
     int nscenes;
     int pad;
     int64_t total_particles;

@@ -2,35 +2,67 @@
 //
 // One explicit update-stress-first step (code overview: USF; introduction:
 // nodal values reset every step, particle-to-node mapping and interpolation
-// back with the same mapping functions):
-//   clear    zero the nodal mass, momentum and force the last step touched
-//   sort     (only when needed) counting sort of particles by brick-major
-//            cell key; rebuild the work list of <= 512-particle chunks of
-//            one 4x4x4-cell brick
-//   p2g      nodal mass (FP64) and momentum, accumulated in an LDS node tile
-//            per work item and flushed with one global atomic per touched
-//            node and component
-//   stress   nodal velocity (with constraints) into LDS, velocity gradient,
-//            strain increment, volume, elastic / Drucker-Prager stress,
-//            internal + external nodal force through an LDS tile
-//   g2p      nodal acceleration and updated velocity (with constraints) into
-//            LDS, FLIP/PIC particle velocity, FP64 position, new cell key,
-//            drift / error checks
-// USL replaces p2g+stress+g2p with p2g_usl (mass, momentum and force from the
-// old stress) and g2p_usl (particle update, then stress from the updated
-// nodal velocity).
+// back with the same mapping functions), with node buffer b holding the
+// step's nodal mass and momentum on entry:
+//   sort      (only when flagged) counting sort of particles by brick-major
+//             cell key, level-major inside each brick; rebuild the work list
+//             of <= 512-particle chunks of one 4x4x4-cell brick; the last
+//             workgroup then runs the step control (which scenes step, which
+//             node buffer they use, work offsets)
+//   stress    zero the other node buffer (the previous step's data); nodal
+//             velocity with constraints into an LDS tile; velocity gradient,
+//             strain increment, volume, elastic / Drucker-Prager stress;
+//             internal + external nodal force through an LDS tile (FP64
+//             accumulators), one global atomic per touched node and component
+//   g2p_p2g   nodal acceleration and updated velocity with constraints into
+//             LDS; FLIP/PIC particle velocity, FP64 position, new cell, drift
+//             and error checks; the next step's nodal mass (FP64) and
+//             momentum from the updated particle into the other buffer
+// The first step of a call runs p2g alone to fill buffer b.  USL runs p2g_usl
+// (mass, momentum and force from the old stress) and g2p_usl (particle
+// update, then stress from the updated nodal velocity, and the clear of the
+// other buffer).
 //
-// Every per-item kernel is persistent: a fixed grid strides over the
-// flattened (scene, item) list whose offsets live in device memory, so a
-// launch needs no host knowledge of how many items each scene has.
+// The item kernels are persistent: a fixed grid strides over the flattened
+// (scene, item) list whose offsets live in device memory, so a launch needs
+// no host knowledge of how many items each scene has.  Particle and node
+// indices are 32-bit and every array is addressed through a global-memory
+// pointer, so accesses use a scalar base plus a 32-bit offset.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "mpmx_dev.h"
 
+#define GLOBAL __attribute__((address_space(1)))
+
 namespace mpmx {
 
 // ------------------------------------------------------------ helpers ----
+
+template <typename T>
+__device__ inline GLOBAL T *gp(T *p)
+{
+    return (GLOBAL T *)p;
+}
+
+template <typename T>
+__device__ inline const GLOBAL T *gp(const T *p)
+{
+    return (const GLOBAL T *)p;
+}
+
+// Element b (0 or 1) of a two-buffer field of a scene descriptor.
+template <typename T>
+__device__ inline T pick(const T (&a)[2], int b)
+{
+    return b ? a[1] : a[0];
+}
+
+template <typename T>
+__device__ inline void gadd(GLOBAL T *p, T v)
+{
+    __hip_atomic_fetch_add((T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <typename T>
 __device__ inline int find_scene(const T *offs, int nscenes, int64_t g)
@@ -68,33 +100,50 @@ __device__ inline uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-__device__ inline void key_to_cell(const SceneDev &S, uint32_t key, int c[3])
+__device__ inline uint32_t pack_cell(const int c[3])
 {
-    uint32_t b = key >> 6, l = key & 63u;
-    uint32_t bx = b % (uint32_t)S.nb[0];
-    uint32_t t = b / (uint32_t)S.nb[0];
-    uint32_t by = t % (uint32_t)S.nb[1];
-    uint32_t bz = t / (uint32_t)S.nb[1];
-    c[0] = (int)(bx * 4 + (l & 3u));
-    c[1] = (int)(by * 4 + ((l >> 2) & 3u));
-    c[2] = (int)(bz * 4 + (l >> 4));
+    return (uint32_t)c[0] | ((uint32_t)c[1] << 11) | ((uint32_t)c[2] << 22);
 }
 
-__device__ inline uint32_t cell_to_key(const SceneDev &S, const int c[3])
+__device__ inline void unpack_cell(uint32_t p, int c[3])
 {
-    uint32_t b = (uint32_t)(c[0] >> 2) +
-                 (uint32_t)S.nb[0] * ((uint32_t)(c[1] >> 2) + (uint32_t)S.nb[1] * (uint32_t)(c[2] >> 2));
+    c[0] = (int)(p & 2047u);
+    c[1] = (int)((p >> 11) & 2047u);
+    c[2] = (int)(p >> 22);
+}
+
+__device__ inline uint32_t brick_key(const SceneDev &S, uint32_t packed)
+{
+    int c[3];
+    unpack_cell(packed, c);
+    const uint32_t b = (uint32_t)(c[0] >> 2) +
+                       (uint32_t)S.nb[0] * ((uint32_t)(c[1] >> 2) + (uint32_t)S.nb[1] * (uint32_t)(c[2] >> 2));
     return b * 64u + (uint32_t)((c[0] & 3) + 4 * ((c[1] & 3) + 4 * (c[2] & 3)));
 }
 
-// Cell of a position: floor((x - o) / h) in IEEE FP64 per axis.  Returns 0,
-// ERR_OUT_OF_MESH or ERR_NONFINITE.
+__device__ inline void brick_origin(const SceneDev &S, uint32_t b, int o[3])
+{
+    o[0] = (int)(b % (uint32_t)S.nb[0]) * kBrick;
+    o[1] = (int)((b / (uint32_t)S.nb[0]) % (uint32_t)S.nb[1]) * kBrick;
+    o[2] = (int)(b / ((uint32_t)S.nb[0] * (uint32_t)S.nb[1])) * kBrick;
+}
+
+// Cell of a position: floor((x - o) / h) with the IEEE FP64 quotient per
+// axis.  The quotient is first estimated as (x - o) * (1/h), within a few ulp
+// of it; only when the estimate lies that close to an integer (a cell face)
+// is the division done, so the cell equals the one the exact quotient gives.
+// Returns 0, ERR_OUT_OF_MESH or ERR_NONFINITE.
 __device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3])
 {
     for (int a = 0; a < 3; ++a) {
         if (!isfinite(x[a]))
             return ERR_NONFINITE;
-        double t = floor((x[a] - S.origin[a]) / S.h);
+        const double d = x[a] - S.origin[a];
+        const double q = d * S.inv_h;
+        double t = floor(q);
+        const double eps = 1e-14 * fmax(fabs(q), 1.0);
+        if (!(q - t > eps && q - t < 1.0 - eps))
+            t = floor(d / S.h);
         if (!(t >= 0.0 && t < (double)S.n[a]))
             return ERR_OUT_OF_MESH;
         c[a] = (int)t;
@@ -102,10 +151,17 @@ __device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3]
     return 0;
 }
 
-__device__ inline int64_t node_id(const SceneDev &S, int i, int j, int k)
+// Node index (32-bit: the runtime bounds every scene below 2^31 nodes).
+__device__ inline uint32_t node_id(const SceneDev &S, int i, int j, int k)
 {
     const int g = S.ghost;
-    return (int64_t)(i + g) + (int64_t)S.N[0] * ((int64_t)(j + g) + (int64_t)S.N[1] * (int64_t)(k + g));
+    return (uint32_t)((i + g) + S.N[0] * ((j + g) + S.N[1] * (k + g)));
+}
+
+__device__ inline bool node_in_mesh(const SceneDev &S, int i, int j, int k)
+{
+    const int g = S.ghost;
+    return i >= -g && i <= S.n[0] + g && j >= -g && j <= S.n[1] + g && k >= -g && k <= S.n[2] + g;
 }
 
 // Components fixed by the face rules at node (i,j,k): bit a = component a.
@@ -114,8 +170,8 @@ __device__ inline uint32_t face_mask(const SceneDev &S, int i, int j, int k)
     const int idx[3] = {i, j, k};
     uint32_t m = 0;
     for (int b = 0; b < 3; ++b) {
-        uint32_t lo = idx[b] <= 0 ? (S.face_bits >> (4 * b)) & 3u : 0u;
-        uint32_t hi = idx[b] >= S.n[b] ? (S.face_bits >> (4 * b + 2)) & 3u : 0u;
+        const uint32_t lo = idx[b] <= 0 ? (S.face_bits >> (4 * b)) & 3u : 0u;
+        const uint32_t hi = idx[b] >= S.n[b] ? (S.face_bits >> (4 * b + 2)) & 3u : 0u;
         if (lo == 1u || hi == 1u)
             m = 7u;
         if (lo == 2u || hi == 2u)
@@ -129,50 +185,71 @@ struct alignas(4 * sizeof(R)) R4 {
     R x, y, z, w;
 };
 
+// Component arrays of one node buffer.
+template <typename R>
+struct NodeBuf {
+    GLOBAL double *m;
+    GLOBAL R *p[3];
+    GLOBAL R *f[3];
+};
+
+template <typename R>
+__device__ inline NodeBuf<R> node_buf(const SceneDev &S, int b)
+{
+    NodeBuf<R> nb;
+    nb.m = gp(pick(S.nm, b));
+    GLOBAL R *P = gp((R *)pick(S.np_, b));
+    GLOBAL R *F = gp((R *)pick(S.nf, b));
+    for (int a = 0; a < 3; ++a) {
+        nb.p[a] = P + (size_t)a * (size_t)S.nn;
+        nb.f[a] = F + (size_t)a * (size_t)S.nn;
+    }
+    return nb;
+}
+
 // Nodal velocity v = p / m (0 on void nodes) with velocity constraints.
 template <typename R>
-__device__ inline void node_velocity(const SceneDev &S, int i, int j, int k, R v[3])
+__device__ inline void node_velocity(const SceneDev &S, const NodeBuf<R> &nb, int i, int j, int k, R v[3])
 {
-    const int64_t I = node_id(S, i, j, k);
-    const double m = S.nm[I];
-    const R *P = (const R *)S.np_;
+    const uint32_t I = node_id(S, i, j, k);
+    const double m = nb.m[I];
+    const double inv = m > S.eps_m ? 1.0 / m : 0.0;   // void node: v = 0
     for (int a = 0; a < 3; ++a)
-        v[a] = m > S.eps_m ? (R)((double)P[a * S.nn + I] / m) : (R)0;
-    uint32_t fm = face_mask(S, i, j, k);
+        v[a] = (R)((double)nb.p[a][I] * inv);
+    const uint32_t fm = face_mask(S, i, j, k);
     for (int a = 0; a < 3; ++a)
         if (fm & (1u << a))
             v[a] = (R)0;
     if (S.bc_mask) {
-        uint32_t em = S.bc_mask[I];
+        const uint32_t em = gp(S.bc_mask)[I];
         for (int a = 0; a < 3; ++a)
             if (em & (1u << a))
-                v[a] = (R)S.bc_val[3 * I + a];
+                v[a] = (R)gp(S.bc_val)[3 * (size_t)I + a];
     }
 }
 
 // Nodal acceleration a = f / m and updated velocity vn = v + dt a, with the
 // constraints applied to v (prescribed), a (zero) and vn (prescribed).
 template <typename R>
-__device__ inline void node_update(const SceneDev &S, int i, int j, int k, R a[3], R vn[3])
+__device__ inline void node_update(const SceneDev &S, const NodeBuf<R> &nb, int i, int j, int k, R a[3], R vn[3])
 {
-    const int64_t I = node_id(S, i, j, k);
-    const double m = S.nm[I];
-    const R *P = (const R *)S.np_;
-    const R *F = (const R *)S.nf;
+    const uint32_t I = node_id(S, i, j, k);
+    const double m = nb.m[I];
+    const double inv = m > S.eps_m ? 1.0 / m : 0.0;   // void node: v = a = 0
     R v[3];
     for (int c = 0; c < 3; ++c) {
-        v[c] = m > S.eps_m ? (R)((double)P[c * S.nn + I] / m) : (R)0;
-        a[c] = m > S.eps_m ? (R)((double)F[c * S.nn + I] / m) : (R)0;
+        v[c] = (R)((double)nb.p[c][I] * inv);
+        a[c] = (R)((double)nb.f[c][I] * inv);
     }
-    uint32_t fm = face_mask(S, i, j, k);
-    uint32_t em = S.bc_mask ? (uint32_t)S.bc_mask[I] : 0u;
+    const uint32_t fm = face_mask(S, i, j, k);
+    const uint32_t em = S.bc_mask ? (uint32_t)gp(S.bc_mask)[I] : 0u;
     for (int c = 0; c < 3; ++c) {
         if (fm & (1u << c)) {
             v[c] = (R)0;
             a[c] = (R)0;
         }
         if (em & (1u << c)) {
-            v[c] = (R)S.bc_val[3 * I + c];
+            v[c] = (R)gp(S.bc_val)[3 * (size_t)I + c];
             a[c] = (R)0;
         }
     }
@@ -183,25 +260,30 @@ __device__ inline void node_update(const SceneDev &S, int i, int j, int k, R a[3
         if (fm & (1u << c))
             vn[c] = (R)0;
         if (em & (1u << c))
-            vn[c] = (R)S.bc_val[3 * I + c];
+            vn[c] = (R)gp(S.bc_val)[3 * (size_t)I + c];
     }
 }
 
 // ------------------------------------------------------ shape functions --
 
+// NS nodes per axis in a particle's support; a work item's node tile
+// extends its cell box by lo nodes below and hi above; cap: tile nodes for a
+// brick with one cell of drift on every side (7^3 linear, 9^3 GIMP).
 template <int SH>
 struct ShapeTraits;
 template <>
 struct ShapeTraits<0> {   // trilinear 8-node hexahedron
     static constexpr int NS = 2;
-    static constexpr int lo = 0;   // node tile extends cells [lo, hi] by
-    static constexpr int hi = 1;   // -lo .. +hi nodes
+    static constexpr int lo = 0;
+    static constexpr int hi = 1;
+    static constexpr int cap = 343;
 };
 template <>
 struct ShapeTraits<1> {   // uGIMP, particle half-length h/4, 27 nodes
     static constexpr int NS = 3;
     static constexpr int lo = 1;
     static constexpr int hi = 2;
+    static constexpr int cap = 729;
 };
 
 template <typename R, int SH>
@@ -238,11 +320,11 @@ __device__ inline void gimp1(R rho, R &S, R &dS)
 template <typename R, int SH>
 __device__ inline void make_support(const SceneDev &S, const double x[3], const int c[3], Support<R, SH> &sp)
 {
-    const double h = S.h;
-    const R inv_h = (R)(1.0 / h);
+    const double h = S.h, ih = S.inv_h;
+    const R inv_h = (R)ih;
     if constexpr (SH == 0) {
         for (int a = 0; a < 3; ++a) {
-            const R r = (R)((x[a] - (S.origin[a] + h * (double)c[a])) / h);
+            const R r = (R)((x[a] - (S.origin[a] + h * (double)c[a])) * ih);
             sp.base[a] = c[a];
             sp.w[a][0] = (R)1 - r;
             sp.w[a][1] = r;
@@ -252,10 +334,12 @@ __device__ inline void make_support(const SceneDev &S, const double x[3], const 
     } else {
         const double l = 0.25 * h;
         for (int a = 0; a < 3; ++a) {
-            const int i0 = (int)floor((x[a] - S.origin[a] - l) / h);
+            // support starts at c-1 or c; the weight of the node it would
+            // otherwise include is zero, so rounding here cannot matter
+            const int i0 = (int)floor((x[a] - S.origin[a] - l) * ih);
             sp.base[a] = i0;
             for (int t = 0; t < 3; ++t) {
-                const R rho = (R)((x[a] - (S.origin[a] + h * (double)(i0 + t))) / h);
+                const R rho = (R)((x[a] - (S.origin[a] + h * (double)(i0 + t))) * ih);
                 R w, d;
                 gimp1(rho, w, d);
                 sp.w[a][t] = w;
@@ -315,33 +399,187 @@ struct ItemRef {
     int it;
 };
 
-__device__ inline ItemRef item_ref(const BatchDev &B, int64_t g)
+__device__ inline ItemRef item_ref(const uint32_t *offs, const BatchDev &B, int64_t g)
 {
-    const int s = find_scene(B.ioffs, B.nscenes, g);
-    return {B.scenes[s], (int)(g - (int64_t)B.ioffs[s])};
+    const int s = find_scene(offs, B.nscenes, g);
+    return {B.scenes[s], (int)(g - (int64_t)offs[s])};
 }
 
-// A scene takes part in the coming step: not stopped by an error and with
-// steps left.  Read by the clear and sort kernels, during which neither
-// word changes.
-__device__ inline bool scene_pending(const SceneDev &S)
+// The scene reorders in the coming step: read by the sort kernels, during
+// which none of these words changes.
+__device__ inline bool scene_sorting(const SceneDev &S)
 {
-    return S.ctl[CTL_ERR] == 0u && S.ctl[CTL_REMAIN] > 0u;
+    return S.ctl[CTL_ERR] == 0u && S.ctl[CTL_REMAIN] > 0u && S.ctl[CTL_NEED_SORT] != 0u;
 }
 
-// The stage kernels after step_control test CTL_ACTIVE only: it is fixed for
-// the whole step, whereas CTL_ERR may be raised by another workgroup of the
-// same kernel, and every thread of a workgroup must take the same branch
+// The stage kernels after the step control test CTL_ACTIVE only: it is fixed
+// for the whole step, whereas CTL_ERR may be raised by another workgroup of
+// the same kernel, and every thread of a workgroup must take the same branch
 // around its barriers.
 __device__ inline bool scene_active(const SceneDev &S)
 {
     return S.ctl[CTL_ACTIVE] != 0u;
 }
 
+// Last workgroup of a grid to arrive (threadfence reduction pattern: every
+// workgroup publishes its writes, then takes a ticket; no workgroup waits).
+__device__ inline bool last_block(uint32_t *ticket, int *flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t t = atomicAdd(ticket, 1u);
+        *flag = (t == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag != 0;
+    if (last)
+        __threadfence();
+    return last;
+}
+
+// Block-wide min/max of per-thread cell boxes (mn = +big, mx = -big for a
+// thread with nothing); result in red[0..2] (min), red[3..5] (max).
+__device__ inline void block_box(int mn[3], int mx[3], int *red)
+{
+    for (int a = 0; a < 3; ++a) {
+        mn[a] = wave_min(mn[a]);
+        mx[a] = wave_max(mx[a]);
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            red[a] = 1 << 30;
+            red[3 + a] = -(1 << 30);
+        }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&red[a], mn[a]);
+            atomicMax(&red[3 + a], mx[a]);
+        }
+    __syncthreads();
+}
+
+template <int SH>
+__device__ inline Tile tile_of_cells(const int lo[3], const int hi[3])
+{
+    Tile t;
+    for (int a = 0; a < 3; ++a) {
+        t.lo[a] = lo[a] - ShapeTraits<SH>::lo;
+        t.dim[a] = hi[a] >= lo[a] ? hi[a] + ShapeTraits<SH>::hi - t.lo[a] + 1 : 0;
+    }
+    const int vol = t.dim[0] * t.dim[1] * t.dim[2];
+    t.fits = vol <= ShapeTraits<SH>::cap ? 1 : 0;
+    t.pad = 0;
+    return t;
+}
+
+// Node box of the item's particles (their cell box extended by the support).
+template <int SH>
+__device__ inline Tile item_tile(const Item &item, const GLOBAL uint32_t *cell, int *red)
+{
+    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
+        int c[3];
+        unpack_cell(cell[item.start + q], c);
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = min(mn[a], c[a]);
+            mx[a] = max(mx[a], c[a]);
+        }
+    }
+    block_box(mn, mx, red);
+    const int lo[3] = {red[0], red[1], red[2]}, hi[3] = {red[3], red[4], red[5]};
+    __syncthreads();
+    return tile_of_cells<SH>(lo, hi);
+}
+
+// LDS node tile of the next step's scatter in g2p_p2g: the nodes supporting
+// the cells of the item's brick widened by one cell on every side (the
+// reorder keeps every particle of the item there, except between a drift
+// past it and the next reorder).
+template <int SH>
+__device__ inline Tile home_tile(const int o[3])
+{
+    Tile t;
+    for (int a = 0; a < 3; ++a) {
+        t.lo[a] = o[a] - 1 - ShapeTraits<SH>::lo;
+        t.dim[a] = kBrick + 2 + ShapeTraits<SH>::lo + ShapeTraits<SH>::hi;
+    }
+    t.fits = 1;
+    t.pad = 0;
+    return t;
+}
+
+__device__ inline bool in_home(const int c[3], const int o[3])
+{
+    return c[0] >= o[0] - 1 && c[0] <= o[0] + kBrick && c[1] >= o[1] - 1 && c[1] <= o[1] + kBrick &&
+           c[2] >= o[2] - 1 && c[2] <= o[2] + kBrick;
+}
+
+__device__ inline void tile_node(const Tile &t, int q, int &i, int &j, int &k)
+{
+    i = t.lo[0] + q % t.dim[0];
+    j = t.lo[1] + (q / t.dim[0]) % t.dim[1];
+    k = t.lo[2] + q / (t.dim[0] * t.dim[1]);
+}
+
+// Index of a particle's first support node in a tile and in the node array;
+// corner (i,j,k) then adds i + j*sy + k*sz with the strides below.
+struct Corners {
+    int t0, ty, tz;   // tile
+    uint32_t n0;
+    int ny, nz;       // node array
+};
+
+__device__ inline Corners corners(const SceneDev &S, const Tile &t, const int base[3])
+{
+    Corners c;
+    c.ty = t.dim[0];
+    c.tz = t.dim[0] * t.dim[1];
+    c.t0 = (base[0] - t.lo[0]) + c.ty * (base[1] - t.lo[1]) + c.tz * (base[2] - t.lo[2]);
+    c.ny = S.N[0];
+    c.nz = S.N[0] * S.N[1];
+    c.n0 = node_id(S, base[0], base[1], base[2]);
+    return c;
+}
+
+// Zero node buffer `buf` over the given node box.
+template <typename R>
+__device__ inline void clear_box(const SceneDev &S, const NodeBuf<R> &nb, const Tile &t)
+{
+    const int vol = t.dim[0] * t.dim[1] * t.dim[2];
+    for (int q = threadIdx.x; q < vol; q += blockDim.x) {
+        int i, j, k;
+        tile_node(t, q, i, j, k);
+        const uint32_t I = node_id(S, i, j, k);
+        nb.m[I] = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            nb.p[a][I] = (R)0;
+            nb.f[a][I] = (R)0;
+        }
+    }
+}
+
+// Zero the other node buffer of every active scene over the boxes recorded
+// when it was filled (the previous step's data).
+template <typename R>
+__device__ inline void clear_previous(const BatchDev &B)
+{
+    const int64_t total = B.coffs[B.nscenes];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const ItemRef r = item_ref(B.coffs, B, g);
+        const SceneDev &S = *r.S;
+        if (!scene_active(S))
+            continue;
+        const int other = (int)S.ctl[CTL_NBUF] ^ 1;
+        clear_box<R>(S, node_buf<R>(S, other), pick(S.tiles, other)[r.it]);
+    }
+}
+
 // ----------------------------------------------------- load / read out --
 
-// Inputs are row-major doubles (n x 3, n x 6, n); fills buffer 0, sets the
-// identity permutation and each particle's key.
+// Inputs are row-major doubles (n x 3, n x 6, n); fills particle buffer 0,
+// sets the identity permutation and each particle's cell.
 template <typename R>
 __global__ void k_load(SceneDev *Sd, const double *x, const double *v, const double *sig, const double *vol,
                        const double *mass)
@@ -378,7 +616,7 @@ __global__ void k_load(SceneDev *Sd, const double *x, const double *v, const dou
             atomicOr(&S.ctl[CTL_ERR], e);
             c[0] = c[1] = c[2] = 0;
         }
-        S.key[0][p] = cell_to_key(S, c);
+        S.cell[0][p] = pack_cell(c);
         S.pid[0][p] = (uint32_t)p;
     }
 }
@@ -409,7 +647,7 @@ __global__ void k_read_out(const SceneDev *Sd, double *x, double *v, double *sig
             vol[o] = (double)VO[p];
         if (cell) {
             int c[3];
-            key_to_cell(S, S.key[cur][p], c);
+            unpack_cell(S.cell[cur][p], c);
             cell[o] = c[0] + S.n[0] * (c[1] + S.n[1] * c[2]);
         }
     }
@@ -421,20 +659,22 @@ __global__ void k_cell_counts(const SceneDev *Sd, uint32_t *counts)
     const int cur = (int)S.ctl[CTL_CUR];
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < S.np; p += (int64_t)gridDim.x * blockDim.x) {
         int c[3];
-        key_to_cell(S, S.key[cur][p], c);
+        unpack_cell(S.cell[cur][p], c);
         atomicAdd(&counts[c[0] + (int64_t)S.n[0] * (c[1] + (int64_t)S.n[1] * c[2])], 1u);
     }
 }
 
+// Nodal fields of the last completed step (node buffer CTL_NBUF).
 template <typename R>
 __global__ void k_nodes_out(const SceneDev *Sd, double *m, double *p, double *f)
 {
     const SceneDev &S = *Sd;
-    const R *P = (const R *)S.np_;
-    const R *F = (const R *)S.nf;
+    const int b = (int)S.ctl[CTL_NBUF];
+    const R *P = (const R *)S.np_[b];
+    const R *F = (const R *)S.nf[b];
     for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < S.nn; I += (int64_t)gridDim.x * blockDim.x) {
         if (m)
-            m[I] = S.nm[I];
+            m[I] = S.nm[b][I];
         for (int a = 0; a < 3; ++a) {
             if (p)
                 p[3 * I + a] = (double)P[a * S.nn + I];
@@ -446,205 +686,216 @@ __global__ void k_nodes_out(const SceneDev *Sd, double *m, double *p, double *f)
 
 // ------------------------------------------------------- step control --
 
-// Item offsets of the batch; mode 0: every scene with steps left counts with
-// all its items (start of a call, used by the first clear); mode 1: end of
-// the sort stage of a step: apply a pending reorder, decide which scenes
-// take part in this step, decrement their remaining steps, offsets over the
-// active scenes only.
-__global__ void k_step_control(BatchDev B, int mode)
+// Start of a call: steps to run per scene, and whether any scene starts with
+// a reorder pending (a fresh scene always does).
+__global__ void k_begin(BatchDev B, const int64_t *nsteps)
 {
-    __shared__ uint32_t part[1024];
-    __shared__ uint32_t carry;
+    __shared__ int any;
+    if (threadIdx.x == 0)
+        any = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < B.nscenes; s += blockDim.x) {
+        const int64_t k = nsteps[s];
+        uint32_t *ctl = B.scenes[s]->ctl;
+        ctl[CTL_REMAIN] = (uint32_t)(k < 0 ? 0 : (k > 0x7fffffff ? 0x7fffffff : k));
+        if (ctl[CTL_NEED_SORT] && ctl[CTL_ERR] == 0u && k > 0)
+            any = 1;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        carry = 0;
+        B.flags[BF_ANY_SORT] = any ? 1u : 0u;
+        B.flags[BF_TICKET_BRICKS] = 0u;
+        B.flags[BF_TICKET_MOVE] = 0u;
+    }
+}
+
+// Per-step control, run by one workgroup: apply a finished reorder, decide
+// which scenes take part in this step, pick their node buffers, and write the
+// offsets of this step's items (ioffs) and of the boxes to clear (coffs).
+__device__ void step_control(const BatchDev &B)
+{
+    __shared__ uint32_t pi[kBlock], pc[kBlock];
+    __shared__ uint32_t ci, cc;
+    if (threadIdx.x == 0) {
+        ci = cc = 0;
         B.ioffs[0] = 0;
+        B.coffs[0] = 0;
     }
     __syncthreads();
     for (int base = 0; base < B.nscenes; base += blockDim.x) {
         const int s = base + threadIdx.x;
-        uint32_t items = 0;
+        uint32_t items = 0, clears = 0;
         if (s < B.nscenes) {
             const SceneDev &S = *B.scenes[s];
             uint32_t *ctl = S.ctl;
-            if (mode == 0) {
+            const bool go = ctl[CTL_ERR] == 0u && ctl[CTL_REMAIN] > 0u;
+            if (go && ctl[CTL_NEED_SORT]) {
+                ctl[CTL_CUR] ^= 1u;
+                ctl[CTL_NEED_SORT] = 0u;
+                ctl[CTL_N_SORTS] += 1u;
+            }
+            ctl[CTL_ACTIVE] = go ? 1u : 0u;
+            if (go) {
+                ctl[CTL_REMAIN] -= 1u;
+                ctl[CTL_STEPS] += 1u;
+                if (S.algo == 0) {          // USF: the previous g2p_p2g filled the other buffer
+                    if (ctl[CTL_READY]) {
+                        ctl[CTL_NBUF] ^= 1u;
+                        ctl[CTL_READY] = 0u;
+                        ctl[CTL_HAVE_P2G] = 1u;
+                    } else {
+                        ctl[CTL_HAVE_P2G] = 0u;
+                    }
+                } else {                    // USL: p2g_usl fills a fresh buffer every step
+                    ctl[CTL_NBUF] ^= 1u;
+                    ctl[CTL_HAVE_P2G] = 0u;
+                }
                 items = ctl[CTL_N_ITEMS];
-            } else {
-                const bool go = ctl[CTL_ERR] == 0u && ctl[CTL_REMAIN] > 0u;
-                if (go && ctl[CTL_NEED_SORT]) {
-                    ctl[CTL_CUR] ^= 1u;
-                    ctl[CTL_NEED_SORT] = 0u;
-                    ctl[CTL_N_SORTS] += 1u;
-                }
-                ctl[CTL_ACTIVE] = go ? 1u : 0u;
-                if (go) {
-                    ctl[CTL_REMAIN] -= 1u;
-                    ctl[CTL_STEPS] += 1u;
-                }
-                items = go ? ctl[CTL_N_ITEMS] : 0u;
+                clears = ctl[CTL_ACC0 + (ctl[CTL_NBUF] ^ 1u)];
             }
         }
-        part[threadIdx.x] = items;
+        pi[threadIdx.x] = items;
+        pc[threadIdx.x] = clears;
         __syncthreads();
-        // inclusive scan (Hillis-Steele) of this chunk
         for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-            uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+            const uint32_t a = threadIdx.x >= (unsigned)o ? pi[threadIdx.x - o] : 0u;
+            const uint32_t c = threadIdx.x >= (unsigned)o ? pc[threadIdx.x - o] : 0u;
             __syncthreads();
-            part[threadIdx.x] += t;
+            pi[threadIdx.x] += a;
+            pc[threadIdx.x] += c;
             __syncthreads();
         }
-        if (s < B.nscenes)
-            B.ioffs[s + 1] = carry + part[threadIdx.x];
-        __syncthreads();
-        if (threadIdx.x == blockDim.x - 1)
-            carry += part[threadIdx.x];
-        __syncthreads();
-    }
-}
-
-// Steps left per scene for this call (written before the first step).
-__global__ void k_set_remaining(BatchDev B, const int64_t *nsteps)
-{
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < B.nscenes; s += gridDim.x * blockDim.x) {
-        int64_t k = nsteps[s];
-        B.scenes[s]->ctl[CTL_REMAIN] = (uint32_t)(k < 0 ? 0 : (k > 0x7fffffff ? 0x7fffffff : k));
-    }
-}
-
-// ---------------------------------------------------------------- clear --
-
-// Zero m, p, f over the node tiles of the previous step's items.
-template <typename R>
-__global__ void __launch_bounds__(kBlock) k_clear(BatchDev B)
-{
-    const int64_t total = B.ioffs[B.nscenes];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const ItemRef r = item_ref(B, g);
-        const SceneDev &S = *r.S;
-        if (!scene_pending(S))
-            continue;
-        const Tile t = S.tiles[r.it];
-        const int vol = t.dim[0] * t.dim[1] * t.dim[2];
-        R *P = (R *)S.np_;
-        R *F = (R *)S.nf;
-        for (int q = threadIdx.x; q < vol; q += blockDim.x) {
-            const int i = t.lo[0] + q % t.dim[0];
-            const int j = t.lo[1] + (q / t.dim[0]) % t.dim[1];
-            const int k = t.lo[2] + q / (t.dim[0] * t.dim[1]);
-            const int64_t I = node_id(S, i, j, k);
-            S.nm[I] = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                P[a * S.nn + I] = (R)0;
-                F[a * S.nn + I] = (R)0;
-            }
+        if (s < B.nscenes) {
+            B.ioffs[s + 1] = ci + pi[threadIdx.x];
+            B.coffs[s + 1] = cc + pc[threadIdx.x];
         }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) {
+            ci += pi[threadIdx.x];
+            cc += pc[threadIdx.x];
+        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0)
+        B.flags[BF_ANY_SORT] = 0u;
 }
 
 // ----------------------------------------------------------------- sort --
 
-// rank[p] = arrival order of p among the particles of its key.
-__global__ void k_sort_count(BatchDev B)
+// rank[p] = arrival order of p among the particles of its cell.
+__global__ void __launch_bounds__(kBlock) k_sort_count(BatchDev B)
 {
+    if (!B.flags[BF_ANY_SORT])
+        return;
     for (int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gp < B.total_particles;
          gp += (int64_t)gridDim.x * blockDim.x) {
         const int s = find_scene(B.poffs, B.nscenes, gp);
         const SceneDev &S = *B.scenes[s];
-        if (!scene_pending(S) || !S.ctl[CTL_NEED_SORT])
+        if (!scene_sorting(S))
             continue;
         const int64_t p = gp - B.poffs[s];
         const int cur = (int)S.ctl[CTL_CUR];
-        S.rank[p] = atomicAdd(&S.cnt[S.key[cur][p]], 1u);
+        S.rank[p] = atomicAdd(&S.cnt[brick_key(S, pick(S.cell, cur)[p])], 1u);
     }
 }
 
-// One wavefront per brick: particles and work items of the brick.
-__global__ void k_sort_bricks(BatchDev B)
+// Exclusive scan of the particle and item counts of a scene's bricks by one
+// workgroup.
+__device__ void scan_bricks(const SceneDev &S)
 {
+    __shared__ uint32_t sp[kBlock], si[kBlock];
+    const int64_t nb = S.nbricks;
+    const int64_t per = (nb + blockDim.x - 1) / blockDim.x;
+    const int64_t b0 = min((int64_t)threadIdx.x * per, nb);
+    const int64_t b1 = min(b0 + per, nb);
+    uint32_t tp = 0, ti = 0;
+    for (int64_t b = b0; b < b1; ++b) {
+        tp += S.bcnt[b];
+        ti += S.bitem[b];
+    }
+    sp[threadIdx.x] = tp;
+    si[threadIdx.x] = ti;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const uint32_t a = threadIdx.x >= (unsigned)o ? sp[threadIdx.x - o] : 0u;
+        const uint32_t c = threadIdx.x >= (unsigned)o ? si[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sp[threadIdx.x] += a;
+        si[threadIdx.x] += c;
+        __syncthreads();
+    }
+    uint32_t rp = sp[threadIdx.x] - tp, ri = si[threadIdx.x] - ti;
+    for (int64_t b = b0; b < b1; ++b) {
+        S.bstart[b] = rp;
+        S.istart[b] = ri;
+        rp += S.bcnt[b];
+        ri += S.bitem[b];
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        S.bstart[nb] = sp[threadIdx.x];
+        S.istart[nb] = si[threadIdx.x];
+        S.ctl[CTL_N_ITEMS] = si[threadIdx.x];
+    }
+    __syncthreads();
+}
+
+// One wavefront per brick: particles and work items of the brick; the last
+// workgroup to finish scans them per scene.
+__global__ void __launch_bounds__(kBlock) k_sort_bricks(BatchDev B)
+{
+    __shared__ int last;
+    if (!B.flags[BF_ANY_SORT])
+        return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
         const int s = find_scene(B.boffs, B.nscenes, gb);
         const SceneDev &S = *B.scenes[s];
-        if (!scene_pending(S) || !S.ctl[CTL_NEED_SORT])
+        if (!scene_sorting(S))
             continue;
         const int64_t b = gb - B.boffs[s];
-        const uint32_t c = S.cnt[b * 64 + lane];
-        const uint32_t tot = wave_sum(c);
+        const uint32_t tot = wave_sum(S.cnt[b * 64 + lane]);
         if (lane == 0) {
             S.bcnt[b] = tot;
             S.bitem[b] = (tot + kChunk - 1) / kChunk;
         }
     }
-}
-
-// One workgroup per scene: exclusive scans of particles and items per brick.
-__global__ void __launch_bounds__(1024) k_sort_scan(BatchDev B)
-{
-    __shared__ uint32_t sp[1024], si[1024];
-    for (int s = blockIdx.x; s < B.nscenes; s += gridDim.x) {
+    if (!last_block(&B.flags[BF_TICKET_BRICKS], &last))
+        return;
+    for (int s = 0; s < B.nscenes; ++s) {
         const SceneDev &S = *B.scenes[s];
-        if (!scene_pending(S) || !S.ctl[CTL_NEED_SORT])
-            continue;
-        const int64_t nb = S.nbricks;
-        const int64_t per = (nb + blockDim.x - 1) / blockDim.x;
-        const int64_t b0 = threadIdx.x * per;
-        const int64_t b1 = min(b0 + per, nb);
-        uint32_t tp = 0, ti = 0;
-        for (int64_t b = b0; b < b1; ++b) {
-            tp += S.bcnt[b];
-            ti += S.bitem[b];
-        }
-        sp[threadIdx.x] = tp;
-        si[threadIdx.x] = ti;
-        __syncthreads();
-        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-            uint32_t a = threadIdx.x >= (unsigned)o ? sp[threadIdx.x - o] : 0u;
-            uint32_t c = threadIdx.x >= (unsigned)o ? si[threadIdx.x - o] : 0u;
-            __syncthreads();
-            sp[threadIdx.x] += a;
-            si[threadIdx.x] += c;
-            __syncthreads();
-        }
-        uint32_t rp = sp[threadIdx.x] - tp, ri = si[threadIdx.x] - ti;   // exclusive
-        for (int64_t b = b0; b < b1; ++b) {
-            S.bstart[b] = rp;
-            S.istart[b] = ri;
-            rp += S.bcnt[b];
-            ri += S.bitem[b];
-        }
-        if (threadIdx.x == blockDim.x - 1) {
-            S.bstart[nb] = sp[threadIdx.x];
-            S.istart[nb] = si[threadIdx.x];
-            S.ctl[CTL_N_ITEMS] = si[threadIdx.x];
-        }
-        __syncthreads();
+        if (scene_sorting(S))
+            scan_bricks(S);
     }
+    if (threadIdx.x == 0)
+        B.flags[BF_TICKET_BRICKS] = 0u;
 }
 
-// One wavefront per brick: start of each cell's run, the brick's work items;
-// resets the counts for the next sort.
-__global__ void k_sort_cells(BatchDev B)
+// One wavefront per brick: start of each cell's run in cell-major order and
+// the brick's work items.
+__global__ void __launch_bounds__(kBlock) k_sort_cells(BatchDev B)
 {
+    if (!B.flags[BF_ANY_SORT])
+        return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
         const int s = find_scene(B.boffs, B.nscenes, gb);
         const SceneDev &S = *B.scenes[s];
-        if (!scene_pending(S) || !S.ctl[CTL_NEED_SORT])
+        if (!scene_sorting(S))
             continue;
         const int64_t b = gb - B.boffs[s];
         const uint32_t c = S.cnt[b * 64 + lane];
         uint32_t inc = c;
         for (int o = 1; o < 64; o <<= 1) {
-            uint32_t t = __shfl_up(inc, o);
+            const uint32_t t = __shfl_up(inc, o);
             if (lane >= o)
                 inc += t;
         }
         const uint32_t bs = S.bstart[b];
         S.cstart[b * 64 + lane] = bs + inc - c;
-        S.cnt[b * 64 + lane] = 0u;
         const uint32_t nit = S.bitem[b], tot = S.bcnt[b], i0 = S.istart[b];
         for (uint32_t i = lane; i < nit; i += 64) {
             Item it;
@@ -657,152 +908,182 @@ __global__ void k_sort_cells(BatchDev B)
     }
 }
 
-// Move every particle to its sorted slot in the other buffer.
-template <typename R>
-__global__ void k_sort_scatter(BatchDev B)
+// perm lists the particles cell-major: slot cstart[key] + rank holds p.
+__global__ void __launch_bounds__(kBlock) k_sort_perm(BatchDev B)
 {
+    if (!B.flags[BF_ANY_SORT])
+        return;
     for (int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gp < B.total_particles;
          gp += (int64_t)gridDim.x * blockDim.x) {
         const int s = find_scene(B.poffs, B.nscenes, gp);
         const SceneDev &S = *B.scenes[s];
-        if (!scene_pending(S) || !S.ctl[CTL_NEED_SORT])
+        if (!scene_sorting(S))
             continue;
-        const int64_t n = S.np;
         const int64_t p = gp - B.poffs[s];
-        const int cur = (int)S.ctl[CTL_CUR], nxt = cur ^ 1;
-        const uint32_t key = S.key[cur][p];
-        const int64_t d = (int64_t)S.cstart[key] + S.rank[p];
-        for (int a = 0; a < 3; ++a) {
-            S.x[nxt][a * n + d] = S.x[cur][a * n + p];
-            ((R *)S.v[nxt])[a * n + d] = ((const R *)S.v[cur])[a * n + p];
-        }
-        for (int k = 0; k < 6; ++k)
-            ((R *)S.sig[nxt])[k * n + d] = ((const R *)S.sig[cur])[k * n + p];
-        ((R *)S.vol[nxt])[d] = ((const R *)S.vol[cur])[p];
-        ((R *)S.mass[nxt])[d] = ((const R *)S.mass[cur])[p];
-        S.key[nxt][d] = key;
-        S.pid[nxt][d] = S.pid[cur][p];
+        const int cur = (int)S.ctl[CTL_CUR];
+        S.perm[S.cstart[brick_key(S, pick(S.cell, cur)[p])] + S.rank[p]] = (uint32_t)p;
     }
 }
 
-// ---------------------------------------------------- per-item helpers --
-
-// Node box of the item's particles (cell bbox extended by the support).
-template <int SH>
-__device__ inline Tile item_tile(const SceneDev &S, const Item &item, const uint32_t *key, int *red)
+// One wavefront per brick, lane = cell: write the brick's particles to the
+// other buffer in level-major order -- the first particle of every occupied
+// cell, then the second of every cell holding two or more, and so on.  A
+// wavefront of consecutive particles then spans distinct cells, so the
+// scatter kernels' LDS atomics for one node corner do not collide.  Resets
+// the per-cell counts for the next sort.  The last workgroup to finish runs
+// the step control (every step, reorder or not).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_sort_move(BatchDev B)
 {
-    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-    for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
-        int c[3];
-        key_to_cell(S, key[item.start + q], c);
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = min(mn[a], c[a]);
-            mx[a] = max(mx[a], c[a]);
+    __shared__ int last;
+    if (B.flags[BF_ANY_SORT]) {
+        const int lane = threadIdx.x & 63;
+        const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+        const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
+            const int s = find_scene(B.boffs, B.nscenes, gb);
+            const SceneDev &S = *B.scenes[s];
+            if (!scene_sorting(S))
+                continue;
+            const int64_t b = gb - B.boffs[s];
+            const int64_t n = S.np;
+            const int cur = (int)S.ctl[CTL_CUR], nxt = cur ^ 1;
+            const uint32_t nc = S.cnt[b * 64 + lane];
+            const uint32_t cs = S.cstart[b * 64 + lane];
+            S.cnt[b * 64 + lane] = 0u;
+            uint32_t levels = nc;
+            for (int o = 32; o > 0; o >>= 1)
+                levels = max(levels, (uint32_t)__shfl_xor(levels, o));
+            int64_t base = S.bstart[b];
+            for (uint32_t j = 0; j < levels; ++j) {
+                const bool act = j < nc;
+                const uint64_t m = __ballot(act);
+                if (act) {
+                    const int64_t p = S.perm[cs + j];
+                    const int64_t d = base + __popcll(m & below);
+                    for (int a = 0; a < 3; ++a) {
+                        pick(S.x, nxt)[a * n + d] = pick(S.x, cur)[a * n + p];
+                        ((R *)pick(S.v, nxt))[a * n + d] = ((const R *)pick(S.v, cur))[a * n + p];
+                    }
+                    for (int k = 0; k < 6; ++k)
+                        ((R *)pick(S.sig, nxt))[k * n + d] = ((const R *)pick(S.sig, cur))[k * n + p];
+                    ((R *)pick(S.vol, nxt))[d] = ((const R *)pick(S.vol, cur))[p];
+                    ((R *)pick(S.mass, nxt))[d] = ((const R *)pick(S.mass, cur))[p];
+                    pick(S.cell, nxt)[d] = pick(S.cell, cur)[p];
+                    pick(S.pid, nxt)[d] = pick(S.pid, cur)[p];
+                }
+                base += __popcll(m);
+            }
         }
     }
-    for (int a = 0; a < 3; ++a) {
-        mn[a] = wave_min(mn[a]);
-        mx[a] = wave_max(mx[a]);
-    }
+    if (!last_block(&B.flags[BF_TICKET_MOVE], &last))
+        return;
+    step_control(B);
     if (threadIdx.x == 0)
-        for (int a = 0; a < 3; ++a) {
-            red[a] = 1 << 30;
-            red[3 + a] = -(1 << 30);
-        }
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&red[a], mn[a]);
-            atomicMax(&red[3 + a], mx[a]);
-        }
-    __syncthreads();
-    Tile t;
-    for (int a = 0; a < 3; ++a) {
-        t.lo[a] = red[a] - ShapeTraits<SH>::lo;
-        t.dim[a] = red[3 + a] + ShapeTraits<SH>::hi - t.lo[a] + 1;
-    }
-    t.fits = (t.dim[0] * t.dim[1] * t.dim[2] <= kMaxTileNodes) ? 1 : 0;
-    t.pad = 0;
-    __syncthreads();
-    return t;
+        B.flags[BF_TICKET_MOVE] = 0u;
 }
 
-template <int SH>
-__device__ inline int tile_index(const Tile &t, const int base[3], int i, int j, int k)
+// ------------------------------------------------------- item kernels --
+// One workgroup per work item.  Particles are taken 256 at a time in storage
+// (level-major) order, so one instruction's lanes belong to distinct cells.
+// Scatters accumulate in FP64 in the workgroup's LDS node tile (an LDS add
+// of doubles is far cheaper than one of floats on gfx950) and are flushed
+// with one global atomic per touched node and component.
+
+// Particle arrays of one buffer, as global-memory pointers.
+template <typename R>
+struct Parts {
+    GLOBAL double *x[3];
+    GLOBAL R *v[3];
+    GLOBAL R *sig[6];
+    GLOBAL R *vol;
+    GLOBAL R *mass;
+    GLOBAL uint32_t *cell;
+};
+
+template <typename R>
+__device__ inline Parts<R> parts(const SceneDev &S, int cur)
 {
-    return (base[0] + i - t.lo[0]) + t.dim[0] * ((base[1] + j - t.lo[1]) + t.dim[1] * (base[2] + k - t.lo[2]));
+    Parts<R> P;
+    const size_t n = (size_t)S.np;
+    for (int a = 0; a < 3; ++a) {
+        P.x[a] = gp(pick(S.x, cur)) + a * n;
+        P.v[a] = gp((R *)pick(S.v, cur)) + a * n;
+    }
+    for (int k = 0; k < 6; ++k)
+        P.sig[k] = gp((R *)pick(S.sig, cur)) + k * n;
+    P.vol = gp((R *)pick(S.vol, cur));
+    P.mass = gp((R *)pick(S.mass, cur));
+    P.cell = gp(pick(S.cell, cur));
+    return P;
 }
 
-// ------------------------------------------------------------------ p2g --
-
-// Nodal mass and momentum (USF); with WITH_FORCE also the nodal force from
-// the current stress and volume (USL).
+// Nodal mass and momentum into the step's node buffer (first step of a call;
+// USF scenes whose buffer is already filled skip it); with WITH_FORCE also
+// the nodal force from the current stress and volume (USL, every step).
 template <typename R, int SH, bool WITH_FORCE>
-__global__ void __launch_bounds__(kBlock) k_p2g(BatchDev B)
+__global__ void __launch_bounds__(kItemThreads) k_p2g(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
-    __shared__ double lm[kMaxTileNodes];
-    __shared__ R lp[3][kMaxTileNodes];
-    __shared__ R lf[WITH_FORCE ? 3 : 1][WITH_FORCE ? kMaxTileNodes : 1];
+    constexpr int CAP = ShapeTraits<SH>::cap;
+    constexpr int NACC = WITH_FORCE ? 7 : 4;
+    __shared__ double acc[NACC][CAP];
     __shared__ int red[6];
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const ItemRef r = item_ref(B, g);
+        const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev &S = *r.S;
-        if (!scene_active(S))
+        if (!scene_active(S) || (!WITH_FORCE && S.ctl[CTL_HAVE_P2G]))
             continue;
         const Item item = S.items[r.it];
         const int cur = (int)S.ctl[CTL_CUR];
-        const int64_t n = S.np;
-        const Tile t = item_tile<SH>(S, item, S.key[cur], red);
-        if (threadIdx.x == 0)
-            S.tiles[r.it] = t;
+        const int buf = (int)S.ctl[CTL_NBUF];
+        const Parts<R> P = parts<R>(S, cur);
+        const NodeBuf<R> nb = node_buf<R>(S, buf);
+        const Tile t = item_tile<SH>(item, P.cell, red);
+        if (threadIdx.x == 0) {
+            pick(S.tiles, buf)[r.it] = t;
+            if (r.it == 0)
+                S.ctl[CTL_ACC0 + buf] = S.ctl[CTL_N_ITEMS];
+        }
         if (!t.fits) {
             if (threadIdx.x == 0)
                 atomicOr(&S.ctl[CTL_ERR], ERR_TILE);
             continue;
         }
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
-        for (int q = threadIdx.x; q < tv; q += blockDim.x) {
-            lm[q] = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                lp[a][q] = (R)0;
-                if constexpr (WITH_FORCE)
-                    lf[a][q] = (R)0;
-            }
-        }
+        for (int q = threadIdx.x; q < tv; q += blockDim.x)
+            for (int c = 0; c < NACC; ++c)
+                acc[c][q] = 0.0;
         __syncthreads();
-        const double *X = S.x[cur];
-        const R *V = (const R *)S.v[cur];
-        const R *M = (const R *)S.mass[cur];
-        const R *SG = (const R *)S.sig[cur];
-        const R *VO = (const R *)S.vol[cur];
         const R gx = (R)S.g[0], gy = (R)S.g[1], gz = (R)S.g[2];
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
-            const int64_t p = item.start + q;
-            const double xp[3] = {X[p], X[n + p], X[2 * n + p]};
+            const uint32_t p = item.start + q;
+            const double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
             int c[3];
-            key_to_cell(S, S.key[cur][p], c);
+            unpack_cell(P.cell[p], c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
-            const R mp = M[p];
-            const R mv[3] = {mp * V[p], mp * V[n + p], mp * V[2 * n + p]};
+            const Corners cn = corners(S, t, sp.base);
+            const R mp = P.mass[p];
+            const R mv[3] = {mp * P.v[0][p], mp * P.v[1][p], mp * P.v[2][p]};
             R sg[6], vol = (R)0;
             if constexpr (WITH_FORCE) {
                 for (int k = 0; k < 6; ++k)
-                    sg[k] = SG[k * n + p];
-                vol = VO[p];
+                    sg[k] = P.sig[k][p];
+                vol = P.vol[p];
             }
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
                     for (int i = 0; i < NS; ++i) {
                         const R wyz = sp.w[1][j] * sp.w[2][k];
                         const R N = sp.w[0][i] * wyz;
-                        const int li = tile_index<SH>(t, sp.base, i, j, k);
-                        atomicAdd(&lm[li], (double)(N * mp));
-                        atomicAdd(&lp[0][li], N * mv[0]);
-                        atomicAdd(&lp[1][li], N * mv[1]);
-                        atomicAdd(&lp[2][li], N * mv[2]);
+                        const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                        atomicAdd(&acc[0][li], (double)(N * mp));
+                        atomicAdd(&acc[1][li], (double)(N * mv[0]));
+                        atomicAdd(&acc[2][li], (double)(N * mv[1]));
+                        atomicAdd(&acc[3][li], (double)(N * mv[2]));
                         if constexpr (WITH_FORCE) {
                             const R gxN = sp.dw[0][i] * wyz;
                             const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
@@ -810,81 +1091,152 @@ __global__ void __launch_bounds__(kBlock) k_p2g(BatchDev B)
                             const R fx = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mp * gx;
                             const R fy = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy;
                             const R fz = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz;
-                            atomicAdd(&lf[0][li], fx);
-                            atomicAdd(&lf[1][li], fy);
-                            atomicAdd(&lf[2][li], fz);
+                            atomicAdd(&acc[4][li], (double)fx);
+                            atomicAdd(&acc[5][li], (double)fy);
+                            atomicAdd(&acc[6][li], (double)fz);
                         }
                     }
         }
         __syncthreads();
-        R *P = (R *)S.np_;
-        R *F = (R *)S.nf;
         for (int q = threadIdx.x; q < tv; q += blockDim.x) {
-            const double m = lm[q];
+            const double m = acc[0][q];
             if (m == 0.0)
                 continue;
-            const int i = t.lo[0] + q % t.dim[0];
-            const int j = t.lo[1] + (q / t.dim[0]) % t.dim[1];
-            const int k = t.lo[2] + q / (t.dim[0] * t.dim[1]);
-            const int64_t I = node_id(S, i, j, k);
-            atomicAdd(&S.nm[I], m);
+            int i, j, k;
+            tile_node(t, q, i, j, k);
+            const uint32_t I = node_id(S, i, j, k);
+            gadd(nb.m + I, m);
             for (int a = 0; a < 3; ++a)
-                atomicAdd(&P[a * S.nn + I], lp[a][q]);
+                gadd(nb.p[a] + I, (R)acc[1 + a][q]);
             if constexpr (WITH_FORCE)
                 for (int a = 0; a < 3; ++a)
-                    atomicAdd(&F[a * S.nn + I], lf[a][q]);
+                    gadd(nb.f[a] + I, (R)acc[4 + a][q]);
         }
         __syncthreads();
     }
 }
 
-// --------------------------------------------------------------- stress --
+// Per-thread support cache of the item kernels.  With T threads per item,
+// thread t takes the item's particles t, t + T, t + 2T, ...; in level-major
+// order these are successive particles of one cell, so with linear shape
+// functions they share one support.  The thread then gathers that support's
+// nodal values from LDS once and sums its particles' scatter contributions
+// in registers, touching LDS again only when the support changes.  GIMP
+// supports differ between particles of a cell, so GIMP gathers and scatters
+// per particle.
+template <int SH>
+struct Cache {
+    static constexpr bool on = SH == 0;
+    static constexpr int nodes = on ? ShapeTraits<SH>::NS * ShapeTraits<SH>::NS * ShapeTraits<SH>::NS : 1;
+};
 
-// USF: nodal velocity, strain increment, volume and stress update, nodal
-// internal + external force.
+__device__ inline bool same_base(const int a[3], const int b[3])
+{
+    return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
+}
+
+// USF: zero the previous step's node buffer; nodal velocity, strain
+// increment, volume and stress update, nodal internal + external force.
 template <typename R, int SH>
-__global__ void __launch_bounds__(kBlock) k_stress(BatchDev B)
+__global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
-    __shared__ R4<R> lv[kMaxTileNodes];
-    __shared__ R lf[3][kMaxTileNodes];
+    constexpr int CAP = ShapeTraits<SH>::cap;
+    constexpr int KP = kChunk / kItemThreads;
+    constexpr bool CACHE = Cache<SH>::on;
+    constexpr int CN = Cache<SH>::nodes;
+    __shared__ R4<R> lv[CAP];
+    __shared__ double lf[3][CAP];
+    __shared__ int red[6];
+    clear_previous<R>(B);
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const ItemRef r = item_ref(B, g);
+        const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev &S = *r.S;
         if (!scene_active(S))
             continue;
         const Item item = S.items[r.it];
-        const Tile t = S.tiles[r.it];
-        if (!t.fits)
-            continue;
         const int cur = (int)S.ctl[CTL_CUR];
-        const int64_t n = S.np;
+        const int buf = (int)S.ctl[CTL_NBUF];
+        const Parts<R> P = parts<R>(S, cur);
+        const NodeBuf<R> nb = node_buf<R>(S, buf);
+        uint32_t pcell[KP];
+        int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+        for (int rr = 0; rr < KP; ++rr) {
+            const uint32_t q = threadIdx.x + rr * kItemThreads;
+            if (q >= item.count)
+                continue;
+            pcell[rr] = P.cell[item.start + q];
+            int c[3];
+            unpack_cell(pcell[rr], c);
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = min(mn[a], c[a]);
+                mx[a] = max(mx[a], c[a]);
+            }
+        }
+        block_box(mn, mx, red);
+        const int blo[3] = {red[0], red[1], red[2]}, bhi[3] = {red[3], red[4], red[5]};
+        const Tile t = tile_of_cells<SH>(blo, bhi);
+        if (threadIdx.x == 0)
+            S.tstep[r.it] = t;
+        if (!t.fits) {
+            if (threadIdx.x == 0)
+                atomicOr(&S.ctl[CTL_ERR], ERR_TILE);
+            __syncthreads();
+            continue;
+        }
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
         for (int q = threadIdx.x; q < tv; q += blockDim.x) {
-            const int i = t.lo[0] + q % t.dim[0];
-            const int j = t.lo[1] + (q / t.dim[0]) % t.dim[1];
-            const int k = t.lo[2] + q / (t.dim[0] * t.dim[1]);
+            int i, j, k;
+            tile_node(t, q, i, j, k);
             R v[3];
-            node_velocity<R>(S, i, j, k, v);
+            node_velocity<R>(S, nb, i, j, k, v);
             lv[q] = R4<R>{v[0], v[1], v[2], (R)0};
-            lf[0][q] = lf[1][q] = lf[2][q] = (R)0;
+            lf[0][q] = lf[1][q] = lf[2][q] = 0.0;
         }
         __syncthreads();
-        const double *X = S.x[cur];
-        const R *M = (const R *)S.mass[cur];
-        R *SG = (R *)S.sig[cur];
-        R *VO = (R *)S.vol[cur];
         const R dt = (R)S.dt;
         const R gx = (R)S.g[0], gy = (R)S.g[1], gz = (R)S.g[2];
         uint32_t bad = 0;
-        for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
-            const int64_t p = item.start + q;
-            const double xp[3] = {X[p], X[n + p], X[2 * n + p]};
+        int kb[3] = {-(1 << 30), 0, 0};   // support base held in the cache
+        Corners kc{};
+        R cv[CN][3], fa[CN][3];
+        auto flush = [&]() {
+            for (int n = 0; n < CN; ++n) {
+                const int li = kc.t0 + (n & 1) + ((n >> 1) & 1) * kc.ty + (n >> 2) * kc.tz;
+                for (int a = 0; a < 3; ++a)
+                    atomicAdd(&lf[a][li], (double)fa[n][a]);
+            }
+        };
+#pragma unroll
+        for (int rr = 0; rr < KP; ++rr) {
+            const uint32_t q = threadIdx.x + rr * kItemThreads;
+            if (q >= item.count)
+                break;
+            const uint32_t p = item.start + q;
+            const double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
             int c[3];
-            key_to_cell(S, S.key[cur][p], c);
+            unpack_cell(pcell[rr], c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
+            const Corners cn = corners(S, t, sp.base);
+            if constexpr (CACHE) {
+                if (!same_base(sp.base, kb)) {
+                    if (kb[0] != -(1 << 30))
+                        flush();
+                    for (int a = 0; a < 3; ++a)
+                        kb[a] = sp.base[a];
+                    kc = cn;
+                    for (int n = 0; n < CN; ++n) {
+                        const R4<R> v = lv[cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz];
+                        cv[n][0] = v.x;
+                        cv[n][1] = v.y;
+                        cv[n][2] = v.z;
+                        fa[n][0] = fa[n][1] = fa[n][2] = (R)0;
+                    }
+                }
+            }
             R L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
@@ -892,31 +1244,42 @@ __global__ void __launch_bounds__(kBlock) k_stress(BatchDev B)
                         const R gxN = sp.dw[0][i] * sp.w[1][j] * sp.w[2][k];
                         const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
                         const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
-                        const R4<R> v = lv[tile_index<SH>(t, sp.base, i, j, k)];
-                        L[0][0] += v.x * gxN;
-                        L[0][1] += v.x * gyN;
-                        L[0][2] += v.x * gzN;
-                        L[1][0] += v.y * gxN;
-                        L[1][1] += v.y * gyN;
-                        L[1][2] += v.y * gzN;
-                        L[2][0] += v.z * gxN;
-                        L[2][1] += v.z * gyN;
-                        L[2][2] += v.z * gzN;
+                        R v[3];
+                        if constexpr (CACHE) {
+                            const int n = i + 2 * j + 4 * k;
+                            v[0] = cv[n][0];
+                            v[1] = cv[n][1];
+                            v[2] = cv[n][2];
+                        } else {
+                            const R4<R> w = lv[cn.t0 + i + j * cn.ty + k * cn.tz];
+                            v[0] = w.x;
+                            v[1] = w.y;
+                            v[2] = w.z;
+                        }
+                        L[0][0] += v[0] * gxN;
+                        L[0][1] += v[0] * gyN;
+                        L[0][2] += v[0] * gzN;
+                        L[1][0] += v[1] * gxN;
+                        L[1][1] += v[1] * gyN;
+                        L[1][2] += v[1] * gzN;
+                        L[2][0] += v[2] * gxN;
+                        L[2][1] += v[2] * gyN;
+                        L[2][2] += v[2] * gzN;
                     }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-            R vol = VO[p] * ((R)1 + de[0] + de[1] + de[2]);
+            const R vol = P.vol[p] * ((R)1 + de[0] + de[1] + de[2]);
             R sg[6];
             for (int k = 0; k < 6; ++k)
-                sg[k] = SG[k * n + p];
+                sg[k] = P.sig[k][p];
             constitutive<R>(S, de, sg);
             for (int k = 0; k < 6; ++k) {
-                SG[k * n + p] = sg[k];
+                P.sig[k][p] = sg[k];
                 if (!isfinite(sg[k]))
                     bad = ERR_NONFINITE;
             }
-            VO[p] = vol;
-            const R mp = M[p];
+            P.vol[p] = vol;
+            const R mp = P.mass[p];
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
                     for (int i = 0; i < NS; ++i) {
@@ -925,85 +1288,317 @@ __global__ void __launch_bounds__(kBlock) k_stress(BatchDev B)
                         const R gxN = sp.dw[0][i] * wyz;
                         const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
                         const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
-                        const int li = tile_index<SH>(t, sp.base, i, j, k);
-                        atomicAdd(&lf[0][li], -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mp * gx);
-                        atomicAdd(&lf[1][li], -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy);
-                        atomicAdd(&lf[2][li], -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz);
+                        const R f0 = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mp * gx;
+                        const R f1 = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy;
+                        const R f2 = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz;
+                        if constexpr (CACHE) {
+                            const int n = i + 2 * j + 4 * k;
+                            fa[n][0] += f0;
+                            fa[n][1] += f1;
+                            fa[n][2] += f2;
+                        } else {
+                            const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                            atomicAdd(&lf[0][li], (double)f0);
+                            atomicAdd(&lf[1][li], (double)f1);
+                            atomicAdd(&lf[2][li], (double)f2);
+                        }
                     }
         }
+        if constexpr (CACHE)
+            if (kb[0] != -(1 << 30))
+                flush();
         if (bad)
             atomicOr(&S.ctl[CTL_ERR], bad);
         __syncthreads();
-        R *F = (R *)S.nf;
         for (int q = threadIdx.x; q < tv; q += blockDim.x) {
-            const R f0 = lf[0][q], f1 = lf[1][q], f2 = lf[2][q];
+            const R f0 = (R)lf[0][q], f1 = (R)lf[1][q], f2 = (R)lf[2][q];
             if (f0 == (R)0 && f1 == (R)0 && f2 == (R)0)
                 continue;
-            const int i = t.lo[0] + q % t.dim[0];
-            const int j = t.lo[1] + (q / t.dim[0]) % t.dim[1];
-            const int k = t.lo[2] + q / (t.dim[0] * t.dim[1]);
-            const int64_t I = node_id(S, i, j, k);
-            atomicAdd(&F[I], f0);
-            atomicAdd(&F[S.nn + I], f1);
-            atomicAdd(&F[2 * S.nn + I], f2);
+            int i, j, k;
+            tile_node(t, q, i, j, k);
+            const uint32_t I = node_id(S, i, j, k);
+            gadd(nb.f[0] + I, f0);
+            gadd(nb.f[1] + I, f1);
+            gadd(nb.f[2] + I, f2);
         }
         __syncthreads();
     }
 }
 
-// ------------------------------------------------------------------ g2p --
+// Load the acceleration and updated velocity of the item's node tile.
+template <typename R>
+__device__ inline void load_update_tile(const SceneDev &S, const NodeBuf<R> &nb, const Tile &t, R4<R> *la,
+                                        R4<R> *lvn)
+{
+    const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+    for (int q = threadIdx.x; q < tv; q += blockDim.x) {
+        int i, j, k;
+        tile_node(t, q, i, j, k);
+        R a[3], vn[3];
+        node_update<R>(S, nb, i, j, k, a, vn);
+        la[q] = R4<R>{a[0], a[1], a[2], (R)0};
+        lvn[q] = R4<R>{vn[0], vn[1], vn[2], (R)0};
+    }
+}
 
-// Particle velocity and position from the nodal acceleration and updated
-// velocity; new cell key; reorder and error flags.  WITH_STRESS (USL): then
-// the strain increment from the updated nodal velocity and the stress update.
-template <typename R, int SH, bool WITH_STRESS>
-__global__ void __launch_bounds__(kBlock) k_g2p(BatchDev B)
+// USF: particle velocity (FLIP/PIC) and position from the nodal acceleration
+// and updated velocity; new cell, error and reorder flags; then the next
+// step's nodal mass and momentum from the updated particle into the other
+// (zeroed) node buffer, through an LDS tile over the item's home region
+// (particles that drifted past it add to global memory directly).
+template <typename R, int SH>
+__global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
-    __shared__ R4<R> la[kMaxTileNodes];
-    __shared__ R4<R> lvn[kMaxTileNodes];
+    constexpr int CAP = ShapeTraits<SH>::cap;
+    constexpr int KP = kChunk / kItemThreads;
+    constexpr bool CACHE = Cache<SH>::on;
+    constexpr int CN = Cache<SH>::nodes;
+    __shared__ R4<R> la[CAP];
+    __shared__ R4<R> lvn[CAP];
+    __shared__ double acc[4][CAP];
+    __shared__ int red[6];
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const ItemRef r = item_ref(B, g);
+        const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev &S = *r.S;
         if (!scene_active(S))
             continue;
         const Item item = S.items[r.it];
-        const Tile t = S.tiles[r.it];
+        const Tile t = S.tstep[r.it];
         if (!t.fits)
             continue;
         const int cur = (int)S.ctl[CTL_CUR];
-        const int64_t n = S.np;
-        const int tv = t.dim[0] * t.dim[1] * t.dim[2];
-        for (int q = threadIdx.x; q < tv; q += blockDim.x) {
-            const int i = t.lo[0] + q % t.dim[0];
-            const int j = t.lo[1] + (q / t.dim[0]) % t.dim[1];
-            const int k = t.lo[2] + q / (t.dim[0] * t.dim[1]);
-            R a[3], vn[3];
-            node_update<R>(S, i, j, k, a, vn);
-            la[q] = R4<R>{a[0], a[1], a[2], (R)0};
-            lvn[q] = R4<R>{vn[0], vn[1], vn[2], (R)0};
-        }
+        const int buf = (int)S.ctl[CTL_NBUF], nbuf = buf ^ 1;
+        const Parts<R> P = parts<R>(S, cur);
+        const NodeBuf<R> nb = node_buf<R>(S, buf);
+        const NodeBuf<R> nn = node_buf<R>(S, nbuf);
+        int o[3];
+        brick_origin(S, item.brick, o);
+        const Tile ht = home_tile<SH>(o);
+        load_update_tile<R>(S, nb, t, la, lvn);
+        for (int q = threadIdx.x; q < CAP; q += blockDim.x)
+            acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
         __syncthreads();
-        double *X = S.x[cur];
-        R *V = (R *)S.v[cur];
-        R *SG = (R *)S.sig[cur];
-        R *VO = (R *)S.vol[cur];
-        uint32_t *KEY = S.key[cur];
         const R dt = (R)S.dt;
         const int pic = S.vel_update == 1;
-        // home region: the item's brick widened by one cell
-        const uint32_t bb = item.brick;
-        const int hb[3] = {(int)(bb % (uint32_t)S.nb[0]) * 4, (int)((bb / (uint32_t)S.nb[0]) % (uint32_t)S.nb[1]) * 4,
-                           (int)(bb / ((uint32_t)S.nb[0] * (uint32_t)S.nb[1])) * 4};
         uint32_t err = 0, drift = 0;
-        for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
-            const int64_t p = item.start + q;
-            double xp[3] = {X[p], X[n + p], X[2 * n + p]};
+        int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+        // gather cache (old support) and scatter cache (new support)
+        int gb[3] = {-(1 << 30), 0, 0}, sb[3] = {-(1 << 30), 0, 0};
+        R ca[CN][3], cu[CN][3], sp_[CN][3];
+        double sm[CN];
+        Corners sc{};
+        bool s_in = true;
+        auto flush = [&]() {
+            for (int n = 0; n < CN; ++n) {
+                const int di = n & 1, dj = (n >> 1) & 1, dk = n >> 2;
+                if (s_in) {
+                    const int li = sc.t0 + di + dj * sc.ty + dk * sc.tz;
+                    atomicAdd(&acc[0][li], sm[n]);
+                    for (int a = 0; a < 3; ++a)
+                        atomicAdd(&acc[1 + a][li], (double)sp_[n][a]);
+                } else {
+                    const uint32_t I = sc.n0 + (uint32_t)(di + dj * sc.ny + dk * sc.nz);
+                    gadd(nn.m + I, sm[n]);
+                    for (int a = 0; a < 3; ++a)
+                        gadd(nn.p[a] + I, sp_[n][a]);
+                }
+            }
+        };
+#pragma unroll
+        for (int rr = 0; rr < KP; ++rr) {
+            const uint32_t q = threadIdx.x + rr * kItemThreads;
+            if (q >= item.count)
+                break;
+            const uint32_t p = item.start + q;
+            double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
+            const R pv[3] = {P.v[0][p], P.v[1][p], P.v[2][p]};
+            const R mp = P.mass[p];
             int c[3];
-            key_to_cell(S, KEY[p], c);
+            unpack_cell(P.cell[p], c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
+            const Corners cn = corners(S, t, sp.base);
+            if constexpr (CACHE) {
+                if (!same_base(sp.base, gb)) {
+                    for (int a = 0; a < 3; ++a)
+                        gb[a] = sp.base[a];
+                    for (int n = 0; n < CN; ++n) {
+                        const int li = cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz;
+                        const R4<R> a4 = la[li], u4 = lvn[li];
+                        ca[n][0] = a4.x;
+                        ca[n][1] = a4.y;
+                        ca[n][2] = a4.z;
+                        cu[n][0] = u4.x;
+                        cu[n][1] = u4.y;
+                        cu[n][2] = u4.z;
+                    }
+                }
+            }
+            R dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+            for (int k = 0; k < NS; ++k)
+                for (int j = 0; j < NS; ++j)
+                    for (int i = 0; i < NS; ++i) {
+                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                        R a[3], u[3];
+                        if constexpr (CACHE) {
+                            const int n = i + 2 * j + 4 * k;
+                            for (int e = 0; e < 3; ++e) {
+                                a[e] = ca[n][e];
+                                u[e] = cu[n][e];
+                            }
+                        } else {
+                            const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                            const R4<R> a4 = la[li], u4 = lvn[li];
+                            a[0] = a4.x;
+                            a[1] = a4.y;
+                            a[2] = a4.z;
+                            u[0] = u4.x;
+                            u[1] = u4.y;
+                            u[2] = u4.z;
+                        }
+                        for (int e = 0; e < 3; ++e) {
+                            dv[e] += N * a[e];
+                            vp[e] += N * u[e];
+                        }
+                    }
+            R nv[3];
+            for (int a = 0; a < 3; ++a) {
+                nv[a] = pic ? vp[a] : pv[a] + dt * dv[a];
+                P.v[a][p] = nv[a];
+                xp[a] += S.dt * (double)vp[a];
+                P.x[a][p] = xp[a];
+                if (!isfinite(nv[a]))
+                    err |= ERR_NONFINITE;
+            }
+            int nc[3];
+            const uint32_t e = locate(S, xp, nc);
+            if (e) {
+                err |= e;   // keep the old cell; the scene stops after this step
+                continue;
+            }
+            P.cell[p] = pack_cell(nc);
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = min(mn[a], nc[a]);
+                mx[a] = max(mx[a], nc[a]);
+            }
+            const bool in = in_home(nc, o);
+            drift |= in ? 0u : 1u;
+            // the next step's P2G from the updated particle
+            make_support<R, SH>(S, xp, nc, sp);
+            const Corners hn = corners(S, ht, sp.base);
+            const R mv[3] = {mp * nv[0], mp * nv[1], mp * nv[2]};
+            if constexpr (CACHE) {
+                if (!same_base(sp.base, sb)) {
+                    if (sb[0] != -(1 << 30))
+                        flush();
+                    for (int a = 0; a < 3; ++a)
+                        sb[a] = sp.base[a];
+                    sc = hn;
+                    s_in = in;
+                    for (int n = 0; n < CN; ++n) {
+                        sm[n] = 0.0;
+                        sp_[n][0] = sp_[n][1] = sp_[n][2] = (R)0;
+                    }
+                }
+            }
+            for (int k = 0; k < NS; ++k)
+                for (int j = 0; j < NS; ++j)
+                    for (int i = 0; i < NS; ++i) {
+                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                        if constexpr (CACHE) {
+                            const int n = i + 2 * j + 4 * k;
+                            sm[n] += (double)(N * mp);
+                            for (int a = 0; a < 3; ++a)
+                                sp_[n][a] += N * mv[a];
+                        } else if (in) {
+                            const int li = hn.t0 + i + j * hn.ty + k * hn.tz;
+                            atomicAdd(&acc[0][li], (double)(N * mp));
+                            atomicAdd(&acc[1][li], (double)(N * mv[0]));
+                            atomicAdd(&acc[2][li], (double)(N * mv[1]));
+                            atomicAdd(&acc[3][li], (double)(N * mv[2]));
+                        } else {
+                            const uint32_t I = hn.n0 + (uint32_t)(i + j * hn.ny + k * hn.nz);
+                            gadd(nn.m + I, (double)(N * mp));
+                            for (int a = 0; a < 3; ++a)
+                                gadd(nn.p[a] + I, N * mv[a]);
+                        }
+                    }
+        }
+        if constexpr (CACHE)
+            if (sb[0] != -(1 << 30))
+                flush();
+        if (err)
+            atomicOr(&S.ctl[CTL_ERR], err);
+        if (drift || (S.sort_always && threadIdx.x == 0)) {
+            S.ctl[CTL_NEED_SORT] = 1u;
+            B.flags[BF_ANY_SORT] = 1u;
+        }
+        block_box(mn, mx, red);
+        const int blo[3] = {red[0], red[1], red[2]}, bhi[3] = {red[3], red[4], red[5]};
+        if (threadIdx.x == 0) {
+            pick(S.tiles, nbuf)[r.it] = tile_of_cells<SH>(blo, bhi);
+            if (r.it == 0) {
+                S.ctl[CTL_ACC0 + nbuf] = S.ctl[CTL_N_ITEMS];
+                S.ctl[CTL_READY] = 1u;
+            }
+        }
+        for (int q = threadIdx.x; q < CAP; q += blockDim.x) {
+            const double m = acc[0][q];
+            int i, j, k;
+            tile_node(ht, q, i, j, k);
+            if (m == 0.0 || !node_in_mesh(S, i, j, k))
+                continue;
+            const uint32_t I = node_id(S, i, j, k);
+            gadd(nn.m + I, m);
+            for (int a = 0; a < 3; ++a)
+                gadd(nn.p[a] + I, (R)acc[1 + a][q]);
+        }
+        __syncthreads();
+    }
+}
+
+// USL: particle velocity and position, then the strain increment from the
+// updated nodal velocity and the stress update; zeroes the previous step's
+// node buffer.
+template <typename R, int SH>
+__global__ void __launch_bounds__(kItemThreads) k_g2p_usl(BatchDev B)
+{
+    constexpr int NS = ShapeTraits<SH>::NS;
+    constexpr int CAP = ShapeTraits<SH>::cap;
+    __shared__ R4<R> la[CAP];
+    __shared__ R4<R> lvn[CAP];
+    clear_previous<R>(B);
+    const int64_t total = B.ioffs[B.nscenes];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const ItemRef r = item_ref(B.ioffs, B, g);
+        const SceneDev &S = *r.S;
+        if (!scene_active(S))
+            continue;
+        const Item item = S.items[r.it];
+        const int buf = (int)S.ctl[CTL_NBUF];
+        const Tile t = pick(S.tiles, buf)[r.it];
+        if (!t.fits)
+            continue;
+        const int cur = (int)S.ctl[CTL_CUR];
+        const Parts<R> P = parts<R>(S, cur);
+        const NodeBuf<R> nb = node_buf<R>(S, buf);
+        int o[3];
+        brick_origin(S, item.brick, o);
+        load_update_tile<R>(S, nb, t, la, lvn);
+        __syncthreads();
+        const R dt = (R)S.dt;
+        const int pic = S.vel_update == 1;
+        uint32_t err = 0, drift = 0;
+        for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
+            const uint32_t p = item.start + q;
+            double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
+            int c[3];
+            unpack_cell(P.cell[p], c);
+            Support<R, SH> sp;
+            make_support<R, SH>(S, xp, c, sp);
+            const Corners cn = corners(S, t, sp.base);
             R dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
             R L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
             for (int k = 0; k < NS; ++k)
@@ -1011,77 +1606,66 @@ __global__ void __launch_bounds__(kBlock) k_g2p(BatchDev B)
                     for (int i = 0; i < NS; ++i) {
                         const R wyz = sp.w[1][j] * sp.w[2][k];
                         const R N = sp.w[0][i] * wyz;
-                        const int li = tile_index<SH>(t, sp.base, i, j, k);
+                        const R gxN = sp.dw[0][i] * wyz;
+                        const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
+                        const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
+                        const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
                         const R4<R> a = la[li];
-                        const R4<R> w = lvn[li];
+                        const R4<R> u = lvn[li];
                         dv[0] += N * a.x;
                         dv[1] += N * a.y;
                         dv[2] += N * a.z;
-                        vp[0] += N * w.x;
-                        vp[1] += N * w.y;
-                        vp[2] += N * w.z;
-                        if constexpr (WITH_STRESS) {
-                            const R gxN = sp.dw[0][i] * wyz;
-                            const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
-                            const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
-                            L[0][0] += w.x * gxN;
-                            L[0][1] += w.x * gyN;
-                            L[0][2] += w.x * gzN;
-                            L[1][0] += w.y * gxN;
-                            L[1][1] += w.y * gyN;
-                            L[1][2] += w.y * gzN;
-                            L[2][0] += w.z * gxN;
-                            L[2][1] += w.z * gyN;
-                            L[2][2] += w.z * gzN;
-                        }
+                        vp[0] += N * u.x;
+                        vp[1] += N * u.y;
+                        vp[2] += N * u.z;
+                        L[0][0] += u.x * gxN;
+                        L[0][1] += u.x * gyN;
+                        L[0][2] += u.x * gzN;
+                        L[1][0] += u.y * gxN;
+                        L[1][1] += u.y * gyN;
+                        L[1][2] += u.y * gzN;
+                        L[2][0] += u.z * gxN;
+                        L[2][1] += u.z * gyN;
+                        L[2][2] += u.z * gzN;
                     }
             for (int a = 0; a < 3; ++a) {
-                const R nv = pic ? vp[a] : V[a * n + p] + dt * dv[a];
-                V[a * n + p] = nv;
+                const R nva = pic ? vp[a] : P.v[a][p] + dt * dv[a];
+                P.v[a][p] = nva;
                 xp[a] += S.dt * (double)vp[a];
-                X[a * n + p] = xp[a];
-                if (!isfinite(nv))
+                P.x[a][p] = xp[a];
+                if (!isfinite(nva))
                     err |= ERR_NONFINITE;
             }
-            if constexpr (WITH_STRESS) {
-                const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
-                                 dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-                VO[p] = VO[p] * ((R)1 + de[0] + de[1] + de[2]);
-                R sg[6];
-                for (int k = 0; k < 6; ++k)
-                    sg[k] = SG[k * n + p];
-                constitutive<R>(S, de, sg);
-                for (int k = 0; k < 6; ++k) {
-                    SG[k * n + p] = sg[k];
-                    if (!isfinite(sg[k]))
-                        err |= ERR_NONFINITE;
-                }
+            const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
+                             dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
+            P.vol[p] = P.vol[p] * ((R)1 + de[0] + de[1] + de[2]);
+            R sg[6];
+            for (int k = 0; k < 6; ++k)
+                sg[k] = P.sig[k][p];
+            constitutive<R>(S, de, sg);
+            for (int k = 0; k < 6; ++k) {
+                P.sig[k][p] = sg[k];
+                if (!isfinite(sg[k]))
+                    err |= ERR_NONFINITE;
             }
             int nc[3];
             const uint32_t e = locate(S, xp, nc);
             if (e) {
                 err |= e;
-                continue;   // keep the old key; the scene stops
+                continue;
             }
-            KEY[p] = cell_to_key(S, nc);
-            for (int a = 0; a < 3; ++a)
-                if (nc[a] < hb[a] - 1 || nc[a] > hb[a] + kBrick)
-                    drift = 1;
+            P.cell[p] = pack_cell(nc);
+            drift |= in_home(nc, o) ? 0u : 1u;
         }
         if (err)
             atomicOr(&S.ctl[CTL_ERR], err);
-        if (drift || (S.sort_always && threadIdx.x == 0))
+        if (drift || (S.sort_always && threadIdx.x == 0)) {
             S.ctl[CTL_NEED_SORT] = 1u;
+            B.flags[BF_ANY_SORT] = 1u;
+        }
         __syncthreads();
     }
 }
-
-// ------------------------------------------------------ instantiations --
-
-template __global__ void k_load<float>(SceneDev *, const double *, const double *, const double *, const double *,
-                                       const double *);
-template __global__ void k_load<double>(SceneDev *, const double *, const double *, const double *, const double *,
-                                        const double *);
 
 }  // namespace mpmx
 
@@ -1098,13 +1682,12 @@ static KernelSet make_set()
     k.load = (const void *)&k_load<R>;
     k.read_out = (const void *)&k_read_out<R>;
     k.nodes_out = (const void *)&k_nodes_out<R>;
-    k.clear = (const void *)&k_clear<R>;
-    k.scatter = (const void *)&k_sort_scatter<R>;
+    k.move = (const void *)&k_sort_move<R>;
     k.p2g = (const void *)&k_p2g<R, SH, false>;
     k.stress = (const void *)&k_stress<R, SH>;
-    k.g2p = (const void *)&k_g2p<R, SH, false>;
+    k.g2p_p2g = (const void *)&k_g2p_p2g<R, SH>;
     k.p2g_usl = (const void *)&k_p2g<R, SH, true>;
-    k.g2p_usl = (const void *)&k_g2p<R, SH, true>;
+    k.g2p_usl = (const void *)&k_g2p_usl<R, SH>;
     return k;
 }
 
@@ -1117,10 +1700,9 @@ const KernelSet &kernel_set(int prec, int shape)
 
 const CommonKernels &common_kernels()
 {
-    static const CommonKernels c = {(const void *)&k_step_control, (const void *)&k_set_remaining,
-                                    (const void *)&k_sort_count,   (const void *)&k_sort_bricks,
-                                    (const void *)&k_sort_scan,    (const void *)&k_sort_cells,
-                                    (const void *)&k_cell_counts};
+    static const CommonKernels c = {(const void *)&k_begin,      (const void *)&k_sort_count,
+                                    (const void *)&k_sort_bricks, (const void *)&k_sort_cells,
+                                    (const void *)&k_sort_perm,   (const void *)&k_cell_counts};
     return c;
 }
 

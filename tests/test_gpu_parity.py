@@ -226,6 +226,37 @@ def test_column_full_size_first_steps(ctx, mp):
     s.destroy()
 
 
+def test_column_full_run_against_stored_oracle_sample(ctx, mp):
+    """All 1000 steps of the 2.1M-particle column in the benchmark's launch
+    configuration against the oracle's final state, stored for every 1024th
+    particle by tests/golden/make_column_golden.py (which calls only the
+    oracle).  Displacement and stress bars as above on the sample; the
+    particles-per-cell histogram of all particles may differ from the
+    oracle's only by particles that sit on a cell face in one of the two runs,
+    which moves a particle between neighbouring cells: the differing mass of
+    the histograms is bounded by 1e-4 of all particles."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "column_2m_1000.npz")
+    gold = np.load(path)
+    sc = scenes.c2()
+    idx = gold["index"]
+    np.testing.assert_array_equal(sc["x"][idx], gold["x0"])
+    np.testing.assert_array_equal(oracle.cell_counts(sc["mesh"], sc["x"]), gold["hist0"])
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(int(gold["nsteps"]))
+    got = s.read()
+    sub = {k: got[k][idx] for k in ("x", "v", "stress", "vol")}
+    ref = {k: gold[k] for k in ("x", "v", "stress", "vol")}
+    check_state("column/fp32/1000", sub, ref, gold["x0"], U_TOL, S_TOL, 1e-3)
+    hc = s.cell_counts().astype(np.int64)
+    hr = gold["hist"].astype(np.int64)
+    moved = int(np.abs(hc - hr).sum())
+    print(f"[column/fp32/1000] histogram L1 difference {moved} of {len(sc['x'])} particles", flush=True)
+    assert hc.sum() == hr.sum() == len(sc["x"])
+    assert moved <= 1e-4 * len(sc["x"])
+    s.destroy()
+
+
 @pytest.mark.parametrize("shape", [1, 0])
 def test_column_subsample_steps(ctx, mp, shape):
     """The 1/64 subsample of the 25M-particle column (393,216 particles,
