@@ -98,6 +98,96 @@ def cpu_baseline(sc: dict, steps: int) -> dict:
             "seconds": round(dt, 3)}
 
 
+def _csv_rows(root: str, suffix: str):
+    import csv
+    for dirpath, _, files in os.walk(root):
+        for f in files:
+            if f.endswith(suffix):
+                with open(os.path.join(dirpath, f), newline="") as fh:
+                    yield from csv.DictReader(fh)
+
+
+def _short(name: str) -> str:
+    name = name.split("(")[0].replace("void ", "").replace("mpmx::", "")
+    return name.strip()
+
+
+def _counter_means(root: str) -> dict:
+    """Mean counter value per dispatch, per kernel and counter, from the
+    counter_collection CSV files under root."""
+    acc: dict = {}
+    for r in _csv_rows(root, "counter_collection.csv"):
+        key = (_short(r["Kernel_Name"]), r["Counter_Name"])
+        tot = acc.setdefault(key, {})
+        d = r.get("Dispatch_Id", str(len(tot)))
+        tot[d] = tot.get(d, 0.0) + float(r["Counter_Value"])
+    return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+
+def summarize(root: str, workload: str, commands: str):
+    """Kernel-trace statistics and HBM traffic per launch from rocprofv3 CSV
+    output: root/trace (--kernel-trace --stats), root/copy_FETCH_SIZE,
+    root/copy_WRITE_SIZE (the 1 GiB device copy of --calibrate-copy 1024),
+    root/FETCH_SIZE, root/WRITE_SIZE (the step).  Counters are KiB per
+    dispatch; each is scaled by (known bytes of the copy) / (what the same
+    counter reads for the copy kernel)."""
+    stats = list(_csv_rows(os.path.join(root, "trace"), "kernel_stats.csv"))
+    lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (repository root, rocprofv3 from ROCm 7.2):", ""]
+    lines += [f"    {c}" for c in commands.split(";;") if c.strip()] + [""]
+    lines.append(f"{'kernel':34s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_%':>8s}")
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{_short(r['Name'])[:34]:34s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):8.2f}")
+    bench_line = None
+    log = os.path.join(root, "trace.log")
+    if os.path.exists(log):
+        for ln in open(log):
+            if ln.startswith("{") and '"metric"' in ln:
+                bench_line = json.loads(ln)
+    if bench_line and "kernels" in bench_line:
+        lines += ["", "Same run, HIP events around each launch on the library's stream (bench.py's own timing):",
+                  f"ms_per_step {bench_line['ms_per_step']:.4f}, value {bench_line['value']:.4g} "
+                  f"{bench_line['unit']}", ""]
+        lines.append(f"{'kernel':34s} {'events_avg_us':>14s} {'rocprof_avg_us':>15s}")
+        rp = {_short(r["Name"]).split("<")[0].replace("k_", ""): float(r["AverageNs"]) / 1e3 for r in stats}
+        for k, v in sorted(bench_line["kernels"].items()):
+            lines.append(f"{k:34s} {v['avg_us']:14.2f} {rp.get(k, float('nan')):15.2f}")
+    traffic = {}
+    copy_bytes = 1024 << 20
+    scale = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cm = _counter_means(os.path.join(root, "copy_" + c))
+        kib = [v for (k, cn), v in cm.items() if cn == c and "copyBuffer" in k]
+        if kib:
+            scale[c] = copy_bytes / (max(kib) * 1024.0)
+    if len(scale) == 2:
+        lines += ["", "HBM traffic per launch (rocprofv3 --pmc, KiB per dispatch scaled by the copy calibration:",
+                  f"FETCH_SIZE x {scale['FETCH_SIZE']:.4f}, WRITE_SIZE x {scale['WRITE_SIZE']:.4f}; "
+                  f"the copy moves {copy_bytes} bytes each way)", ""]
+        lines.append(f"{'kernel':34s} {'read_MB':>10s} {'write_MB':>10s} {'total_MB':>10s}")
+        fm = _counter_means(os.path.join(root, "FETCH_SIZE"))
+        wm = _counter_means(os.path.join(root, "WRITE_SIZE"))
+        for k in sorted({k for k, _ in fm} & {k for k, _ in wm}):
+            rd = fm[(k, "FETCH_SIZE")] * 1024.0 * scale["FETCH_SIZE"]
+            wr = wm[(k, "WRITE_SIZE")] * 1024.0 * scale["WRITE_SIZE"]
+            lines.append(f"{k[:34]:34s} {rd / 1e6:10.2f} {wr / 1e6:10.2f} {(rd + wr) / 1e6:10.2f}")
+            base = k.split("<")[0].replace("k_", "")
+            traffic[base] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+                             "source_hash": source_hash()}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    name = {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
+            "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
+    with open(os.path.join(ROOT, "profiles", name + ".txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    if traffic:
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        data = json.load(open(path)) if os.path.exists(path) else {}
+        data[workload] = traffic
+        with open(path, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,7 +201,14 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (a plain copy kernel of known size, for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="only summarize the rocprofv3 CSV output under DIR (kernel trace + counter passes) "
+                         "into profiles/ and exit; no GPU needed")
+    ap.add_argument("--commands", default="", help="with --summarize: the commands that produced DIR")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.workload, args.commands)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         raise SystemExit(2)

@@ -27,6 +27,14 @@ constexpr int kBrickCells = 64;           // cells per brick
 constexpr int kChunk = 512;               // max particles per work item
 constexpr int kBlock = 256;               // threads per workgroup of the sort and control kernels
 constexpr int kItemThreads = 128;         // threads per work-item workgroup
+// Linear shape functions: per-thread register cache of the gathered support
+// nodes, and per-thread register sums of the scattered values, per kernel
+// (chosen by measurement on the 2M-particle column: the stress kernel is
+// faster with neither, G2P+P2G with the gather cache only).
+constexpr bool kStressCacheGather = false;
+constexpr bool kStressCacheScatter = false;
+constexpr bool kG2PCacheGather = true;
+constexpr bool kG2PCacheScatter = false;
 constexpr int kMaxCells[3] = {2047, 2047, 1023};   // packed-cell limits
 constexpr int64_t kMaxIndex = (int64_t)1 << 31;     // particle and node indices are 32-bit
 

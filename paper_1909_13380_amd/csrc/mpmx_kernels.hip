@@ -394,6 +394,48 @@ __device__ inline void constitutive(const SceneDev &S, const R de[6], R sig[6])
 
 // -------------------------------------------------------- scene lookup --
 
+// Wave-uniform copies of values loaded through vector memory: the compiler
+// then keeps them in scalar registers and forms addresses as a scalar base
+// plus a 32-bit vector offset.
+__device__ inline uint32_t uni(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+template <typename T>
+__device__ inline T *uni(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    return (T *)(((uint64_t)uni((uint32_t)(v >> 32)) << 32) | (uint64_t)uni((uint32_t)v));
+}
+
+// Copy of a plain struct with every 32-bit word made wave-uniform.
+template <typename T>
+__device__ inline T uni_struct(const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+    T out;
+    const uint32_t *src = (const uint32_t *)&v;
+    uint32_t *dst = (uint32_t *)&out;
+    for (int w = 0; w < (int)(sizeof(T) / 4); ++w)
+        dst[w] = uni(src[w]);
+    return out;
+}
+
+// Scene descriptor through the scalar cache: it is written once at creation
+// and never changes afterwards.
+__device__ inline SceneDev load_scene(const SceneDev *p)
+{
+    static_assert(sizeof(SceneDev) % 4 == 0, "word-sized struct");
+    typedef const __attribute__((address_space(4))) uint32_t CWord;
+    CWord *src = (CWord *)uni(p);
+    SceneDev out;
+    uint32_t *dst = (uint32_t *)&out;
+    for (int w = 0; w < (int)(sizeof(SceneDev) / 4); ++w)
+        dst[w] = src[w];
+    return out;
+}
+
 struct ItemRef {
     const SceneDev *S;
     int it;
@@ -401,8 +443,8 @@ struct ItemRef {
 
 __device__ inline ItemRef item_ref(const uint32_t *offs, const BatchDev &B, int64_t g)
 {
-    const int s = find_scene(offs, B.nscenes, g);
-    return {B.scenes[s], (int)(g - (int64_t)offs[s])};
+    const int s = (int)uni((uint32_t)find_scene(offs, B.nscenes, g));
+    return {uni(B.scenes[s]), (int)uni((uint32_t)(g - (int64_t)offs[s]))};
 }
 
 // The scene reorders in the coming step: read by the sort kernels, during
@@ -418,7 +460,7 @@ __device__ inline bool scene_sorting(const SceneDev &S)
 // around its barriers.
 __device__ inline bool scene_active(const SceneDev &S)
 {
-    return S.ctl[CTL_ACTIVE] != 0u;
+    return uni(S.ctl[CTL_ACTIVE]) != 0u;
 }
 
 // Last workgroup of a grid to arrive (threadfence reduction pattern: every
@@ -568,10 +610,10 @@ __device__ inline void clear_previous(const BatchDev &B)
     const int64_t total = B.coffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const ItemRef r = item_ref(B.coffs, B, g);
-        const SceneDev &S = *r.S;
+        const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const int other = (int)S.ctl[CTL_NBUF] ^ 1;
+        const int other = (int)uni(S.ctl[CTL_NBUF]) ^ 1;
         clear_box<R>(S, node_buf<R>(S, other), pick(S.tiles, other)[r.it]);
     }
 }
@@ -627,7 +669,7 @@ __global__ void k_read_out(const SceneDev *Sd, double *x, double *v, double *sig
 {
     const SceneDev &S = *Sd;
     const int64_t n = S.np;
-    const int cur = (int)S.ctl[CTL_CUR];
+    const int cur = (int)uni(S.ctl[CTL_CUR]);
     const double *X = S.x[cur];
     const R *V = (const R *)S.v[cur];
     const R *SG = (const R *)S.sig[cur];
@@ -656,7 +698,7 @@ __global__ void k_read_out(const SceneDev *Sd, double *x, double *v, double *sig
 __global__ void k_cell_counts(const SceneDev *Sd, uint32_t *counts)
 {
     const SceneDev &S = *Sd;
-    const int cur = (int)S.ctl[CTL_CUR];
+    const int cur = (int)uni(S.ctl[CTL_CUR]);
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < S.np; p += (int64_t)gridDim.x * blockDim.x) {
         int c[3];
         unpack_cell(S.cell[cur][p], c);
@@ -669,7 +711,7 @@ template <typename R>
 __global__ void k_nodes_out(const SceneDev *Sd, double *m, double *p, double *f)
 {
     const SceneDev &S = *Sd;
-    const int b = (int)S.ctl[CTL_NBUF];
+    const int b = (int)uni(S.ctl[CTL_NBUF]);
     const R *P = (const R *)S.np_[b];
     const R *F = (const R *)S.nf[b];
     for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < S.nn; I += (int64_t)gridDim.x * blockDim.x) {
@@ -794,7 +836,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_count(BatchDev B)
         if (!scene_sorting(S))
             continue;
         const int64_t p = gp - B.poffs[s];
-        const int cur = (int)S.ctl[CTL_CUR];
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
         S.rank[p] = atomicAdd(&S.cnt[brick_key(S, pick(S.cell, cur)[p])], 1u);
     }
 }
@@ -920,7 +962,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_perm(BatchDev B)
         if (!scene_sorting(S))
             continue;
         const int64_t p = gp - B.poffs[s];
-        const int cur = (int)S.ctl[CTL_CUR];
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
         S.perm[S.cstart[brick_key(S, pick(S.cell, cur)[p])] + S.rank[p]] = (uint32_t)p;
     }
 }
@@ -948,7 +990,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_move(BatchDev B)
                 continue;
             const int64_t b = gb - B.boffs[s];
             const int64_t n = S.np;
-            const int cur = (int)S.ctl[CTL_CUR], nxt = cur ^ 1;
+            const int cur = (int)uni(S.ctl[CTL_CUR]), nxt = cur ^ 1;
             const uint32_t nc = S.cnt[b * 64 + lane];
             const uint32_t cs = S.cstart[b * 64 + lane];
             S.cnt[b * 64 + lane] = 0u;
@@ -1033,12 +1075,12 @@ __global__ void __launch_bounds__(kItemThreads) k_p2g(BatchDev B)
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const ItemRef r = item_ref(B.ioffs, B, g);
-        const SceneDev &S = *r.S;
+        const SceneDev S = load_scene(r.S);
         if (!scene_active(S) || (!WITH_FORCE && S.ctl[CTL_HAVE_P2G]))
             continue;
-        const Item item = S.items[r.it];
-        const int cur = (int)S.ctl[CTL_CUR];
-        const int buf = (int)S.ctl[CTL_NBUF];
+        const Item item = uni_struct(S.items[r.it]);
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const int buf = (int)uni(S.ctl[CTL_NBUF]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         const Tile t = item_tile<SH>(item, P.cell, red);
@@ -1124,10 +1166,12 @@ __global__ void __launch_bounds__(kItemThreads) k_p2g(BatchDev B)
 // in registers, touching LDS again only when the support changes.  GIMP
 // supports differ between particles of a cell, so GIMP gathers and scatters
 // per particle.
-template <int SH>
+template <int SH, bool G, bool S>
 struct Cache {
-    static constexpr bool on = SH == 0;
-    static constexpr int nodes = on ? ShapeTraits<SH>::NS * ShapeTraits<SH>::NS * ShapeTraits<SH>::NS : 1;
+    static constexpr bool gather = SH == 0 && G;
+    static constexpr bool scatter = SH == 0 && S;
+    static constexpr int gnodes = gather ? 8 : 1;
+    static constexpr int snodes = scatter ? 8 : 1;
 };
 
 __device__ inline bool same_base(const int a[3], const int b[3])
@@ -1143,8 +1187,9 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
     constexpr int KP = kChunk / kItemThreads;
-    constexpr bool CACHE = Cache<SH>::on;
-    constexpr int CN = Cache<SH>::nodes;
+    using C = Cache<SH, kStressCacheGather, kStressCacheScatter>;
+    constexpr bool GC = C::gather, SC = C::scatter;
+    constexpr int GN = C::gnodes, SN = C::snodes;
     __shared__ R4<R> lv[CAP];
     __shared__ double lf[3][CAP];
     __shared__ int red[6];
@@ -1152,12 +1197,12 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const ItemRef r = item_ref(B.ioffs, B, g);
-        const SceneDev &S = *r.S;
+        const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = S.items[r.it];
-        const int cur = (int)S.ctl[CTL_CUR];
-        const int buf = (int)S.ctl[CTL_NBUF];
+        const Item item = uni_struct(S.items[r.it]);
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const int buf = (int)uni(S.ctl[CTL_NBUF]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         uint32_t pcell[KP];
@@ -1199,11 +1244,12 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
         const R dt = (R)S.dt;
         const R gx = (R)S.g[0], gy = (R)S.g[1], gz = (R)S.g[2];
         uint32_t bad = 0;
-        int kb[3] = {-(1 << 30), 0, 0};   // support base held in the cache
+        int kb[3] = {-(1 << 30), 0, 0};   // support base held in the gather cache
+        int fb[3] = {-(1 << 30), 0, 0};   // support base of the force accumulators
         Corners kc{};
-        R cv[CN][3], fa[CN][3];
+        R cv[GN][3], fa[SN][3];
         auto flush = [&]() {
-            for (int n = 0; n < CN; ++n) {
+            for (int n = 0; n < SN; ++n) {
                 const int li = kc.t0 + (n & 1) + ((n >> 1) & 1) * kc.ty + (n >> 2) * kc.tz;
                 for (int a = 0; a < 3; ++a)
                     atomicAdd(&lf[a][li], (double)fa[n][a]);
@@ -1221,20 +1267,27 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
             const Corners cn = corners(S, t, sp.base);
-            if constexpr (CACHE) {
+            if constexpr (GC) {
                 if (!same_base(sp.base, kb)) {
-                    if (kb[0] != -(1 << 30))
-                        flush();
                     for (int a = 0; a < 3; ++a)
                         kb[a] = sp.base[a];
-                    kc = cn;
-                    for (int n = 0; n < CN; ++n) {
+                    for (int n = 0; n < GN; ++n) {
                         const R4<R> v = lv[cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz];
                         cv[n][0] = v.x;
                         cv[n][1] = v.y;
                         cv[n][2] = v.z;
-                        fa[n][0] = fa[n][1] = fa[n][2] = (R)0;
                     }
+                }
+            }
+            if constexpr (SC) {
+                if (!same_base(sp.base, fb)) {
+                    if (fb[0] != -(1 << 30))
+                        flush();
+                    for (int a = 0; a < 3; ++a)
+                        fb[a] = sp.base[a];
+                    kc = cn;
+                    for (int n = 0; n < SN; ++n)
+                        fa[n][0] = fa[n][1] = fa[n][2] = (R)0;
                 }
             }
             R L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -1245,7 +1298,7 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
                         const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
                         const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
                         R v[3];
-                        if constexpr (CACHE) {
+                        if constexpr (GC) {
                             const int n = i + 2 * j + 4 * k;
                             v[0] = cv[n][0];
                             v[1] = cv[n][1];
@@ -1291,7 +1344,7 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
                         const R f0 = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mp * gx;
                         const R f1 = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy;
                         const R f2 = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz;
-                        if constexpr (CACHE) {
+                        if constexpr (SC) {
                             const int n = i + 2 * j + 4 * k;
                             fa[n][0] += f0;
                             fa[n][1] += f1;
@@ -1304,8 +1357,8 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
                         }
                     }
         }
-        if constexpr (CACHE)
-            if (kb[0] != -(1 << 30))
+        if constexpr (SC)
+            if (fb[0] != -(1 << 30))
                 flush();
         if (bad)
             atomicOr(&S.ctl[CTL_ERR], bad);
@@ -1352,8 +1405,9 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
     constexpr int KP = kChunk / kItemThreads;
-    constexpr bool CACHE = Cache<SH>::on;
-    constexpr int CN = Cache<SH>::nodes;
+    using C = Cache<SH, kG2PCacheGather, kG2PCacheScatter>;
+    constexpr bool GC = C::gather, SC = C::scatter;
+    constexpr int GN = C::gnodes, SN = C::snodes;
     __shared__ R4<R> la[CAP];
     __shared__ R4<R> lvn[CAP];
     __shared__ double acc[4][CAP];
@@ -1361,15 +1415,15 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const ItemRef r = item_ref(B.ioffs, B, g);
-        const SceneDev &S = *r.S;
+        const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = S.items[r.it];
-        const Tile t = S.tstep[r.it];
+        const Item item = uni_struct(S.items[r.it]);
+        const Tile t = uni_struct(S.tstep[r.it]);
         if (!t.fits)
             continue;
-        const int cur = (int)S.ctl[CTL_CUR];
-        const int buf = (int)S.ctl[CTL_NBUF], nbuf = buf ^ 1;
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const int buf = (int)uni(S.ctl[CTL_NBUF]), nbuf = buf ^ 1;
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         const NodeBuf<R> nn = node_buf<R>(S, nbuf);
@@ -1386,21 +1440,20 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
         int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
         // gather cache (old support) and scatter cache (new support)
         int gb[3] = {-(1 << 30), 0, 0}, sb[3] = {-(1 << 30), 0, 0};
-        R ca[CN][3], cu[CN][3], sp_[CN][3];
-        double sm[CN];
+        R ca[GN][3], cu[GN][3], sp_[SN][3], sm[SN];
         Corners sc{};
         bool s_in = true;
         auto flush = [&]() {
-            for (int n = 0; n < CN; ++n) {
+            for (int n = 0; n < SN; ++n) {
                 const int di = n & 1, dj = (n >> 1) & 1, dk = n >> 2;
                 if (s_in) {
                     const int li = sc.t0 + di + dj * sc.ty + dk * sc.tz;
-                    atomicAdd(&acc[0][li], sm[n]);
+                    atomicAdd(&acc[0][li], (double)sm[n]);
                     for (int a = 0; a < 3; ++a)
                         atomicAdd(&acc[1 + a][li], (double)sp_[n][a]);
                 } else {
                     const uint32_t I = sc.n0 + (uint32_t)(di + dj * sc.ny + dk * sc.nz);
-                    gadd(nn.m + I, sm[n]);
+                    gadd(nn.m + I, (double)sm[n]);
                     for (int a = 0; a < 3; ++a)
                         gadd(nn.p[a] + I, sp_[n][a]);
                 }
@@ -1420,11 +1473,11 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
             const Corners cn = corners(S, t, sp.base);
-            if constexpr (CACHE) {
+            if constexpr (GC) {
                 if (!same_base(sp.base, gb)) {
                     for (int a = 0; a < 3; ++a)
                         gb[a] = sp.base[a];
-                    for (int n = 0; n < CN; ++n) {
+                    for (int n = 0; n < GN; ++n) {
                         const int li = cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz;
                         const R4<R> a4 = la[li], u4 = lvn[li];
                         ca[n][0] = a4.x;
@@ -1442,7 +1495,7 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
                     for (int i = 0; i < NS; ++i) {
                         const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
                         R a[3], u[3];
-                        if constexpr (CACHE) {
+                        if constexpr (GC) {
                             const int n = i + 2 * j + 4 * k;
                             for (int e = 0; e < 3; ++e) {
                                 a[e] = ca[n][e];
@@ -1489,7 +1542,7 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
             make_support<R, SH>(S, xp, nc, sp);
             const Corners hn = corners(S, ht, sp.base);
             const R mv[3] = {mp * nv[0], mp * nv[1], mp * nv[2]};
-            if constexpr (CACHE) {
+            if constexpr (SC) {
                 if (!same_base(sp.base, sb)) {
                     if (sb[0] != -(1 << 30))
                         flush();
@@ -1497,8 +1550,8 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
                         sb[a] = sp.base[a];
                     sc = hn;
                     s_in = in;
-                    for (int n = 0; n < CN; ++n) {
-                        sm[n] = 0.0;
+                    for (int n = 0; n < SN; ++n) {
+                        sm[n] = (R)0;
                         sp_[n][0] = sp_[n][1] = sp_[n][2] = (R)0;
                     }
                 }
@@ -1507,9 +1560,9 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
                 for (int j = 0; j < NS; ++j)
                     for (int i = 0; i < NS; ++i) {
                         const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
-                        if constexpr (CACHE) {
+                        if constexpr (SC) {
                             const int n = i + 2 * j + 4 * k;
-                            sm[n] += (double)(N * mp);
+                            sm[n] += N * mp;
                             for (int a = 0; a < 3; ++a)
                                 sp_[n][a] += N * mv[a];
                         } else if (in) {
@@ -1526,7 +1579,7 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
                         }
                     }
         }
-        if constexpr (CACHE)
+        if constexpr (SC)
             if (sb[0] != -(1 << 30))
                 flush();
         if (err)
@@ -1573,15 +1626,15 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_usl(BatchDev B)
     const int64_t total = B.ioffs[B.nscenes];
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         const ItemRef r = item_ref(B.ioffs, B, g);
-        const SceneDev &S = *r.S;
+        const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = S.items[r.it];
-        const int buf = (int)S.ctl[CTL_NBUF];
+        const Item item = uni_struct(S.items[r.it]);
+        const int buf = (int)uni(S.ctl[CTL_NBUF]);
         const Tile t = pick(S.tiles, buf)[r.it];
         if (!t.fits)
             continue;
-        const int cur = (int)S.ctl[CTL_CUR];
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         int o[3];
