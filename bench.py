@@ -7,10 +7,12 @@ with FP64 positions and nodal mass.  One "step" is one full update-stress-
 first time step (reorder check, nodal clear, P2G, stress + force, G2P) of all
 particles.  Inputs are resident in device memory before timing starts.
 
-Prints one JSON line: particle-updates/s over the K timed steps, the
-dominant kernel's achieved bandwidth against the HBM peak (HIP events on the
-library's stream around every launch in the timed region), and the FP64
-oracle timed on a bounded sample on the host CPU.
+Prints one JSON line: particle-updates/s over the K timed steps (launched as
+the library launches them: tuned launch shape, K-step HIP graphs), the
+dominant kernel's achieved bandwidth against the HBM peak (from a second
+pass of K steps in which every kernel is launched directly between two HIP
+events on the library's stream), and the FP64 oracle timed on a bounded
+sample on the host CPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1]
 """
@@ -192,7 +194,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="column")
     ap.add_argument("--sort", default="on_demand", choices=["on_demand", "always"])
     ap.add_argument("--cpu-steps", type=int, default=5)
@@ -233,20 +235,33 @@ def main():
     policy = mpmx.SORT_ALWAYS if args.sort == "always" else mpmx.SORT_ON_DEMAND
     s = ctx.create_scene(sc, precision=mpmx.FP32, sort_policy=policy)
     print(f"# scene created: {desc}", file=sys.stderr, flush=True)
-    s.step(args.warmup)
+    # untimed: the warm-up, which also runs the launch-shape tuner (it needs
+    # a call of at least TUNE_MIN_STEPS steps)
+    untimed = max(args.warmup, mpmx.TUNE_MIN_STEPS)
+    s.step(untimed)
     torch.cuda.synchronize()
     nodes = s.nodes()
     n_nodes = int(np.count_nonzero(nodes["m"]))
-    if not args.no_profile:
-        ctx.profile(True)
-        ctx.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile_read() if not args.no_profile else {}
-    ctx.profile(False)
+    print(f"# timed {args.steps} steps: {1e3 * (t1 - t0) / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
+    launch = {"stress_threads": ctx.get_option(mpmx.OPT_STRESS_THREADS),
+              "g2p_threads": ctx.get_option(mpmx.OPT_G2P_THREADS),
+              "blocks_per_cu": ctx.get_option(mpmx.OPT_BLOCKS_PER_CU),
+              "graph_steps": ctx.get_option(mpmx.OPT_GRAPH_STEPS),
+              "graph_launches": ctx.get_option(mpmx.OPT_GRAPH_LAUNCHES)}
+    prof = {}
+    if not args.no_profile:
+        # per-kernel durations: the same number of steps again, every kernel
+        # launched directly between a pair of HIP events on the library's stream
+        ctx.profile(True)
+        ctx.profile_reset()
+        s.step(args.steps)
+        prof = ctx.profile_read()
+        ctx.profile(False)
     st = s.stats()
     if st["error_bits"]:
         raise SystemExit(f"scene stopped with error bits {st['error_bits']}")
@@ -257,7 +272,8 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": desc, "particles": n, "mesh": list(sc["mesh"]["n"]), "dt": sc["scheme"]["dt"],
                       "precision": "fp32 state, fp64 positions and nodal mass", "sort_policy": args.sort,
-                      "reorders_in_run": st["n_sorts"], "work_items": st["n_items"], "touched_nodes": n_nodes}}
+                      "reorders_in_run": st["n_sorts"], "work_items": st["n_items"], "touched_nodes": n_nodes,
+                      "untimed_steps_before": untimed, "launch": launch}}
     if prof:
         kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1), "total_ms": v[1]}
                    for k, v in prof.items()}

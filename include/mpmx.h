@@ -178,6 +178,43 @@ void mpmx_destroy(mpmx_ctx *ctx);
 /* Message of the last failed call on ctx (valid until the next call). */
 const char *mpmx_last_error(const mpmx_ctx *ctx);
 
+/* Launch options of a context (not of the method: results do not depend on
+ * them beyond the order of floating-point sums).
+ *   MPMX_OPT_GRAPH_STEPS   steps recorded into one HIP graph and replayed
+ *                          with one launch; 0 launches every kernel
+ *                          directly.  Default 8.  Graphs are not used while
+ *                          per-kernel profiling is on.
+ *   MPMX_OPT_AUTOTUNE      1 (default): on the first call that runs at least
+ *                          MPMX_TUNE_MIN_STEPS steps on a batch layout
+ *                          (precision, shape function, algorithm and the
+ *                          power-of-two bucket of its particle count), time
+ *                          the item kernels at every workgroup size and
+ *                          grid density, then keep the fastest for that
+ *                          layout.  The timed steps are steps of the call.
+ *                          0: use the values below.
+ *   MPMX_OPT_STRESS_THREADS  workgroup size of the stress kernel (USL: the
+ *                          P2G kernel): 64, 128 or 256.  Setting it, or one
+ *                          of the next two, turns autotuning off.
+ *   MPMX_OPT_G2P_THREADS   same for the G2P(+P2G) kernel.
+ *   MPMX_OPT_BLOCKS_PER_CU item-kernel workgroups per compute unit, 1..64.
+ *   MPMX_OPT_GRAPH_LAUNCHES  read-only: graph launches so far.
+ *   MPMX_OPT_TUNE_RUNS     read-only: tuning passes so far.
+ * mpmx_get_option of the three launch shapes returns the values of the
+ * last call that stepped a batch.  Errors: MPMX_E_INVALID_ARG for an
+ * unknown option or a value out of range. */
+#define MPMX_TUNE_MIN_STEPS 24
+enum {
+    MPMX_OPT_GRAPH_STEPS = 1,
+    MPMX_OPT_AUTOTUNE = 2,
+    MPMX_OPT_STRESS_THREADS = 3,
+    MPMX_OPT_G2P_THREADS = 4,
+    MPMX_OPT_BLOCKS_PER_CU = 5,
+    MPMX_OPT_GRAPH_LAUNCHES = 6,
+    MPMX_OPT_TUNE_RUNS = 7
+};
+int mpmx_set_option(mpmx_ctx *ctx, int option, int64_t value);
+int mpmx_get_option(mpmx_ctx *ctx, int option, int64_t *value);
+
 /* Per-kernel timing with HIP events on the context stream.  enable != 0
  * records an event pair around every kernel launch from now on;
  * mpmx_profile_read synchronises and returns, for up to `cap` kernels, the

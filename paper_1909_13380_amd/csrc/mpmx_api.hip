@@ -44,6 +44,18 @@ struct Profiler {
     std::map<std::string, std::pair<int64_t, double>> totals;
 };
 
+// Launch shape of the item kernels: workgroup size (index into
+// kItemThreadChoices) of the stress-side and G2P-side kernels, and
+// workgroups per compute unit of their persistent grid.
+struct LaunchCfg {
+    int t_stress = 1, t_g2p = 1;
+    int blocks_per_cu = 16;
+    bool operator==(const LaunchCfg &o) const
+    {
+        return t_stress == o.t_stress && t_g2p == o.t_g2p && blocks_per_cu == o.blocks_per_cu;
+    }
+};
+
 struct Batch {
     std::vector<uint64_t> ids;
     SceneDev **d_scenes = nullptr;
@@ -51,8 +63,20 @@ struct Batch {
     uint32_t *d_ioffs = nullptr, *d_coffs = nullptr, *d_flags = nullptr;
     BatchDev bd{};
     int prec = 0, shape = 0, algo = 0;
+    // executable graph of `gsteps` steps recorded with launch shape gcfg
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    LaunchCfg gcfg;
+    void drop_graph()
+    {
+        if (gexec)
+            (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        gsteps = 0;
+    }
     void release()
     {
+        drop_graph();
         for (void *p : {(void *)d_scenes, (void *)d_poffs, (void *)d_boffs, (void *)d_nsteps, (void *)d_ioffs,
                         (void *)d_coffs, (void *)d_flags})
             if (p)
@@ -85,6 +109,15 @@ struct mpmx_ctx {
     std::map<uint64_t, std::unique_ptr<Scene>> scenes;
     Batch cached_batch;
     Profiler prof;
+    // launch options
+    int graph_steps = 8;
+    bool autotune = true;
+    LaunchCfg fixed;                       // used when autotune is off
+    LaunchCfg last;                        // shape of the last stepped batch
+    std::map<uint64_t, LaunchCfg> tuned;   // per batch layout
+    int64_t graph_launches = 0, tune_runs = 0;
+    hipStream_t capture = nullptr;         // private stream for graph capture
+    hipStream_t launch_stream = nullptr;   // stream of the launches being issued
 };
 
 namespace {
@@ -143,6 +176,11 @@ hipEvent_t pool_event(mpmx_ctx *ctx)
 
 int launch(mpmx_ctx *ctx, const char *name, const void *fn, dim3 grid, dim3 block, void **args)
 {
+    const hipStream_t st = ctx->launch_stream ? ctx->launch_stream : ctx->stream;
+    if (st != ctx->stream) {
+        HIPCHK(ctx, hipLaunchKernel(fn, grid, block, args, 0, st));
+        return MPMX_OK;
+    }
     hipEvent_t a = nullptr, b = nullptr;
     if (ctx->prof.on) {
         if (ctx->prof.pending.size() > 8192) {
@@ -355,8 +393,174 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     return MPMX_OK;
 }
 
+// Launches of one step of every scene of b (the first step of a call also
+// fills the node buffer of USF scenes that need it).  `ev`, when given,
+// receives events around the item kernels: [0] before, [1] between, [2]
+// after.
+int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipEvent_t *ev)
+{
+    const KernelSet &K = kernel_set(b.prec, b.shape);
+    const CommonKernels &C = common_kernels();
+    BatchDev bd = b.bd;
+    void *a_bd[] = {&bd};
+    const hipStream_t st = ctx->launch_stream ? ctx->launch_stream : ctx->stream;
+    // sort kernels stride over their range with one block per CU: they
+    // return at once on steps that need no reorder
+    const dim3 pg = particle_grid(bd.total_particles, ctx->num_cu);
+    const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), ctx->num_cu));
+    const dim3 ig((unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(bd.max_items, (int64_t)cfg.blocks_per_cu * ctx->num_cu)));
+    const dim3 ts(kItemThreadChoices[cfg.t_stress]), tg(kItemThreadChoices[cfg.t_g2p]);
+    int rc;
+    if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)) ||
+        (rc = launch(ctx, "sort_bricks", C.sort_bricks, bg, dim3(256), a_bd)) ||
+        (rc = launch(ctx, "sort_cells", C.sort_cells, bg, dim3(256), a_bd)) ||
+        (rc = launch(ctx, "sort_perm", C.sort_perm, pg, dim3(kParticleBlock), a_bd)) ||
+        (rc = launch(ctx, "sort_move", K.move, bg, dim3(256), a_bd)))
+        return rc;
+    if (b.algo == MPMX_USF && first && (rc = launch(ctx, "p2g", K.p2g[cfg.t_g2p], ig, tg, a_bd)))
+        return rc;
+    if (ev)
+        HIPCHK(ctx, hipEventRecord(ev[0], st));
+    if (b.algo == MPMX_USF)
+        rc = launch(ctx, "stress", K.stress[cfg.t_stress], ig, ts, a_bd);
+    else
+        rc = launch(ctx, "p2g_usl", K.p2g_usl[cfg.t_stress], ig, ts, a_bd);
+    if (rc)
+        return rc;
+    if (ev)
+        HIPCHK(ctx, hipEventRecord(ev[1], st));
+    if (b.algo == MPMX_USF)
+        rc = launch(ctx, "g2p_p2g", K.g2p_p2g[cfg.t_g2p], ig, tg, a_bd);
+    else
+        rc = launch(ctx, "g2p_usl", K.g2p_usl[cfg.t_g2p], ig, tg, a_bd);
+    if (rc)
+        return rc;
+    if (ev)
+        HIPCHK(ctx, hipEventRecord(ev[2], st));
+    return MPMX_OK;
+}
+
+uint64_t layout_key(const Batch &b)
+{
+    int bucket = 0;
+    while (bucket < 62 && ((int64_t)1 << (bucket + 1)) <= b.bd.total_particles)
+        ++bucket;
+    return (uint64_t)b.prec | (uint64_t)b.shape << 2 | (uint64_t)b.algo << 4 | (uint64_t)bucket << 8;
+}
+
+// Online tuning of the item kernels' launch shape on real steps of the call:
+// every workgroup size for both kernels (their times are separate, so each
+// kernel takes its fastest), then the grid density with those sizes.  Each
+// candidate runs two steps and keeps the faster.  Uses kTuneSteps steps.
+constexpr int kTuneReps = 2;
+constexpr int kTuneDensity[] = {4, 8, 16, 32};
+constexpr int kTuneSteps = kTuneReps * (kNumItemThreadChoices + 4);
+static_assert(kTuneSteps + 1 <= MPMX_TUNE_MIN_STEPS, "tuning must fit in the calls it runs on");
+
+int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
+{
+    std::vector<hipEvent_t> ev(3 * kTuneSteps, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &x : ev)
+                if (x)
+                    (void)hipEventDestroy(x);
+            return fail(ctx, MPMX_E_HIP, "tuning: event creation failed");
+        }
+    int rc = MPMX_OK;
+    int k = 0;
+    LaunchCfg cfg = best;
+    for (int t = 0; t < kNumItemThreadChoices && !rc; ++t) {
+        cfg.t_stress = cfg.t_g2p = t;
+        for (int r = 0; r < kTuneReps && !rc; ++r, ++k)
+            rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
+    }
+    if (!rc && hipEventSynchronize(ev[3 * k - 1]) != hipSuccess)
+        rc = fail(ctx, MPMX_E_HIP, "tuning: event wait failed");
+    float bs = 1e30f, bg = 1e30f;
+    for (int t = 0, q = 0; t < kNumItemThreadChoices && !rc; ++t)
+        for (int r = 0; r < kTuneReps; ++r, ++q) {
+            float m1 = 0.f, m2 = 0.f;
+            if (hipEventElapsedTime(&m1, ev[3 * q], ev[3 * q + 1]) != hipSuccess ||
+                hipEventElapsedTime(&m2, ev[3 * q + 1], ev[3 * q + 2]) != hipSuccess) {
+                rc = fail(ctx, MPMX_E_HIP, "tuning: event timing failed");
+                break;
+            }
+            if (m1 < bs) {
+                bs = m1;
+                best.t_stress = t;
+            }
+            if (m2 < bg) {
+                bg = m2;
+                best.t_g2p = t;
+            }
+        }
+    cfg = best;
+    const int k0 = k;
+    for (int d : kTuneDensity) {
+        if (rc)
+            break;
+        cfg.blocks_per_cu = d;
+        for (int r = 0; r < kTuneReps && !rc; ++r, ++k)
+            rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
+    }
+    if (!rc && hipEventSynchronize(ev[3 * k - 1]) != hipSuccess)
+        rc = fail(ctx, MPMX_E_HIP, "tuning: event wait failed");
+    float bt = 1e30f;
+    for (int i = 0, q = k0; i < 4 && !rc; ++i)
+        for (int r = 0; r < kTuneReps; ++r, ++q) {
+            float m = 0.f;
+            if (hipEventElapsedTime(&m, ev[3 * q], ev[3 * q + 2]) != hipSuccess) {
+                rc = fail(ctx, MPMX_E_HIP, "tuning: event timing failed");
+                break;
+            }
+            if (m < bt) {
+                bt = m;
+                best.blocks_per_cu = kTuneDensity[i];
+            }
+        }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    ctx->tune_runs += rc ? 0 : 1;
+    return rc;
+}
+
+// Record `steps` non-first steps of b into an executable graph.
+int record_graph(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, int steps)
+{
+    b.drop_graph();
+    if (!ctx->capture)
+        HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    ctx->launch_stream = ctx->capture;
+    int rc = MPMX_OK;
+    for (int i = 0; i < steps && !rc; ++i)
+        rc = enqueue_step(ctx, b, cfg, false, nullptr);
+    ctx->launch_stream = nullptr;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+    if (rc) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return fail(ctx, MPMX_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&b.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        b.gexec = nullptr;
+        return fail(ctx, MPMX_E_HIP, "graph instantiate: %s", hipGetErrorString(ei));
+    }
+    b.gsteps = steps;
+    b.gcfg = cfg;
+    return MPMX_OK;
+}
+
 // Queue `steps` steps of every scene of b (scene i: nsteps[i], or `uniform`
-// for all when nsteps is null).
+// for all when nsteps is null).  The host never waits on the GPU, except
+// once per batch layout while tuning.
 int run_steps(mpmx_ctx *ctx, Batch &b, const int64_t *nsteps, int64_t uniform)
 {
     const int n = b.bd.nscenes;
@@ -370,47 +574,48 @@ int run_steps(mpmx_ctx *ctx, Batch &b, const int64_t *nsteps, int64_t uniform)
     }
     if (smax <= 0)
         return MPMX_OK;
+    ctx->launch_stream = nullptr;
     HIPCHK(ctx, hipMemcpyAsync(b.d_nsteps, ns.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, ctx->stream));
-    const KernelSet &K = kernel_set(b.prec, b.shape);
     const CommonKernels &C = common_kernels();
     BatchDev bd = b.bd;
     const int64_t *dns = b.d_nsteps;
-    void *a_bd[] = {&bd};
     void *a_begin[] = {&bd, &dns};
     int rc;
     if ((rc = launch(ctx, "begin", C.begin, dim3(1), dim3(1024), a_begin)))
         return rc;
-    // sort kernels stride over their range with one block per CU: they
-    // return at once on steps that need no reorder
-    const dim3 pg = particle_grid(bd.total_particles, ctx->num_cu);
-    const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), ctx->num_cu));
-    const dim3 ig((unsigned)std::max<int64_t>(1, std::min<int64_t>(bd.max_items, 16 * ctx->num_cu)));
-    const dim3 it(kItemThreads);
-    for (int64_t s = 0; s < smax; ++s) {
-        if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)))
-            return rc;
-        if ((rc = launch(ctx, "sort_bricks", C.sort_bricks, bg, dim3(256), a_bd)))
-            return rc;
-        if ((rc = launch(ctx, "sort_cells", C.sort_cells, bg, dim3(256), a_bd)))
-            return rc;
-        if ((rc = launch(ctx, "sort_perm", C.sort_perm, pg, dim3(kParticleBlock), a_bd)))
-            return rc;
-        if ((rc = launch(ctx, "sort_move", K.move, bg, dim3(256), a_bd)))
-            return rc;
-        if (b.algo == MPMX_USF) {
-            if (s == 0 && (rc = launch(ctx, "p2g", K.p2g, ig, it, a_bd)))
-                return rc;
-            if ((rc = launch(ctx, "stress", K.stress, ig, it, a_bd)))
-                return rc;
-            if ((rc = launch(ctx, "g2p_p2g", K.g2p_p2g, ig, it, a_bd)))
-                return rc;
-        } else {
-            if ((rc = launch(ctx, "p2g_usl", K.p2g_usl, ig, it, a_bd)))
-                return rc;
-            if ((rc = launch(ctx, "g2p_usl", K.g2p_usl, ig, it, a_bd)))
-                return rc;
+    LaunchCfg cfg = ctx->fixed;
+    const uint64_t key = layout_key(b);
+    bool tuned = !ctx->autotune;
+    if (ctx->autotune) {
+        auto it = ctx->tuned.find(key);
+        if (it != ctx->tuned.end()) {
+            cfg = it->second;
+            tuned = true;
         }
     }
+    if ((rc = enqueue_step(ctx, b, cfg, true, nullptr)))
+        return rc;
+    int64_t left = smax - 1;
+    if (!tuned && !ctx->prof.on && smax >= MPMX_TUNE_MIN_STEPS) {
+        if ((rc = tune(ctx, b, cfg)))
+            return rc;
+        ctx->tuned[key] = cfg;
+        left -= kTuneSteps;
+    }
+    ctx->last = cfg;
+    const int K = ctx->graph_steps;
+    if (K > 0 && !ctx->prof.on && left >= K) {
+        if (!b.gexec || b.gsteps != K || !(b.gcfg == cfg))
+            if ((rc = record_graph(ctx, b, cfg, K)))
+                return rc;
+        for (; left >= K; left -= K) {
+            HIPCHK(ctx, hipGraphLaunch(b.gexec, ctx->stream));
+            ++ctx->graph_launches;
+        }
+    }
+    for (; left > 0; --left)
+        if ((rc = enqueue_step(ctx, b, cfg, false, nullptr)))
+            return rc;
     return MPMX_OK;
 }
 
@@ -486,12 +691,71 @@ void mpmx_destroy(mpmx_ctx *ctx)
     }
     for (auto e : ctx->prof.pool)
         (void)hipEventDestroy(e);
+    if (ctx->capture)
+        (void)hipStreamDestroy(ctx->capture);
     if (ctx->own_stream)
         (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
 
 const char *mpmx_last_error(const mpmx_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int mpmx_set_option(mpmx_ctx *ctx, int option, int64_t value)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    auto tindex = [](int64_t v) {
+        for (int i = 0; i < kNumItemThreadChoices; ++i)
+            if (kItemThreadChoices[i] == v)
+                return i;
+        return -1;
+    };
+    switch (option) {
+    case MPMX_OPT_GRAPH_STEPS:
+        if (value < 0 || value > 1024)
+            return fail(ctx, MPMX_E_INVALID_ARG, "graph steps must be 0..1024");
+        ctx->graph_steps = (int)value;
+        return MPMX_OK;
+    case MPMX_OPT_AUTOTUNE:
+        if (value != 0 && value != 1)
+            return fail(ctx, MPMX_E_INVALID_ARG, "autotune must be 0 or 1");
+        ctx->autotune = value != 0;
+        return MPMX_OK;
+    case MPMX_OPT_STRESS_THREADS:
+    case MPMX_OPT_G2P_THREADS: {
+        const int t = tindex(value);
+        if (t < 0)
+            return fail(ctx, MPMX_E_INVALID_ARG, "workgroup size must be 64, 128 or 256");
+        (option == MPMX_OPT_STRESS_THREADS ? ctx->fixed.t_stress : ctx->fixed.t_g2p) = t;
+        ctx->autotune = false;
+        return MPMX_OK;
+    }
+    case MPMX_OPT_BLOCKS_PER_CU:
+        if (value < 1 || value > 64)
+            return fail(ctx, MPMX_E_INVALID_ARG, "blocks per CU must be 1..64");
+        ctx->fixed.blocks_per_cu = (int)value;
+        ctx->autotune = false;
+        return MPMX_OK;
+    default:
+        return fail(ctx, MPMX_E_INVALID_ARG, "unknown or read-only option %d", option);
+    }
+}
+
+int mpmx_get_option(mpmx_ctx *ctx, int option, int64_t *value)
+{
+    if (!ctx || !value)
+        return MPMX_E_INVALID_ARG;
+    switch (option) {
+    case MPMX_OPT_GRAPH_STEPS: *value = ctx->graph_steps; return MPMX_OK;
+    case MPMX_OPT_AUTOTUNE: *value = ctx->autotune ? 1 : 0; return MPMX_OK;
+    case MPMX_OPT_STRESS_THREADS: *value = kItemThreadChoices[ctx->last.t_stress]; return MPMX_OK;
+    case MPMX_OPT_G2P_THREADS: *value = kItemThreadChoices[ctx->last.t_g2p]; return MPMX_OK;
+    case MPMX_OPT_BLOCKS_PER_CU: *value = ctx->last.blocks_per_cu; return MPMX_OK;
+    case MPMX_OPT_GRAPH_LAUNCHES: *value = ctx->graph_launches; return MPMX_OK;
+    case MPMX_OPT_TUNE_RUNS: *value = ctx->tune_runs; return MPMX_OK;
+    default: return fail(ctx, MPMX_E_INVALID_ARG, "unknown option %d", option);
+    }
+}
 
 int mpmx_profile_enable(mpmx_ctx *ctx, int enable)
 {

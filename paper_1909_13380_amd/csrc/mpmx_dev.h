@@ -26,7 +26,6 @@ constexpr int kBrick = 4;                 // cells per brick edge
 constexpr int kBrickCells = 64;           // cells per brick
 constexpr int kChunk = 512;               // max particles per work item
 constexpr int kBlock = 256;               // threads per workgroup of the sort and control kernels
-constexpr int kItemThreads = 128;         // threads per work-item workgroup
 // Linear shape functions: per-thread register cache of the gathered support
 // nodes, and per-thread register sums of the scattered values, per kernel
 // (chosen by measurement on the 2M-particle column: the stress kernel is

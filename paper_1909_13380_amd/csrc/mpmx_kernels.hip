@@ -1064,8 +1064,8 @@ __device__ inline Parts<R> parts(const SceneDev &S, int cur)
 // Nodal mass and momentum into the step's node buffer (first step of a call;
 // USF scenes whose buffer is already filled skip it); with WITH_FORCE also
 // the nodal force from the current stress and volume (USL, every step).
-template <typename R, int SH, bool WITH_FORCE>
-__global__ void __launch_bounds__(kItemThreads) k_p2g(BatchDev B)
+template <typename R, int SH, bool WITH_FORCE, int T>
+__global__ void __launch_bounds__(T) k_p2g(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
@@ -1181,12 +1181,12 @@ __device__ inline bool same_base(const int a[3], const int b[3])
 
 // USF: zero the previous step's node buffer; nodal velocity, strain
 // increment, volume and stress update, nodal internal + external force.
-template <typename R, int SH>
-__global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
+template <typename R, int SH, int T>
+__global__ void __launch_bounds__(T) k_stress(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
-    constexpr int KP = kChunk / kItemThreads;
+    constexpr int KP = kChunk / T;
     using C = Cache<SH, kStressCacheGather, kStressCacheScatter>;
     constexpr bool GC = C::gather, SC = C::scatter;
     constexpr int GN = C::gnodes, SN = C::snodes;
@@ -1209,7 +1209,7 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
         int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
         for (int rr = 0; rr < KP; ++rr) {
-            const uint32_t q = threadIdx.x + rr * kItemThreads;
+            const uint32_t q = threadIdx.x + rr * T;
             if (q >= item.count)
                 continue;
             pcell[rr] = P.cell[item.start + q];
@@ -1257,7 +1257,7 @@ __global__ void __launch_bounds__(kItemThreads) k_stress(BatchDev B)
         };
 #pragma unroll
         for (int rr = 0; rr < KP; ++rr) {
-            const uint32_t q = threadIdx.x + rr * kItemThreads;
+            const uint32_t q = threadIdx.x + rr * T;
             if (q >= item.count)
                 break;
             const uint32_t p = item.start + q;
@@ -1399,12 +1399,12 @@ __device__ inline void load_update_tile(const SceneDev &S, const NodeBuf<R> &nb,
 // step's nodal mass and momentum from the updated particle into the other
 // (zeroed) node buffer, through an LDS tile over the item's home region
 // (particles that drifted past it add to global memory directly).
-template <typename R, int SH>
-__global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
+template <typename R, int SH, int T>
+__global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
-    constexpr int KP = kChunk / kItemThreads;
+    constexpr int KP = kChunk / T;
     using C = Cache<SH, kG2PCacheGather, kG2PCacheScatter>;
     constexpr bool GC = C::gather, SC = C::scatter;
     constexpr int GN = C::gnodes, SN = C::snodes;
@@ -1461,7 +1461,7 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
         };
 #pragma unroll
         for (int rr = 0; rr < KP; ++rr) {
-            const uint32_t q = threadIdx.x + rr * kItemThreads;
+            const uint32_t q = threadIdx.x + rr * T;
             if (q >= item.count)
                 break;
             const uint32_t p = item.start + q;
@@ -1615,8 +1615,8 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_p2g(BatchDev B)
 // USL: particle velocity and position, then the strain increment from the
 // updated nodal velocity and the stress update; zeroes the previous step's
 // node buffer.
-template <typename R, int SH>
-__global__ void __launch_bounds__(kItemThreads) k_g2p_usl(BatchDev B)
+template <typename R, int SH, int T>
+__global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
@@ -1728,6 +1728,17 @@ __global__ void __launch_bounds__(kItemThreads) k_g2p_usl(BatchDev B)
 
 namespace mpmx {
 
+template <typename R, int SH, int TI>
+static void set_items(KernelSet &k)
+{
+    constexpr int T = kItemThreadChoices[TI];
+    k.p2g[TI] = (const void *)&k_p2g<R, SH, false, T>;
+    k.stress[TI] = (const void *)&k_stress<R, SH, T>;
+    k.g2p_p2g[TI] = (const void *)&k_g2p_p2g<R, SH, T>;
+    k.p2g_usl[TI] = (const void *)&k_p2g<R, SH, true, T>;
+    k.g2p_usl[TI] = (const void *)&k_g2p_usl<R, SH, T>;
+}
+
 template <typename R, int SH>
 static KernelSet make_set()
 {
@@ -1736,11 +1747,9 @@ static KernelSet make_set()
     k.read_out = (const void *)&k_read_out<R>;
     k.nodes_out = (const void *)&k_nodes_out<R>;
     k.move = (const void *)&k_sort_move<R>;
-    k.p2g = (const void *)&k_p2g<R, SH, false>;
-    k.stress = (const void *)&k_stress<R, SH>;
-    k.g2p_p2g = (const void *)&k_g2p_p2g<R, SH>;
-    k.p2g_usl = (const void *)&k_p2g<R, SH, true>;
-    k.g2p_usl = (const void *)&k_g2p_usl<R, SH>;
+    set_items<R, SH, 0>(k);
+    set_items<R, SH, 1>(k);
+    set_items<R, SH, 2>(k);
     return k;
 }
 

@@ -4,17 +4,23 @@
 
 namespace mpmx {
 
-// Kernels instantiated per (precision, shape function).
+// Workgroup sizes the item kernels are built for (the autotuner picks one
+// per kernel).
+constexpr int kItemThreadChoices[3] = {64, 128, 256};
+constexpr int kNumItemThreadChoices = 3;
+
+// Kernels instantiated per (precision, shape function); the item kernels
+// also per workgroup size (index into kItemThreadChoices).
 struct KernelSet {
     const void *load;       // (SceneDev*, x, v, sig, vol, mass)
     const void *read_out;   // (const SceneDev*, x, v, sig, vol, cell)
     const void *nodes_out;  // (const SceneDev*, m, p, f)
     const void *move;       // (BatchDev): reorder, then the step control
-    const void *p2g;            // (BatchDev)
-    const void *stress;         // (BatchDev)
-    const void *g2p_p2g;        // (BatchDev)
-    const void *p2g_usl;        // (BatchDev)
-    const void *g2p_usl;        // (BatchDev)
+    const void *p2g[kNumItemThreadChoices];      // (BatchDev)
+    const void *stress[kNumItemThreadChoices];   // (BatchDev)
+    const void *g2p_p2g[kNumItemThreadChoices];  // (BatchDev)
+    const void *p2g_usl[kNumItemThreadChoices];  // (BatchDev)
+    const void *g2p_usl[kNumItemThreadChoices];  // (BatchDev)
 };
 
 struct CommonKernels {

@@ -45,6 +45,9 @@ FP32, FP64 = 0, 1
 SORT_ON_DEMAND, SORT_ALWAYS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 ERRBIT_OUT_OF_MESH, ERRBIT_NONFINITE = 1, 2
+OPT_GRAPH_STEPS, OPT_AUTOTUNE, OPT_STRESS_THREADS, OPT_G2P_THREADS, OPT_BLOCKS_PER_CU, OPT_GRAPH_LAUNCHES, \
+    OPT_TUNE_RUNS = 1, 2, 3, 4, 5, 6, 7
+TUNE_MIN_STEPS = 24
 
 _P = ctypes.POINTER
 _d, _i32, _i64, _u32, _u64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
@@ -96,6 +99,8 @@ _SIGNATURES = {
     "mpmx_create": ([_P(_vp), ctypes.c_int, _vp], ctypes.c_int),
     "mpmx_destroy": ([_vp], None),
     "mpmx_last_error": ([_vp], ctypes.c_char_p),
+    "mpmx_set_option": ([_vp, ctypes.c_int, _i64], ctypes.c_int),
+    "mpmx_get_option": ([_vp, ctypes.c_int, _P(_i64)], ctypes.c_int),
     "mpmx_profile_enable": ([_vp, ctypes.c_int], ctypes.c_int),
     "mpmx_profile_reset": ([_vp], ctypes.c_int),
     "mpmx_profile_read": ([_vp, ctypes.c_int, _P(ctypes.c_char_p), _P(_i64), _P(_d), _P(ctypes.c_int)],
@@ -274,6 +279,14 @@ class Context:
         self._check(_lib.mpmx_batch_step(self._h, ids, ns, n), "batch_step")
 
     # -- profiling
+    def set_option(self, option: int, value: int):
+        self._check(_lib.mpmx_set_option(self._h, int(option), int(value)), "set_option")
+
+    def get_option(self, option: int) -> int:
+        v = _i64()
+        self._check(_lib.mpmx_get_option(self._h, int(option), ctypes.byref(v)), "get_option")
+        return int(v.value)
+
     def profile(self, enable: bool = True):
         self._check(_lib.mpmx_profile_enable(self._h, 1 if enable else 0), "profile_enable")
 

@@ -310,6 +310,90 @@ def test_batch_equals_alone(ctx, mp):
         b.destroy()
 
 
+def _fixed(c, mp, graph_steps, t_stress=128, t_g2p=128, blocks=16):
+    c.set_option(mp.OPT_STRESS_THREADS, t_stress)
+    c.set_option(mp.OPT_G2P_THREADS, t_g2p)
+    c.set_option(mp.OPT_BLOCKS_PER_CU, blocks)
+    c.set_option(mp.OPT_GRAPH_STEPS, graph_steps)
+    assert c.get_option(mp.OPT_AUTOTUNE) == 0
+
+
+def test_graph_replays_match_direct_launches(mp):
+    """K-step HIP graphs replayed on the context stream, with reads, cell
+    counts and other eager work in between, against the same steps
+    launched kernel by kernel: every replay agrees to FP64 rounding."""
+    sc = block(material=MATERIALS["dp"], seed=51, n_cells=(10, 8, 6))
+    cg, ce = mp.Context(0), mp.Context(0)
+    try:
+        _fixed(cg, mp, 4)
+        _fixed(ce, mp, 0)
+        # reorder every step, so the recorded sort kernels do real work
+        sg = cg.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS)
+        se = ce.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS)
+        for rep in range(5):
+            sg.step(9)          # 1 direct step, then 2 graph launches of 4
+            se.step(9)
+            a, b = sg.read(), se.read()
+            np.testing.assert_array_equal(sg.cell_counts(), se.cell_counts())
+            check_state(f"graph/rep{rep}", a, b, sc["x"], 1e-12, 1e-12, 1e-12)
+            assert cg.get_option(mp.OPT_GRAPH_LAUNCHES) == 2 * (rep + 1)
+            assert sg.stats()["n_sorts"] == se.stats()["n_sorts"] == 9 * (rep + 1)
+        assert ce.get_option(mp.OPT_GRAPH_LAUNCHES) == 0
+        ref = oracle.run(sc, 45)
+        check_state("graph/oracle", sg.read(), ref, sc["x"], 1e-9, 1e-9, 1e-9)
+    finally:
+        cg.close()
+        ce.close()
+
+
+@pytest.mark.parametrize("t_stress,t_g2p,blocks", [(64, 256, 1), (256, 64, 3), (128, 128, 40)])
+def test_every_launch_shape_matches_oracle(mp, t_stress, t_g2p, blocks):
+    sc = block(material=MATERIALS["dpc"], seed=52, n_cells=(12, 9, 7))
+    c = mp.Context(0)
+    try:
+        _fixed(c, mp, 0, t_stress, t_g2p, blocks)
+        for shape in (0, 1):
+            sc["scheme"]["shape"] = shape
+            s = c.create_scene(sc, precision=mp.FP64)
+            s.step(6)
+            check_state(f"shape{t_stress}/{t_g2p}/{blocks}/{shape}", s.read(), oracle.run(sc, 6), sc["x"], 1e-9,
+                        1e-9, 1e-9)
+            assert c.get_option(mp.OPT_STRESS_THREADS) == t_stress
+            assert c.get_option(mp.OPT_G2P_THREADS) == t_g2p
+            assert c.get_option(mp.OPT_BLOCKS_PER_CU) == blocks
+            s.destroy()
+    finally:
+        c.close()
+
+
+def test_autotuner_runs_once_per_layout_on_real_steps(mp):
+    """The tuner times the launch shapes on steps of the call itself: the
+    result after 40 steps equals the oracle's 40 steps, the chosen shapes
+    are valid, and a second call on the same layout reuses them."""
+    sc = block(material=MATERIALS["dp"], seed=53, n_cells=(10, 8, 6))
+    c = mp.Context(0)
+    try:
+        assert c.get_option(mp.OPT_AUTOTUNE) == 1
+        s = c.create_scene(sc, precision=mp.FP64)
+        s.step(10)                       # below the tuning threshold
+        assert c.get_option(mp.OPT_TUNE_RUNS) == 0
+        s.step(30)
+        assert c.get_option(mp.OPT_TUNE_RUNS) == 1
+        assert c.get_option(mp.OPT_STRESS_THREADS) in (64, 128, 256)
+        assert c.get_option(mp.OPT_G2P_THREADS) in (64, 128, 256)
+        assert c.get_option(mp.OPT_BLOCKS_PER_CU) in (4, 8, 16, 32)
+        check_state("tuned/40", s.read(), oracle.run(sc, 40), sc["x"], 1e-9, 1e-9, 1e-9)
+        s.step(30)
+        assert c.get_option(mp.OPT_TUNE_RUNS) == 1
+        assert s.stats()["steps_done"] == 70
+        with pytest.raises(mp.MpmxError):
+            c.set_option(mp.OPT_STRESS_THREADS, 96)
+        with pytest.raises(mp.MpmxError):
+            c.set_option(mp.OPT_GRAPH_LAUNCHES, 1)
+    finally:
+        c.close()
+
+
 def test_out_of_mesh_stops_the_scene(ctx, mp):
     sc = block(seed=40)
     sc["v"][:, 2] = 300.0               # the block rises out of the open top within ~25 steps
