@@ -14,7 +14,7 @@ pass of K steps in which every kernel is launched directly between two HIP
 events on the library's stream), and the FP64 oracle timed on a bounded
 sample on the host CPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1|batch|serve]
 """
 from __future__ import annotations
 
@@ -190,6 +190,140 @@ def summarize(root: str, workload: str, commands: str):
     print("\n".join(lines))
 
 
+def _percentiles(vals):
+    v = np.sort(np.asarray(vals, dtype=np.float64))
+    return {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+            "max_ms": float(v[-1]), "n": int(len(v))}
+
+
+def run_batch(args):
+    """The batched set: 256 independent scenes (1k-250k particles, elastic
+    or Drucker-Prager), 500 steps each, FP32.  Batched: one launch per
+    stage over all scenes.  Plain: the same kernels per scene, scenes one
+    after another in FIFO order, on a second copy of the inputs.  Per-scene
+    completion latency is measured from the start of the timed region to the
+    scene's completion (HIP event after its last launch)."""
+    import torch
+    from paper_1909_13380_amd import mpmx, scenes
+    n_sc = args.scenes
+    steps = args.steps if args.steps_given else 500
+    scs = scenes.c3(n_sc, nsteps=steps)
+    total = int(sum(len(sc["x"]) for sc in scs))
+    print(f"# {n_sc} scenes, {total} particles", file=sys.stderr, flush=True)
+    torch.cuda.init()
+    stream = torch.cuda.Stream()          # a real stream: the library and torch's events share it
+    torch.cuda.set_stream(stream)
+    ctx = mpmx.Context(0, stream=stream.cuda_stream)
+    untimed = max(args.warmup, mpmx.TUNE_MIN_STEPS)
+    out = {"metric": METRIC, "unit": "particle-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic"}
+    # batched
+    batch = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
+    ctx.batch_step(batch, [untimed] * n_sc)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    ctx.batch_step(batch, [steps] * n_sc)
+    e1.record()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    launch_b = {"stress_threads": ctx.get_option(mpmx.OPT_STRESS_THREADS),
+                "g2p_threads": ctx.get_option(mpmx.OPT_G2P_THREADS),
+                "blocks_per_cu": ctx.get_option(mpmx.OPT_BLOCKS_PER_CU)}
+    errs = [b.stats()["error_bits"] for b in batch]
+    if any(errs):
+        raise SystemExit(f"batched scenes stopped with error bits {errs}")
+    for b in batch:
+        b.destroy()
+    # plain, FIFO
+    plain = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
+    for s in plain:
+        s.step(untimed)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in plain]
+    p0 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    p0.record()
+    for s, e in zip(plain, evs):
+        s.step(steps)
+        e.record()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    lat_plain = [p0.elapsed_time(e) for e in evs]
+    for s in plain:
+        s.destroy()
+    ctx.close()
+    pu = total * steps
+    out["value"] = pu / tb
+    out["ms_per_step"] = 1e3 * tb / steps
+    out["config"] = {"workload": f"{n_sc} independent scenes, 1k-250k particles each (log-uniform), elastic or "
+                                 f"Drucker-Prager, 0.02 m cells, CFL 0.3, {steps} steps, batched",
+                     "scenes": n_sc, "particles": total, "untimed_steps_before": untimed, "launch": launch_b}
+    out["plain"] = {"value": pu / tp, "seconds": tp, "order": "FIFO, one scene at a time, same kernels"}
+    out["speedup_vs_plain"] = tp / tb
+    out["latency"] = {"batched": _percentiles([e0.elapsed_time(e1)] * n_sc), "plain": _percentiles(lat_plain)}
+    if not args.no_cpu_baseline:
+        small = min(scs, key=lambda sc: len(sc["x"]))
+        cb = cpu_baseline(small, min(args.cpu_steps * 20, steps))
+        cb["sample"] = f"smallest scene of the set ({len(small['x'])} particles), " + cb["sample"].split(", ", 1)[1]
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Serving: a Poisson stream of requests from the batched-scene
+    generator (seed 4), steps uniform in 100..2000, admitted against a 64 GiB
+    device budget by the library's request loop, final particle state
+    returned to host memory.  Latency is arrival -> result on the host."""
+    import torch
+    from paper_1909_13380_amd import mpmx, scenes
+    n_req = args.requests
+    rates = [float(r) for r in args.rates.split(",")]
+    base = scenes.c4_requests(1.0, n_req)        # arrival times at 1/s; other rates scale them
+    total_pu = int(sum(len(sc["x"]) * k for _, sc, k in base))
+    print(f"# {n_req} requests generated, {total_pu:.3e} particle-updates", file=sys.stderr, flush=True)
+    torch.cuda.init()
+    ctx = mpmx.Context(0)
+    results = []
+    for rate in rates:
+        srv = mpmx.Server(ctx, 64 << 30, max_tick_steps=args.tick_steps)
+        arrivals = [t / rate for t, _, _ in base]
+        lat, pu, i, ticks = [], 0, 0, 0
+        t0 = srv.clock()
+        while len(lat) < n_req:
+            now = srv.clock() - t0
+            while i < n_req and arrivals[i] <= now:
+                _, sc, k = base[i]
+                srv.submit(sc, k, precision=mpmx.FP32, tag=i)
+                i += 1
+            r, q = srv.tick()
+            ticks += 1
+            for c in srv.poll(256, copy_state=False):
+                if c["status"] != mpmx.OK:
+                    raise SystemExit(f"request {c['tag']} failed with status {c['status']}")
+                lat.append(1e3 * (c["t_done"] - t0 - arrivals[c["tag"]]))
+                pu += c["n"] * c["steps_done"]
+            if r == 0 and q == 0 and i < n_req:
+                time.sleep(max(0.0, min(0.002, arrivals[i] - (srv.clock() - t0))))
+        span = srv.clock() - t0
+        srv.close()
+        row = {"rate_per_s": rate, "requests": n_req, "seconds": span, "value": pu / span, "ticks": ticks,
+               **_percentiles(lat)}
+        print(f"# rate {rate}/s: {json.dumps(row)}", file=sys.stderr, flush=True)
+        results.append(row)
+    ctx.close()
+    best = max(results, key=lambda r: r["value"])
+    out = {"metric": METRIC, "value": best["value"], "unit": "particle-updates/s", "n_gpus": 1, "steps": None,
+           "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+           "data": "synthetic",
+           "config": {"workload": f"serving: Poisson stream of {n_req} requests per rate from the batched-scene "
+                                  f"generator (seed 4), 1k-250k particles, 100-2000 steps each, 64 GiB budget",
+                      "max_tick_steps": args.tick_steps, "particle_updates_per_rate": total_pu},
+           "rates": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +341,12 @@ def main():
                     help="only summarize the rocprofv3 CSV output under DIR (kernel trace + counter passes) "
                          "into profiles/ and exit; no GPU needed")
     ap.add_argument("--commands", default="", help="with --summarize: the commands that produced DIR")
+    ap.add_argument("--scenes", type=int, default=256, help="--workload batch: number of scenes")
+    ap.add_argument("--requests", type=int, default=2000, help="--workload serve: requests per arrival rate")
+    ap.add_argument("--rates", default="25,50,100", help="--workload serve: arrival rates (requests/s)")
+    ap.add_argument("--tick-steps", type=int, default=64, help="--workload serve: most steps per server tick")
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.summarize:
         summarize(args.summarize, args.workload, args.commands)
         return
@@ -224,6 +363,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes_each_way": n * 4, "launches": 3}))
+        return
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
     from paper_1909_13380_amd import mpmx
 

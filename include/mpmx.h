@@ -274,6 +274,73 @@ int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene);
  * sums. */
 int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n);
 
+/* ------------------------------------------------------------- serving -- */
+
+/* A request loop over one context: independent scenes arrive at any time,
+ * are admitted in arrival order while their device bytes (mpmx_scene_bytes,
+ * plus per-node constraint arrays) fit the budget, stay resident on the
+ * device while they step, and leave their final particle state in host
+ * memory.  Not a method of the paper: it serves many of the paper's
+ * problems (mesh, particles, material, constraints, scheme, step count) on
+ * one GPU.  A server drives its context from one host thread; scenes the
+ * caller creates on the same context are not touched by it. */
+typedef struct mpmx_server mpmx_server;
+
+typedef struct mpmx_request {
+    uint32_t size;                       /* sizeof(mpmx_request) */
+    int32_t pad_;
+    const mpmx_mesh *mesh;
+    const mpmx_material *material;
+    const mpmx_bc *bc;
+    const mpmx_scheme *scheme;
+    const mpmx_particles *particles;     /* MPMX_MEM_HOST */
+    int64_t nsteps;                      /* >= 0 */
+    uint64_t tag;                        /* returned in the completion */
+} mpmx_request;
+
+typedef struct mpmx_completion {
+    uint32_t size;                       /* sizeof(mpmx_completion) */
+    int32_t status;                      /* MPMX_OK or the scene's error code */
+    uint64_t request;                    /* id from mpmx_server_submit */
+    uint64_t tag;
+    int64_t n;                           /* particles */
+    int64_t steps_done;
+    /* final state in the original particle order, host memory owned by the
+     * server until mpmx_server_release: x, v (n x 3), stress (n x 6), vol */
+    const double *x, *v, *stress, *vol;
+    double t_submit, t_admit, t_done;    /* seconds, mpmx_server_clock */
+} mpmx_completion;
+
+/* Create a server on ctx with a device-memory budget (bytes) and the most
+ * steps one tick runs.  Errors: MPMX_E_INVALID_ARG. */
+int mpmx_server_create(mpmx_ctx *ctx, uint64_t budget_bytes, int64_t max_tick_steps, mpmx_server **out);
+
+/* Queue a request; its inputs are copied before return.  *id identifies it.
+ * MPMX_E_BUDGET if the scene alone exceeds the budget; descriptor errors as
+ * mpmx_scene_create. */
+int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id);
+
+/* One scheduling round: admit queued requests in arrival order while they
+ * fit; advance every resident scene, one batch per (precision, shape,
+ * algorithm) group, by the number of steps until the first of them
+ * completes (at most max_tick_steps); copy finished scenes to host memory,
+ * free them and record their completions.  Synchronises.  Optional outputs:
+ * resident and queued request counts after the round. */
+int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued);
+
+/* Move up to max completions (oldest first) into out[]; *n gets the count.
+ * Their arrays stay valid until mpmx_server_release(id). */
+int mpmx_server_poll(mpmx_server *srv, mpmx_completion *out, int max, int *n);
+
+/* Free the host arrays of a polled completion. */
+int mpmx_server_release(mpmx_server *srv, uint64_t id);
+
+/* Seconds on the server's monotonic clock (the completion timestamps). */
+double mpmx_server_clock(const mpmx_server *srv);
+
+/* Free the server, its queued requests, resident scenes and completions. */
+void mpmx_server_destroy(mpmx_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,17 @@ class Stats(ctypes.Structure):
                 ("active_cells", _i64), ("error_bits", _u32), ("pad_", _u32), ("device_bytes", _u64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("size", _u32), ("pad_", _i32), ("mesh", _P(Mesh)), ("material", _P(Material)), ("bc", _P(Bc)),
+                ("scheme", _P(Scheme)), ("particles", _P(Particles)), ("nsteps", _i64), ("tag", _u64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("size", _u32), ("status", _i32), ("request", _u64), ("tag", _u64), ("n", _i64),
+                ("steps_done", _i64), ("x", _P(_d)), ("v", _P(_d)), ("stress", _P(_d)), ("vol", _P(_d)),
+                ("t_submit", _d), ("t_admit", _d), ("t_done", _d)]
+
+
 _vp = ctypes.c_void_p
 _SIGNATURES = {
     "mpmx_version": ([], ctypes.c_int),
@@ -115,6 +126,13 @@ _SIGNATURES = {
     "mpmx_scene_stats": ([_vp, _u64, _P(Stats)], ctypes.c_int),
     "mpmx_scene_destroy": ([_vp, _u64], ctypes.c_int),
     "mpmx_batch_step": ([_vp, _P(_u64), _P(_i64), ctypes.c_int], ctypes.c_int),
+    "mpmx_server_create": ([_vp, _u64, _i64, _P(_vp)], ctypes.c_int),
+    "mpmx_server_submit": ([_vp, _P(Request), _P(_u64)], ctypes.c_int),
+    "mpmx_server_tick": ([_vp, _P(ctypes.c_int), _P(ctypes.c_int)], ctypes.c_int),
+    "mpmx_server_poll": ([_vp, _P(Completion), ctypes.c_int, _P(ctypes.c_int)], ctypes.c_int),
+    "mpmx_server_release": ([_vp, _u64], ctypes.c_int),
+    "mpmx_server_clock": ([_vp], _d),
+    "mpmx_server_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGNATURES.items():
     _f = getattr(_lib, _name)
@@ -174,6 +192,24 @@ def scene_bytes(scene: dict, precision: int = FP32, n_particles: int | None = No
     return int(out.value)
 
 
+def _bc(bc: dict, keep: list) -> Bc:
+    cbc = Bc()
+    cbc.size = ctypes.sizeof(Bc)
+    for k in range(6):
+        cbc.face[k] = int(bc["face"][k])
+    extra = bc.get("extra")
+    if extra is not None and len(extra[0]) > 0:
+        node = np.ascontiguousarray(extra[0], dtype=np.int64)
+        axis = np.ascontiguousarray(extra[1], dtype=np.int32)
+        value = np.ascontiguousarray(extra[2], dtype=np.float64)
+        keep += [node, axis, value]
+        cbc.n_extra = len(node)
+        cbc.node = node.ctypes.data_as(_P(_i64))
+        cbc.axis = axis.ctypes.data_as(_P(_i32))
+        cbc.value = value.ctypes.data_as(_P(_d))
+    return cbc
+
+
 def _host_f64(a, shape):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
 
@@ -221,22 +257,8 @@ class Context:
         """Upload a scene (dict from ``scenes``); ``state`` may replace the
         particle arrays (numpy, or torch CUDA float64 tensors)."""
         src = state if state is not None else scene
-        bc = scene["bc"]
-        cbc = Bc()
-        cbc.size = ctypes.sizeof(Bc)
-        for k in range(6):
-            cbc.face[k] = int(bc["face"][k])
         keep = []
-        extra = bc.get("extra")
-        if extra is not None and len(extra[0]) > 0:
-            node = np.ascontiguousarray(extra[0], dtype=np.int64)
-            axis = np.ascontiguousarray(extra[1], dtype=np.int32)
-            value = np.ascontiguousarray(extra[2], dtype=np.float64)
-            keep += [node, axis, value]
-            cbc.n_extra = len(node)
-            cbc.node = node.ctypes.data_as(_P(_i64))
-            cbc.axis = axis.ctypes.data_as(_P(_i32))
-            cbc.value = value.ctypes.data_as(_P(_d))
+        cbc = _bc(scene["bc"], keep)
         parts = Particles()
         parts.size = ctypes.sizeof(Particles)
         x = src["x"]
@@ -364,3 +386,82 @@ class Scene:
             self.ctx._check(_lib.mpmx_scene_destroy(self.ctx._h, self.id), "scene_destroy")
             self.ctx.scenes.pop(self.id, None)
             self.id = 0
+
+
+class Server:
+    """Request loop over a context (mpmx_server_*): submit scenes at any
+    time, call tick() to admit and advance them, poll() for finished ones."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_tick_steps: int = 256):
+        self.ctx = ctx
+        self._h = _vp()
+        rc = _lib.mpmx_server_create(ctx._h, int(budget_bytes), int(max_tick_steps), ctypes.byref(self._h))
+        if rc != OK:
+            raise MpmxError(rc, "server_create")
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            msg = _lib.mpmx_last_error(self.ctx._h)
+            raise MpmxError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def clock(self) -> float:
+        return float(_lib.mpmx_server_clock(self._h))
+
+    def submit(self, scene: dict, nsteps: int, precision: int = FP32, tag: int = 0) -> int:
+        keep = []
+        n = len(scene["x"])
+        arrs = [_host_f64(scene["x"], (n, 3)), _host_f64(scene["v"], (n, 3)),
+                _host_f64(scene["stress"], (n, 6)) if scene.get("stress") is not None else None,
+                _host_f64(scene["vol"], (n,)), _host_f64(scene["mass"], (n,))]
+        parts = Particles()
+        parts.size = ctypes.sizeof(Particles)
+        parts.mem = MEM_HOST
+        parts.n = n
+        parts.x, parts.v, parts.stress, parts.vol, parts.mass = [a.ctypes.data if a is not None else None
+                                                                 for a in arrs]
+        mesh = _mesh(scene["mesh"])
+        mat = _material(scene["material"])
+        cbc = _bc(scene["bc"], keep)
+        sch = _scheme(scene["scheme"], precision, SORT_ON_DEMAND)
+        req = Request(ctypes.sizeof(Request), 0, ctypes.pointer(mesh), ctypes.pointer(mat), ctypes.pointer(cbc),
+                      ctypes.pointer(sch), ctypes.pointer(parts), int(nsteps), int(tag))
+        rid = _u64()
+        self._check(_lib.mpmx_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)), "server_submit")
+        return int(rid.value)
+
+    def tick(self) -> tuple[int, int]:
+        r, q = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.mpmx_server_tick(self._h, ctypes.byref(r), ctypes.byref(q)), "server_tick")
+        return r.value, q.value
+
+    def poll(self, max_n: int = 64, copy_state: bool = True) -> list[dict]:
+        """Finished requests (oldest first); their host arrays are copied
+        out (or skipped with copy_state=False) and released."""
+        buf = (Completion * max_n)()
+        n = ctypes.c_int()
+        self._check(_lib.mpmx_server_poll(self._h, buf, max_n, ctypes.byref(n)), "server_poll")
+        out = []
+        for c in buf[:n.value]:
+            d = {"request": int(c.request), "tag": int(c.tag), "status": int(c.status), "n": int(c.n),
+                 "steps_done": int(c.steps_done), "t_submit": c.t_submit, "t_admit": c.t_admit,
+                 "t_done": c.t_done}
+            if copy_state and c.n > 0 and c.x:
+                k = int(c.n)
+                d["x"] = np.ctypeslib.as_array(c.x, shape=(k, 3)).copy()
+                d["v"] = np.ctypeslib.as_array(c.v, shape=(k, 3)).copy()
+                d["stress"] = np.ctypeslib.as_array(c.stress, shape=(k, 6)).copy()
+                d["vol"] = np.ctypeslib.as_array(c.vol, shape=(k,)).copy()
+            self._check(_lib.mpmx_server_release(self._h, c.request), "server_release")
+            out.append(d)
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.mpmx_server_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

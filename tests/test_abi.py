@@ -29,7 +29,8 @@ def test_library_exports_every_declared_function(mpmx):
 def test_descriptor_layouts_match_the_c_header(mpmx, tmp_path):
     structs = {"mpmx_mesh": mpmx.Mesh, "mpmx_material": mpmx.Material, "mpmx_bc": mpmx.Bc,
                "mpmx_scheme": mpmx.Scheme, "mpmx_particles": mpmx.Particles,
-               "mpmx_particles_out": mpmx.ParticlesOut, "mpmx_stats": mpmx.Stats}
+               "mpmx_particles_out": mpmx.ParticlesOut, "mpmx_stats": mpmx.Stats,
+               "mpmx_request": mpmx.Request, "mpmx_completion": mpmx.Completion}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpmx.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -85,3 +86,40 @@ def test_context_creation_fails_cleanly_without_a_gpu(mpmx):
     with pytest.raises(mpmx.MpmxError) as e:
         mpmx.Context(0)
     assert e.value.code == mpmx.E_HIP
+
+
+def test_server_queue_without_a_gpu(mpmx):
+    """The server's host side (copying requests, budget check, queue,
+    polling) needs no device: a server on a placeholder context accepts and
+    queues requests, rejects one that can never fit its budget, and has
+    nothing to report before a tick.  (Ticks need a GPU.)"""
+    import ctypes
+    from paper_1909_13380_amd import scenes
+    sc = scenes.c1()
+    need = mpmx.scene_bytes(sc, mpmx.FP32)
+    h = ctypes.c_void_p()
+    placeholder = ctypes.c_void_p(1)            # never dereferenced by submit/poll
+    assert mpmx._lib.mpmx_server_create(placeholder, 0, 16, ctypes.byref(h)) == mpmx.E_INVALID_ARG
+    assert mpmx._lib.mpmx_server_create(placeholder, need, 0, ctypes.byref(h)) == mpmx.E_INVALID_ARG
+    assert mpmx._lib.mpmx_server_create(placeholder, need, 16, ctypes.byref(h)) == mpmx.OK
+
+    class _Ctx:
+        _h = placeholder
+    srv = mpmx.Server.__new__(mpmx.Server)
+    srv.ctx, srv._h = _Ctx(), h
+    srv._check = lambda rc, what: (_ for _ in ()).throw(mpmx.MpmxError(rc, what)) if rc else None
+    ids = [srv.submit(sc, 10, tag=7), srv.submit(sc, 0)]
+    assert ids == [1, 2]
+    big = dict(sc, x=np.concatenate([sc["x"]] * 2), v=np.concatenate([sc["v"]] * 2),
+               vol=np.concatenate([sc["vol"]] * 2), mass=np.concatenate([sc["mass"]] * 2), stress=None)
+    with pytest.raises(mpmx.MpmxError) as e:
+        srv.submit(big, 10)
+    assert e.value.code == mpmx.E_BUDGET
+    with pytest.raises(mpmx.MpmxError) as e:
+        srv.submit(sc, -1)
+    assert e.value.code == mpmx.E_INVALID_ARG
+    assert srv.poll() == []
+    assert mpmx._lib.mpmx_server_release(h, ids[0]) == mpmx.E_NOT_FOUND
+    t = srv.clock()
+    assert 0.0 <= t < 60.0
+    srv.close()

@@ -257,6 +257,28 @@ def test_column_full_run_against_stored_oracle_sample(ctx, mp):
     s.destroy()
 
 
+def test_batched_set_full_run_against_oracle(ctx, mp):
+    """All 256 scenes of the batched set (9.6M particles) for their 500
+    steps in one batch, in FP32: every scene completes without error, and
+    the six smallest (all launched in the same batch as the large ones)
+    meet the displacement and stress bars against the oracle, with
+    particles-per-cell histograms matching."""
+    scs = scenes.c3()
+    batch = [ctx.create_scene(sc, precision=mp.FP32) for sc in scs]
+    ctx.batch_step(batch, [sc["nsteps"] for sc in scs])
+    order = np.argsort([len(sc["x"]) for sc in scs])
+    for i in order[:6]:
+        sc, b = scs[i], batch[i]
+        got = b.read()
+        ref = oracle.run(sc, sc["nsteps"])
+        check_state(f"batched/{sc['name']}/{len(sc['x'])}", got, ref, sc["x"], U_TOL, S_TOL, 1e-3)
+        check_histograms(sc, b.cell_counts(), got["x"], ref["x"])
+    for sc, b in zip(scs, batch):
+        st = b.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == sc["nsteps"], (sc["name"], st)
+        b.destroy()
+
+
 @pytest.mark.parametrize("shape", [1, 0])
 def test_column_subsample_steps(ctx, mp, shape):
     """The 1/64 subsample of the 25M-particle column (393,216 particles,

@@ -1,0 +1,58 @@
+"""GPU tests of the request loop (mpmx_server_* through the C ABI): scenes
+admitted in arrival order within the device-memory budget, advanced in
+shared batches, and returned with the oracle's final state."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_13380_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_server_runs_requests_to_the_oracle_state_within_budget():
+    from paper_1909_13380_amd import mpmx
+    steps = [7, 30, 0, 45, 12, 20, 33]
+    scs = []
+    for i, k in enumerate(steps):
+        mat = scenes.drucker_prager() if i % 2 else scenes.elastic()
+        sc = scenes.random_block(n_cells=(6, 5, 4), mesh_cells=(12, 10, 8), h=0.05, seed=60 + i, material=mat,
+                                 stress_scale=2e3)
+        scs.append(sc)
+    bad = scenes.random_block(seed=70)
+    bad["x"] = bad["x"].copy()
+    bad["x"][3, 2] = -1.0                     # below the mesh
+    per = mpmx.scene_bytes(scs[0], mpmx.FP64)
+    ctx = mpmx.Context(0)
+    srv = mpmx.Server(ctx, int(2.5 * per), max_tick_steps=16)
+    try:
+        ids = [srv.submit(sc, k, precision=mpmx.FP64, tag=100 + i) for i, (sc, k) in enumerate(zip(scs, steps))]
+        bad_id = srv.submit(bad, 5, precision=mpmx.FP64, tag=999)
+        done = {}
+        for _ in range(200):
+            r, q = srv.tick()
+            assert r <= 2, "budget admits at most two of these scenes at a time"
+            for c in srv.poll():
+                done[c["request"]] = c
+            if len(done) == len(ids) + 1:
+                break
+        assert len(done) == len(ids) + 1
+        assert done[bad_id]["status"] == mpmx.E_OUT_OF_MESH and done[bad_id]["tag"] == 999
+        admits = [done[i]["t_admit"] for i in ids]
+        assert admits == sorted(admits), "admission in arrival order"
+        for i, (sc, k) in enumerate(zip(scs, steps)):
+            c = done[ids[i]]
+            assert c["status"] == mpmx.OK and c["tag"] == 100 + i and c["steps_done"] == k
+            assert c["t_submit"] <= c["t_admit"] <= c["t_done"]
+            ref = oracle.run(sc, k) if k else {"x": sc["x"], "stress": sc["stress"], "v": sc["v"]}
+            eu = _rel(c["x"] - sc["x"], ref["x"] - sc["x"]) if k else np.abs(c["x"] - sc["x"]).max()
+            es = _rel(c["stress"], ref["stress"])
+            print(f"[server/{i}/{k}] err_u={eu:.3e} err_sigma={es:.3e}", flush=True)
+            assert eu <= 1e-9 and es <= 1e-9
+    finally:
+        srv.close()
+        ctx.close()
