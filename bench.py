@@ -52,7 +52,7 @@ def kernel_bytes(kernel: str, n_particles: int, n_nodes: int) -> int:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("mpmx_kernels.hip", "mpmx_api.hip", "mpmx_dev.h"):
+    for f in ("mpmx_kernels.hip", "mpmx_api.hip", "mpmx_dev.h", "mpmx_launch.h"):
         with open(os.path.join(ROOT, "paper_1909_13380_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -151,9 +151,22 @@ def summarize(root: str, workload: str, commands: str):
                   f"ms_per_step {bench_line['ms_per_step']:.4f}, value {bench_line['value']:.4g} "
                   f"{bench_line['unit']}", ""]
         lines.append(f"{'kernel':34s} {'events_avg_us':>14s} {'rocprof_avg_us':>15s}")
-        rp = {_short(r["Name"]).split("<")[0].replace("k_", ""): float(r["AverageNs"]) / 1e3 for r in stats}
+        # item kernels exist per workgroup size: compare the instantiation the
+        # tuned launch shape used
+        launch = bench_line.get("config", {}).get("launch", {})
+        want = {"stress": launch.get("stress_threads"), "g2p_p2g": launch.get("g2p_threads"),
+                "p2g": launch.get("g2p_threads")}
+        rp = {}
+        for r in stats:
+            name = _short(r["Name"])
+            base = name.split("<")[0].replace("k_", "")
+            targs = [a.strip() for a in name[len(name.split("<")[0]) + 1:-1].split(",")] if "<" in name else []
+            if base in want and want[base] is not None and (not targs or targs[-1] != str(want[base])):
+                continue
+            rp[base] = (float(r["AverageNs"]) / 1e3, name)
         for k, v in sorted(bench_line["kernels"].items()):
-            lines.append(f"{k:34s} {v['avg_us']:14.2f} {rp.get(k, float('nan')):15.2f}")
+            avg, name = rp.get(k, (float("nan"), ""))
+            lines.append(f"{k:34s} {v['avg_us']:14.2f} {avg:15.2f}   {name}")
     traffic = {}
     copy_bytes = 1024 << 20
     scale = {}
@@ -174,8 +187,14 @@ def summarize(root: str, workload: str, commands: str):
             wr = wm[(k, "WRITE_SIZE")] * 1024.0 * scale["WRITE_SIZE"]
             lines.append(f"{k[:34]:34s} {rd / 1e6:10.2f} {wr / 1e6:10.2f} {(rd + wr) / 1e6:10.2f}")
             base = k.split("<")[0].replace("k_", "")
-            traffic[base] = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
-                             "source_hash": source_hash()}
+            entry = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr, "source_hash": source_hash(),
+                     "instantiation": k}
+            # one entry per kernel: the tuned instantiation when there are several
+            tw = (bench_line or {}).get("config", {}).get("launch", {})
+            t_use = {"stress": tw.get("stress_threads"), "g2p_p2g": tw.get("g2p_threads")}.get(base)
+            if base in traffic and t_use is not None and not k.rstrip(">").endswith(str(t_use)):
+                continue
+            traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     name = {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
             "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
