@@ -950,6 +950,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         h.xic = xi * mat->c;
         h.etab = etab;
         h.has_apex = eta > 0.0;
+        h.inv_hard = 1.0 / (h.G + h.K * eta * etab);
         h.apex_p = eta > 0.0 ? xi * mat->c / eta : 0.0;
     }
     h.algo = sch->algo;

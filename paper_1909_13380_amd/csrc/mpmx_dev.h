@@ -51,6 +51,7 @@ enum Ctl : int {
     CTL_HAVE_P2G = 10,  // node buffer CTL_NBUF holds this step's P2G
     CTL_ACC0 = 11,      // items whose tiles[b] cover node buffer b's data (b = 0, 1)
     CTL_ACC1 = 12,
+    CTL_BOX_OK = 13,    // tiles[CTL_NBUF] holds this step's node box of every item
     CTL_WORDS = 16
 };
 
@@ -91,6 +92,7 @@ struct SceneDev {
     int sort_always;
     double lam, G, K;
     double eta, xic, etab, apex_p;  // DP: eta, xi*c, eta_bar, apex pressure
+    double inv_hard;                // DP: 1 / (G + K eta eta_bar)
     int has_apex;
     // scheme
     int algo, shape, vel_update, prec;

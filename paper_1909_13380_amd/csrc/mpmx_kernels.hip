@@ -364,20 +364,31 @@ __device__ inline void constitutive(const SceneDev &S, const R de[6], R sig[6])
         return;
     // Drucker-Prager, perfectly plastic: f = sqrt(J2) + eta p - xi c.
     const R K = (R)S.K, eta = (R)S.eta, etab = (R)S.etab;
-    const R p = (sig[0] + sig[1] + sig[2]) / (R)3;
+    constexpr bool F32 = sizeof(R) == 4;
+    const R p = F32 ? (sig[0] + sig[1] + sig[2]) * (R)(1.0 / 3.0) : (sig[0] + sig[1] + sig[2]) / (R)3;
     R s[6];
     for (int a = 0; a < 3; ++a)
         s[a] = sig[a] - p;
     for (int a = 3; a < 6; ++a)
         s[a] = sig[a];
     const R J2 = (R)0.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2]) + s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
-    const R q = sqrt(J2);
+    // FP32: the hardware square root and reciprocal (about 1 ulp) in place
+    // of the correctly rounded sequences
+    R q;
+    if constexpr (F32)
+        q = __builtin_amdgcn_sqrtf(J2);
+    else
+        q = sqrt(J2);
     const R f = q + eta * p - (R)S.xic;
     if (!(f > (R)0))
         return;
-    const R dgam = f / (G + K * eta * etab);
+    const R dgam = F32 ? f * (R)S.inv_hard : f / (G + K * eta * etab);
     if (q - G * dgam >= (R)0) {
-        const R scale = (R)1 - G * dgam / q;
+        R scale;
+        if constexpr (F32)
+            scale = (R)1 - G * dgam * __builtin_amdgcn_rcpf(q);
+        else
+            scale = (R)1 - G * dgam / q;
         const R pn = p - K * etab * dgam;
         for (int a = 0; a < 3; ++a)
             sig[a] = scale * s[a] + pn;
@@ -771,7 +782,8 @@ __device__ void step_control(const BatchDev &B)
             const SceneDev &S = *B.scenes[s];
             uint32_t *ctl = S.ctl;
             const bool go = ctl[CTL_ERR] == 0u && ctl[CTL_REMAIN] > 0u;
-            if (go && ctl[CTL_NEED_SORT]) {
+            const bool sorted = go && ctl[CTL_NEED_SORT];
+            if (sorted) {
                 ctl[CTL_CUR] ^= 1u;
                 ctl[CTL_NEED_SORT] = 0u;
                 ctl[CTL_N_SORTS] += 1u;
@@ -785,12 +797,17 @@ __device__ void step_control(const BatchDev &B)
                         ctl[CTL_NBUF] ^= 1u;
                         ctl[CTL_READY] = 0u;
                         ctl[CTL_HAVE_P2G] = 1u;
+                        // its boxes belong to the items it ran, valid unless
+                        // this step reordered the particles
+                        ctl[CTL_BOX_OK] = sorted ? 0u : 1u;
                     } else {
                         ctl[CTL_HAVE_P2G] = 0u;
+                        ctl[CTL_BOX_OK] = 1u;   // p2g records them after the reorder
                     }
                 } else {                    // USL: p2g_usl fills a fresh buffer every step
                     ctl[CTL_NBUF] ^= 1u;
                     ctl[CTL_HAVE_P2G] = 0u;
+                    ctl[CTL_BOX_OK] = 0u;
                 }
                 items = ctl[CTL_N_ITEMS];
                 clears = ctl[CTL_ACC0 + (ctl[CTL_NBUF] ^ 1u)];
@@ -1220,9 +1237,16 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                 mx[a] = max(mx[a], c[a]);
             }
         }
-        block_box(mn, mx, red);
-        const int blo[3] = {red[0], red[1], red[2]}, bhi[3] = {red[3], red[4], red[5]};
-        const Tile t = tile_of_cells<SH>(blo, bhi);
+        // the node box: recorded by the kernel that filled this node buffer
+        // when the items are unchanged since, else reduced here
+        Tile t;
+        if (uni(S.ctl[CTL_BOX_OK])) {
+            t = uni_struct(pick(S.tiles, buf)[r.it]);
+        } else {
+            block_box(mn, mx, red);
+            const int blo[3] = {red[0], red[1], red[2]}, bhi[3] = {red[3], red[4], red[5]};
+            t = tile_of_cells<SH>(blo, bhi);
+        }
         if (threadIdx.x == 0)
             S.tstep[r.it] = t;
         if (!t.fits) {
@@ -1291,6 +1315,44 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                 }
             }
             R L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            // linear shape functions: dN/dx_a is +-1/h times the product of the
+            // other two axes' weights (pair products below, shared with the
+            // force), so the gradient is a weighted sum of nodal differences
+            R Pyz[4], Pxz[4], Pxy[4];
+            if constexpr (SH == 0) {
+                for (int u = 0; u < 2; ++u)
+                    for (int w = 0; w < 2; ++w) {
+                        Pyz[u + 2 * w] = sp.w[1][u] * sp.w[2][w];
+                        Pxz[u + 2 * w] = sp.w[0][u] * sp.w[2][w];
+                        Pxy[u + 2 * w] = sp.w[0][u] * sp.w[1][w];
+                    }
+                R v8[8][3];
+                for (int n = 0; n < 8; ++n) {
+                    if constexpr (GC) {
+                        v8[n][0] = cv[n][0];
+                        v8[n][1] = cv[n][1];
+                        v8[n][2] = cv[n][2];
+                    } else {
+                        const R4<R> w = lv[cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz];
+                        v8[n][0] = w.x;
+                        v8[n][1] = w.y;
+                        v8[n][2] = w.z;
+                    }
+                }
+                const R ih = (R)S.inv_h;
+                for (int e = 0; e < 3; ++e) {
+                    R gx = 0, gy = 0, gz = 0;
+                    for (int u = 0; u < 2; ++u)
+                        for (int w = 0; w < 2; ++w) {
+                            gx += Pyz[u + 2 * w] * (v8[1 + 2 * u + 4 * w][e] - v8[2 * u + 4 * w][e]);
+                            gy += Pxz[u + 2 * w] * (v8[u + 2 + 4 * w][e] - v8[u + 4 * w][e]);
+                            gz += Pxy[u + 2 * w] * (v8[u + 2 * w + 4][e] - v8[u + 2 * w][e]);
+                        }
+                    L[e][0] = ih * gx;
+                    L[e][1] = ih * gy;
+                    L[e][2] = ih * gz;
+                }
+            } else {
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
                     for (int i = 0; i < NS; ++i) {
@@ -1319,6 +1381,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                         L[2][1] += v[2] * gyN;
                         L[2][2] += v[2] * gzN;
                     }
+            }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
             const R vol = P.vol[p] * ((R)1 + de[0] + de[1] + de[2]);
@@ -1333,6 +1396,36 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             }
             P.vol[p] = vol;
             const R mp = P.mass[p];
+            auto deposit = [&](int i, int j, int k, R f0, R f1, R f2) {
+                if constexpr (SC) {
+                    const int n = i + 2 * j + 4 * k;
+                    fa[n][0] += f0;
+                    fa[n][1] += f1;
+                    fa[n][2] += f2;
+                } else {
+                    const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                    atomicAdd(&lf[0][li], (double)f0);
+                    atomicAdd(&lf[1][li], (double)f1);
+                    atomicAdd(&lf[2][li], (double)f2);
+                }
+            };
+            if constexpr (SH == 0) {
+                // f_I = -V sigma . grad N_I + N_I m g with grad N_I = (1/h) (sx Pyz,
+                // sy Pxz, sz Pxy), s = -1 for the lower node of an axis
+                const R c = -vol * (R)S.inv_h;
+                const R A[6] = {c * sg[0], c * sg[1], c * sg[2], c * sg[3], c * sg[4], c * sg[5]};
+                const R mg0 = mp * gx, mg1 = mp * gy, mg2 = mp * gz;
+                for (int k = 0; k < 2; ++k)
+                    for (int j = 0; j < 2; ++j)
+                        for (int i = 0; i < 2; ++i) {
+                            const R yz = Pyz[j + 2 * k], xz = Pxz[i + 2 * k], xy = Pxy[i + 2 * j];
+                            const R ax = i ? yz : -yz, ay = j ? xz : -xz, az = k ? xy : -xy;
+                            const R N = sp.w[0][i] * yz;
+                            deposit(i, j, k, N * mg0 + A[0] * ax + A[3] * ay + A[5] * az,
+                                    N * mg1 + A[3] * ax + A[1] * ay + A[4] * az,
+                                    N * mg2 + A[5] * ax + A[4] * ay + A[2] * az);
+                        }
+            } else {
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
                     for (int i = 0; i < NS; ++i) {
@@ -1344,18 +1437,9 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                         const R f0 = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mp * gx;
                         const R f1 = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy;
                         const R f2 = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz;
-                        if constexpr (SC) {
-                            const int n = i + 2 * j + 4 * k;
-                            fa[n][0] += f0;
-                            fa[n][1] += f1;
-                            fa[n][2] += f2;
-                        } else {
-                            const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
-                            atomicAdd(&lf[0][li], (double)f0);
-                            atomicAdd(&lf[1][li], (double)f1);
-                            atomicAdd(&lf[2][li], (double)f2);
-                        }
+                        deposit(i, j, k, f0, f1, f2);
                     }
+            }
         }
         if constexpr (SC)
             if (fb[0] != -(1 << 30))
