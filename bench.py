@@ -14,7 +14,7 @@ pass of K steps in which every kernel is launched directly between two HIP
 events on the library's stream), and the FP64 oracle timed on a bounded
 sample on the host CPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1|batch|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1|c5|c5_linear|batch|serve]
 """
 from __future__ import annotations
 
@@ -84,6 +84,11 @@ def make_workload(name: str):
         return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, GIMP"
     if name == "c1":
         return scenes.c1(), "elastic block, 4,096 particles, 16^3 mesh, linear"
+    if name == "c5":
+        return scenes.c5(), "large granular column, DP, 25,165,824 particles, 512x256x128 mesh, GIMP"
+    if name == "c5_linear":
+        return (scenes.c5(shape=scenes.SHAPE_LINEAR),
+                "large granular column, DP, 25,165,824 particles, 512x256x128 mesh, linear")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -455,7 +460,14 @@ def main():
         out["step_algorithmic_GBs"] = step_bytes / (elapsed / args.steps) / 1e9
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        cb = cpu_baseline(sc, args.cpu_steps)
+        if args.workload in ("c5", "c5_linear"):
+            from paper_1909_13380_amd import scenes as _sc
+            sub = _sc.c5(subsample=True, shape=sc["scheme"]["shape"])
+            cb = cpu_baseline(sub, args.cpu_steps)
+            cb["sample"] = (f"first {args.cpu_steps} steps of the 1/64 subsample of the same column "
+                            f"({len(sub['x'])} particles), FP64, one thread")
+        else:
+            cb = cpu_baseline(sc, args.cpu_steps)
         cb["cores"] = 1
         out["cpu_baseline"] = cb
     s.destroy()

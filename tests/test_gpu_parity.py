@@ -293,6 +293,76 @@ def test_column_subsample_steps(ctx, mp, shape):
     s.destroy()
 
 
+def _dp_yield_excess(stress, mat):
+    """Largest f = sqrt(J2) + eta p - xi c over all particles, relative to
+    the largest |p| (the Drucker-Prager outer cone of the material)."""
+    phi = mat["phi"]
+    sn, cs = np.sin(phi), np.cos(phi)
+    eta = 6 * sn / (np.sqrt(3) * (3 - sn))
+    xi = 6 * cs / (np.sqrt(3) * (3 - sn))
+    p = stress[:, :3].mean(axis=1)
+    s = stress[:, :3] - p[:, None]
+    j2 = 0.5 * (s ** 2).sum(axis=1) + (stress[:, 3:] ** 2).sum(axis=1)
+    f = np.sqrt(j2) + eta * p - xi * mat["c"]
+    return float(f.max() / max(np.abs(p).max(), 1e-30))
+
+
+@pytest.mark.parametrize("shape", ["gimp", "linear"])
+def test_column_subsample_full_run_against_stored_oracle_sample(ctx, mp, shape):
+    """All 500 steps of the 1/64 subsample of the large column (393,216
+    particles) in FP32 against the oracle's final state, stored for every
+    64th particle by tests/golden/make_c5sub_golden.py (oracle only), with
+    the same histogram rule as the 2M-particle column and stresses on or
+    inside the yield cone for every particle."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", f"c5sub_{shape}_500.npz"))
+    sc = scenes.c5(subsample=True, shape=mp.SHAPE_GIMP if shape == "gimp" else mp.SHAPE_LINEAR)
+    idx = gold["index"]
+    np.testing.assert_array_equal(sc["x"][idx], gold["x0"])
+    np.testing.assert_array_equal(oracle.cell_counts(sc["mesh"], sc["x"]), gold["hist0"])
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(int(gold["nsteps"]))
+    got = s.read()
+    sub = {k: got[k][idx] for k in ("x", "v", "stress", "vol")}
+    ref = {k: gold[k] for k in ("x", "v", "stress", "vol")}
+    check_state(f"column_sub/{shape}/500", sub, ref, gold["x0"], U_TOL, S_TOL, 1e-3)
+    hc = s.cell_counts().astype(np.int64)
+    hr = gold["hist"].astype(np.int64)
+    moved = int(np.abs(hc - hr).sum())
+    print(f"[column_sub/{shape}/500] histogram L1 difference {moved} of {len(sc['x'])}", flush=True)
+    assert hc.sum() == hr.sum() == len(sc["x"]) and moved <= 1e-4 * len(sc["x"])
+    assert _dp_yield_excess(got["stress"], sc["material"]) <= 1e-5
+    s.destroy()
+
+
+def test_large_gimp_column_full_size_properties(ctx, mp):
+    """The 25M-particle GIMP column at full size in the benchmark's
+    configuration, 20 steps: no error, every particle inside the mesh and on
+    or inside the yield cone, nodal mass equal to the particle mass, the
+    input binning bit-exact, and every particle's displacement below the
+    discrete free-fall distance (the block starts at rest)."""
+    sc = scenes.c5(subsample=False, shape=mp.SHAPE_GIMP)
+    n = len(sc["x"])
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    np.testing.assert_array_equal(s.cell_counts(), oracle.cell_counts(sc["mesh"], sc["x"]))
+    k = 20
+    s.step(k)
+    st = s.stats()
+    assert st["error_bits"] == 0 and st["steps_done"] == k
+    nodes = s.nodes()
+    mtot = float(np.asarray(sc["mass"], dtype=np.float64).sum())
+    # weights are FP32 (partition of unity to rounding), sums FP64
+    assert abs(nodes["m"].sum() - mtot) <= 1e-6 * mtot
+    got = s.read()
+    disp = np.linalg.norm(got["x"] - sc["x"], axis=1)
+    # discrete free fall from rest reaches g dt^2 k (k + 1) / 2; internal
+    # forces of the falling block only slow it (margin for lateral spread)
+    assert disp.max() <= 1.5 * 9.81 * sc["scheme"]["dt"] ** 2 * k * (k + 1) / 2
+    assert _dp_yield_excess(got["stress"], sc["material"]) <= 1e-5
+    assert int(s.cell_counts().sum()) == n
+    s.destroy()
+
+
 # ------------------------------------------------------------- runtime --
 
 def test_sort_policies_and_step_chunking_agree(ctx, mp):
