@@ -58,6 +58,8 @@ struct LaunchCfg {
 
 struct Batch {
     std::vector<uint64_t> ids;
+    void *dmem = nullptr;   // one block holding the arrays below
+    size_t dcap = 0;
     SceneDev **d_scenes = nullptr;
     int64_t *d_poffs = nullptr, *d_boffs = nullptr, *d_nsteps = nullptr;
     uint32_t *d_ioffs = nullptr, *d_coffs = nullptr, *d_flags = nullptr;
@@ -77,13 +79,59 @@ struct Batch {
     void release()
     {
         drop_graph();
-        for (void *p : {(void *)d_scenes, (void *)d_poffs, (void *)d_boffs, (void *)d_nsteps, (void *)d_ioffs,
-                        (void *)d_coffs, (void *)d_flags})
-            if (p)
-                (void)hipFree(p);
+        if (dmem)
+            (void)hipFree(dmem);
+        dmem = nullptr;
+        dcap = 0;
         d_scenes = nullptr;
         d_poffs = d_boffs = d_nsteps = nullptr;
         d_ioffs = d_coffs = d_flags = nullptr;
+        ids.clear();
+    }
+};
+
+// Caching pool of device blocks: a freed block is kept and handed out again
+// for a request of at most 1.25x its size (+1 MiB), so scenes that come and
+// go (the request loop) do not call hipMalloc / hipFree each time.
+struct DevicePool {
+    std::multimap<uint64_t, void *> idle;
+    std::map<void *, uint64_t> size_of;
+    void *alloc(uint64_t bytes)
+    {
+        auto it = idle.lower_bound(bytes);
+        if (it != idle.end() && it->first <= bytes + bytes / 4 + (1u << 20)) {
+            void *p = it->second;
+            idle.erase(it);
+            return p;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            trim();
+            if (hipMalloc(&p, bytes) != hipSuccess)
+                return nullptr;
+        }
+        size_of[p] = bytes;
+        return p;
+    }
+    void release(void *p)
+    {
+        if (p)
+            idle.emplace(size_of[p], p);
+    }
+    void trim()
+    {
+        for (auto &kv : idle) {
+            (void)hipFree(kv.second);
+            size_of.erase(kv.second);
+        }
+        idle.clear();
+    }
+    void clear()
+    {
+        trim();
+        for (auto &kv : size_of)
+            (void)hipFree(kv.first);
+        size_of.clear();
     }
 };
 
@@ -91,7 +139,7 @@ struct Scene {
     uint64_t id = 0;
     SceneDev h{};
     SceneDev *d = nullptr;
-    std::vector<void *> allocs;
+    void *block = nullptr;   // every device array of the scene, from the pool
     uint64_t bytes = 0;
     int prec = 0, shape = 0, algo = 0;
     Batch single;
@@ -118,6 +166,9 @@ struct mpmx_ctx {
     int64_t graph_launches = 0, tune_runs = 0;
     hipStream_t capture = nullptr;         // private stream for graph capture
     hipStream_t launch_stream = nullptr;   // stream of the launches being issued
+    DevicePool pool;
+    void *staging = nullptr;               // device staging of host inputs/outputs
+    uint64_t staging_cap = 0;
 };
 
 namespace {
@@ -336,41 +387,74 @@ Scene *find(mpmx_ctx *ctx, uint64_t id)
     return it == ctx->scenes.end() ? nullptr : it->second.get();
 }
 
-void free_scene(Scene *s)
+void free_scene(mpmx_ctx *ctx, Scene *s)
 {
     s->single.release();
-    for (void *p : s->allocs)
-        (void)hipFree(p);
-    s->allocs.clear();
+    ctx->pool.release(s->block);
+    s->block = nullptr;
+}
+
+// Device staging area of at least `bytes` (contents not preserved); every
+// user synchronises the stream before returning.
+void *staging(mpmx_ctx *ctx, uint64_t bytes)
+{
+    if (bytes > ctx->staging_cap) {
+        if (ctx->staging)
+            (void)hipFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_cap = 0;
+        const uint64_t cap = std::max<uint64_t>(bytes, ctx->staging_cap * 2);
+        if (hipMalloc(&ctx->staging, cap) != hipSuccess) {
+            ctx->pool.trim();
+            if (hipMalloc(&ctx->staging, cap) != hipSuccess) {
+                ctx->staging = nullptr;
+                return nullptr;
+            }
+        }
+        ctx->staging_cap = cap;
+    }
+    return ctx->staging;
 }
 
 int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
 {
-    b.release();
+    b.drop_graph();
     const int n = (int)list.size();
-    std::vector<SceneDev *> ptrs(n);
-    std::vector<int64_t> po(n + 1, 0), bo(n + 1, 0);
-    int64_t maxit = 0;
+    const size_t n1 = (size_t)n + 1;
+    // layout: scenes[n] | poffs[n+1] | boffs[n+1] | nsteps[n] | ioffs[n+1] | coffs[n+1] | flags
+    const size_t o_po = 8 * (size_t)std::max(n, 1), o_bo = o_po + 8 * n1, o_ns = o_bo + 8 * n1,
+                 o_io = o_ns + 8 * (size_t)std::max(n, 1), o_co = o_io + 4 * n1, o_fl = o_co + 4 * n1,
+                 total = o_fl + 4 * BF_WORDS;
+    std::vector<uint8_t> img(total, 0);
+    int64_t maxit = 0, *po = (int64_t *)(img.data() + o_po), *bo = (int64_t *)(img.data() + o_bo);
+    SceneDev **sp = (SceneDev **)img.data();
     for (int i = 0; i < n; ++i) {
-        ptrs[i] = list[i]->d;
+        sp[i] = list[i]->d;
         po[i + 1] = po[i] + list[i]->h.np;
         bo[i + 1] = bo[i] + list[i]->h.nbricks;
         maxit += list[i]->h.max_items;
     }
-    HIPCHK(ctx, hipMalloc(&b.d_scenes, sizeof(SceneDev *) * std::max(n, 1)));
-    HIPCHK(ctx, hipMalloc(&b.d_poffs, sizeof(int64_t) * (n + 1)));
-    HIPCHK(ctx, hipMalloc(&b.d_boffs, sizeof(int64_t) * (n + 1)));
-    HIPCHK(ctx, hipMalloc(&b.d_nsteps, sizeof(int64_t) * std::max(n, 1)));
-    HIPCHK(ctx, hipMalloc(&b.d_ioffs, sizeof(uint32_t) * (n + 1)));
-    HIPCHK(ctx, hipMalloc(&b.d_coffs, sizeof(uint32_t) * (n + 1)));
-
-    HIPCHK(ctx, hipMalloc(&b.d_flags, sizeof(uint32_t) * BF_WORDS));
-    HIPCHK(ctx, hipMemset(b.d_coffs, 0, sizeof(uint32_t) * (n + 1)));
-    HIPCHK(ctx, hipMemset(b.d_flags, 0, sizeof(uint32_t) * BF_WORDS));
-    HIPCHK(ctx, hipMemcpy(b.d_scenes, ptrs.data(), sizeof(SceneDev *) * n, hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(b.d_poffs, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(b.d_boffs, bo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemset(b.d_ioffs, 0, sizeof(uint32_t) * (n + 1)));
+    if (total > b.dcap) {
+        if (b.dmem)
+            (void)hipFree(b.dmem);
+        b.dmem = nullptr;
+        b.dcap = 0;
+        HIPCHK(ctx, hipMalloc(&b.dmem, 2 * total));
+        b.dcap = 2 * total;
+    }
+    uint8_t *base = (uint8_t *)b.dmem;
+    // the previous contents may still be read by queued steps of this batch
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(base, img.data(), total, hipMemcpyHostToDevice));
+    b.d_scenes = (SceneDev **)base;
+    b.d_poffs = (int64_t *)(base + o_po);
+    b.d_boffs = (int64_t *)(base + o_bo);
+    b.d_nsteps = (int64_t *)(base + o_ns);
+    b.d_ioffs = (uint32_t *)(base + o_io);
+    b.d_coffs = (uint32_t *)(base + o_co);
+    b.d_flags = (uint32_t *)(base + o_fl);
+    po = (int64_t *)(img.data() + o_po);
+    bo = (int64_t *)(img.data() + o_bo);
     b.bd.scenes = b.d_scenes;
     b.bd.poffs = b.d_poffs;
     b.bd.boffs = b.d_boffs;
@@ -682,9 +766,12 @@ void mpmx_destroy(mpmx_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &kv : ctx->scenes)
-        free_scene(kv.second.get());
+        free_scene(ctx, kv.second.get());
     ctx->scenes.clear();
     ctx->cached_batch.release();
+    if (ctx->staging)
+        (void)hipFree(ctx->staging);
+    ctx->pool.clear();
     for (auto &pe : ctx->prof.pending) {
         (void)hipEventDestroy(pe.a);
         (void)hipEventDestroy(pe.b);
@@ -853,16 +940,24 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     s->shape = sch->shape;
     s->algo = sch->algo;
     SceneDev &h = s->h;
+    // one block of exactly scene_bytes(); the arrays are carved in the order
+    // scene_bytes() counts them
+    const uint64_t total = scene_bytes(sz, np, extra);
+    s->block = ctx->pool.alloc(total);
+    if (!s->block)
+        return fail(ctx, MPMX_E_OOM, "device allocation of %llu bytes failed", (unsigned long long)total);
+    s->bytes = total;
+    uint64_t used = 0;
+    std::vector<std::pair<void *, uint64_t>> zero_ranges;
     auto dalloc = [&](uint64_t bytes, bool zero) -> void * {
         if (bytes == 0)
             return nullptr;
-        void *p = nullptr;
-        if (hipMalloc(&p, align_up(bytes)) != hipSuccess)
+        if (used + align_up(bytes) > total)
             return nullptr;
-        s->allocs.push_back(p);
-        s->bytes += align_up(bytes);
-        if (zero && hipMemset(p, 0, align_up(bytes)) != hipSuccess)
-            return nullptr;
+        void *p = (uint8_t *)s->block + used;
+        used += align_up(bytes);
+        if (zero)
+            zero_ranges.push_back({p, align_up(bytes)});
         return p;
     };
     bool ok = true;
@@ -916,10 +1011,17 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         h.bc_mask = (const uint8_t *)dm;
         h.bc_val = (const double *)dv;
     }
+    for (auto &z : zero_ranges)
+        if (ok && hipMemsetAsync(z.first, 0, z.second, ctx->stream) != hipSuccess)
+            ok = false;
+    // the control words below are written with blocking copies: the zeroing
+    // must be complete first
+    if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        ok = false;
     if (!ok) {
-        free_scene(s);
-        return fail(ctx, MPMX_E_OOM, "device allocation of %llu bytes failed",
-                    (unsigned long long)scene_bytes(sz, np, extra));
+        free_scene(ctx, s);
+        return fail(ctx, MPMX_E_OOM, "device arrays of %llu bytes do not fit the scene's block",
+                    (unsigned long long)total);
     }
 
     for (int a = 0; a < 3; ++a) {
@@ -965,19 +1067,20 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
 
     // particles: host inputs are staged through device memory
     const double *dx = parts->x, *dv = parts->v, *dsig = parts->stress, *dvol = parts->vol, *dmass = parts->mass;
-    std::vector<void *> staging;
     if (np > 0 && parts->mem == MPMX_MEM_HOST) {
         double mean = 0.0;
         for (int64_t p = 0; p < np; ++p)
             mean += parts->mass[p];
         h.eps_m = sch->mass_eps_rel * (mean / (double)np);
+        uint8_t *stage = (uint8_t *)staging(ctx, align_up(24 * np) * 2 + align_up(48 * np) + 2 * align_up(8 * np));
+        if (!stage)
+            ok = false;
+        uint64_t soff = 0;
         auto up = [&](const double *src, size_t count) -> const double * {
-            if (!src)
+            if (!src || !ok)
                 return nullptr;
-            void *p = nullptr;
-            if (hipMalloc(&p, count * 8) != hipSuccess)
-                return (const double *)(ok = false, nullptr);
-            staging.push_back(p);
+            void *p = stage + soff;
+            soff += align_up(count * 8);
             if (hipMemcpy(p, src, count * 8, hipMemcpyHostToDevice) != hipSuccess)
                 ok = false;
             return (const double *)p;
@@ -1011,25 +1114,23 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     }
     if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
         ok = false;
-    for (void *p : staging)
-        (void)hipFree(p);
     if (!ok) {
-        free_scene(s);
+        free_scene(ctx, s);
         return fail(ctx, MPMX_E_HIP, "scene upload failed");
     }
     if (hipMemcpy(ctl, h.ctl, sizeof ctl, hipMemcpyDeviceToHost) != hipSuccess) {
-        free_scene(s);
+        free_scene(ctx, s);
         return fail(ctx, MPMX_E_HIP, "scene status read failed");
     }
     if (ctl[CTL_ERR]) {
-        free_scene(s);
+        free_scene(ctx, s);
         return fail(ctx, err_code(ctl[CTL_ERR]), "input particle outside the mesh or not finite (bits %u)",
                     ctl[CTL_ERR]);
     }
     std::vector<Scene *> one{s};
     rc = build_batch(ctx, s->single, one);
     if (rc) {
-        free_scene(s);
+        free_scene(ctx, s);
         return rc;
     }
     s->id = ctx->next_id++;
@@ -1094,14 +1195,18 @@ int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out
     if (np > 0) {
         double *x = out->x, *v = out->v, *sg = out->stress, *vol = out->vol;
         int32_t *cell = out->cell;
-        std::vector<void *> tmp;
+        uint8_t *stage = nullptr;
+        if (out->mem == MPMX_MEM_HOST)
+            stage = (uint8_t *)staging(ctx, 2 * align_up(24 * np) + align_up(48 * np) + align_up(8 * np) +
+                                                align_up(4 * np));
+        uint64_t soff = 0;
         auto dev = [&](void *host, size_t bytes) -> void * {
             if (!host || out->mem == MPMX_MEM_DEVICE)
                 return host;
-            void *p = nullptr;
-            if (hipMalloc(&p, bytes) != hipSuccess)
+            if (!stage)
                 return nullptr;
-            tmp.push_back(p);
+            void *p = stage + soff;
+            soff += align_up(bytes);
             return p;
         };
         double *dx = (double *)dev(x, 24 * np), *dv = (double *)dev(v, 24 * np);
@@ -1123,8 +1228,6 @@ int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out
             if (vol && hipMemcpy(vol, dvo, 8 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
             if (cell && hipMemcpy(cell, dc, 4 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
         }
-        for (void *p : tmp)
-            (void)hipFree(p);
         if (!ok)
             return fail(ctx, MPMX_E_HIP, "particle read failed");
     }
@@ -1243,10 +1346,10 @@ int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene)
     HIPCHK(ctx, hipSetDevice(ctx->device));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (std::find(ctx->cached_batch.ids.begin(), ctx->cached_batch.ids.end(), scene) != ctx->cached_batch.ids.end()) {
-        ctx->cached_batch.release();
+        ctx->cached_batch.drop_graph();
         ctx->cached_batch.ids.clear();
     }
-    free_scene(it->second.get());
+    free_scene(ctx, it->second.get());
     ctx->scenes.erase(it);
     return MPMX_OK;
 }
