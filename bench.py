@@ -214,6 +214,14 @@ def summarize(root: str, workload: str, commands: str):
     print("\n".join(lines))
 
 
+def apply_launch_options(ctx, args):
+    from paper_1909_13380_amd import mpmx
+    for opt, val in ((mpmx.OPT_STRESS_THREADS, args.stress_threads), (mpmx.OPT_G2P_THREADS, args.g2p_threads),
+                     (mpmx.OPT_BLOCKS_PER_CU, args.blocks_per_cu)):
+        if val:
+            ctx.set_option(opt, val)
+
+
 def _percentiles(vals):
     v = np.sort(np.asarray(vals, dtype=np.float64))
     return {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
@@ -238,6 +246,7 @@ def run_batch(args):
     stream = torch.cuda.Stream()          # a real stream: the library and torch's events share it
     torch.cuda.set_stream(stream)
     ctx = mpmx.Context(0, stream=stream.cuda_stream)
+    apply_launch_options(ctx, args)
     untimed = max(args.warmup, mpmx.TUNE_MIN_STEPS)
     out = {"metric": METRIC, "unit": "particle-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic"}
@@ -365,6 +374,9 @@ def main():
                     help="only summarize the rocprofv3 CSV output under DIR (kernel trace + counter passes) "
                          "into profiles/ and exit; no GPU needed")
     ap.add_argument("--commands", default="", help="with --summarize: the commands that produced DIR")
+    ap.add_argument("--stress-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
+    ap.add_argument("--g2p-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0, help="fixed grid density (turns autotuning off)")
     ap.add_argument("--scenes", type=int, default=256, help="--workload batch: number of scenes")
     ap.add_argument("--requests", type=int, default=2000, help="--workload serve: requests per arrival rate")
     ap.add_argument("--rates", default="25,50,100", help="--workload serve: arrival rates (requests/s)")
@@ -401,6 +413,7 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = mpmx.Context(0, stream=stream.cuda_stream)
+    apply_launch_options(ctx, args)
     policy = mpmx.SORT_ALWAYS if args.sort == "always" else mpmx.SORT_ON_DEMAND
     s = ctx.create_scene(sc, precision=mpmx.FP32, sort_policy=policy)
     print(f"# scene created: {desc}", file=sys.stderr, flush=True)

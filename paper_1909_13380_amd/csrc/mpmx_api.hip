@@ -3,7 +3,7 @@
 //
 // A scene owns its device buffers (layout in mpmx_dev.h).  Every step
 // is a fixed sequence of launches over a BatchDev (one scene, or many):
-//   sort_count -> sort_bricks -> sort_cells -> sort_perm -> sort_move (its
+//   sort_count -> sort_bricks -> sort_perm -> sort_move (its
 //   last workgroup runs the step control) -> stress -> g2p_p2g      (USF)
 //   sort ... -> p2g_usl -> g2p_usl                                  (USL)
 // plus one p2g at the start of a USF call for scenes whose node buffer is
@@ -498,7 +498,6 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
     int rc;
     if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)) ||
         (rc = launch(ctx, "sort_bricks", C.sort_bricks, bg, dim3(256), a_bd)) ||
-        (rc = launch(ctx, "sort_cells", C.sort_cells, bg, dim3(256), a_bd)) ||
         (rc = launch(ctx, "sort_perm", C.sort_perm, pg, dim3(kParticleBlock), a_bd)) ||
         (rc = launch(ctx, "sort_move", K.move, bg, dim3(256), a_bd)))
         return rc;

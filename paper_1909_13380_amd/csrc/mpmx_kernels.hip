@@ -898,43 +898,12 @@ __device__ void scan_bricks(const SceneDev &S)
     __syncthreads();
 }
 
-// One wavefront per brick: particles and work items of the brick; the last
-// workgroup to finish scans them per scene.
+// One wavefront per brick: the brick's particle count, its work-item count
+// and the cell-major start of every cell inside the brick; the last
+// workgroup to finish scans the bricks per scene.
 __global__ void __launch_bounds__(kBlock) k_sort_bricks(BatchDev B)
 {
     __shared__ int last;
-    if (!B.flags[BF_ANY_SORT])
-        return;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
-        const int s = find_scene(B.boffs, B.nscenes, gb);
-        const SceneDev &S = *B.scenes[s];
-        if (!scene_sorting(S))
-            continue;
-        const int64_t b = gb - B.boffs[s];
-        const uint32_t tot = wave_sum(S.cnt[b * 64 + lane]);
-        if (lane == 0) {
-            S.bcnt[b] = tot;
-            S.bitem[b] = (tot + kChunk - 1) / kChunk;
-        }
-    }
-    if (!last_block(&B.flags[BF_TICKET_BRICKS], &last))
-        return;
-    for (int s = 0; s < B.nscenes; ++s) {
-        const SceneDev &S = *B.scenes[s];
-        if (scene_sorting(S))
-            scan_bricks(S);
-    }
-    if (threadIdx.x == 0)
-        B.flags[BF_TICKET_BRICKS] = 0u;
-}
-
-// One wavefront per brick: start of each cell's run in cell-major order and
-// the brick's work items.
-__global__ void __launch_bounds__(kBlock) k_sort_cells(BatchDev B)
-{
     if (!B.flags[BF_ANY_SORT])
         return;
     const int lane = threadIdx.x & 63;
@@ -953,21 +922,26 @@ __global__ void __launch_bounds__(kBlock) k_sort_cells(BatchDev B)
             if (lane >= o)
                 inc += t;
         }
-        const uint32_t bs = S.bstart[b];
-        S.cstart[b * 64 + lane] = bs + inc - c;
-        const uint32_t nit = S.bitem[b], tot = S.bcnt[b], i0 = S.istart[b];
-        for (uint32_t i = lane; i < nit; i += 64) {
-            Item it;
-            it.start = bs + i * kChunk;
-            it.count = min((uint32_t)kChunk, tot - i * kChunk);
-            it.brick = (uint32_t)b;
-            it.pad = 0;
-            S.items[i0 + i] = it;
+        S.cstart[b * 64 + lane] = inc - c;   // cell-major start inside the brick
+        if (lane == 63) {
+            S.bcnt[b] = inc;
+            S.bitem[b] = (inc + kChunk - 1) / kChunk;
         }
     }
+    if (!last_block(&B.flags[BF_TICKET_BRICKS], &last))
+        return;
+    for (int s = 0; s < B.nscenes; ++s) {
+        const SceneDev &S = *B.scenes[s];
+        if (scene_sorting(S))
+            scan_bricks(S);
+    }
+    if (threadIdx.x == 0)
+        B.flags[BF_TICKET_BRICKS] = 0u;
 }
 
-// perm lists the particles cell-major: slot cstart[key] + rank holds p.
+// perm lists the particles cell-major: slot bstart[brick] + cstart[key] +
+// rank holds p.  The particle that opens a 512-slot chunk of its brick
+// writes that work item.
 __global__ void __launch_bounds__(kBlock) k_sort_perm(BatchDev B)
 {
     if (!B.flags[BF_ANY_SORT])
@@ -980,7 +954,19 @@ __global__ void __launch_bounds__(kBlock) k_sort_perm(BatchDev B)
             continue;
         const int64_t p = gp - B.poffs[s];
         const int cur = (int)uni(S.ctl[CTL_CUR]);
-        S.perm[S.cstart[brick_key(S, pick(S.cell, cur)[p])] + S.rank[p]] = (uint32_t)p;
+        const uint32_t key = brick_key(S, pick(S.cell, cur)[p]);
+        const uint32_t b = key >> 6;
+        const uint32_t local = S.cstart[key] + S.rank[p];
+        const uint32_t bs = S.bstart[b];
+        S.perm[bs + local] = (uint32_t)p;
+        if (local % kChunk == 0) {
+            Item it;
+            it.start = bs + local;
+            it.count = min((uint32_t)kChunk, S.bcnt[b] - local);
+            it.brick = b;
+            it.pad = 0;
+            S.items[S.istart[b] + local / kChunk] = it;
+        }
     }
 }
 
@@ -995,7 +981,13 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_sort_move(BatchDev B)
 {
     __shared__ int last;
-    if (B.flags[BF_ANY_SORT]) {
+    if (!B.flags[BF_ANY_SORT]) {
+        // nothing moves: the first workgroup runs the step control alone
+        if (blockIdx.x == 0)
+            step_control(B);
+        return;
+    }
+    {
         const int lane = threadIdx.x & 63;
         const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
         const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1009,7 +1001,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_move(BatchDev B)
             const int64_t n = S.np;
             const int cur = (int)uni(S.ctl[CTL_CUR]), nxt = cur ^ 1;
             const uint32_t nc = S.cnt[b * 64 + lane];
-            const uint32_t cs = S.cstart[b * 64 + lane];
+            const uint32_t cs = S.bstart[b] + S.cstart[b * 64 + lane];
             S.cnt[b * 64 + lane] = 0u;
             uint32_t levels = nc;
             for (int o = 32; o > 0; o >>= 1)
@@ -1846,9 +1838,9 @@ const KernelSet &kernel_set(int prec, int shape)
 
 const CommonKernels &common_kernels()
 {
-    static const CommonKernels c = {(const void *)&k_begin,      (const void *)&k_sort_count,
-                                    (const void *)&k_sort_bricks, (const void *)&k_sort_cells,
-                                    (const void *)&k_sort_perm,   (const void *)&k_cell_counts};
+    static const CommonKernels c = {(const void *)&k_begin, (const void *)&k_sort_count,
+                                    (const void *)&k_sort_bricks, (const void *)&k_sort_perm,
+                                    (const void *)&k_cell_counts};
     return c;
 }
 

@@ -27,7 +27,6 @@ struct CommonKernels {
     const void *begin;        // (BatchDev, const int64_t*)
     const void *sort_count;   // (BatchDev)
     const void *sort_bricks;  // (BatchDev)
-    const void *sort_cells;   // (BatchDev)
     const void *sort_perm;    // (BatchDev)
     const void *cell_counts;  // (const SceneDev*, uint32_t*)
 };
