@@ -421,15 +421,17 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     b.drop_graph();
     const int n = (int)list.size();
     const size_t n1 = (size_t)n + 1;
-    // layout: scenes[n] | poffs[n+1] | boffs[n+1] | nsteps[n] | ioffs[n+1] | coffs[n+1] | flags
-    const size_t o_po = 8 * (size_t)std::max(n, 1), o_bo = o_po + 8 * n1, o_ns = o_bo + 8 * n1,
-                 o_io = o_ns + 8 * (size_t)std::max(n, 1), o_co = o_io + 4 * n1, o_fl = o_co + 4 * n1,
-                 total = o_fl + 4 * BF_WORDS;
+    // layout: scenes[n] | poffs[n+1] | boffs[n+1] | nsteps[n] | ctls[n] | ioffs[n+1] | coffs[n+1] | flags
+    const size_t n8 = 8 * (size_t)std::max(n, 1);
+    const size_t o_po = n8, o_bo = o_po + 8 * n1, o_ns = o_bo + 8 * n1, o_ct = o_ns + n8, o_io = o_ct + n8,
+                 o_co = o_io + 4 * n1, o_fl = o_co + 4 * n1, total = o_fl + 4 * BF_WORDS;
     std::vector<uint8_t> img(total, 0);
     int64_t maxit = 0, *po = (int64_t *)(img.data() + o_po), *bo = (int64_t *)(img.data() + o_bo);
     SceneDev **sp = (SceneDev **)img.data();
+    uint32_t **cp = (uint32_t **)(img.data() + o_ct);
     for (int i = 0; i < n; ++i) {
         sp[i] = list[i]->d;
+        cp[i] = list[i]->h.ctl;
         po[i + 1] = po[i] + list[i]->h.np;
         bo[i + 1] = bo[i] + list[i]->h.nbricks;
         maxit += list[i]->h.max_items;
@@ -456,6 +458,7 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     po = (int64_t *)(img.data() + o_po);
     bo = (int64_t *)(img.data() + o_bo);
     b.bd.scenes = b.d_scenes;
+    b.bd.ctls = (uint32_t *const *)(base + o_ct);
     b.bd.poffs = b.d_poffs;
     b.bd.boffs = b.d_boffs;
     b.bd.ioffs = b.d_ioffs;
@@ -492,8 +495,11 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
     // return at once on steps that need no reorder
     const dim3 pg = particle_grid(bd.total_particles, ctx->num_cu);
     const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), ctx->num_cu));
-    const dim3 ig((unsigned)std::max<int64_t>(
-        1, std::min<int64_t>(bd.max_items, (int64_t)cfg.blocks_per_cu * ctx->num_cu)));
+    // item grids: a multiple of the XCD count unless there are fewer items
+    int64_t ign = std::min<int64_t>(bd.max_items, (int64_t)cfg.blocks_per_cu * ctx->num_cu);
+    if (ign >= kXcds)
+        ign -= ign % kXcds;
+    const dim3 ig((unsigned)std::max<int64_t>(1, ign));
     const dim3 ts(kItemThreadChoices[cfg.t_stress]), tg(kItemThreadChoices[cfg.t_g2p]);
     int rc;
     if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)) ||
@@ -920,8 +926,8 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     const int64_t np = parts->n;
     if (np > 0 && (!parts->x || !parts->v || !parts->vol || !parts->mass))
         return fail(ctx, MPMX_E_INVALID_ARG, "particles: x, v, vol and mass are required");
-    if (np >= (int64_t)1 << 31)
-        return fail(ctx, MPMX_E_INVALID_ARG, "particles: at most 2^31 - 1 per scene");
+    if (np >= kMaxIndex)
+        return fail(ctx, MPMX_E_INVALID_ARG, "particles: at most 2^29 - 1 per scene");
     const Sizes sz = sizes_of(mesh, sch->shape, sch->precision, np);
     if (sz.nkeys >= (int64_t)1 << 32 || sz.nn >= kMaxIndex)
         return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys and node indices");
@@ -1100,6 +1106,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     }
     uint32_t ctl[CTL_WORDS] = {0};
     ctl[CTL_NEED_SORT] = 1;
+    ctl[CTL_ALGO] = (uint32_t)h.algo;
     if (ok && hipMemcpy(h.ctl, ctl, sizeof ctl, hipMemcpyHostToDevice) != hipSuccess)
         ok = false;
     if (ok && hipMemcpy(s->d, &h, sizeof(SceneDev), hipMemcpyHostToDevice) != hipSuccess)

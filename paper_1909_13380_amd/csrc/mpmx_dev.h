@@ -25,6 +25,7 @@ namespace mpmx {
 constexpr int kBrick = 4;                 // cells per brick edge
 constexpr int kBrickCells = 64;           // cells per brick
 constexpr int kChunk = 512;               // max particles per work item
+constexpr int kXcds = 8;                  // accelerator dies (one L2 each) of the GPU
 constexpr int kBlock = 256;               // threads per workgroup of the sort and control kernels
 // Linear shape functions: per-thread register cache of the gathered support
 // nodes, and per-thread register sums of the scattered values, per kernel
@@ -35,7 +36,9 @@ constexpr bool kStressCacheScatter = false;
 constexpr bool kG2PCacheGather = true;
 constexpr bool kG2PCacheScatter = false;
 constexpr int kMaxCells[3] = {2047, 2047, 1023};   // packed-cell limits
-constexpr int64_t kMaxIndex = (int64_t)1 << 31;     // particle and node indices are 32-bit
+// particle and node indices are 32-bit, and so are the byte offsets into one
+// array component (8-byte elements at most)
+constexpr int64_t kMaxIndex = (int64_t)1 << 29;
 
 enum Ctl : int {
     CTL_CUR = 0,        // which particle buffer is current (0/1)
@@ -52,6 +55,7 @@ enum Ctl : int {
     CTL_ACC0 = 11,      // items whose tiles[b] cover node buffer b's data (b = 0, 1)
     CTL_ACC1 = 12,
     CTL_BOX_OK = 13,    // tiles[CTL_NBUF] holds this step's node box of every item
+    CTL_ALGO = 14,      // the scene's algorithm (0 USF, 1 USL), set at creation
     CTL_WORDS = 16
 };
 
@@ -134,6 +138,7 @@ enum BatchFlag : int {
 // A launch over several scenes: work is flattened over scenes in order.
 struct BatchDev {
     const SceneDev *const *scenes;  // device array of device pointers
+    uint32_t *const *ctls;          // each scene's control block (CTL_WORDS words)
     const int64_t *poffs;           // particle offsets [nscenes+1] (static)
     const int64_t *boffs;           // brick offsets [nscenes+1] (static)
     uint32_t *ioffs;                // this step's item offsets [nscenes+1]

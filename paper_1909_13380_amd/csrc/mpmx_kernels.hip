@@ -64,6 +64,28 @@ __device__ inline void gadd(GLOBAL T *p, T v)
     __hip_atomic_fetch_add((T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Element i of a global array as a scalar base plus a 32-bit byte offset
+// (every particle and node array component holds fewer than 2^32 bytes), so
+// the address needs no 64-bit vector arithmetic.
+template <typename T>
+__device__ inline T ldg(const GLOBAL T *b, uint32_t i)
+{
+    return *(const GLOBAL T *)((const GLOBAL char *)b + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ inline void stg(GLOBAL T *b, uint32_t i, T v)
+{
+    *(GLOBAL T *)((GLOBAL char *)b + i * (uint32_t)sizeof(T)) = v;
+}
+
+template <typename T>
+__device__ inline void addg(GLOBAL T *b, uint32_t i, T v)
+{
+    __hip_atomic_fetch_add((GLOBAL T *)((GLOBAL char *)b + i * (uint32_t)sizeof(T)), v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T>
 __device__ inline int find_scene(const T *offs, int nscenes, int64_t g)
 {
@@ -141,12 +163,15 @@ __device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3]
         const double d = x[a] - S.origin[a];
         const double q = d * S.inv_h;
         double t = floor(q);
-        const double eps = 1e-14 * fmax(fabs(q), 1.0);
-        if (!(q - t > eps && q - t < 1.0 - eps))
+        // the estimate is within 1e-12 of the quotient for |q| < 4096 (any
+        // larger q is outside the mesh either way)
+        const double f = q - t;
+        if (!(f > 1e-11 && f < 1.0 - 1e-11))
             t = floor(d / S.h);
-        if (!(t >= 0.0 && t < (double)S.n[a]))
+        const int ci = (int)t;
+        if ((unsigned)ci >= (unsigned)S.n[a])
             return ERR_OUT_OF_MESH;
-        c[a] = (int)t;
+        c[a] = ci;
     }
     return 0;
 }
@@ -207,20 +232,20 @@ __device__ inline NodeBuf<R> node_buf(const SceneDev &S, int b)
     return nb;
 }
 
-// Nodal velocity v = p / m (0 on void nodes) with velocity constraints.
+// Nodal velocity v = p / m (0 on void nodes) with velocity constraints, from
+// the node's mass and momentum.
 template <typename R>
-__device__ inline void node_velocity(const SceneDev &S, const NodeBuf<R> &nb, int i, int j, int k, R v[3])
+__device__ inline void velocity_from_raw(const SceneDev &S, double m, const R p[3], int i, int j, int k, R v[3])
 {
-    const uint32_t I = node_id(S, i, j, k);
-    const double m = nb.m[I];
     const double inv = m > S.eps_m ? 1.0 / m : 0.0;   // void node: v = 0
     for (int a = 0; a < 3; ++a)
-        v[a] = (R)((double)nb.p[a][I] * inv);
+        v[a] = (R)((double)p[a] * inv);
     const uint32_t fm = face_mask(S, i, j, k);
     for (int a = 0; a < 3; ++a)
         if (fm & (1u << a))
             v[a] = (R)0;
     if (S.bc_mask) {
+        const uint32_t I = node_id(S, i, j, k);
         const uint32_t em = gp(S.bc_mask)[I];
         for (int a = 0; a < 3; ++a)
             if (em & (1u << a))
@@ -228,21 +253,34 @@ __device__ inline void node_velocity(const SceneDev &S, const NodeBuf<R> &nb, in
     }
 }
 
-// Nodal acceleration a = f / m and updated velocity vn = v + dt a, with the
-// constraints applied to v (prescribed), a (zero) and vn (prescribed).
 template <typename R>
-__device__ inline void node_update(const SceneDev &S, const NodeBuf<R> &nb, int i, int j, int k, R a[3], R vn[3])
+__device__ inline void node_velocity(const SceneDev &S, const NodeBuf<R> &nb, int i, int j, int k, R v[3])
 {
     const uint32_t I = node_id(S, i, j, k);
-    const double m = nb.m[I];
+    const R p[3] = {ldg(nb.p[0], I), ldg(nb.p[1], I), ldg(nb.p[2], I)};
+    velocity_from_raw<R>(S, ldg(nb.m, I), p, i, j, k, v);
+}
+
+// Nodal acceleration a = f / m and updated velocity vn = v + dt a, with the
+// constraints applied to v (prescribed), a (zero) and vn (prescribed), from
+// the node's mass, momentum and force.
+template <typename R>
+__device__ inline void update_from_raw(const SceneDev &S, double m, const R p[3], const R f[3], int i, int j, int k,
+                                       R a[3], R vn[3])
+{
     const double inv = m > S.eps_m ? 1.0 / m : 0.0;   // void node: v = a = 0
     R v[3];
     for (int c = 0; c < 3; ++c) {
-        v[c] = (R)((double)nb.p[c][I] * inv);
-        a[c] = (R)((double)nb.f[c][I] * inv);
+        v[c] = (R)((double)p[c] * inv);
+        a[c] = (R)((double)f[c] * inv);
     }
     const uint32_t fm = face_mask(S, i, j, k);
-    const uint32_t em = S.bc_mask ? (uint32_t)gp(S.bc_mask)[I] : 0u;
+    uint32_t em = 0u;
+    uint32_t I = 0u;
+    if (S.bc_mask) {
+        I = node_id(S, i, j, k);
+        em = gp(S.bc_mask)[I];
+    }
     for (int c = 0; c < 3; ++c) {
         if (fm & (1u << c)) {
             v[c] = (R)0;
@@ -262,6 +300,15 @@ __device__ inline void node_update(const SceneDev &S, const NodeBuf<R> &nb, int 
         if (em & (1u << c))
             vn[c] = (R)gp(S.bc_val)[3 * (size_t)I + c];
     }
+}
+
+template <typename R>
+__device__ inline void node_update(const SceneDev &S, const NodeBuf<R> &nb, int i, int j, int k, R a[3], R vn[3])
+{
+    const uint32_t I = node_id(S, i, j, k);
+    const R p[3] = {ldg(nb.p[0], I), ldg(nb.p[1], I), ldg(nb.p[2], I)};
+    const R f[3] = {ldg(nb.f[0], I), ldg(nb.f[1], I), ldg(nb.f[2], I)};
+    update_from_raw<R>(S, ldg(nb.m, I), p, f, i, j, k, a, vn);
 }
 
 // ------------------------------------------------------ shape functions --
@@ -491,6 +538,24 @@ __device__ inline bool last_block(uint32_t *ticket, int *flag)
     return last;
 }
 
+// Item order of the persistent grids.  Workgroup w runs on XCD w % 8, and
+// each XCD has its own L2; the XCDs get contiguous ranges of the item list,
+// so bricks that share node rows (consecutive items) are processed under one
+// L2 rather than fetched into several.  A grid that is not a multiple of 8
+// strides over the whole list.
+struct ItemRange {
+    int64_t first, step, end;
+};
+
+__device__ inline ItemRange item_range(int64_t total)
+{
+    const int nx = (gridDim.x % kXcds == 0) ? kXcds : 1;
+    const int64_t per = gridDim.x / nx;
+    const int64_t chunk = (total + nx - 1) / nx;
+    const int64_t lo = (int64_t)(blockIdx.x % nx) * chunk;
+    return {lo + blockIdx.x / nx, per, min(total, lo + chunk)};
+}
+
 // Block-wide min/max of per-thread cell boxes (mn = +big, mx = -big for a
 // thread with nothing); result in red[0..2] (min), red[3..5] (max).
 __device__ inline void block_box(int mn[3], int mx[3], int *red)
@@ -596,6 +661,68 @@ __device__ inline Corners corners(const SceneDev &S, const Tile &t, const int ba
     return c;
 }
 
+// ------------------------------------------------------ tile helpers --
+
+// Corner n = i + 2j + 4k of a support at tile index t0 with strides ty, tz.
+__device__ inline int corner_off(int n, int ty, int tz)
+{
+    return (n & 1) + ((n >> 1) & 1) * ty + (n >> 2) * tz;
+}
+
+// Node (i, j, k) of entry q of a tile with at most 2^12 entries and edges of
+// at most 64 nodes: the quotients by a float reciprocal, exact in that range.
+__device__ inline void tile_node_small(const Tile &t, int q, int &i, int &j, int &k)
+{
+    const int dxy = t.dim[0] * t.dim[1];
+    const int kq = (int)(((float)q + 0.5f) * __builtin_amdgcn_rcpf((float)dxy));
+    const int r = q - kq * dxy;
+    const int jq = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)t.dim[0]));
+    i = t.lo[0] + r - jq * t.dim[0];
+    j = t.lo[1] + jq;
+    k = t.lo[2] + kq;
+}
+
+// Wave-wide min / max through DPP lane moves (every lane active); the result
+// is wave-uniform.
+template <bool MAX>
+__device__ inline int wave_reduce(int v)
+{
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));   // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Workgroup-wide cell box of the threads' mn/mx (every thread calls it);
+// red holds 6 words per wave.
+template <int T>
+__device__ inline void item_box(const int mn[3], const int mx[3], int *red, int lo[3], int hi[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_reduce<false>(mn[a]);
+        hi[a] = wave_reduce<true>(mx[a]);
+    }
+    if constexpr (T > 64) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+            for (int a = 0; a < 3; ++a) {
+                red[6 * w + a] = lo[a];
+                red[6 * w + 3 + a] = hi[a];
+            }
+        __syncthreads();
+        for (int v = 0; v < T / 64; ++v)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = min(lo[a], red[6 * v + a]);
+                hi[a] = max(hi[a], red[6 * v + 3 + a]);
+            }
+        __syncthreads();
+    }
+}
+
 // Zero node buffer `buf` over the given node box.
 template <typename R>
 __device__ inline void clear_box(const SceneDev &S, const NodeBuf<R> &nb, const Tile &t)
@@ -603,12 +730,15 @@ __device__ inline void clear_box(const SceneDev &S, const NodeBuf<R> &nb, const 
     const int vol = t.dim[0] * t.dim[1] * t.dim[2];
     for (int q = threadIdx.x; q < vol; q += blockDim.x) {
         int i, j, k;
-        tile_node(t, q, i, j, k);
+        if (t.fits)
+            tile_node_small(t, q, i, j, k);
+        else
+            tile_node(t, q, i, j, k);
         const uint32_t I = node_id(S, i, j, k);
-        nb.m[I] = 0.0;
+        stg(nb.m, I, 0.0);
         for (int a = 0; a < 3; ++a) {
-            nb.p[a][I] = (R)0;
-            nb.f[a][I] = (R)0;
+            stg(nb.p[a], I, (R)0);
+            stg(nb.f[a], I, (R)0);
         }
     }
 }
@@ -619,7 +749,8 @@ template <typename R>
 __device__ inline void clear_previous(const BatchDev &B)
 {
     const int64_t total = B.coffs[B.nscenes];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
         const ItemRef r = item_ref(B.coffs, B, g);
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
@@ -765,12 +896,16 @@ __global__ void k_begin(BatchDev B, const int64_t *nsteps)
 // Per-step control, run by one workgroup: apply a finished reorder, decide
 // which scenes take part in this step, pick their node buffers, and write the
 // offsets of this step's items (ioffs) and of the boxes to clear (coffs).
+// Each thread handles one scene through one read and one write of its
+// 64-byte control block (no other kernel runs meanwhile), so the work is a
+// short chain of memory round trips whatever the number of scenes.
 __device__ void step_control(const BatchDev &B)
 {
-    __shared__ uint32_t pi[kBlock], pc[kBlock];
-    __shared__ uint32_t ci, cc;
+    __shared__ uint32_t wi[kBlock / 64], wc[kBlock / 64];
+    __shared__ uint32_t carry[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) {
-        ci = cc = 0;
+        carry[0] = carry[1] = 0u;
         B.ioffs[0] = 0;
         B.coffs[0] = 0;
     }
@@ -779,59 +914,76 @@ __device__ void step_control(const BatchDev &B)
         const int s = base + threadIdx.x;
         uint32_t items = 0, clears = 0;
         if (s < B.nscenes) {
-            const SceneDev &S = *B.scenes[s];
-            uint32_t *ctl = S.ctl;
-            const bool go = ctl[CTL_ERR] == 0u && ctl[CTL_REMAIN] > 0u;
-            const bool sorted = go && ctl[CTL_NEED_SORT];
-            if (sorted) {
-                ctl[CTL_CUR] ^= 1u;
-                ctl[CTL_NEED_SORT] = 0u;
-                ctl[CTL_N_SORTS] += 1u;
+            uint4 *blk = (uint4 *)B.ctls[s];
+            uint32_t c[CTL_WORDS];
+            for (int q = 0; q < CTL_WORDS / 4; ++q) {
+                const uint4 w = blk[q];
+                c[4 * q] = w.x;
+                c[4 * q + 1] = w.y;
+                c[4 * q + 2] = w.z;
+                c[4 * q + 3] = w.w;
             }
-            ctl[CTL_ACTIVE] = go ? 1u : 0u;
+            const bool go = c[CTL_ERR] == 0u && c[CTL_REMAIN] > 0u;
+            const bool sorted = go && c[CTL_NEED_SORT];   // the sort kernels reordered it
+            if (sorted) {
+                c[CTL_CUR] ^= 1u;
+                c[CTL_NEED_SORT] = 0u;
+                c[CTL_N_SORTS] += 1u;
+            }
+            c[CTL_ACTIVE] = go ? 1u : 0u;
             if (go) {
-                ctl[CTL_REMAIN] -= 1u;
-                ctl[CTL_STEPS] += 1u;
-                if (S.algo == 0) {          // USF: the previous g2p_p2g filled the other buffer
-                    if (ctl[CTL_READY]) {
-                        ctl[CTL_NBUF] ^= 1u;
-                        ctl[CTL_READY] = 0u;
-                        ctl[CTL_HAVE_P2G] = 1u;
+                c[CTL_REMAIN] -= 1u;
+                c[CTL_STEPS] += 1u;
+                if (c[CTL_ALGO] == 0u) {        // USF: the previous g2p_p2g filled the other buffer
+                    if (c[CTL_READY]) {
+                        c[CTL_NBUF] ^= 1u;
+                        c[CTL_READY] = 0u;
+                        c[CTL_HAVE_P2G] = 1u;
                         // its boxes belong to the items it ran, valid unless
                         // this step reordered the particles
-                        ctl[CTL_BOX_OK] = sorted ? 0u : 1u;
+                        c[CTL_BOX_OK] = sorted ? 0u : 1u;
                     } else {
-                        ctl[CTL_HAVE_P2G] = 0u;
-                        ctl[CTL_BOX_OK] = 1u;   // p2g records them after the reorder
+                        c[CTL_HAVE_P2G] = 0u;
+                        c[CTL_BOX_OK] = 1u;   // p2g records them after the reorder
                     }
-                } else {                    // USL: p2g_usl fills a fresh buffer every step
-                    ctl[CTL_NBUF] ^= 1u;
-                    ctl[CTL_HAVE_P2G] = 0u;
-                    ctl[CTL_BOX_OK] = 0u;
+                } else {                        // USL: p2g_usl fills a fresh buffer every step
+                    c[CTL_NBUF] ^= 1u;
+                    c[CTL_HAVE_P2G] = 0u;
+                    c[CTL_BOX_OK] = 0u;
                 }
-                items = ctl[CTL_N_ITEMS];
-                clears = ctl[CTL_ACC0 + (ctl[CTL_NBUF] ^ 1u)];
+                items = c[CTL_N_ITEMS];
+                clears = c[CTL_NBUF] ? c[CTL_ACC0] : c[CTL_ACC1];   // boxes of the other buffer
+            }
+            for (int q = 0; q < CTL_WORDS / 4; ++q)
+                blk[q] = uint4{c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]};
+        }
+        // inclusive scan over the workgroup: waves, then wave totals
+        uint32_t si = items, sc = clears;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t ti = __shfl_up(si, o), tc = __shfl_up(sc, o);
+            if (lane >= o) {
+                si += ti;
+                sc += tc;
             }
         }
-        pi[threadIdx.x] = items;
-        pc[threadIdx.x] = clears;
+        if (lane == 63) {
+            wi[wave] = si;
+            wc[wave] = sc;
+        }
         __syncthreads();
-        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-            const uint32_t a = threadIdx.x >= (unsigned)o ? pi[threadIdx.x - o] : 0u;
-            const uint32_t c = threadIdx.x >= (unsigned)o ? pc[threadIdx.x - o] : 0u;
-            __syncthreads();
-            pi[threadIdx.x] += a;
-            pc[threadIdx.x] += c;
-            __syncthreads();
+        uint32_t pi = carry[0], pc = carry[1];
+        for (int v = 0; v < wave; ++v) {
+            pi += wi[v];
+            pc += wc[v];
         }
         if (s < B.nscenes) {
-            B.ioffs[s + 1] = ci + pi[threadIdx.x];
-            B.coffs[s + 1] = cc + pc[threadIdx.x];
+            B.ioffs[s + 1] = pi + si;
+            B.coffs[s + 1] = pc + sc;
         }
         __syncthreads();
         if (threadIdx.x == blockDim.x - 1) {
-            ci += pi[threadIdx.x];
-            cc += pc[threadIdx.x];
+            carry[0] = pi + si;
+            carry[1] = pc + sc;
         }
         __syncthreads();
     }
@@ -1080,9 +1232,10 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
     constexpr int CAP = ShapeTraits<SH>::cap;
     constexpr int NACC = WITH_FORCE ? 7 : 4;
     __shared__ double acc[NACC][CAP];
-    __shared__ int red[6];
+    __shared__ int red[6 * (T / 64)];
     const int64_t total = B.ioffs[B.nscenes];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
         const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S) || (!WITH_FORCE && S.ctl[CTL_HAVE_P2G]))
@@ -1092,7 +1245,21 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
         const int buf = (int)uni(S.ctl[CTL_NBUF]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
-        const Tile t = item_tile<SH>(item, P.cell, red);
+        Tile t;
+        {
+            int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+            for (uint32_t q = threadIdx.x; q < item.count; q += T) {
+                int c[3];
+                unpack_cell(ldg(P.cell, item.start + q), c);
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = min(mn[a], c[a]);
+                    mx[a] = max(mx[a], c[a]);
+                }
+            }
+            int lo[3], hi[3];
+            item_box<T>(mn, mx, red, lo, hi);
+            t = tile_of_cells<SH>(lo, hi);
+        }
         if (threadIdx.x == 0) {
             pick(S.tiles, buf)[r.it] = t;
             if (r.it == 0)
@@ -1111,19 +1278,19 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
         const R gx = (R)S.g[0], gy = (R)S.g[1], gz = (R)S.g[2];
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
-            const double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
+            const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
             int c[3];
-            unpack_cell(P.cell[p], c);
+            unpack_cell(ldg(P.cell, p), c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
             const Corners cn = corners(S, t, sp.base);
-            const R mp = P.mass[p];
-            const R mv[3] = {mp * P.v[0][p], mp * P.v[1][p], mp * P.v[2][p]};
+            const R mp = ldg(P.mass, p);
+            const R mv[3] = {mp * ldg(P.v[0], p), mp * ldg(P.v[1], p), mp * ldg(P.v[2], p)};
             R sg[6], vol = (R)0;
             if constexpr (WITH_FORCE) {
                 for (int k = 0; k < 6; ++k)
-                    sg[k] = P.sig[k][p];
-                vol = P.vol[p];
+                    sg[k] = ldg(P.sig[k], p);
+                vol = ldg(P.vol, p);
             }
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
@@ -1154,14 +1321,14 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
             if (m == 0.0)
                 continue;
             int i, j, k;
-            tile_node(t, q, i, j, k);
+            tile_node_small(t, q, i, j, k);
             const uint32_t I = node_id(S, i, j, k);
-            gadd(nb.m + I, m);
+            addg(nb.m, I, m);
             for (int a = 0; a < 3; ++a)
-                gadd(nb.p[a] + I, (R)acc[1 + a][q]);
+                addg(nb.p[a], I, (R)acc[1 + a][q]);
             if constexpr (WITH_FORCE)
                 for (int a = 0; a < 3; ++a)
-                    gadd(nb.f[a] + I, (R)acc[4 + a][q]);
+                    addg(nb.f[a], I, (R)acc[4 + a][q]);
         }
         __syncthreads();
     }
@@ -1201,10 +1368,11 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
     constexpr int GN = C::gnodes, SN = C::snodes;
     __shared__ R4<R> lv[CAP];
     __shared__ double lf[3][CAP];
-    __shared__ int red[6];
+    __shared__ int red[6 * (T / 64)];
     clear_previous<R>(B);
     const int64_t total = B.ioffs[B.nscenes];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
         const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
@@ -1221,7 +1389,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             const uint32_t q = threadIdx.x + rr * T;
             if (q >= item.count)
                 continue;
-            pcell[rr] = P.cell[item.start + q];
+            pcell[rr] = ldg(P.cell, item.start + q);
             int c[3];
             unpack_cell(pcell[rr], c);
             for (int a = 0; a < 3; ++a) {
@@ -1235,8 +1403,8 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
         if (uni(S.ctl[CTL_BOX_OK])) {
             t = uni_struct(pick(S.tiles, buf)[r.it]);
         } else {
-            block_box(mn, mx, red);
-            const int blo[3] = {red[0], red[1], red[2]}, bhi[3] = {red[3], red[4], red[5]};
+            int blo[3], bhi[3];
+            item_box<T>(mn, mx, red, blo, bhi);
             t = tile_of_cells<SH>(blo, bhi);
         }
         if (threadIdx.x == 0)
@@ -1250,7 +1418,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
         for (int q = threadIdx.x; q < tv; q += blockDim.x) {
             int i, j, k;
-            tile_node(t, q, i, j, k);
+            tile_node_small(t, q, i, j, k);
             R v[3];
             node_velocity<R>(S, nb, i, j, k, v);
             lv[q] = R4<R>{v[0], v[1], v[2], (R)0};
@@ -1277,7 +1445,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             if (q >= item.count)
                 break;
             const uint32_t p = item.start + q;
-            const double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
+            const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
             int c[3];
             unpack_cell(pcell[rr], c);
             Support<R, SH> sp;
@@ -1376,18 +1544,18 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-            const R vol = P.vol[p] * ((R)1 + de[0] + de[1] + de[2]);
+            const R vol = ldg(P.vol, p) * ((R)1 + de[0] + de[1] + de[2]);
             R sg[6];
             for (int k = 0; k < 6; ++k)
-                sg[k] = P.sig[k][p];
+                sg[k] = ldg(P.sig[k], p);
             constitutive<R>(S, de, sg);
             for (int k = 0; k < 6; ++k) {
-                P.sig[k][p] = sg[k];
+                stg(P.sig[k], p, sg[k]);
                 if (!isfinite(sg[k]))
                     bad = ERR_NONFINITE;
             }
-            P.vol[p] = vol;
-            const R mp = P.mass[p];
+            stg(P.vol, p, vol);
+            const R mp = ldg(P.mass, p);
             auto deposit = [&](int i, int j, int k, R f0, R f1, R f2) {
                 if constexpr (SC) {
                     const int n = i + 2 * j + 4 * k;
@@ -1444,11 +1612,11 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             if (f0 == (R)0 && f1 == (R)0 && f2 == (R)0)
                 continue;
             int i, j, k;
-            tile_node(t, q, i, j, k);
+            tile_node_small(t, q, i, j, k);
             const uint32_t I = node_id(S, i, j, k);
-            gadd(nb.f[0] + I, f0);
-            gadd(nb.f[1] + I, f1);
-            gadd(nb.f[2] + I, f2);
+            addg(nb.f[0], I, f0);
+            addg(nb.f[1], I, f1);
+            addg(nb.f[2], I, f2);
         }
         __syncthreads();
     }
@@ -1462,7 +1630,7 @@ __device__ inline void load_update_tile(const SceneDev &S, const NodeBuf<R> &nb,
     const int tv = t.dim[0] * t.dim[1] * t.dim[2];
     for (int q = threadIdx.x; q < tv; q += blockDim.x) {
         int i, j, k;
-        tile_node(t, q, i, j, k);
+        tile_node_small(t, q, i, j, k);
         R a[3], vn[3];
         node_update<R>(S, nb, i, j, k, a, vn);
         la[q] = R4<R>{a[0], a[1], a[2], (R)0};
@@ -1487,9 +1655,10 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
     __shared__ R4<R> la[CAP];
     __shared__ R4<R> lvn[CAP];
     __shared__ double acc[4][CAP];
-    __shared__ int red[6];
+    __shared__ int red[6 * (T / 64)];
     const int64_t total = B.ioffs[B.nscenes];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
         const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
@@ -1529,9 +1698,9 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                         atomicAdd(&acc[1 + a][li], (double)sp_[n][a]);
                 } else {
                     const uint32_t I = sc.n0 + (uint32_t)(di + dj * sc.ny + dk * sc.nz);
-                    gadd(nn.m + I, (double)sm[n]);
+                    addg(nn.m, I, (double)sm[n]);
                     for (int a = 0; a < 3; ++a)
-                        gadd(nn.p[a] + I, sp_[n][a]);
+                        addg(nn.p[a], I, sp_[n][a]);
                 }
             }
         };
@@ -1541,11 +1710,11 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             if (q >= item.count)
                 break;
             const uint32_t p = item.start + q;
-            double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
-            const R pv[3] = {P.v[0][p], P.v[1][p], P.v[2][p]};
-            const R mp = P.mass[p];
+            double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            const R pv[3] = {ldg(P.v[0], p), ldg(P.v[1], p), ldg(P.v[2], p)};
+            const R mp = ldg(P.mass, p);
             int c[3];
-            unpack_cell(P.cell[p], c);
+            unpack_cell(ldg(P.cell, p), c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
             const Corners cn = corners(S, t, sp.base);
@@ -1595,9 +1764,9 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             R nv[3];
             for (int a = 0; a < 3; ++a) {
                 nv[a] = pic ? vp[a] : pv[a] + dt * dv[a];
-                P.v[a][p] = nv[a];
+                stg(P.v[a], p, nv[a]);
                 xp[a] += S.dt * (double)vp[a];
-                P.x[a][p] = xp[a];
+                stg(P.x[a], p, xp[a]);
                 if (!isfinite(nv[a]))
                     err |= ERR_NONFINITE;
             }
@@ -1607,7 +1776,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 err |= e;   // keep the old cell; the scene stops after this step
                 continue;
             }
-            P.cell[p] = pack_cell(nc);
+            stg(P.cell, p, pack_cell(nc));
             for (int a = 0; a < 3; ++a) {
                 mn[a] = min(mn[a], nc[a]);
                 mx[a] = max(mx[a], nc[a]);
@@ -1649,9 +1818,9 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                             atomicAdd(&acc[3][li], (double)(N * mv[2]));
                         } else {
                             const uint32_t I = hn.n0 + (uint32_t)(i + j * hn.ny + k * hn.nz);
-                            gadd(nn.m + I, (double)(N * mp));
+                            addg(nn.m, I, (double)(N * mp));
                             for (int a = 0; a < 3; ++a)
-                                gadd(nn.p[a] + I, N * mv[a]);
+                                addg(nn.p[a], I, N * mv[a]);
                         }
                     }
         }
@@ -1664,8 +1833,8 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             S.ctl[CTL_NEED_SORT] = 1u;
             B.flags[BF_ANY_SORT] = 1u;
         }
-        block_box(mn, mx, red);
-        const int blo[3] = {red[0], red[1], red[2]}, bhi[3] = {red[3], red[4], red[5]};
+        int blo[3], bhi[3];
+        item_box<T>(mn, mx, red, blo, bhi);
         if (threadIdx.x == 0) {
             pick(S.tiles, nbuf)[r.it] = tile_of_cells<SH>(blo, bhi);
             if (r.it == 0) {
@@ -1673,16 +1842,18 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 S.ctl[CTL_READY] = 1u;
             }
         }
+        constexpr int HD = kBrick + 2 + ShapeTraits<SH>::lo + ShapeTraits<SH>::hi;   // home tile edge
         for (int q = threadIdx.x; q < CAP; q += blockDim.x) {
             const double m = acc[0][q];
-            int i, j, k;
-            tile_node(ht, q, i, j, k);
-            if (m == 0.0 || !node_in_mesh(S, i, j, k))
+            if (m == 0.0)
+                continue;
+            const int i = ht.lo[0] + q % HD, j = ht.lo[1] + (q / HD) % HD, k = ht.lo[2] + q / (HD * HD);
+            if (!node_in_mesh(S, i, j, k))
                 continue;
             const uint32_t I = node_id(S, i, j, k);
-            gadd(nn.m + I, m);
+            addg(nn.m, I, m);
             for (int a = 0; a < 3; ++a)
-                gadd(nn.p[a] + I, (R)acc[1 + a][q]);
+                addg(nn.p[a], I, (R)acc[1 + a][q]);
         }
         __syncthreads();
     }
@@ -1700,7 +1871,8 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
     __shared__ R4<R> lvn[CAP];
     clear_previous<R>(B);
     const int64_t total = B.ioffs[B.nscenes];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
         const ItemRef r = item_ref(B.ioffs, B, g);
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
