@@ -926,11 +926,14 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     const int64_t np = parts->n;
     if (np > 0 && (!parts->x || !parts->v || !parts->vol || !parts->mass))
         return fail(ctx, MPMX_E_INVALID_ARG, "particles: x, v, vol and mass are required");
-    if (np >= kMaxIndex)
-        return fail(ctx, MPMX_E_INVALID_ARG, "particles: at most 2^29 - 1 per scene");
     const Sizes sz = sizes_of(mesh, sch->shape, sch->precision, np);
-    if (sz.nkeys >= (int64_t)1 << 32 || sz.nn >= kMaxIndex)
-        return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys and node indices");
+    // the kernels address one field (all its components) with 32-bit byte offsets
+    const int64_t rb = (int64_t)sz.real;
+    if (np * std::max<int64_t>(24, 6 * rb) >= (int64_t)1 << 32)
+        return fail(ctx, MPMX_E_INVALID_ARG, "particles: at most %lld per scene at this precision",
+                    (long long)((((int64_t)1 << 32) - 1) / std::max<int64_t>(24, 6 * rb)));
+    if (sz.nkeys >= (int64_t)1 << 32 || sz.nn * std::max<int64_t>(8, 3 * rb) >= (int64_t)1 << 32)
+        return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys and node offsets");
     const bool extra = bc->n_extra > 0;
     for (int64_t e = 0; e < bc->n_extra; ++e)
         if (bc->node[e] < 0 || bc->node[e] >= sz.nn || bc->axis[e] < 0 || bc->axis[e] > 2 ||

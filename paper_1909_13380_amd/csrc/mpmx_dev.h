@@ -36,9 +36,6 @@ constexpr bool kStressCacheScatter = false;
 constexpr bool kG2PCacheGather = true;
 constexpr bool kG2PCacheScatter = false;
 constexpr int kMaxCells[3] = {2047, 2047, 1023};   // packed-cell limits
-// particle and node indices are 32-bit, and so are the byte offsets into one
-// array component (8-byte elements at most)
-constexpr int64_t kMaxIndex = (int64_t)1 << 29;
 
 enum Ctl : int {
     CTL_CUR = 0,        // which particle buffer is current (0/1)

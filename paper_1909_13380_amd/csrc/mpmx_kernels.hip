@@ -86,6 +86,33 @@ __device__ inline void addg(GLOBAL T *b, uint32_t i, T v)
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One component of a structure-of-arrays field: the field's base and the
+// component's first element.  All components share one scalar base, and an
+// element's byte offset stays below 2^32 (the runtime bounds every field).
+template <typename T>
+struct Comp {
+    GLOBAL T *base;
+    uint32_t off;
+};
+
+template <typename T>
+__device__ inline T ldg(const Comp<T> &c, uint32_t i)
+{
+    return ldg(c.base, c.off + i);
+}
+
+template <typename T>
+__device__ inline void stg(const Comp<T> &c, uint32_t i, T v)
+{
+    stg(c.base, c.off + i, v);
+}
+
+template <typename T>
+__device__ inline void addg(const Comp<T> &c, uint32_t i, T v)
+{
+    addg(c.base, c.off + i, v);
+}
+
 template <typename T>
 __device__ inline int find_scene(const T *offs, int nscenes, int64_t g)
 {
@@ -214,8 +241,8 @@ struct alignas(4 * sizeof(R)) R4 {
 template <typename R>
 struct NodeBuf {
     GLOBAL double *m;
-    GLOBAL R *p[3];
-    GLOBAL R *f[3];
+    Comp<R> p[3];
+    Comp<R> f[3];
 };
 
 template <typename R>
@@ -226,8 +253,8 @@ __device__ inline NodeBuf<R> node_buf(const SceneDev &S, int b)
     GLOBAL R *P = gp((R *)pick(S.np_, b));
     GLOBAL R *F = gp((R *)pick(S.nf, b));
     for (int a = 0; a < 3; ++a) {
-        nb.p[a] = P + (size_t)a * (size_t)S.nn;
-        nb.f[a] = F + (size_t)a * (size_t)S.nn;
+        nb.p[a] = Comp<R>{P, (uint32_t)(a * S.nn)};
+        nb.f[a] = Comp<R>{F, (uint32_t)(a * S.nn)};
     }
     return nb;
 }
@@ -1194,12 +1221,12 @@ __global__ void __launch_bounds__(kBlock) k_sort_move(BatchDev B)
 // of doubles is far cheaper than one of floats on gfx950) and are flushed
 // with one global atomic per touched node and component.
 
-// Particle arrays of one buffer, as global-memory pointers.
+// Particle arrays of one buffer: one scalar base per field.
 template <typename R>
 struct Parts {
-    GLOBAL double *x[3];
-    GLOBAL R *v[3];
-    GLOBAL R *sig[6];
+    Comp<double> x[3];
+    Comp<R> v[3];
+    Comp<R> sig[6];
     GLOBAL R *vol;
     GLOBAL R *mass;
     GLOBAL uint32_t *cell;
@@ -1209,13 +1236,13 @@ template <typename R>
 __device__ inline Parts<R> parts(const SceneDev &S, int cur)
 {
     Parts<R> P;
-    const size_t n = (size_t)S.np;
+    const uint32_t n = (uint32_t)S.np;
     for (int a = 0; a < 3; ++a) {
-        P.x[a] = gp(pick(S.x, cur)) + a * n;
-        P.v[a] = gp((R *)pick(S.v, cur)) + a * n;
+        P.x[a] = Comp<double>{gp(pick(S.x, cur)), a * n};
+        P.v[a] = Comp<R>{gp((R *)pick(S.v, cur)), a * n};
     }
     for (int k = 0; k < 6; ++k)
-        P.sig[k] = gp((R *)pick(S.sig, cur)) + k * n;
+        P.sig[k] = Comp<R>{gp((R *)pick(S.sig, cur)), k * n};
     P.vol = gp((R *)pick(S.vol, cur));
     P.mass = gp((R *)pick(S.mass, cur));
     P.cell = gp(pick(S.cell, cur));
@@ -1894,9 +1921,9 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
         uint32_t err = 0, drift = 0;
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
-            double xp[3] = {P.x[0][p], P.x[1][p], P.x[2][p]};
+            double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
             int c[3];
-            unpack_cell(P.cell[p], c);
+            unpack_cell(ldg(P.cell, p), c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
             const Corners cn = corners(S, t, sp.base);
@@ -1930,22 +1957,22 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
                         L[2][2] += u.z * gzN;
                     }
             for (int a = 0; a < 3; ++a) {
-                const R nva = pic ? vp[a] : P.v[a][p] + dt * dv[a];
-                P.v[a][p] = nva;
+                const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
+                stg(P.v[a], p, nva);
                 xp[a] += S.dt * (double)vp[a];
-                P.x[a][p] = xp[a];
+                stg(P.x[a], p, xp[a]);
                 if (!isfinite(nva))
                     err |= ERR_NONFINITE;
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-            P.vol[p] = P.vol[p] * ((R)1 + de[0] + de[1] + de[2]);
+            stg(P.vol, p, ldg(P.vol, p) * ((R)1 + de[0] + de[1] + de[2]));
             R sg[6];
             for (int k = 0; k < 6; ++k)
-                sg[k] = P.sig[k][p];
+                sg[k] = ldg(P.sig[k], p);
             constitutive<R>(S, de, sg);
             for (int k = 0; k < 6; ++k) {
-                P.sig[k][p] = sg[k];
+                stg(P.sig[k], p, sg[k]);
                 if (!isfinite(sg[k]))
                     err |= ERR_NONFINITE;
             }
@@ -1955,7 +1982,7 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
                 err |= e;
                 continue;
             }
-            P.cell[p] = pack_cell(nc);
+            stg(P.cell, p, pack_cell(nc));
             drift |= in_home(nc, o) ? 0u : 1u;
         }
         if (err)
