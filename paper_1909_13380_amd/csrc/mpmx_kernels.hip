@@ -184,23 +184,28 @@ __device__ inline void brick_origin(const SceneDev &S, uint32_t b, int o[3])
 // Returns 0, ERR_OUT_OF_MESH or ERR_NONFINITE.
 __device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3])
 {
+    if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2]))
+        return ERR_NONFINITE;
+    double d[3], t[3];
+    bool near = false;
     for (int a = 0; a < 3; ++a) {
-        if (!isfinite(x[a]))
-            return ERR_NONFINITE;
-        const double d = x[a] - S.origin[a];
-        const double q = d * S.inv_h;
-        double t = floor(q);
+        d[a] = x[a] - S.origin[a];
+        const double q = d[a] * S.inv_h;
+        t[a] = floor(q);
         // the estimate is within 1e-12 of the quotient for |q| < 4096 (any
         // larger q is outside the mesh either way)
-        const double f = q - t;
-        if (!(f > 1e-11 && f < 1.0 - 1e-11))
-            t = floor(d / S.h);
-        const int ci = (int)t;
-        if ((unsigned)ci >= (unsigned)S.n[a])
-            return ERR_OUT_OF_MESH;
-        c[a] = ci;
+        const double f = q - t[a];
+        near = near || !(f > 1e-11 && f < 1.0 - 1e-11);
     }
-    return 0;
+    if (near)
+        for (int a = 0; a < 3; ++a)
+            t[a] = floor(d[a] / S.h);
+    uint32_t out = 0;
+    for (int a = 0; a < 3; ++a) {
+        c[a] = (int)t[a];
+        out |= (unsigned)c[a] >= (unsigned)S.n[a] ? 1u : 0u;
+    }
+    return out ? ERR_OUT_OF_MESH : 0u;
 }
 
 // Node index (32-bit: the runtime bounds every scene below 2^31 nodes).
@@ -1828,28 +1833,38 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                     }
                 }
             }
-            for (int k = 0; k < NS; ++k)
-                for (int j = 0; j < NS; ++j)
-                    for (int i = 0; i < NS; ++i) {
-                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
-                        if constexpr (SC) {
+            if constexpr (SC) {
+                for (int k = 0; k < NS; ++k)
+                    for (int j = 0; j < NS; ++j)
+                        for (int i = 0; i < NS; ++i) {
+                            const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
                             const int n = i + 2 * j + 4 * k;
                             sm[n] += N * mp;
                             for (int a = 0; a < 3; ++a)
                                 sp_[n][a] += N * mv[a];
-                        } else if (in) {
+                        }
+            } else if (in) {
+                for (int k = 0; k < NS; ++k)
+                    for (int j = 0; j < NS; ++j)
+                        for (int i = 0; i < NS; ++i) {
+                            const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
                             const int li = hn.t0 + i + j * hn.ty + k * hn.tz;
                             atomicAdd(&acc[0][li], (double)(N * mp));
                             atomicAdd(&acc[1][li], (double)(N * mv[0]));
                             atomicAdd(&acc[2][li], (double)(N * mv[1]));
                             atomicAdd(&acc[3][li], (double)(N * mv[2]));
-                        } else {
+                        }
+            } else {
+                for (int k = 0; k < NS; ++k)
+                    for (int j = 0; j < NS; ++j)
+                        for (int i = 0; i < NS; ++i) {
+                            const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
                             const uint32_t I = hn.n0 + (uint32_t)(i + j * hn.ny + k * hn.nz);
                             addg(nn.m, I, (double)(N * mp));
                             for (int a = 0; a < 3; ++a)
                                 addg(nn.p[a], I, N * mv[a]);
                         }
-                    }
+            }
         }
         if constexpr (SC)
             if (sb[0] != -(1 << 30))
