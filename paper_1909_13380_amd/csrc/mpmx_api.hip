@@ -1107,6 +1107,18 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
             mean += m[p];
         h.eps_m = sch->mass_eps_rel * (mean / (double)np);
     }
+    h.f_dt = (float)h.dt;
+    h.f_inv_h = (float)h.inv_h;
+    for (int e = 0; e < 3; ++e)
+        h.f_g[e] = (float)h.g[e];
+    h.f_lam = (float)h.lam;
+    h.f_G = (float)h.G;
+    h.f_K = (float)h.K;
+    h.f_eta = (float)h.eta;
+    h.f_xic = (float)h.xic;
+    h.f_etab = (float)h.etab;
+    h.f_apex = (float)h.apex_p;
+    h.f_inv_hard = (float)h.inv_hard;
     uint32_t ctl[CTL_WORDS] = {0};
     ctl[CTL_NEED_SORT] = 1;
     ctl[CTL_ALGO] = (uint32_t)h.algo;

@@ -123,6 +123,9 @@ struct SceneDev {
     Tile *tiles[2];  // per node buffer: boxes its data was accumulated over
     Tile *tstep;     // per item: node box of its particles in the current step
     uint32_t *ctl;
+    // FP32 copies of the constants above, rounded once on the host
+    float f_dt, f_inv_h, f_g[3];
+    float f_lam, f_G, f_K, f_eta, f_xic, f_etab, f_apex, f_inv_hard;
 };
 
 enum BatchFlag : int {

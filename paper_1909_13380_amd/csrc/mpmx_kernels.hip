@@ -177,6 +177,17 @@ __device__ inline void brick_origin(const SceneDev &S, uint32_t b, int o[3])
     o[2] = (int)(b / ((uint32_t)S.nb[0] * (uint32_t)S.nb[1])) * kBrick;
 }
 
+// A per-scene constant in the state precision: the FP32 copy the host
+// rounded once, or the FP64 value.
+template <typename R>
+__device__ inline R cst(double d, float f)
+{
+    if constexpr (sizeof(R) == 4)
+        return f;
+    else
+        return (R)d;
+}
+
 // Cell of a position: floor((x - o) / h) with the IEEE FP64 quotient per
 // axis.  The quotient is first estimated as (x - o) * (1/h), within a few ulp
 // of it; only when the estimate lies that close to an integer (a cell face)
@@ -323,7 +334,7 @@ __device__ inline void update_from_raw(const SceneDev &S, double m, const R p[3]
             a[c] = (R)0;
         }
     }
-    const R dt = (R)S.dt;
+    const R dt = cst<R>(S.dt, S.f_dt);
     for (int c = 0; c < 3; ++c)
         vn[c] = v[c] + dt * a[c];
     for (int c = 0; c < 3; ++c) {
@@ -400,7 +411,7 @@ template <typename R, int SH>
 __device__ inline void make_support(const SceneDev &S, const double x[3], const int c[3], Support<R, SH> &sp)
 {
     const double h = S.h, ih = S.inv_h;
-    const R inv_h = (R)ih;
+    const R inv_h = cst<R>(S.inv_h, S.f_inv_h);
     if constexpr (SH == 0) {
         for (int a = 0; a < 3; ++a) {
             const R r = (R)((x[a] - (S.origin[a] + h * (double)c[a])) * ih);
@@ -433,7 +444,7 @@ __device__ inline void make_support(const SceneDev &S, const double x[3], const 
 template <typename R>
 __device__ inline void constitutive(const SceneDev &S, const R de[6], R sig[6])
 {
-    const R lam = (R)S.lam, G = (R)S.G;
+    const R lam = cst<R>(S.lam, S.f_lam), G = cst<R>(S.G, S.f_G);
     const R tr = de[0] + de[1] + de[2];
     for (int a = 0; a < 3; ++a)
         sig[a] += lam * tr + (R)2 * G * de[a];
@@ -442,7 +453,7 @@ __device__ inline void constitutive(const SceneDev &S, const R de[6], R sig[6])
     if (S.model != 1)
         return;
     // Drucker-Prager, perfectly plastic: f = sqrt(J2) + eta p - xi c.
-    const R K = (R)S.K, eta = (R)S.eta, etab = (R)S.etab;
+    const R K = cst<R>(S.K, S.f_K), eta = cst<R>(S.eta, S.f_eta), etab = cst<R>(S.etab, S.f_etab);
     constexpr bool F32 = sizeof(R) == 4;
     const R p = F32 ? (sig[0] + sig[1] + sig[2]) * (R)(1.0 / 3.0) : (sig[0] + sig[1] + sig[2]) / (R)3;
     R s[6];
@@ -458,10 +469,10 @@ __device__ inline void constitutive(const SceneDev &S, const R de[6], R sig[6])
         q = __builtin_amdgcn_sqrtf(J2);
     else
         q = sqrt(J2);
-    const R f = q + eta * p - (R)S.xic;
+    const R f = q + eta * p - cst<R>(S.xic, S.f_xic);
     if (!(f > (R)0))
         return;
-    const R dgam = F32 ? f * (R)S.inv_hard : f / (G + K * eta * etab);
+    const R dgam = F32 ? f * cst<R>(S.inv_hard, S.f_inv_hard) : f / (G + K * eta * etab);
     if (q - G * dgam >= (R)0) {
         R scale;
         if constexpr (F32)
@@ -474,7 +485,7 @@ __device__ inline void constitutive(const SceneDev &S, const R de[6], R sig[6])
         for (int a = 3; a < 6; ++a)
             sig[a] = scale * s[a];
     } else {
-        const R pa = S.has_apex ? (R)S.apex_p : p;
+        const R pa = S.has_apex ? cst<R>(S.apex_p, S.f_apex) : p;
         for (int a = 0; a < 3; ++a)
             sig[a] = pa;
         for (int a = 3; a < 6; ++a)
@@ -1307,7 +1318,7 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
             for (int c = 0; c < NACC; ++c)
                 acc[c][q] = 0.0;
         __syncthreads();
-        const R gx = (R)S.g[0], gy = (R)S.g[1], gz = (R)S.g[2];
+        const R gx = cst<R>(S.g[0], S.f_g[0]), gy = cst<R>(S.g[1], S.f_g[1]), gz = cst<R>(S.g[2], S.f_g[2]);
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
             const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
@@ -1457,8 +1468,8 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             lf[0][q] = lf[1][q] = lf[2][q] = 0.0;
         }
         __syncthreads();
-        const R dt = (R)S.dt;
-        const R gx = (R)S.g[0], gy = (R)S.g[1], gz = (R)S.g[2];
+        const R dt = cst<R>(S.dt, S.f_dt);
+        const R gx = cst<R>(S.g[0], S.f_g[0]), gy = cst<R>(S.g[1], S.f_g[1]), gz = cst<R>(S.g[2], S.f_g[2]);
         uint32_t bad = 0;
         int kb[3] = {-(1 << 30), 0, 0};   // support base held in the gather cache
         int fb[3] = {-(1 << 30), 0, 0};   // support base of the force accumulators
@@ -1531,7 +1542,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                         v8[n][2] = w.z;
                     }
                 }
-                const R ih = (R)S.inv_h;
+                const R ih = cst<R>(S.inv_h, S.f_inv_h);
                 for (int e = 0; e < 3; ++e) {
                     R gx = 0, gy = 0, gz = 0;
                     for (int u = 0; u < 2; ++u)
@@ -1604,7 +1615,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             if constexpr (SH == 0) {
                 // f_I = -V sigma . grad N_I + N_I m g with grad N_I = (1/h) (sx Pyz,
                 // sy Pxz, sz Pxy), s = -1 for the lower node of an axis
-                const R c = -vol * (R)S.inv_h;
+                const R c = -vol * cst<R>(S.inv_h, S.f_inv_h);
                 const R A[6] = {c * sg[0], c * sg[1], c * sg[2], c * sg[3], c * sg[4], c * sg[5]};
                 const R mg0 = mp * gx, mg1 = mp * gy, mg2 = mp * gz;
                 for (int k = 0; k < 2; ++k)
@@ -1711,7 +1722,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         for (int q = threadIdx.x; q < CAP; q += blockDim.x)
             acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
         __syncthreads();
-        const R dt = (R)S.dt;
+        const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
         uint32_t err = 0, drift = 0;
         int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
@@ -1931,7 +1942,7 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
         brick_origin(S, item.brick, o);
         load_update_tile<R>(S, nb, t, la, lvn);
         __syncthreads();
-        const R dt = (R)S.dt;
+        const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
         uint32_t err = 0, drift = 0;
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
