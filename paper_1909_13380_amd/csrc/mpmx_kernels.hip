@@ -193,11 +193,14 @@ __device__ inline R cst(double d, float f)
 // of it; only when the estimate lies that close to an integer (a cell face)
 // is the division done, so the cell equals the one the exact quotient gives.
 // Returns 0, ERR_OUT_OF_MESH or ERR_NONFINITE.
-__device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3])
+// With FRAC, also the position's local coordinate in its cell, (x - X_c)/h,
+// as the estimate's fractional part (recomputed from X_c near a face).
+template <bool FRAC = false>
+__device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3], double *frac = nullptr)
 {
     if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2]))
         return ERR_NONFINITE;
-    double d[3], t[3];
+    double d[3], t[3], f[3];
     bool near = false;
     for (int a = 0; a < 3; ++a) {
         d[a] = x[a] - S.origin[a];
@@ -205,16 +208,21 @@ __device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3]
         t[a] = floor(q);
         // the estimate is within 1e-12 of the quotient for |q| < 4096 (any
         // larger q is outside the mesh either way)
-        const double f = q - t[a];
-        near = near || !(f > 1e-11 && f < 1.0 - 1e-11);
+        f[a] = q - t[a];
+        near = near || !(f[a] > 1e-11 && f[a] < 1.0 - 1e-11);
     }
     if (near)
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
             t[a] = floor(d[a] / S.h);
+            if constexpr (FRAC)
+                f[a] = (x[a] - (S.origin[a] + S.h * t[a])) * S.inv_h;
+        }
     uint32_t out = 0;
     for (int a = 0; a < 3; ++a) {
         c[a] = (int)t[a];
         out |= (unsigned)c[a] >= (unsigned)S.n[a] ? 1u : 0u;
+        if constexpr (FRAC)
+            frac[a] = f[a];
     }
     return out ? ERR_OUT_OF_MESH : 0u;
 }
@@ -1814,7 +1822,8 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                     err |= ERR_NONFINITE;
             }
             int nc[3];
-            const uint32_t e = locate(S, xp, nc);
+            double fr[3];
+            const uint32_t e = locate<SH == 0>(S, xp, nc, fr);
             if (e) {
                 err |= e;   // keep the old cell; the scene stops after this step
                 continue;
@@ -1826,8 +1835,21 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             }
             const bool in = in_home(nc, o);
             drift |= in ? 0u : 1u;
-            // the next step's P2G from the updated particle
-            make_support<R, SH>(S, xp, nc, sp);
+            // the next step's P2G from the updated particle (trilinear: the
+            // local coordinate is the cell search's fractional part)
+            if constexpr (SH == 0) {
+                const R ih = cst<R>(S.inv_h, S.f_inv_h);
+                for (int a = 0; a < 3; ++a) {
+                    const R r = (R)fr[a];
+                    sp.base[a] = nc[a];
+                    sp.w[a][0] = (R)1 - r;
+                    sp.w[a][1] = r;
+                    sp.dw[a][0] = -ih;
+                    sp.dw[a][1] = ih;
+                }
+            } else {
+                make_support<R, SH>(S, xp, nc, sp);
+            }
             const Corners hn = corners(S, ht, sp.base);
             const R mv[3] = {mp * nv[0], mp * nv[1], mp * nv[2]};
             if constexpr (SC) {
