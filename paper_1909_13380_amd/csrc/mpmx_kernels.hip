@@ -1591,6 +1591,9 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                         L[2][0] += v[2] * gxN;
                         L[2][1] += v[2] * gyN;
                         L[2][2] += v[2] * gzN;
+                        if constexpr (SH == 1)
+                            if (i == NS - 1)
+                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
@@ -1649,6 +1652,9 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                         const R f1 = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy;
                         const R f2 = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz;
                         deposit(i, j, k, f0, f1, f2);
+                        if constexpr (SH == 1)
+                            if (i == NS - 1)
+                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
             }
         }
@@ -1811,6 +1817,9 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                             dv[e] += N * a[e];
                             vp[e] += N * u[e];
                         }
+                        if constexpr (SH == 1)
+                            if (i == NS - 1)
+                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
             R nv[3];
             for (int a = 0; a < 3; ++a) {
@@ -2003,6 +2012,9 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
                         L[2][0] += u.z * gxN;
                         L[2][1] += u.z * gyN;
                         L[2][2] += u.z * gzN;
+                        if constexpr (SH == 1)
+                            if (i == NS - 1)
+                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
             for (int a = 0; a < 3; ++a) {
                 const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
