@@ -23,11 +23,12 @@
 // update, then stress from the updated nodal velocity, and the clear of the
 // other buffer).
 //
-// The item kernels are persistent: a fixed grid strides over the flattened
+// The item kernels are persistent: a fixed grid walks the flattened
 // (scene, item) list whose offsets live in device memory, so a launch needs
-// no host knowledge of how many items each scene has.  Particle and node
-// indices are 32-bit and every array is addressed through a global-memory
-// pointer, so accesses use a scalar base plus a 32-bit offset.
+// no host knowledge of how many items each scene has; each of the GPU's 8
+// XCDs takes a contiguous range of the list.  Particle and node indices are
+// 32-bit and every field is addressed from one scalar base with a 32-bit
+// byte offset.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -56,12 +57,6 @@ template <typename T>
 __device__ inline T pick(const T (&a)[2], int b)
 {
     return b ? a[1] : a[0];
-}
-
-template <typename T>
-__device__ inline void gadd(GLOBAL T *p, T v)
-{
-    __hip_atomic_fetch_add((T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Element i of a global array as a scalar base plus a 32-bit byte offset
@@ -126,27 +121,6 @@ __device__ inline int find_scene(const T *offs, int nscenes, int64_t g)
             hi = mid - 1;
     }
     return lo;
-}
-
-__device__ inline int wave_min(int v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = min(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ inline int wave_max(int v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ inline uint32_t wave_sum(uint32_t v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o);
-    return v;
 }
 
 __device__ inline uint32_t pack_cell(const int c[3])
@@ -227,7 +201,7 @@ __device__ inline uint32_t locate(const SceneDev &S, const double x[3], int c[3]
     return out ? ERR_OUT_OF_MESH : 0u;
 }
 
-// Node index (32-bit: the runtime bounds every scene below 2^31 nodes).
+// Node index (32-bit: the runtime bounds every node field below 2^32 bytes).
 __device__ inline uint32_t node_id(const SceneDev &S, int i, int j, int k)
 {
     const int g = S.ghost;
@@ -607,28 +581,6 @@ __device__ inline ItemRange item_range(int64_t total)
     return {lo + blockIdx.x / nx, per, min(total, lo + chunk)};
 }
 
-// Block-wide min/max of per-thread cell boxes (mn = +big, mx = -big for a
-// thread with nothing); result in red[0..2] (min), red[3..5] (max).
-__device__ inline void block_box(int mn[3], int mx[3], int *red)
-{
-    for (int a = 0; a < 3; ++a) {
-        mn[a] = wave_min(mn[a]);
-        mx[a] = wave_max(mx[a]);
-    }
-    if (threadIdx.x == 0)
-        for (int a = 0; a < 3; ++a) {
-            red[a] = 1 << 30;
-            red[3 + a] = -(1 << 30);
-        }
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&red[a], mn[a]);
-            atomicMax(&red[3 + a], mx[a]);
-        }
-    __syncthreads();
-}
-
 template <int SH>
 __device__ inline Tile tile_of_cells(const int lo[3], const int hi[3])
 {
@@ -641,25 +593,6 @@ __device__ inline Tile tile_of_cells(const int lo[3], const int hi[3])
     t.fits = vol <= ShapeTraits<SH>::cap ? 1 : 0;
     t.pad = 0;
     return t;
-}
-
-// Node box of the item's particles (their cell box extended by the support).
-template <int SH>
-__device__ inline Tile item_tile(const Item &item, const GLOBAL uint32_t *cell, int *red)
-{
-    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-    for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
-        int c[3];
-        unpack_cell(cell[item.start + q], c);
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = min(mn[a], c[a]);
-            mx[a] = max(mx[a], c[a]);
-        }
-    }
-    block_box(mn, mx, red);
-    const int lo[3] = {red[0], red[1], red[2]}, hi[3] = {red[3], red[4], red[5]};
-    __syncthreads();
-    return tile_of_cells<SH>(lo, hi);
 }
 
 // LDS node tile of the next step's scatter in g2p_p2g: the nodes supporting
@@ -713,12 +646,6 @@ __device__ inline Corners corners(const SceneDev &S, const Tile &t, const int ba
 }
 
 // ------------------------------------------------------ tile helpers --
-
-// Corner n = i + 2j + 4k of a support at tile index t0 with strides ty, tz.
-__device__ inline int corner_off(int n, int ty, int tz)
-{
-    return (n & 1) + ((n >> 1) & 1) * ty + (n >> 2) * tz;
-}
 
 // Node (i, j, k) of entry q of a tile with at most 2^12 entries and edges of
 // at most 64 nodes: the quotients by a float reciprocal, exact in that range.
