@@ -379,7 +379,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="fixed grid density (turns autotuning off)")
     ap.add_argument("--scenes", type=int, default=256, help="--workload batch: number of scenes")
     ap.add_argument("--requests", type=int, default=2000, help="--workload serve: requests per arrival rate")
-    ap.add_argument("--rates", default="25,50,100", help="--workload serve: arrival rates (requests/s)")
+    ap.add_argument("--rates", default="50,100,150",
+                    help="--workload serve: arrival rates (requests/s); about 0.3, 0.6 and 0.9 of the saturated rate")
     ap.add_argument("--tick-steps", type=int, default=64, help="--workload serve: most steps per server tick")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
