@@ -1636,9 +1636,16 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
     using C = Cache<SH, kG2PCacheGather, kG2PCacheScatter>;
     constexpr bool GC = C::gather, SC = C::scatter;
     constexpr int GN = C::gnodes, SN = C::snodes;
-    __shared__ R4<R> la[CAP];
-    __shared__ R4<R> lvn[CAP];
-    __shared__ double acc[4][CAP];
+    // GIMP: the gather tile and the scatter accumulators share LDS (all
+    // particles are updated before the scatter starts), which admits one
+    // more workgroup per CU
+    constexpr bool OVERLAY = SH == 1;
+    constexpr int TILE_BYTES = 2 * CAP * (int)sizeof(R4<R>), ACC_BYTES = 4 * CAP * (int)sizeof(double);
+    __shared__ __attribute__((aligned(16))) char lds[OVERLAY ? (TILE_BYTES > ACC_BYTES ? TILE_BYTES : ACC_BYTES)
+                                                             : TILE_BYTES + ACC_BYTES];
+    R4<R> *la = (R4<R> *)lds;
+    R4<R> *lvn = la + CAP;
+    double (*acc)[CAP] = (double (*)[CAP])(lds + (OVERLAY ? 0 : TILE_BYTES));
     __shared__ int red[6 * (T / 64)];
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
@@ -1660,8 +1667,9 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         brick_origin(S, item.brick, o);
         const Tile ht = home_tile<SH>(o);
         load_update_tile<R>(S, nb, t, la, lvn);
-        for (int q = threadIdx.x; q < CAP; q += blockDim.x)
-            acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
+        if constexpr (!OVERLAY)
+            for (int q = threadIdx.x; q < CAP; q += blockDim.x)
+                acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
         __syncthreads();
         const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
@@ -1672,6 +1680,44 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         R ca[GN][3], cu[GN][3], sp_[SN][3], sm[SN];
         Corners sc{};
         bool s_in = true;
+        // the moved particles awaiting the scatter (OVERLAY)
+        struct Moved {
+            double x[3];
+            R m, mv[3];
+            int c[3];
+            bool ok, in;
+        };
+        Moved mvd[OVERLAY ? KP : 1];
+        if constexpr (OVERLAY)
+            for (int rr = 0; rr < KP; ++rr)
+                mvd[rr].ok = false;
+        // next step's mass and momentum of one particle with support sp:
+        // into the home tile's accumulators, or (drifted) global memory
+        auto scatter = [&](const Support<R, SH> &sq, bool inh, R m, const R mvq[3]) {
+            const Corners hq = corners(S, ht, sq.base);
+            if (inh) {
+                for (int k = 0; k < NS; ++k)
+                    for (int j = 0; j < NS; ++j)
+                        for (int i = 0; i < NS; ++i) {
+                            const R N = sq.w[0][i] * sq.w[1][j] * sq.w[2][k];
+                            const int li = hq.t0 + i + j * hq.ty + k * hq.tz;
+                            atomicAdd(&acc[0][li], (double)(N * m));
+                            atomicAdd(&acc[1][li], (double)(N * mvq[0]));
+                            atomicAdd(&acc[2][li], (double)(N * mvq[1]));
+                            atomicAdd(&acc[3][li], (double)(N * mvq[2]));
+                        }
+            } else {
+                for (int k = 0; k < NS; ++k)
+                    for (int j = 0; j < NS; ++j)
+                        for (int i = 0; i < NS; ++i) {
+                            const R N = sq.w[0][i] * sq.w[1][j] * sq.w[2][k];
+                            const uint32_t I = hq.n0 + (uint32_t)(i + j * hq.ny + k * hq.nz);
+                            addg(nn.m, I, (double)(N * m));
+                            for (int a = 0; a < 3; ++a)
+                                addg(nn.p[a], I, N * mvq[a]);
+                        }
+            }
+        };
         auto flush = [&]() {
             for (int n = 0; n < SN; ++n) {
                 const int di = n & 1, dj = (n >> 1) & 1, dk = n >> 2;
@@ -1771,6 +1817,18 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             }
             const bool in = in_home(nc, o);
             drift |= in ? 0u : 1u;
+            if constexpr (OVERLAY) {
+                Moved &mq = mvd[rr];
+                for (int a = 0; a < 3; ++a) {
+                    mq.x[a] = xp[a];
+                    mq.c[a] = nc[a];
+                    mq.mv[a] = mp * nv[a];
+                }
+                mq.m = mp;
+                mq.in = in;
+                mq.ok = true;
+                continue;
+            }
             // the next step's P2G from the updated particle (trilinear: the
             // local coordinate is the cell search's fractional part)
             if constexpr (SH == 0) {
@@ -1812,28 +1870,23 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                             for (int a = 0; a < 3; ++a)
                                 sp_[n][a] += N * mv[a];
                         }
-            } else if (in) {
-                for (int k = 0; k < NS; ++k)
-                    for (int j = 0; j < NS; ++j)
-                        for (int i = 0; i < NS; ++i) {
-                            const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
-                            const int li = hn.t0 + i + j * hn.ty + k * hn.tz;
-                            atomicAdd(&acc[0][li], (double)(N * mp));
-                            atomicAdd(&acc[1][li], (double)(N * mv[0]));
-                            atomicAdd(&acc[2][li], (double)(N * mv[1]));
-                            atomicAdd(&acc[3][li], (double)(N * mv[2]));
-                        }
             } else {
-                for (int k = 0; k < NS; ++k)
-                    for (int j = 0; j < NS; ++j)
-                        for (int i = 0; i < NS; ++i) {
-                            const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
-                            const uint32_t I = hn.n0 + (uint32_t)(i + j * hn.ny + k * hn.nz);
-                            addg(nn.m, I, (double)(N * mp));
-                            for (int a = 0; a < 3; ++a)
-                                addg(nn.p[a], I, N * mv[a]);
-                        }
+                scatter(sp, in, mp, mv);
             }
+        }
+        if constexpr (OVERLAY) {
+            // every gather from the tile is done: the same LDS now accumulates
+            __syncthreads();
+            for (int q = threadIdx.x; q < CAP; q += blockDim.x)
+                acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int rr = 0; rr < KP; ++rr)
+                if (mvd[rr].ok) {
+                    Support<R, SH> sq;
+                    make_support<R, SH>(S, mvd[rr].x, mvd[rr].c, sq);
+                    scatter(sq, mvd[rr].in, mvd[rr].m, mvd[rr].mv);
+                }
         }
         if constexpr (SC)
             if (sb[0] != -(1 << 30))
