@@ -235,7 +235,10 @@ int mpmx_scene_bytes(const mpmx_mesh *mesh, const mpmx_scheme *scheme, int64_t n
 /* Create a scene: validate and copy the descriptors, upload the particles,
  * bin them into cells.  *scene receives an id > 0.  A particle outside the
  * mesh or a non-finite input fails with MPMX_E_OUT_OF_MESH /
- * MPMX_E_NONFINITE and creates nothing. */
+ * MPMX_E_NONFINITE and creates nothing.  The kernels address each particle
+ * and node field with 32-bit byte offsets, so a scene holds fewer than
+ * 2^32 / 24 particles at MPMX_FP32 (2^32 / 48 at MPMX_FP64) and fewer than
+ * 2^32 / 12 nodes (2^32 / 24); larger ones fail with MPMX_E_INVALID_ARG. */
 int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat,
                       const mpmx_bc *bc, const mpmx_scheme *scheme,
                       const mpmx_particles *particles, uint64_t *scene);
