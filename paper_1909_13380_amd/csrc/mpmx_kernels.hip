@@ -647,8 +647,9 @@ __device__ inline Corners corners(const SceneDev &S, const Tile &t, const int ba
 
 // ------------------------------------------------------ tile helpers --
 
-// Node (i, j, k) of entry q of a tile with at most 2^12 entries and edges of
-// at most 64 nodes: the quotients by a float reciprocal, exact in that range.
+// Node (i, j, k) of entry q < 2^20 of a tile, the quotients taken through a
+// float reciprocal: (q + 0.5) / d lies at least 0.5 / d from an integer, and
+// the float product is within 2^-21 q / d of it, so the truncation is exact.
 __device__ inline void tile_node_small(const Tile &t, int q, int &i, int &j, int &k)
 {
     const int dxy = t.dim[0] * t.dim[1];
