@@ -402,6 +402,34 @@ def test_batch_equals_alone(ctx, mp):
         b.destroy()
 
 
+def test_batches_with_fewer_items_than_workgroups_per_xcd(mp):
+    """Tiny scenes (one brick each): a batch whose item grid is smaller than
+    the 8 XCDs strides over the whole item list, and one with a larger scene
+    splits its items into uneven XCD ranges; every scene still matches the
+    oracle to FP64 rounding, graphs included."""
+    def first(sc, k):   # the scene's first k particles
+        for key in ("x", "v", "vol", "mass", "stress"):
+            sc[key] = np.ascontiguousarray(sc[key][:k])
+        return sc
+    # two particles: the item grid has 3 workgroups, fewer than the XCDs
+    pair = first(block(material=MATERIALS["le"], seed=89, n_cells=(1, 1, 1)), 2)
+    tiny = [block(material=MATERIALS["le"], seed=90 + i, n_cells=n) for i, n in
+            enumerate(((1, 1, 1), (2, 1, 1), (3, 2, 1)))]
+    mixed = tiny + [block(material=MATERIALS["dp"], seed=95, n_cells=(9, 7, 6))]
+    c = mp.Context(0)
+    try:
+        _fixed(c, mp, graph_steps=4, t_stress=64, t_g2p=64, blocks=1)
+        for scs in ([pair], tiny, mixed):
+            ss = [c.create_scene(sc, precision=mp.FP64) for sc in scs]
+            c.batch_step(ss, [11] * len(ss))
+            for sc, s in zip(scs, ss):
+                ref = oracle.run(sc, 11)
+                check_state(f"xcd/{len(scs)}/{len(sc['x'])}", s.read(), ref, sc["x"], 1e-9, 1e-9, 1e-9)
+                s.destroy()
+    finally:
+        c.close()
+
+
 def _fixed(c, mp, graph_steps, t_stress=128, t_g2p=128, blocks=16):
     c.set_option(mp.OPT_STRESS_THREADS, t_stress)
     c.set_option(mp.OPT_G2P_THREADS, t_g2p)
