@@ -3,13 +3,12 @@
 //
 // A scene owns its device buffers (layout in mpmx_dev.h).  Every step
 // is a fixed sequence of launches over a BatchDev (one scene, or many):
-//   sort_count -> sort_bricks -> sort_perm -> sort_move (its
-//   last workgroup runs the step control) -> stress -> g2p_p2g      (USF)
-//   sort ... -> p2g_usl -> g2p_usl                                  (USL)
+//   reorder (its last workgroup runs the step control) -> stress -> g2p_p2g   (USF)
+//   reorder -> p2g_usl -> g2p_usl                                              (USL)
 // plus one p2g at the start of a USF call for scenes whose node buffer is
-// not yet filled.  The sort kernels return at once unless a scene flagged a
-// reorder; all counts the kernels need live in device memory, so the host
-// never waits on the GPU between steps.
+// not yet filled.  The reorder kernel goes straight to the step control
+// unless a scene flagged a reorder; all counts the kernels need live in
+// device memory, so the host never waits on the GPU between steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -487,14 +486,15 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
 int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipEvent_t *ev)
 {
     const KernelSet &K = kernel_set(b.prec, b.shape);
-    const CommonKernels &C = common_kernels();
     BatchDev bd = b.bd;
     void *a_bd[] = {&bd};
     const hipStream_t st = ctx->launch_stream ? ctx->launch_stream : ctx->stream;
-    // sort kernels stride over their range with one block per CU: they
-    // return at once on steps that need no reorder
-    const dim3 pg = particle_grid(bd.total_particles, ctx->num_cu);
-    const dim3 bg((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(bd.total_bricks, 1), 4), ctx->num_cu));
+    // the reorder kernel strides over its ranges with at most one workgroup
+    // per CU (its grid barriers need every workgroup resident); it returns
+    // at once on steps that need no reorder
+    const int64_t rwork = std::max({ceil_div(bd.total_particles, kParticleBlock), ceil_div(bd.total_bricks, 4),
+                                    (int64_t)bd.nscenes, (int64_t)1});
+    const dim3 rg((unsigned)std::min<int64_t>(rwork, ctx->num_cu));
     // item grids: a multiple of the XCD count unless there are fewer items
     int64_t ign = std::min<int64_t>(bd.max_items, (int64_t)cfg.blocks_per_cu * ctx->num_cu);
     if (ign >= kXcds)
@@ -502,10 +502,7 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
     const dim3 ig((unsigned)std::max<int64_t>(1, ign));
     const dim3 ts(kItemThreadChoices[cfg.t_stress]), tg(kItemThreadChoices[cfg.t_g2p]);
     int rc;
-    if ((rc = launch(ctx, "sort_count", C.sort_count, pg, dim3(kParticleBlock), a_bd)) ||
-        (rc = launch(ctx, "sort_bricks", C.sort_bricks, bg, dim3(256), a_bd)) ||
-        (rc = launch(ctx, "sort_perm", C.sort_perm, pg, dim3(kParticleBlock), a_bd)) ||
-        (rc = launch(ctx, "sort_move", K.move, bg, dim3(256), a_bd)))
+    if ((rc = launch(ctx, "reorder", K.reorder, rg, dim3(kBlock), a_bd)))
         return rc;
     if (b.algo == MPMX_USF && first && (rc = launch(ctx, "p2g", K.p2g[cfg.t_g2p], ig, tg, a_bd)))
         return rc;

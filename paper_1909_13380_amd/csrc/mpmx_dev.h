@@ -58,7 +58,10 @@ enum Ctl : int {
 
 // ERR_TILE: an item's particles spread beyond the LDS node tile, which the
 // reorder rule makes impossible; reported rather than silently mishandled.
-enum ErrBit : uint32_t { ERR_OUT_OF_MESH = 1u, ERR_NONFINITE = 2u, ERR_TILE = 4u };
+// ERR_SORT: the reorder kernel gave up waiting at a grid barrier (its
+// workgroups are all resident, so this does not happen); the particles stay
+// in their previous order.
+enum ErrBit : uint32_t { ERR_OUT_OF_MESH = 1u, ERR_NONFINITE = 2u, ERR_TILE = 4u, ERR_SORT = 8u };
 
 struct Item {
     uint32_t start;  // first particle (storage order)
@@ -130,8 +133,9 @@ struct SceneDev {
 
 enum BatchFlag : int {
     BF_ANY_SORT = 0,      // some scene of the batch reorders this step
-    BF_TICKET_BRICKS = 1, // finished-block counters (the last block runs the
-    BF_TICKET_MOVE = 2,   // single-workgroup tail of the kernel)
+    BF_GRID = 1,          // arrivals at the reorder kernel's grid barriers
+    BF_TICKET_MOVE = 2,   // finished workgroups (the last runs the step control)
+    BF_SORT_FAIL = 3,     // a workgroup gave up waiting at a grid barrier
     BF_WORDS = 4
 };
 

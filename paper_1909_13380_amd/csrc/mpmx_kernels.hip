@@ -867,8 +867,9 @@ __global__ void k_begin(BatchDev B, const int64_t *nsteps)
     __syncthreads();
     if (threadIdx.x == 0) {
         B.flags[BF_ANY_SORT] = any ? 1u : 0u;
-        B.flags[BF_TICKET_BRICKS] = 0u;
+        B.flags[BF_GRID] = 0u;
         B.flags[BF_TICKET_MOVE] = 0u;
+        B.flags[BF_SORT_FAIL] = 0u;
     }
 }
 
@@ -883,6 +884,7 @@ __device__ void step_control(const BatchDev &B)
     __shared__ uint32_t wi[kBlock / 64], wc[kBlock / 64];
     __shared__ uint32_t carry[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool fail = __hip_atomic_load(&B.flags[BF_SORT_FAIL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
     if (threadIdx.x == 0) {
         carry[0] = carry[1] = 0u;
         B.ioffs[0] = 0;
@@ -902,8 +904,12 @@ __device__ void step_control(const BatchDev &B)
                 c[4 * q + 2] = w.z;
                 c[4 * q + 3] = w.w;
             }
-            const bool go = c[CTL_ERR] == 0u && c[CTL_REMAIN] > 0u;
-            const bool sorted = go && c[CTL_NEED_SORT];   // the sort kernels reordered it
+            bool go = c[CTL_ERR] == 0u && c[CTL_REMAIN] > 0u;
+            if (go && c[CTL_NEED_SORT] && fail) {   // its reorder was abandoned
+                c[CTL_ERR] |= ERR_SORT;
+                go = false;
+            }
+            const bool sorted = go && c[CTL_NEED_SORT];   // the reorder phases moved it
             if (sorted) {
                 c[CTL_CUR] ^= 1u;
                 c[CTL_NEED_SORT] = 0u;
@@ -971,12 +977,46 @@ __device__ void step_control(const BatchDev &B)
 }
 
 // ----------------------------------------------------------------- sort --
+// The reorder runs as one launch of at most one workgroup per compute unit,
+// in five phases separated by grid-wide barriers.  Steps that reorder no
+// scene skip straight to the step control, so they pay a single launch.
+
+// Wait until every workgroup of the launch has arrived at barrier `round`
+// (1, 2, ...).  The arrival counter only grows within a launch, so no reset
+// is needed between barriers.  The grid is far below what the device holds
+// at once, so every workgroup is resident and the wait ends; it is bounded
+// all the same (kBarrierTicks of the constant-rate wall clock), and a
+// workgroup that gives up raises BF_SORT_FAIL before it arrives anywhere
+// else.  Returns whether the reorder may go on: the flag is read after the
+// wait, so a workgroup that continues has seen the previous phase complete
+// on every workgroup.
+constexpr uint64_t kBarrierTicks = 100000000ull;   // 1 s at 100 MHz
+
+__device__ bool grid_barrier(uint32_t *flags, uint32_t round, int *sh)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // publish this workgroup's writes of the phase
+        atomicAdd(&flags[BF_GRID], 1u);
+        const uint32_t target = round * gridDim.x;
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(&flags[BF_GRID], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (wall_clock64() - t0 > kBarrierTicks) {
+                atomicOr(&flags[BF_SORT_FAIL], 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();   // see the other workgroups' writes
+        *sh = __hip_atomic_load(&flags[BF_SORT_FAIL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    }
+    __syncthreads();
+    return *sh != 0;
+}
 
 // rank[p] = arrival order of p among the particles of its cell.
-__global__ void __launch_bounds__(kBlock) k_sort_count(BatchDev B)
+__device__ void sort_count(const BatchDev &B)
 {
-    if (!B.flags[BF_ANY_SORT])
-        return;
     for (int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gp < B.total_particles;
          gp += (int64_t)gridDim.x * blockDim.x) {
         const int s = find_scene(B.poffs, B.nscenes, gp);
@@ -986,6 +1026,34 @@ __global__ void __launch_bounds__(kBlock) k_sort_count(BatchDev B)
         const int64_t p = gp - B.poffs[s];
         const int cur = (int)uni(S.ctl[CTL_CUR]);
         S.rank[p] = atomicAdd(&S.cnt[brick_key(S, pick(S.cell, cur)[p])], 1u);
+    }
+}
+
+// One wavefront per brick: the brick's particle count, its work-item count
+// and the cell-major start of every cell inside the brick.
+__device__ void sort_bricks(const BatchDev &B)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
+        const int s = find_scene(B.boffs, B.nscenes, gb);
+        const SceneDev &S = *B.scenes[s];
+        if (!scene_sorting(S))
+            continue;
+        const int64_t b = gb - B.boffs[s];
+        const uint32_t c = S.cnt[b * 64 + lane];
+        uint32_t inc = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o)
+                inc += t;
+        }
+        S.cstart[b * 64 + lane] = inc - c;   // cell-major start inside the brick
+        if (lane == 63) {
+            S.bcnt[b] = inc;
+            S.bitem[b] = (inc + kChunk - 1) / kChunk;
+        }
     }
 }
 
@@ -1029,54 +1097,11 @@ __device__ void scan_bricks(const SceneDev &S)
     __syncthreads();
 }
 
-// One wavefront per brick: the brick's particle count, its work-item count
-// and the cell-major start of every cell inside the brick; the last
-// workgroup to finish scans the bricks per scene.
-__global__ void __launch_bounds__(kBlock) k_sort_bricks(BatchDev B)
-{
-    __shared__ int last;
-    if (!B.flags[BF_ANY_SORT])
-        return;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
-        const int s = find_scene(B.boffs, B.nscenes, gb);
-        const SceneDev &S = *B.scenes[s];
-        if (!scene_sorting(S))
-            continue;
-        const int64_t b = gb - B.boffs[s];
-        const uint32_t c = S.cnt[b * 64 + lane];
-        uint32_t inc = c;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(inc, o);
-            if (lane >= o)
-                inc += t;
-        }
-        S.cstart[b * 64 + lane] = inc - c;   // cell-major start inside the brick
-        if (lane == 63) {
-            S.bcnt[b] = inc;
-            S.bitem[b] = (inc + kChunk - 1) / kChunk;
-        }
-    }
-    if (!last_block(&B.flags[BF_TICKET_BRICKS], &last))
-        return;
-    for (int s = 0; s < B.nscenes; ++s) {
-        const SceneDev &S = *B.scenes[s];
-        if (scene_sorting(S))
-            scan_bricks(S);
-    }
-    if (threadIdx.x == 0)
-        B.flags[BF_TICKET_BRICKS] = 0u;
-}
-
 // perm lists the particles cell-major: slot bstart[brick] + cstart[key] +
 // rank holds p.  The particle that opens a 512-slot chunk of its brick
 // writes that work item.
-__global__ void __launch_bounds__(kBlock) k_sort_perm(BatchDev B)
+__device__ void sort_perm(const BatchDev &B)
 {
-    if (!B.flags[BF_ANY_SORT])
-        return;
     for (int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gp < B.total_particles;
          gp += (int64_t)gridDim.x * blockDim.x) {
         const int s = find_scene(B.poffs, B.nscenes, gp);
@@ -1106,64 +1131,85 @@ __global__ void __launch_bounds__(kBlock) k_sort_perm(BatchDev B)
 // cell, then the second of every cell holding two or more, and so on.  A
 // wavefront of consecutive particles then spans distinct cells, so the
 // scatter kernels' LDS atomics for one node corner do not collide.  Resets
-// the per-cell counts for the next sort.  The last workgroup to finish runs
-// the step control (every step, reorder or not).
+// the per-cell counts for the next sort.
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_sort_move(BatchDev B)
+__device__ void sort_move(const BatchDev &B)
 {
-    __shared__ int last;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
+        const int s = find_scene(B.boffs, B.nscenes, gb);
+        const SceneDev &S = *B.scenes[s];
+        if (!scene_sorting(S))
+            continue;
+        const int64_t b = gb - B.boffs[s];
+        const int64_t n = S.np;
+        const int cur = (int)uni(S.ctl[CTL_CUR]), nxt = cur ^ 1;
+        const uint32_t nc = S.cnt[b * 64 + lane];
+        const uint32_t cs = S.bstart[b] + S.cstart[b * 64 + lane];
+        S.cnt[b * 64 + lane] = 0u;
+        uint32_t levels = nc;
+        for (int o = 32; o > 0; o >>= 1)
+            levels = max(levels, (uint32_t)__shfl_xor(levels, o));
+        int64_t base = S.bstart[b];
+        for (uint32_t j = 0; j < levels; ++j) {
+            const bool act = j < nc;
+            const uint64_t m = __ballot(act);
+            if (act) {
+                const int64_t p = S.perm[cs + j];
+                const int64_t d = base + __popcll(m & below);
+                for (int a = 0; a < 3; ++a) {
+                    pick(S.x, nxt)[a * n + d] = pick(S.x, cur)[a * n + p];
+                    ((R *)pick(S.v, nxt))[a * n + d] = ((const R *)pick(S.v, cur))[a * n + p];
+                }
+                for (int k = 0; k < 6; ++k)
+                    ((R *)pick(S.sig, nxt))[k * n + d] = ((const R *)pick(S.sig, cur))[k * n + p];
+                ((R *)pick(S.vol, nxt))[d] = ((const R *)pick(S.vol, cur))[p];
+                ((R *)pick(S.mass, nxt))[d] = ((const R *)pick(S.mass, cur))[p];
+                pick(S.cell, nxt)[d] = pick(S.cell, cur)[p];
+                pick(S.pid, nxt)[d] = pick(S.pid, cur)[p];
+            }
+            base += __popcll(m);
+        }
+    }
+}
+
+// Reorder of the flagged scenes (count, per-brick scan, per-scene scan,
+// permutation, move), then the step control in the last workgroup to finish.
+// A phase runs only if no workgroup gave up waiting at the barrier before
+// it; the step control then fails the reordering scenes (ERR_SORT) and
+// keeps their particles where they were.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_reorder(BatchDev B)
+{
+    __shared__ int sh;
     if (!B.flags[BF_ANY_SORT]) {
         // nothing moves: the first workgroup runs the step control alone
         if (blockIdx.x == 0)
             step_control(B);
         return;
     }
-    {
-        const int lane = threadIdx.x & 63;
-        const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-        const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
-            const int s = find_scene(B.boffs, B.nscenes, gb);
-            const SceneDev &S = *B.scenes[s];
-            if (!scene_sorting(S))
-                continue;
-            const int64_t b = gb - B.boffs[s];
-            const int64_t n = S.np;
-            const int cur = (int)uni(S.ctl[CTL_CUR]), nxt = cur ^ 1;
-            const uint32_t nc = S.cnt[b * 64 + lane];
-            const uint32_t cs = S.bstart[b] + S.cstart[b * 64 + lane];
-            S.cnt[b * 64 + lane] = 0u;
-            uint32_t levels = nc;
-            for (int o = 32; o > 0; o >>= 1)
-                levels = max(levels, (uint32_t)__shfl_xor(levels, o));
-            int64_t base = S.bstart[b];
-            for (uint32_t j = 0; j < levels; ++j) {
-                const bool act = j < nc;
-                const uint64_t m = __ballot(act);
-                if (act) {
-                    const int64_t p = S.perm[cs + j];
-                    const int64_t d = base + __popcll(m & below);
-                    for (int a = 0; a < 3; ++a) {
-                        pick(S.x, nxt)[a * n + d] = pick(S.x, cur)[a * n + p];
-                        ((R *)pick(S.v, nxt))[a * n + d] = ((const R *)pick(S.v, cur))[a * n + p];
-                    }
-                    for (int k = 0; k < 6; ++k)
-                        ((R *)pick(S.sig, nxt))[k * n + d] = ((const R *)pick(S.sig, cur))[k * n + p];
-                    ((R *)pick(S.vol, nxt))[d] = ((const R *)pick(S.vol, cur))[p];
-                    ((R *)pick(S.mass, nxt))[d] = ((const R *)pick(S.mass, cur))[p];
-                    pick(S.cell, nxt)[d] = pick(S.cell, cur)[p];
-                    pick(S.pid, nxt)[d] = pick(S.pid, cur)[p];
-                }
-                base += __popcll(m);
-            }
-        }
-    }
-    if (!last_block(&B.flags[BF_TICKET_MOVE], &last))
+    sort_count(B);
+    if (grid_barrier(B.flags, 1, &sh))
+        sort_bricks(B);
+    if (grid_barrier(B.flags, 2, &sh))
+        for (int s = blockIdx.x; s < B.nscenes; s += gridDim.x)
+            if (scene_sorting(*B.scenes[s]))
+                scan_bricks(*B.scenes[s]);
+    if (grid_barrier(B.flags, 3, &sh))
+        sort_perm(B);
+    if (grid_barrier(B.flags, 4, &sh))
+        sort_move<R>(B);
+    if (!last_block(&B.flags[BF_TICKET_MOVE], &sh))
         return;
     step_control(B);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         B.flags[BF_TICKET_MOVE] = 0u;
+        B.flags[BF_GRID] = 0u;
+        B.flags[BF_SORT_FAIL] = 0u;
+    }
 }
 
 // ------------------------------------------------------- item kernels --
@@ -2062,7 +2108,7 @@ static KernelSet make_set()
     k.load = (const void *)&k_load<R>;
     k.read_out = (const void *)&k_read_out<R>;
     k.nodes_out = (const void *)&k_nodes_out<R>;
-    k.move = (const void *)&k_sort_move<R>;
+    k.reorder = (const void *)&k_reorder<R>;
     set_items<R, SH, 0>(k);
     set_items<R, SH, 1>(k);
     set_items<R, SH, 2>(k);
@@ -2078,9 +2124,7 @@ const KernelSet &kernel_set(int prec, int shape)
 
 const CommonKernels &common_kernels()
 {
-    static const CommonKernels c = {(const void *)&k_begin, (const void *)&k_sort_count,
-                                    (const void *)&k_sort_bricks, (const void *)&k_sort_perm,
-                                    (const void *)&k_cell_counts};
+    static const CommonKernels c = {(const void *)&k_begin, (const void *)&k_cell_counts};
     return c;
 }
 

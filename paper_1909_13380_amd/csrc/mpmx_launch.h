@@ -15,7 +15,7 @@ struct KernelSet {
     const void *load;       // (SceneDev*, x, v, sig, vol, mass)
     const void *read_out;   // (const SceneDev*, x, v, sig, vol, cell)
     const void *nodes_out;  // (const SceneDev*, m, p, f)
-    const void *move;       // (BatchDev): reorder, then the step control
+    const void *reorder;    // (BatchDev): reorder, then the step control
     const void *p2g[kNumItemThreadChoices];      // (BatchDev)
     const void *stress[kNumItemThreadChoices];   // (BatchDev)
     const void *g2p_p2g[kNumItemThreadChoices];  // (BatchDev)
@@ -25,9 +25,6 @@ struct KernelSet {
 
 struct CommonKernels {
     const void *begin;        // (BatchDev, const int64_t*)
-    const void *sort_count;   // (BatchDev)
-    const void *sort_bricks;  // (BatchDev)
-    const void *sort_perm;    // (BatchDev)
     const void *cell_counts;  // (const SceneDev*, uint32_t*)
 };
 
