@@ -151,6 +151,7 @@ struct mpmx_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int num_cu = 256;
+    int reorder_per_cu[2] = {0, 0};   // by precision; 0 until first queried
     std::string err;
     uint64_t next_id = 1;
     std::map<uint64_t, std::unique_ptr<Scene>> scenes;
@@ -420,10 +421,15 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     b.drop_graph();
     const int n = (int)list.size();
     const size_t n1 = (size_t)n + 1;
-    // layout: scenes[n] | poffs[n+1] | boffs[n+1] | nsteps[n] | ctls[n] | ioffs[n+1] | coffs[n+1] | flags
+    // layout: scenes[n] | poffs[n+1] | boffs[n+1] | nsteps[n] | ctls[n] | ioffs[n+1] | coffs[n+1] |
+    // flags (128-byte aligned) | scan[4 per reorder workgroup] | bricks[total bricks]
     const size_t n8 = 8 * (size_t)std::max(n, 1);
+    int64_t nbr = 0;
+    for (auto *sc : list)
+        nbr += sc->h.nbricks;
     const size_t o_po = n8, o_bo = o_po + 8 * n1, o_ns = o_bo + 8 * n1, o_ct = o_ns + n8, o_io = o_ct + n8,
-                 o_co = o_io + 4 * n1, o_fl = o_co + 4 * n1, total = o_fl + 4 * BF_WORDS;
+                 o_co = o_io + 4 * n1, o_fl = (o_co + 4 * n1 + 127) & ~(size_t)127, o_sc = o_fl + 4 * BF_WORDS,
+                 o_br = o_sc + 16 * (size_t)kReorderPerCu * ctx->num_cu, total = o_br + 4 * (size_t)std::max<int64_t>(nbr, 1);
     std::vector<uint8_t> img(total, 0);
     int64_t maxit = 0, *po = (int64_t *)(img.data() + o_po), *bo = (int64_t *)(img.data() + o_bo);
     SceneDev **sp = (SceneDev **)img.data();
@@ -464,6 +470,8 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     b.bd.coffs = b.d_coffs;
 
     b.bd.flags = b.d_flags;
+    b.bd.scan = (uint32_t *)(base + o_sc);
+    b.bd.bricks = (uint32_t *)(base + o_br);
     b.bd.nscenes = n;
     b.bd.total_particles = po[n];
     b.bd.total_bricks = bo[n];
@@ -479,6 +487,20 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     return MPMX_OK;
 }
 
+// Reorder workgroups per CU: kReorderPerCu, or fewer if the kernel's
+// resources allow fewer resident at once.
+int reorder_per_cu(mpmx_ctx *ctx, int prec, const void *fn)
+{
+    int &n = ctx->reorder_per_cu[prec ? 1 : 0];
+    if (n == 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBlock, 0) != hipSuccess || occ < 1)
+            occ = 1;
+        n = std::min(occ, kReorderPerCu);
+    }
+    return n;
+}
+
 // Launches of one step of every scene of b (the first step of a call also
 // fills the node buffer of USF scenes that need it).  `ev`, when given,
 // receives events around the item kernels: [0] before, [1] between, [2]
@@ -489,12 +511,13 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
     BatchDev bd = b.bd;
     void *a_bd[] = {&bd};
     const hipStream_t st = ctx->launch_stream ? ctx->launch_stream : ctx->stream;
-    // the reorder kernel strides over its ranges with at most one workgroup
-    // per CU (its grid barriers need every workgroup resident); it returns
-    // at once on steps that need no reorder
-    const int64_t rwork = std::max({ceil_div(bd.total_particles, kParticleBlock), ceil_div(bd.total_bricks, 4),
-                                    (int64_t)bd.nscenes, (int64_t)1});
-    const dim3 rg((unsigned)std::min<int64_t>(rwork, ctx->num_cu));
+    // the reorder kernel: enough workgroups for one pass over the particles
+    // and one brick per wavefront, but never more than the device holds at
+    // once (its grid barriers need every workgroup resident); it returns at
+    // once on steps that need no reorder
+    const int64_t rwork = std::max({ceil_div(bd.total_particles, (int64_t)kBlock * kSortU),
+                                    ceil_div(bd.total_bricks, kBlock / 64), (int64_t)bd.nscenes, (int64_t)1});
+    const dim3 rg((unsigned)std::min<int64_t>(rwork, (int64_t)reorder_per_cu(ctx, b.prec, K.reorder) * ctx->num_cu));
     // item grids: a multiple of the XCD count unless there are fewer items
     int64_t ign = std::min<int64_t>(bd.max_items, (int64_t)cfg.blocks_per_cu * ctx->num_cu);
     if (ign >= kXcds)

@@ -26,7 +26,9 @@ constexpr int kBrick = 4;                 // cells per brick edge
 constexpr int kBrickCells = 64;           // cells per brick
 constexpr int kChunk = 512;               // max particles per work item
 constexpr int kXcds = 8;                  // accelerator dies (one L2 each) of the GPU
-constexpr int kBlock = 256;               // threads per workgroup of the sort and control kernels
+constexpr int kBlock = 1024;              // threads per workgroup of the reorder and control kernel
+constexpr int kSortU = 4;                 // particles per lane in flight in the reorder's particle phases
+constexpr int kReorderPerCu = 1;          // most reorder workgroups per compute unit
 // Linear shape functions: per-thread register cache of the gathered support
 // nodes, and per-thread register sums of the scattered values, per kernel
 // (chosen by measurement on the 2M-particle column: the stress kernel is
@@ -131,12 +133,17 @@ struct SceneDev {
     float f_lam, f_G, f_K, f_eta, f_xic, f_etab, f_apex, f_inv_hard;
 };
 
+// Words of BatchDev::flags (the array is 128-byte aligned; the words that
+// many workgroups update or poll at once sit on 128-byte lines of their own).
 enum BatchFlag : int {
     BF_ANY_SORT = 0,      // some scene of the batch reorders this step
-    BF_GRID = 1,          // arrivals at the reorder kernel's grid barriers
-    BF_TICKET_MOVE = 2,   // finished workgroups (the last runs the step control)
-    BF_SORT_FAIL = 3,     // a workgroup gave up waiting at a grid barrier
-    BF_WORDS = 4
+    BF_TICKET_MOVE = 1,   // finished reorder workgroups (the last runs the step control)
+    BF_SORT_FAIL = 2,     // a reorder workgroup gave up waiting at a grid barrier
+    BF_NBRICKS = 32,      // non-empty bricks listed by the reorder
+    BF_GRID = 64,         // grid barrier: arrivals of the workgroup groups
+    BF_GROUP = 96,        // + 32 g: arrivals within group g
+    BF_RELEASE = 96 + 32 * kXcds,   // + 32 g: last barrier round released, polled by group g
+    BF_WORDS = 96 + 64 * kXcds
 };
 
 // A launch over several scenes: work is flattened over scenes in order.
@@ -148,6 +155,8 @@ struct BatchDev {
     uint32_t *ioffs;                // this step's item offsets [nscenes+1]
     uint32_t *coffs;                // offsets of the boxes to clear [nscenes+1]
     uint32_t *flags;                // BF_*
+    uint32_t *scan;                 // reorder: per workgroup, 4 words of brick-scan partial sums
+    uint32_t *bricks;               // reorder: the non-empty bricks (flattened index) [total_bricks]
     int nscenes;
     int pad;
     int64_t total_particles;

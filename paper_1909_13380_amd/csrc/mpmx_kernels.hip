@@ -135,15 +135,6 @@ __device__ inline void unpack_cell(uint32_t p, int c[3])
     c[2] = (int)(p >> 22);
 }
 
-__device__ inline uint32_t brick_key(const SceneDev &S, uint32_t packed)
-{
-    int c[3];
-    unpack_cell(packed, c);
-    const uint32_t b = (uint32_t)(c[0] >> 2) +
-                       (uint32_t)S.nb[0] * ((uint32_t)(c[1] >> 2) + (uint32_t)S.nb[1] * (uint32_t)(c[2] >> 2));
-    return b * 64u + (uint32_t)((c[0] & 3) + 4 * ((c[1] & 3) + 4 * (c[2] & 3)));
-}
-
 __device__ inline void brick_origin(const SceneDev &S, uint32_t b, int o[3])
 {
     o[0] = (int)(b % (uint32_t)S.nb[0]) * kBrick;
@@ -530,13 +521,6 @@ __device__ inline ItemRef item_ref(const uint32_t *offs, const BatchDev &B, int6
     return {uni(B.scenes[s]), (int)uni((uint32_t)(g - (int64_t)offs[s]))};
 }
 
-// The scene reorders in the coming step: read by the sort kernels, during
-// which none of these words changes.
-__device__ inline bool scene_sorting(const SceneDev &S)
-{
-    return S.ctl[CTL_ERR] == 0u && S.ctl[CTL_REMAIN] > 0u && S.ctl[CTL_NEED_SORT] != 0u;
-}
-
 // The stage kernels after the step control test CTL_ACTIVE only: it is fixed
 // for the whole step, whereas CTL_ERR may be raised by another workgroup of
 // the same kernel, and every thread of a workgroup must take the same branch
@@ -865,12 +849,8 @@ __global__ void k_begin(BatchDev B, const int64_t *nsteps)
             any = 1;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        B.flags[BF_ANY_SORT] = any ? 1u : 0u;
-        B.flags[BF_GRID] = 0u;
-        B.flags[BF_TICKET_MOVE] = 0u;
-        B.flags[BF_SORT_FAIL] = 0u;
-    }
+    for (int w = threadIdx.x; w < BF_WORDS; w += blockDim.x)
+        B.flags[w] = (w == BF_ANY_SORT && any) ? 1u : 0u;
 }
 
 // Per-step control, run by one workgroup: apply a finished reorder, decide
@@ -977,35 +957,61 @@ __device__ void step_control(const BatchDev &B)
 }
 
 // ----------------------------------------------------------------- sort --
-// The reorder runs as one launch of at most one workgroup per compute unit,
-// in five phases separated by grid-wide barriers.  Steps that reorder no
-// scene skip straight to the step control, so they pay a single launch.
+// The reorder runs as one launch of a few workgroups per compute unit, in
+// six phases separated by grid-wide barriers: per-cell counts, per-brick
+// cell scan, the scan over bricks (block partial sums, then the rescan with
+// the carried prefix), the permutation, and the move of the non-empty
+// bricks.  Steps that reorder no scene skip straight to the step control,
+// so they pay a single launch.
+//
+// Every wavefront works on one scene at a time, whose descriptor fields are
+// read through the scalar cache; the particle phases keep kSortU particles
+// per lane in flight, the brick phase kBrickU bricks per wavefront, and the
+// move kMoveLevels levels of a brick (half as many in FP64).  One 1024-thread
+// workgroup per CU: every workgroup's barrier fences write back and
+// invalidate its XCD's L2, so fewer, larger workgroups wait less.
+
+constexpr int kBrickU = 4;
+constexpr int kMoveLevels = 4;
 
 // Wait until every workgroup of the launch has arrived at barrier `round`
-// (1, 2, ...).  The arrival counter only grows within a launch, so no reset
-// is needed between barriers.  The grid is far below what the device holds
-// at once, so every workgroup is resident and the wait ends; it is bounded
-// all the same (kBarrierTicks of the constant-rate wall clock), and a
-// workgroup that gives up raises BF_SORT_FAIL before it arrives anywhere
-// else.  Returns whether the reorder may go on: the flag is read after the
-// wait, so a workgroup that continues has seen the previous phase complete
-// on every workgroup.
+// (1, 2, ...).  Workgroups form groups by blockIdx mod 8 (the XCD a
+// workgroup runs on): a workgroup arrives on its group's counter, the
+// group's last arrival on the grid counter, and the grid's last arrival
+// releases every group; a workgroup polls its group's release word.  The
+// counters only grow within a launch, so no reset is needed between
+// barriers.  The grid is far below what the device holds at once, so every
+// workgroup is resident and the wait ends; it is bounded all the same
+// (kBarrierTicks of the constant-rate wall clock), and a workgroup that
+// gives up raises BF_SORT_FAIL before it arrives anywhere else.  Returns
+// whether the reorder may go on: the flag is read after the wait, so a
+// workgroup that continues has seen the previous phase complete on every
+// workgroup.
 constexpr uint64_t kBarrierTicks = 100000000ull;   // 1 s at 100 MHz
 
 __device__ bool grid_barrier(uint32_t *flags, uint32_t round, int *sh)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
+        const uint32_t ng = min(gridDim.x, (uint32_t)kXcds);
+        const uint32_t g = blockIdx.x % ng;
+        const uint32_t size = (gridDim.x - g + ng - 1) / ng;   // workgroups in group g
         __threadfence();   // publish this workgroup's writes of the phase
-        atomicAdd(&flags[BF_GRID], 1u);
-        const uint32_t target = round * gridDim.x;
+        if (atomicAdd(&flags[BF_GROUP + 32 * g], 1u) + 1u == round * size) {
+            __threadfence();
+            if (atomicAdd(&flags[BF_GRID], 1u) + 1u == round * ng) {
+                __threadfence();
+                for (uint32_t q = 0; q < ng; ++q)
+                    __hip_atomic_store(&flags[BF_RELEASE + 32 * q], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(&flags[BF_GRID], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(&flags[BF_RELEASE + 32 * g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
             if (wall_clock64() - t0 > kBarrierTicks) {
                 atomicOr(&flags[BF_SORT_FAIL], 1u);
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(16);
         }
         __threadfence();   // see the other workgroups' writes
         *sh = __hip_atomic_load(&flags[BF_SORT_FAIL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
@@ -1014,173 +1020,497 @@ __device__ bool grid_barrier(uint32_t *flags, uint32_t round, int *sh)
     return *sh != 0;
 }
 
+// Load through the scalar cache: the address is wave-uniform and the data
+// does not change during the kernel.
+template <typename T>
+__device__ inline T cld(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)uni(p);
+}
+
+// Largest s with offs[s] <= g for a wave-uniform g (offs non-decreasing).
+__device__ inline int find_scene_u(const int64_t *offs, int nscenes, int64_t g)
+{
+    int lo = 0, hi = nscenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cld(&offs[mid]) <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// The reorder state of one scene, in scalar registers.
+struct SortView {
+    const SceneDev *S;
+    GLOBAL const uint32_t *cell;   // packed cells, current buffer
+    GLOBAL uint32_t *cnt, *cstart, *rank, *perm;
+    GLOBAL uint32_t *bcnt, *bitem, *bstart, *istart;
+    GLOBAL Item *items;
+    GLOBAL uint32_t *ctl;
+    uint32_t nb0, nb1;
+    uint32_t bo;    // flattened index of the scene's brick 0
+    int cur;
+    bool sorting;   // the scene reorders in the coming step
+    __device__ uint32_t key(uint32_t packed) const
+    {
+        int c[3];
+        unpack_cell(packed, c);
+        const uint32_t b = (uint32_t)(c[0] >> 2) + nb0 * ((uint32_t)(c[1] >> 2) + nb1 * (uint32_t)(c[2] >> 2));
+        return b * 64u + (uint32_t)((c[0] & 3) + 4 * ((c[1] & 3) + 4 * (c[2] & 3)));
+    }
+};
+
+__device__ inline SortView sort_view(const BatchDev &B, int s)
+{
+    SortView v;
+    const SceneDev *S = cld(&B.scenes[s]);
+    v.S = S;
+    uint32_t *ctl = cld(&S->ctl);
+    v.ctl = gp(ctl);
+    v.cur = (int)cld(&ctl[CTL_CUR]);
+    v.sorting = cld(&ctl[CTL_ERR]) == 0u && cld(&ctl[CTL_REMAIN]) > 0u && cld(&ctl[CTL_NEED_SORT]) != 0u;
+    v.cell = gp((const uint32_t *)cld(&S->cell[v.cur]));
+    v.cnt = gp(cld(&S->cnt));
+    v.cstart = gp(cld(&S->cstart));
+    v.rank = gp(cld(&S->rank));
+    v.perm = gp(cld(&S->perm));
+    v.bcnt = gp(cld(&S->bcnt));
+    v.bitem = gp(cld(&S->bitem));
+    v.bstart = gp(cld(&S->bstart));
+    v.istart = gp(cld(&S->istart));
+    v.items = gp(cld(&S->items));
+    v.nb0 = (uint32_t)cld(&S->nb[0]);
+    v.nb1 = (uint32_t)cld(&S->nb[1]);
+    v.bo = (uint32_t)cld(&B.boffs[s]);
+    return v;
+}
+
+__device__ inline uint32_t wave_index() { return uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
+__device__ inline uint32_t wave_count() { return uni((gridDim.x * blockDim.x) >> 6); }
+
+// The particle phases: each wavefront takes 64 * kSortU consecutive
+// particles of the flattened batch per pass and calls
+// f(view, first, lo, hi, off) once per reordering scene the span meets;
+// lane l's particles are first + u * 64 + l (u < kSortU), those in [lo, hi)
+// belong to the scene, whose particle 0 is flattened index off.
+template <typename F>
+__device__ inline void particle_spans(const BatchDev &B, F f)
+{
+    constexpr int64_t SPAN = 64 * kSortU;
+    for (int64_t first = (int64_t)wave_index() * SPAN; first < B.total_particles;
+         first += (int64_t)wave_count() * SPAN) {
+        const int64_t end = min(first + SPAN, B.total_particles);
+        int s = find_scene_u(B.poffs, B.nscenes, first);
+        for (int64_t lo = first; lo < end; ++s) {
+            const int64_t off = cld(&B.poffs[s]), hi = min(end, cld(&B.poffs[s + 1]));
+            if (hi <= lo)
+                continue;
+            const SortView v = sort_view(B, s);
+            if (v.sorting)
+                f(v, first, lo, hi, off);
+            lo = hi;
+        }
+    }
+}
+
 // rank[p] = arrival order of p among the particles of its cell.
 __device__ void sort_count(const BatchDev &B)
 {
-    for (int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gp < B.total_particles;
-         gp += (int64_t)gridDim.x * blockDim.x) {
-        const int s = find_scene(B.poffs, B.nscenes, gp);
-        const SceneDev &S = *B.scenes[s];
-        if (!scene_sorting(S))
-            continue;
-        const int64_t p = gp - B.poffs[s];
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
-        S.rank[p] = atomicAdd(&S.cnt[brick_key(S, pick(S.cell, cur)[p])], 1u);
-    }
+    const int lane = threadIdx.x & 63;
+    particle_spans(B, [&](const SortView &v, int64_t first, int64_t lo, int64_t hi, int64_t off) {
+        // loads for every lane (an idle lane reads particle 0 of the scene),
+        // so all of them are in flight together
+        uint32_t p[kSortU], key[kSortU];
+        bool act[kSortU];
+        for (int u = 0; u < kSortU; ++u) {
+            const int64_t g = first + u * 64 + lane;
+            act[u] = g >= lo && g < hi;
+            p[u] = act[u] ? (uint32_t)(g - off) : 0u;
+        }
+        for (int u = 0; u < kSortU; ++u)
+            key[u] = v.cell[p[u]];
+        for (int u = 0; u < kSortU; ++u)
+            if (act[u])
+                v.rank[p[u]] = atomicAdd((uint32_t *)&v.cnt[v.key(key[u])], 1u);
+    });
 }
 
-// One wavefront per brick: the brick's particle count, its work-item count
-// and the cell-major start of every cell inside the brick.
+// One wavefront per brick (kBrickU of them per pass): the brick's particle
+// count, its work-item count and the cell-major start of every cell inside
+// the brick (written for non-empty bricks only: nothing reads the others).
 __device__ void sort_bricks(const BatchDev &B)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
-        const int s = find_scene(B.boffs, B.nscenes, gb);
-        const SceneDev &S = *B.scenes[s];
-        if (!scene_sorting(S))
-            continue;
-        const int64_t b = gb - B.boffs[s];
-        const uint32_t c = S.cnt[b * 64 + lane];
-        uint32_t inc = c;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(inc, o);
-            if (lane >= o)
-                inc += t;
+    for (int64_t g0 = (int64_t)wave_index() * kBrickU; g0 < B.total_bricks; g0 += (int64_t)wave_count() * kBrickU) {
+        uint32_t c[kBrickU], b[kBrickU];
+        int s[kBrickU];
+        bool act[kBrickU];
+        for (int u = 0; u < kBrickU; ++u) {
+            const int64_t gb = g0 + u;
+            act[u] = gb < B.total_bricks;
+            s[u] = act[u] ? find_scene_u(B.boffs, B.nscenes, gb) : 0;
+            const SortView v = sort_view(B, s[u]);
+            act[u] = act[u] && v.sorting;
+            b[u] = (uint32_t)(gb - v.bo);
+            c[u] = act[u] ? v.cnt[b[u] * 64 + lane] : 0u;
         }
-        S.cstart[b * 64 + lane] = inc - c;   // cell-major start inside the brick
-        if (lane == 63) {
-            S.bcnt[b] = inc;
-            S.bitem[b] = (inc + kChunk - 1) / kChunk;
+        for (int u = 0; u < kBrickU; ++u) {
+            if (!act[u])
+                continue;
+            const SortView v = sort_view(B, s[u]);
+            uint32_t inc = c[u];
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o);
+                if (lane >= o)
+                    inc += t;
+            }
+            const uint32_t tot = uni((uint32_t)__shfl(inc, 63));
+            if (tot)
+                v.cstart[b[u] * 64 + lane] = inc - c[u];   // cell-major start inside the brick
+            if (lane == 0) {
+                v.bcnt[b[u]] = tot;
+                v.bitem[b[u]] = (tot + kChunk - 1) / kChunk;
+            }
         }
     }
 }
 
-// Exclusive scan of the particle and item counts of a scene's bricks by one
-// workgroup.
-__device__ void scan_bricks(const SceneDev &S)
+// --- scan over the bricks of every reordering scene (segmented by scene) --
+// Workgroup j takes a contiguous range of the flattened brick list and each
+// of its threads a contiguous run of that range.
+
+// Particle and item sums after the last scene start of a run (f: a scene
+// starts inside the run); join(a, b) is the run a followed by the run b.
+struct Seg {
+    uint32_t p, i, f;
+};
+
+__device__ inline Seg seg_join(const Seg &a, const Seg &b)
 {
-    __shared__ uint32_t sp[kBlock], si[kBlock];
-    const int64_t nb = S.nbricks;
-    const int64_t per = (nb + blockDim.x - 1) / blockDim.x;
-    const int64_t b0 = min((int64_t)threadIdx.x * per, nb);
-    const int64_t b1 = min(b0 + per, nb);
-    uint32_t tp = 0, ti = 0;
-    for (int64_t b = b0; b < b1; ++b) {
-        tp += S.bcnt[b];
-        ti += S.bitem[b];
+    return b.f ? b : Seg{a.p + b.p, a.i + b.i, a.f};
+}
+
+struct BrickRun {
+    uint32_t lo, hi;   // flattened brick indices [lo, hi)
+};
+
+__device__ inline BrickRun thread_run(const BatchDev &B)
+{
+    const uint32_t total = (uint32_t)B.total_bricks;
+    const uint32_t per_block = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t b0 = min(blockIdx.x * per_block, total), b1 = min(b0 + per_block, total);
+    const uint32_t per = (b1 - b0 + blockDim.x - 1) / blockDim.x;
+    const uint32_t lo = min(b0 + threadIdx.x * per, b1);
+    return {lo, min(lo + per, b1)};
+}
+
+// A thread's walk over its run, scene by scene (vector loads: neighbouring
+// threads may be in different scenes).  f(scene, sorting, brick in scene,
+// first brick of its scene, last brick of its scene).
+template <typename F>
+__device__ inline void walk_run(const BatchDev &B, const BrickRun &r, F f)
+{
+    if (r.lo >= r.hi)
+        return;
+    int s = find_scene(B.boffs, B.nscenes, (int64_t)r.lo);
+    uint32_t s_lo = (uint32_t)B.boffs[s], s_hi = (uint32_t)B.boffs[s + 1];
+    const SceneDev *S = B.scenes[s];
+    bool sorting = S->ctl[CTL_ERR] == 0u && S->ctl[CTL_REMAIN] > 0u && S->ctl[CTL_NEED_SORT] != 0u;
+    for (uint32_t gb = r.lo; gb < r.hi; ++gb) {
+        while (gb >= s_hi) {
+            ++s;
+            s_lo = s_hi;
+            s_hi = (uint32_t)B.boffs[s + 1];
+            S = B.scenes[s];
+            sorting = S->ctl[CTL_ERR] == 0u && S->ctl[CTL_REMAIN] > 0u && S->ctl[CTL_NEED_SORT] != 0u;
+        }
+        f(S, sorting, gb - s_lo, gb == s_lo, gb + 1 == s_hi);
     }
-    sp[threadIdx.x] = tp;
-    si[threadIdx.x] = ti;
+}
+
+// Workgroup-wide inclusive scan of Seg values with seg_join.
+__device__ inline Seg block_seg_scan(Seg v)
+{
+    __shared__ uint32_t sp[kBlock], si[kBlock], sf[kBlock];
+    sp[threadIdx.x] = v.p;
+    si[threadIdx.x] = v.i;
+    sf[threadIdx.x] = v.f;
     __syncthreads();
     for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        const uint32_t a = threadIdx.x >= (unsigned)o ? sp[threadIdx.x - o] : 0u;
-        const uint32_t c = threadIdx.x >= (unsigned)o ? si[threadIdx.x - o] : 0u;
+        Seg a{0u, 0u, 0u};
+        const bool has = threadIdx.x >= (unsigned)o;
+        if (has)
+            a = Seg{sp[threadIdx.x - o], si[threadIdx.x - o], sf[threadIdx.x - o]};
         __syncthreads();
-        sp[threadIdx.x] += a;
-        si[threadIdx.x] += c;
+        if (has)
+            v = seg_join(a, v);
+        sp[threadIdx.x] = v.p;
+        si[threadIdx.x] = v.i;
+        sf[threadIdx.x] = v.f;
         __syncthreads();
     }
-    uint32_t rp = sp[threadIdx.x] - tp, ri = si[threadIdx.x] - ti;
-    for (int64_t b = b0; b < b1; ++b) {
-        S.bstart[b] = rp;
-        S.istart[b] = ri;
-        rp += S.bcnt[b];
-        ri += S.bitem[b];
-    }
+    return v;
+}
+
+// Phase 1 of the scan: this workgroup's partial sums into B.scan.
+__device__ void scan_partials(const BatchDev &B)
+{
+    const BrickRun r = thread_run(B);
+    Seg acc{0u, 0u, 0u};
+    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t b, bool first, bool) {
+        if (first)
+            acc = Seg{0u, 0u, 1u};
+        if (sorting) {
+            acc.p += gp(S->bcnt)[b];
+            acc.i += gp(S->bitem)[b];
+        }
+    });
+    const Seg tot = block_seg_scan(acc);
     if (threadIdx.x == blockDim.x - 1) {
-        S.bstart[nb] = sp[threadIdx.x];
-        S.istart[nb] = si[threadIdx.x];
-        S.ctl[CTL_N_ITEMS] = si[threadIdx.x];
+        gp(B.scan)[4 * blockIdx.x] = tot.p;
+        gp(B.scan)[4 * blockIdx.x + 1] = tot.i;
+        gp(B.scan)[4 * blockIdx.x + 2] = tot.f;
+    }
+}
+
+// Phase 2: the carried prefix from the earlier workgroups' sums (back to
+// the last one in which a scene starts), then every brick's exclusive
+// particle and item start, and each scene's totals.
+__device__ void scan_finish(const BatchDev &B)
+{
+    __shared__ uint32_t red[kBlock / 64][2];
+    __shared__ uint32_t carry[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const GLOBAL uint32_t *P = gp(B.scan);
+    // nearest earlier workgroup whose range holds a scene start
+    int k0 = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += blockDim.x)
+        if (P[4 * k + 2])
+            k0 = max(k0, k);
+    k0 = wave_reduce<true>(k0);
+    if (lane == 0)
+        red[wave][0] = (uint32_t)k0;
+    __syncthreads();
+    k0 = 0;
+    for (int w = 0; w < nw; ++w)
+        k0 = max(k0, (int)red[w][0]);
+    __syncthreads();
+    uint32_t cp = 0, ci = 0;
+    for (int k = k0 + threadIdx.x; k < (int)blockIdx.x; k += blockDim.x) {
+        cp += P[4 * k];
+        ci += P[4 * k + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        cp += __shfl_xor(cp, o);
+        ci += __shfl_xor(ci, o);
+    }
+    if (lane == 0) {
+        red[wave][0] = cp;
+        red[wave][1] = ci;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, c = 0;
+        for (int w = 0; w < nw; ++w) {
+            a += red[w][0];
+            c += red[w][1];
+        }
+        carry[0] = a;
+        carry[1] = c;
+    }
+    __syncthreads();
+    // this thread's run sums, then its start within the workgroup
+    const BrickRun r = thread_run(B);
+    Seg mine{0u, 0u, 0u};
+    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t b, bool first, bool) {
+        if (first)
+            mine = Seg{0u, 0u, 1u};
+        if (sorting) {
+            mine.p += gp(S->bcnt)[b];
+            mine.i += gp(S->bitem)[b];
+        }
+    });
+    const Seg inc = block_seg_scan(mine);
+    // exclusive start of the run: carried prefix joined with the earlier threads
+    __shared__ uint32_t xp[kBlock], xi[kBlock], xf[kBlock];
+    xp[threadIdx.x] = inc.p;
+    xi[threadIdx.x] = inc.i;
+    xf[threadIdx.x] = inc.f;
+    __syncthreads();
+    Seg run{carry[0], carry[1], 0u};
+    if (threadIdx.x > 0)
+        run = seg_join(run, Seg{xp[threadIdx.x - 1], xi[threadIdx.x - 1], xf[threadIdx.x - 1]});
+    __syncthreads();
+    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t b, bool first, bool last) {
+        if (first)
+            run = Seg{0u, 0u, 1u};
+        if (!sorting)
+            return;
+        const uint32_t bc = gp(S->bcnt)[b], bi = gp(S->bitem)[b];
+        gp(S->bstart)[b] = run.p;
+        gp(S->istart)[b] = run.i;
+        run.p += bc;
+        run.i += bi;
+        if (last) {
+            gp(S->bstart)[b + 1] = run.p;
+            gp(S->istart)[b + 1] = run.i;
+            gp(S->ctl)[CTL_N_ITEMS] = run.i;
+        }
+    });
 }
 
 // perm lists the particles cell-major: slot bstart[brick] + cstart[key] +
 // rank holds p.  The particle that opens a 512-slot chunk of its brick
-// writes that work item.
+// writes that work item; the brick's first particle lists the brick.
 __device__ void sort_perm(const BatchDev &B)
 {
-    for (int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gp < B.total_particles;
-         gp += (int64_t)gridDim.x * blockDim.x) {
-        const int s = find_scene(B.poffs, B.nscenes, gp);
-        const SceneDev &S = *B.scenes[s];
-        if (!scene_sorting(S))
-            continue;
-        const int64_t p = gp - B.poffs[s];
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
-        const uint32_t key = brick_key(S, pick(S.cell, cur)[p]);
-        const uint32_t b = key >> 6;
-        const uint32_t local = S.cstart[key] + S.rank[p];
-        const uint32_t bs = S.bstart[b];
-        S.perm[bs + local] = (uint32_t)p;
-        if (local % kChunk == 0) {
-            Item it;
-            it.start = bs + local;
-            it.count = min((uint32_t)kChunk, S.bcnt[b] - local);
-            it.brick = b;
-            it.pad = 0;
-            S.items[S.istart[b] + local / kChunk] = it;
+    const int lane = threadIdx.x & 63;
+    particle_spans(B, [&](const SortView &v, int64_t first, int64_t lo, int64_t hi, int64_t off) {
+        // loads for every lane (an idle lane reads particle 0 of the scene),
+        // so all of them are in flight together
+        uint32_t p[kSortU], key[kSortU], local[kSortU], bs[kSortU];
+        bool act[kSortU];
+        for (int u = 0; u < kSortU; ++u) {
+            const int64_t g = first + u * 64 + lane;
+            act[u] = g >= lo && g < hi;
+            p[u] = act[u] ? (uint32_t)(g - off) : 0u;
         }
-    }
+        for (int u = 0; u < kSortU; ++u)
+            key[u] = v.cell[p[u]];
+        for (int u = 0; u < kSortU; ++u)
+            key[u] = v.key(key[u]);
+        for (int u = 0; u < kSortU; ++u) {
+            local[u] = v.cstart[key[u]] + v.rank[p[u]];
+            bs[u] = v.bstart[key[u] >> 6];
+        }
+        for (int u = 0; u < kSortU; ++u) {
+            if (!act[u])
+                continue;
+            v.perm[bs[u] + local[u]] = p[u];
+            if (local[u] % kChunk == 0) {
+                const uint32_t b = key[u] >> 6;
+                Item it;
+                it.start = bs[u] + local[u];
+                it.count = min((uint32_t)kChunk, v.bcnt[b] - local[u]);
+                it.brick = b;
+                it.pad = 0;
+                ((Item *)v.items)[v.istart[b] + local[u] / kChunk] = it;
+                if (local[u] == 0)
+                    gp(B.bricks)[atomicAdd(&B.flags[BF_NBRICKS], 1u)] = v.bo + b;
+            }
+        }
+    });
 }
 
-// One wavefront per brick, lane = cell: write the brick's particles to the
-// other buffer in level-major order -- the first particle of every occupied
-// cell, then the second of every cell holding two or more, and so on.  A
-// wavefront of consecutive particles then spans distinct cells, so the
-// scatter kernels' LDS atomics for one node corner do not collide.  Resets
-// the per-cell counts for the next sort.
+// Particle arrays of one buffer for the move: one scalar base per field.
+template <typename R>
+struct MoveBuf {
+    GLOBAL double *x;
+    GLOBAL R *v, *sig, *vol, *mass;
+    GLOBAL uint32_t *cell, *pid;
+};
+
+template <typename R>
+__device__ inline MoveBuf<R> move_buf(const SceneDev *S, int b)
+{
+    MoveBuf<R> m;
+    m.x = gp(cld(&S->x[b]));
+    m.v = gp((R *)cld(&S->v[b]));
+    m.sig = gp((R *)cld(&S->sig[b]));
+    m.vol = gp((R *)cld(&S->vol[b]));
+    m.mass = gp((R *)cld(&S->mass[b]));
+    m.cell = gp(cld(&S->cell[b]));
+    m.pid = gp(cld(&S->pid[b]));
+    return m;
+}
+
+// One particle's state in registers.
+template <typename R>
+struct MoveRec {
+    double x[3];
+    R v[3], sig[6], vol, mass;
+    uint32_t cell, pid;
+};
+
+// One wavefront per listed (non-empty) brick, lane = cell: write the
+// brick's particles to the other buffer in level-major order -- the first
+// particle of every occupied cell, then the second of every cell holding two
+// or more, and so on.  A wavefront of consecutive particles then spans
+// distinct cells, so the scatter kernels' LDS atomics for one node corner do
+// not collide.  Each pass reads kMoveLevels levels before it writes any.
+// Resets the brick's per-cell counts for the next sort.
 template <typename R>
 __device__ void sort_move(const BatchDev &B)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t gb = wave; gb < B.total_bricks; gb += nwaves) {
-        const int s = find_scene(B.boffs, B.nscenes, gb);
-        const SceneDev &S = *B.scenes[s];
-        if (!scene_sorting(S))
-            continue;
-        const int64_t b = gb - B.boffs[s];
-        const int64_t n = S.np;
-        const int cur = (int)uni(S.ctl[CTL_CUR]), nxt = cur ^ 1;
-        const uint32_t nc = S.cnt[b * 64 + lane];
-        const uint32_t cs = S.bstart[b] + S.cstart[b * 64 + lane];
-        S.cnt[b * 64 + lane] = 0u;
+    const uint32_t nbr = uni(__hip_atomic_load(&B.flags[BF_NBRICKS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    for (uint32_t i = wave_index(); i < nbr; i += wave_count()) {
+        const uint32_t gb = uni(gp(B.bricks)[i]);
+        const int s = find_scene_u(B.boffs, B.nscenes, gb);
+        const SortView sv = sort_view(B, s);
+        const uint32_t n = (uint32_t)cld(&sv.S->np);
+        const MoveBuf<R> src = move_buf<R>(sv.S, sv.cur), dst = move_buf<R>(sv.S, sv.cur ^ 1);
+        const uint32_t b = gb - sv.bo;
+        const uint32_t nc = sv.cnt[b * 64 + lane];
+        const uint32_t bs = uni(sv.bstart[b]);
+        const uint32_t cs = bs + sv.cstart[b * 64 + lane];
+        sv.cnt[b * 64 + lane] = 0u;
         uint32_t levels = nc;
         for (int o = 32; o > 0; o >>= 1)
             levels = max(levels, (uint32_t)__shfl_xor(levels, o));
-        int64_t base = S.bstart[b];
-        for (uint32_t j = 0; j < levels; ++j) {
-            const bool act = j < nc;
-            const uint64_t m = __ballot(act);
-            if (act) {
-                const int64_t p = S.perm[cs + j];
-                const int64_t d = base + __popcll(m & below);
+        levels = uni(levels);
+        uint32_t base = bs;
+        constexpr int ML = sizeof(R) == 4 ? kMoveLevels : kMoveLevels / 2;   // within 128 VGPRs
+        for (uint32_t j0 = 0; j0 < levels; j0 += ML) {
+            MoveRec<R> r[ML];
+            uint32_t d[ML];
+            bool act[ML];
+            for (int l = 0; l < ML; ++l) {
+                act[l] = j0 + l < nc;
+                const uint64_t m = __ballot(act[l]);
+                d[l] = base + (uint32_t)__popcll(m & below);
+                base += (uint32_t)__popcll(m);
+                if (!act[l])
+                    continue;
+                const uint32_t p = sv.perm[cs + j0 + l];
                 for (int a = 0; a < 3; ++a) {
-                    pick(S.x, nxt)[a * n + d] = pick(S.x, cur)[a * n + p];
-                    ((R *)pick(S.v, nxt))[a * n + d] = ((const R *)pick(S.v, cur))[a * n + p];
+                    r[l].x[a] = ldg(src.x, a * n + p);
+                    r[l].v[a] = ldg(src.v, a * n + p);
                 }
                 for (int k = 0; k < 6; ++k)
-                    ((R *)pick(S.sig, nxt))[k * n + d] = ((const R *)pick(S.sig, cur))[k * n + p];
-                ((R *)pick(S.vol, nxt))[d] = ((const R *)pick(S.vol, cur))[p];
-                ((R *)pick(S.mass, nxt))[d] = ((const R *)pick(S.mass, cur))[p];
-                pick(S.cell, nxt)[d] = pick(S.cell, cur)[p];
-                pick(S.pid, nxt)[d] = pick(S.pid, cur)[p];
+                    r[l].sig[k] = ldg(src.sig, k * n + p);
+                r[l].vol = ldg(src.vol, p);
+                r[l].mass = ldg(src.mass, p);
+                r[l].cell = ldg(src.cell, p);
+                r[l].pid = ldg(src.pid, p);
             }
-            base += __popcll(m);
+            for (int l = 0; l < ML; ++l) {
+                if (!act[l])
+                    continue;
+                const uint32_t q = d[l];
+                for (int a = 0; a < 3; ++a) {
+                    stg(dst.x, a * n + q, r[l].x[a]);
+                    stg(dst.v, a * n + q, r[l].v[a]);
+                }
+                for (int k = 0; k < 6; ++k)
+                    stg(dst.sig, k * n + q, r[l].sig[k]);
+                stg(dst.vol, q, r[l].vol);
+                stg(dst.mass, q, r[l].mass);
+                stg(dst.cell, q, r[l].cell);
+                stg(dst.pid, q, r[l].pid);
+            }
         }
     }
 }
 
-// Reorder of the flagged scenes (count, per-brick scan, per-scene scan,
-// permutation, move), then the step control in the last workgroup to finish.
-// A phase runs only if no workgroup gave up waiting at the barrier before
-// it; the step control then fails the reordering scenes (ERR_SORT) and
-// keeps their particles where they were.
+// Reorder of the flagged scenes, then the step control in the last
+// workgroup to finish.  A phase runs only if no workgroup gave up waiting
+// at the barrier before it; the step control then fails the reordering
+// scenes (ERR_SORT) and keeps their particles where they were.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_reorder(BatchDev B)
 {
@@ -1195,21 +1525,20 @@ __global__ void __launch_bounds__(kBlock) k_reorder(BatchDev B)
     if (grid_barrier(B.flags, 1, &sh))
         sort_bricks(B);
     if (grid_barrier(B.flags, 2, &sh))
-        for (int s = blockIdx.x; s < B.nscenes; s += gridDim.x)
-            if (scene_sorting(*B.scenes[s]))
-                scan_bricks(*B.scenes[s]);
+        scan_partials(B);
     if (grid_barrier(B.flags, 3, &sh))
-        sort_perm(B);
+        scan_finish(B);
     if (grid_barrier(B.flags, 4, &sh))
+        sort_perm(B);
+    if (grid_barrier(B.flags, 5, &sh))
         sort_move<R>(B);
     if (!last_block(&B.flags[BF_TICKET_MOVE], &sh))
         return;
     step_control(B);
-    if (threadIdx.x == 0) {
-        B.flags[BF_TICKET_MOVE] = 0u;
-        B.flags[BF_GRID] = 0u;
-        B.flags[BF_SORT_FAIL] = 0u;
-    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < BF_WORDS; w += blockDim.x)
+        if (w != BF_ANY_SORT)
+            B.flags[w] = 0u;
 }
 
 // ------------------------------------------------------- item kernels --
