@@ -1183,14 +1183,16 @@ __device__ void sort_bricks(const BatchDev &B)
 // of its threads a contiguous run of that range.
 
 // Particle and item sums after the last scene start of a run (f: a scene
-// starts inside the run); join(a, b) is the run a followed by the run b.
+// starts inside the run), and the run's count of non-empty bricks of
+// reordering scenes (not reset at scene starts: it numbers the batch's list
+// of such bricks); join(a, b) is the run a followed by the run b.
 struct Seg {
-    uint32_t p, i, f;
+    uint32_t p, i, f, n;
 };
 
 __device__ inline Seg seg_join(const Seg &a, const Seg &b)
 {
-    return b.f ? b : Seg{a.p + b.p, a.i + b.i, a.f};
+    return b.f ? Seg{b.p, b.i, 1u, a.n + b.n} : Seg{a.p + b.p, a.i + b.i, a.f, a.n + b.n};
 }
 
 struct BrickRun {
@@ -1208,8 +1210,8 @@ __device__ inline BrickRun thread_run(const BatchDev &B)
 }
 
 // A thread's walk over its run, scene by scene (vector loads: neighbouring
-// threads may be in different scenes).  f(scene, sorting, brick in scene,
-// first brick of its scene, last brick of its scene).
+// threads may be in different scenes).  f(scene, sorting, flattened brick,
+// brick in scene, first brick of its scene, last brick of its scene).
 template <typename F>
 __device__ inline void walk_run(const BatchDev &B, const BrickRun &r, F f)
 {
@@ -1227,29 +1229,25 @@ __device__ inline void walk_run(const BatchDev &B, const BrickRun &r, F f)
             S = B.scenes[s];
             sorting = S->ctl[CTL_ERR] == 0u && S->ctl[CTL_REMAIN] > 0u && S->ctl[CTL_NEED_SORT] != 0u;
         }
-        f(S, sorting, gb - s_lo, gb == s_lo, gb + 1 == s_hi);
+        f(S, sorting, gb, gb - s_lo, gb == s_lo, gb + 1 == s_hi);
     }
 }
 
 // Workgroup-wide inclusive scan of Seg values with seg_join.
 __device__ inline Seg block_seg_scan(Seg v)
 {
-    __shared__ uint32_t sp[kBlock], si[kBlock], sf[kBlock];
-    sp[threadIdx.x] = v.p;
-    si[threadIdx.x] = v.i;
-    sf[threadIdx.x] = v.f;
+    __shared__ Seg sv[kBlock];
+    sv[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        Seg a{0u, 0u, 0u};
+        Seg a{0u, 0u, 0u, 0u};
         const bool has = threadIdx.x >= (unsigned)o;
         if (has)
-            a = Seg{sp[threadIdx.x - o], si[threadIdx.x - o], sf[threadIdx.x - o]};
+            a = sv[threadIdx.x - o];
         __syncthreads();
         if (has)
             v = seg_join(a, v);
-        sp[threadIdx.x] = v.p;
-        si[threadIdx.x] = v.i;
-        sf[threadIdx.x] = v.f;
+        sv[threadIdx.x] = v;
         __syncthreads();
     }
     return v;
@@ -1259,13 +1257,15 @@ __device__ inline Seg block_seg_scan(Seg v)
 __device__ void scan_partials(const BatchDev &B)
 {
     const BrickRun r = thread_run(B);
-    Seg acc{0u, 0u, 0u};
-    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t b, bool first, bool) {
+    Seg acc{0u, 0u, 0u, 0u};
+    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t, uint32_t b, bool first, bool) {
         if (first)
-            acc = Seg{0u, 0u, 1u};
+            acc = Seg{0u, 0u, 1u, acc.n};
         if (sorting) {
-            acc.p += gp(S->bcnt)[b];
+            const uint32_t bc = gp(S->bcnt)[b];
+            acc.p += bc;
             acc.i += gp(S->bitem)[b];
+            acc.n += bc ? 1u : 0u;
         }
     });
     const Seg tot = block_seg_scan(acc);
@@ -1273,16 +1273,18 @@ __device__ void scan_partials(const BatchDev &B)
         gp(B.scan)[4 * blockIdx.x] = tot.p;
         gp(B.scan)[4 * blockIdx.x + 1] = tot.i;
         gp(B.scan)[4 * blockIdx.x + 2] = tot.f;
+        gp(B.scan)[4 * blockIdx.x + 3] = tot.n;
     }
 }
 
 // Phase 2: the carried prefix from the earlier workgroups' sums (back to
-// the last one in which a scene starts), then every brick's exclusive
-// particle and item start, and each scene's totals.
+// the last one in which a scene starts; the brick count from all of them),
+// then every brick's exclusive particle and item start, each scene's
+// totals, and the batch's list of non-empty bricks in brick order.
 __device__ void scan_finish(const BatchDev &B)
 {
-    __shared__ uint32_t red[kBlock / 64][2];
-    __shared__ uint32_t carry[2];
+    __shared__ uint32_t red[kBlock / 64][3];
+    __shared__ uint32_t carry[3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const GLOBAL uint32_t *P = gp(B.scan);
     // nearest earlier workgroup whose range holds a scene start
@@ -1298,60 +1300,68 @@ __device__ void scan_finish(const BatchDev &B)
     for (int w = 0; w < nw; ++w)
         k0 = max(k0, (int)red[w][0]);
     __syncthreads();
-    uint32_t cp = 0, ci = 0;
+    uint32_t cp = 0, ci = 0, cn = 0;
     for (int k = k0 + threadIdx.x; k < (int)blockIdx.x; k += blockDim.x) {
         cp += P[4 * k];
         ci += P[4 * k + 1];
     }
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += blockDim.x)
+        cn += P[4 * k + 3];
     for (int o = 32; o > 0; o >>= 1) {
         cp += __shfl_xor(cp, o);
         ci += __shfl_xor(ci, o);
+        cn += __shfl_xor(cn, o);
     }
     if (lane == 0) {
         red[wave][0] = cp;
         red[wave][1] = ci;
+        red[wave][2] = cn;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t a = 0, c = 0;
+        uint32_t a = 0, c = 0, m = 0;
         for (int w = 0; w < nw; ++w) {
             a += red[w][0];
             c += red[w][1];
+            m += red[w][2];
         }
         carry[0] = a;
         carry[1] = c;
+        carry[2] = m;
     }
     __syncthreads();
     // this thread's run sums, then its start within the workgroup
     const BrickRun r = thread_run(B);
-    Seg mine{0u, 0u, 0u};
-    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t b, bool first, bool) {
+    Seg mine{0u, 0u, 0u, 0u};
+    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t, uint32_t b, bool first, bool) {
         if (first)
-            mine = Seg{0u, 0u, 1u};
+            mine = Seg{0u, 0u, 1u, mine.n};
         if (sorting) {
-            mine.p += gp(S->bcnt)[b];
+            const uint32_t bc = gp(S->bcnt)[b];
+            mine.p += bc;
             mine.i += gp(S->bitem)[b];
+            mine.n += bc ? 1u : 0u;
         }
     });
     const Seg inc = block_seg_scan(mine);
     // exclusive start of the run: carried prefix joined with the earlier threads
-    __shared__ uint32_t xp[kBlock], xi[kBlock], xf[kBlock];
-    xp[threadIdx.x] = inc.p;
-    xi[threadIdx.x] = inc.i;
-    xf[threadIdx.x] = inc.f;
+    __shared__ Seg xs[kBlock];
+    xs[threadIdx.x] = inc;
     __syncthreads();
-    Seg run{carry[0], carry[1], 0u};
+    Seg run{carry[0], carry[1], 0u, carry[2]};
     if (threadIdx.x > 0)
-        run = seg_join(run, Seg{xp[threadIdx.x - 1], xi[threadIdx.x - 1], xf[threadIdx.x - 1]});
+        run = seg_join(run, xs[threadIdx.x - 1]);
     __syncthreads();
-    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t b, bool first, bool last) {
+    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t gb, uint32_t b, bool first, bool last) {
         if (first)
-            run = Seg{0u, 0u, 1u};
+            run = Seg{0u, 0u, 1u, run.n};
         if (!sorting)
             return;
         const uint32_t bc = gp(S->bcnt)[b], bi = gp(S->bitem)[b];
         gp(S->bstart)[b] = run.p;
         gp(S->istart)[b] = run.i;
+        if (bc)
+            gp(B.bricks)[run.n++] = gb;
         run.p += bc;
         run.i += bi;
         if (last) {
@@ -1360,11 +1370,13 @@ __device__ void scan_finish(const BatchDev &B)
             gp(S->ctl)[CTL_N_ITEMS] = run.i;
         }
     });
+    if (r.lo < r.hi && r.hi == (uint32_t)B.total_bricks)   // the batch's last brick
+        B.flags[BF_NBRICKS] = run.n;
 }
 
 // perm lists the particles cell-major: slot bstart[brick] + cstart[key] +
 // rank holds p.  The particle that opens a 512-slot chunk of its brick
-// writes that work item; the brick's first particle lists the brick.
+// writes that work item.
 __device__ void sort_perm(const BatchDev &B)
 {
     const int lane = threadIdx.x & 63;
@@ -1398,8 +1410,6 @@ __device__ void sort_perm(const BatchDev &B)
                 it.brick = b;
                 it.pad = 0;
                 ((Item *)v.items)[v.istart[b] + local[u] / kChunk] = it;
-                if (local[u] == 0)
-                    gp(B.bricks)[atomicAdd(&B.flags[BF_NBRICKS], 1u)] = v.bo + b;
             }
         }
     });
