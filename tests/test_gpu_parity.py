@@ -430,6 +430,39 @@ def test_batches_with_fewer_items_than_workgroups_per_xcd(mp):
         c.close()
 
 
+def test_reorder_of_many_scenes_on_large_meshes(ctx, mp):
+    """Small blocks of fast particles on large, mostly empty meshes (up to
+    1,400 bricks each): the batch's brick list spans many reorder
+    workgroups, so one scene's bricks cross several workgroups' ranges of
+    the brick scan and ranges hold scene starts.  Every other scene
+    reorders every step and the rest on demand, with an empty scene among
+    them; in FP64 every scene matches the oracle, and the reorder counts
+    show which reordered."""
+    scs, policies = [], []
+    for i in range(16):
+        mesh_cells = (20 + 3 * i, 16 + 2 * i, 12 + 2 * i)
+        sc = scenes.random_block(n_cells=(2 + i % 4, 3, 2 + i % 3), mesh_cells=mesh_cells, h=0.05, seed=300 + i,
+                                 material=MATERIALS["dp" if i % 2 else "le"], vel=4.0, dt=1e-4)
+        if i == 7:
+            for key in ("x", "v", "vol", "mass", "stress"):
+                sc[key] = np.ascontiguousarray(sc[key][:0])
+        scs.append(sc)
+        policies.append(mp.SORT_ALWAYS if i % 2 == 0 else mp.SORT_ON_DEMAND)
+    ss = [ctx.create_scene(sc, precision=mp.FP64, sort_policy=pol) for sc, pol in zip(scs, policies)]
+    nsteps = 14
+    ctx.batch_step(ss, [nsteps] * len(ss))
+    for i, (sc, s, pol) in enumerate(zip(scs, ss, policies)):
+        st = s.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == nsteps, (i, st)
+        if len(sc["x"]) and pol == mp.SORT_ALWAYS:
+            assert st["n_sorts"] == nsteps, (i, st)
+        got = s.read()
+        if len(sc["x"]):
+            ref = oracle.run(sc, nsteps)
+            check_state(f"reorder/{i}/{len(sc['x'])}", got, ref, sc["x"], 1e-9, 1e-9, 1e-9)
+        s.destroy()
+
+
 def _fixed(c, mp, graph_steps, t_stress=128, t_g2p=128, blocks=16):
     c.set_option(mp.OPT_STRESS_THREADS, t_stress)
     c.set_option(mp.OPT_G2P_THREADS, t_g2p)
