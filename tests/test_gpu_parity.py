@@ -480,7 +480,7 @@ def test_graph_replays_match_direct_launches(mp):
     try:
         _fixed(cg, mp, 4)
         _fixed(ce, mp, 0)
-        # reorder every step, so the recorded sort kernels do real work
+        # reorder every step, so the recorded reorder launches do real work
         sg = cg.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS)
         se = ce.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS)
         for rep in range(5):
