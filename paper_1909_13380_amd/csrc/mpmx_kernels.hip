@@ -957,10 +957,11 @@ __device__ void step_control(const BatchDev &B)
 }
 
 // ----------------------------------------------------------------- sort --
-// The reorder runs as one launch of a few workgroups per compute unit, in
-// six phases separated by grid-wide barriers: per-cell counts, per-brick
-// cell scan, the scan over bricks (block partial sums, then the rescan with
-// the carried prefix), the permutation, and the move of the non-empty
+// The reorder runs as one launch of one workgroup per compute unit, in
+// five phases separated by grid-wide barriers: per-cell counts; per-brick
+// cell scan with each workgroup's partial sums of the scan over bricks; the
+// rest of that scan (the carried prefix, every brick's start, the list of
+// non-empty bricks); the permutation; and the move of the non-empty
 // bricks.  Steps that reorder no scene skip straight to the step control,
 // so they pay a single launch.
 //
@@ -971,7 +972,7 @@ __device__ void step_control(const BatchDev &B)
 // workgroup per CU: every workgroup's barrier fences write back and
 // invalidate its XCD's L2, so fewer, larger workgroups wait less.
 
-constexpr int kBrickU = 4;
+constexpr int kBrickU = 8;
 constexpr int kMoveLevels = 4;
 
 // Wait until every workgroup of the launch has arrived at barrier `round`
@@ -1138,46 +1139,6 @@ __device__ void sort_count(const BatchDev &B)
     });
 }
 
-// One wavefront per brick (kBrickU of them per pass): the brick's particle
-// count, its work-item count and the cell-major start of every cell inside
-// the brick (written for non-empty bricks only: nothing reads the others).
-__device__ void sort_bricks(const BatchDev &B)
-{
-    const int lane = threadIdx.x & 63;
-    for (int64_t g0 = (int64_t)wave_index() * kBrickU; g0 < B.total_bricks; g0 += (int64_t)wave_count() * kBrickU) {
-        uint32_t c[kBrickU], b[kBrickU];
-        int s[kBrickU];
-        bool act[kBrickU];
-        for (int u = 0; u < kBrickU; ++u) {
-            const int64_t gb = g0 + u;
-            act[u] = gb < B.total_bricks;
-            s[u] = act[u] ? find_scene_u(B.boffs, B.nscenes, gb) : 0;
-            const SortView v = sort_view(B, s[u]);
-            act[u] = act[u] && v.sorting;
-            b[u] = (uint32_t)(gb - v.bo);
-            c[u] = act[u] ? v.cnt[b[u] * 64 + lane] : 0u;
-        }
-        for (int u = 0; u < kBrickU; ++u) {
-            if (!act[u])
-                continue;
-            const SortView v = sort_view(B, s[u]);
-            uint32_t inc = c[u];
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t t = __shfl_up(inc, o);
-                if (lane >= o)
-                    inc += t;
-            }
-            const uint32_t tot = uni((uint32_t)__shfl(inc, 63));
-            if (tot)
-                v.cstart[b[u] * 64 + lane] = inc - c[u];   // cell-major start inside the brick
-            if (lane == 0) {
-                v.bcnt[b[u]] = tot;
-                v.bitem[b[u]] = (tot + kChunk - 1) / kChunk;
-            }
-        }
-    }
-}
-
 // --- scan over the bricks of every reordering scene (segmented by scene) --
 // Workgroup j takes a contiguous range of the flattened brick list and each
 // of its threads a contiguous run of that range.
@@ -1233,6 +1194,79 @@ __device__ inline void walk_run(const BatchDev &B, const BrickRun &r, F f)
     }
 }
 
+// One wavefront per brick, over a contiguous run of the workgroup's range
+// of the flattened brick list (kBrickU bricks per pass): the brick's
+// particle count, its work-item count and the cell-major start of every
+// cell inside the brick (written for non-empty bricks only: nothing reads
+// the others).  The workgroup then writes its range's partial sums for the
+// brick scan into B.scan.
+__device__ void sort_bricks(const BatchDev &B)
+{
+    __shared__ Seg wseg[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t total = (uint32_t)B.total_bricks;
+    const uint32_t per_block = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t b0 = min(blockIdx.x * per_block, total), b1 = min(b0 + per_block, total);
+    const uint32_t per_wave = (b1 - b0 + nw - 1) / nw;
+    const uint32_t w0 = uni(min(b0 + wave * per_wave, b1)), w1 = uni(min(w0 + per_wave, b1));
+    Seg acc{0u, 0u, 0u, 0u};
+    if (w0 < w1) {
+        int s = find_scene_u(B.boffs, B.nscenes, w0);
+        uint32_t s_hi = (uint32_t)cld(&B.boffs[s + 1]);
+        SortView v = sort_view(B, s);
+        for (uint32_t gb = w0; gb < w1;) {
+            while (gb >= s_hi) {
+                ++s;
+                s_hi = (uint32_t)cld(&B.boffs[s + 1]);
+                v = sort_view(B, s);
+            }
+            const uint32_t n = min(min(w1, s_hi) - gb, (uint32_t)kBrickU);
+            const uint32_t bb = gb - v.bo;   // brick of the scene
+            if (bb == 0)
+                acc = Seg{0u, 0u, 1u, acc.n};
+            if (v.sorting) {
+                uint32_t c[kBrickU];
+                for (int u = 0; u < kBrickU; ++u)
+                    c[u] = (uint32_t)u < n ? v.cnt[(bb + u) * 64 + lane] : 0u;
+                for (int u = 0; u < kBrickU; ++u) {
+                    if ((uint32_t)u >= n)
+                        break;
+                    uint32_t inc = c[u];
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t t = __shfl_up(inc, o);
+                        if (lane >= o)
+                            inc += t;
+                    }
+                    const uint32_t tot = uni((uint32_t)__shfl(inc, 63));
+                    const uint32_t items = (tot + kChunk - 1) / kChunk;
+                    if (tot)
+                        v.cstart[(bb + u) * 64 + lane] = inc - c[u];   // cell-major start inside the brick
+                    if (lane == 0) {
+                        v.bcnt[bb + u] = tot;
+                        v.bitem[bb + u] = items;
+                    }
+                    acc.p += tot;
+                    acc.i += items;
+                    acc.n += tot ? 1u : 0u;
+                }
+            }
+            gb += n;
+        }
+    }
+    if (lane == 0)
+        wseg[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Seg agg{0u, 0u, 0u, 0u};
+        for (int w = 0; w < nw; ++w)
+            agg = seg_join(agg, wseg[w]);
+        gp(B.scan)[4 * blockIdx.x] = agg.p;
+        gp(B.scan)[4 * blockIdx.x + 1] = agg.i;
+        gp(B.scan)[4 * blockIdx.x + 2] = agg.f;
+        gp(B.scan)[4 * blockIdx.x + 3] = agg.n;
+    }
+}
+
 // Workgroup-wide inclusive scan of Seg values with seg_join.
 __device__ inline Seg block_seg_scan(Seg v)
 {
@@ -1253,31 +1287,7 @@ __device__ inline Seg block_seg_scan(Seg v)
     return v;
 }
 
-// Phase 1 of the scan: this workgroup's partial sums into B.scan.
-__device__ void scan_partials(const BatchDev &B)
-{
-    const BrickRun r = thread_run(B);
-    Seg acc{0u, 0u, 0u, 0u};
-    walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t, uint32_t b, bool first, bool) {
-        if (first)
-            acc = Seg{0u, 0u, 1u, acc.n};
-        if (sorting) {
-            const uint32_t bc = gp(S->bcnt)[b];
-            acc.p += bc;
-            acc.i += gp(S->bitem)[b];
-            acc.n += bc ? 1u : 0u;
-        }
-    });
-    const Seg tot = block_seg_scan(acc);
-    if (threadIdx.x == blockDim.x - 1) {
-        gp(B.scan)[4 * blockIdx.x] = tot.p;
-        gp(B.scan)[4 * blockIdx.x + 1] = tot.i;
-        gp(B.scan)[4 * blockIdx.x + 2] = tot.f;
-        gp(B.scan)[4 * blockIdx.x + 3] = tot.n;
-    }
-}
-
-// Phase 2: the carried prefix from the earlier workgroups' sums (back to
+// Rest of the scan: the carried prefix from the earlier workgroups' sums (back to
 // the last one in which a scene starts; the brick count from all of them),
 // then every brick's exclusive particle and item start, each scene's
 // totals, and the batch's list of non-empty bricks in brick order.
@@ -1535,12 +1545,10 @@ __global__ void __launch_bounds__(kBlock) k_reorder(BatchDev B)
     if (grid_barrier(B.flags, 1, &sh))
         sort_bricks(B);
     if (grid_barrier(B.flags, 2, &sh))
-        scan_partials(B);
-    if (grid_barrier(B.flags, 3, &sh))
         scan_finish(B);
-    if (grid_barrier(B.flags, 4, &sh))
+    if (grid_barrier(B.flags, 3, &sh))
         sort_perm(B);
-    if (grid_barrier(B.flags, 5, &sh))
+    if (grid_barrier(B.flags, 4, &sh))
         sort_move<R>(B);
     if (!last_block(&B.flags[BF_TICKET_MOVE], &sh))
         return;
