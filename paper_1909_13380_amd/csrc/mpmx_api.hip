@@ -561,8 +561,8 @@ uint64_t layout_key(const Batch &b)
 // Online tuning of the item kernels' launch shape on real steps of the call:
 // every workgroup size for both kernels (their times are separate, so each
 // kernel takes its fastest), then the grid density with those sizes.  Each
-// candidate runs two steps and keeps the faster.  Uses kTuneSteps steps.
-constexpr int kTuneReps = 2;
+// candidate runs kTuneReps steps and keeps its fastest.  Uses kTuneSteps steps.
+constexpr int kTuneReps = 3;
 constexpr int kTuneDensity[] = {4, 8, 16, 32};
 constexpr int kTuneSteps = kTuneReps * (kNumItemThreadChoices + 4);
 static_assert(kTuneSteps + 1 <= MPMX_TUNE_MIN_STEPS, "tuning must fit in the calls it runs on");
