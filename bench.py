@@ -131,13 +131,14 @@ def _counter_means(root: str) -> dict:
     return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
 
-def summarize(root: str, workload: str, commands: str):
+def summarize(root: str, workload: str, commands: str, name: str = ""):
     """Kernel-trace statistics and HBM traffic per launch from rocprofv3 CSV
     output: root/trace (--kernel-trace --stats), root/copy_FETCH_SIZE,
     root/copy_WRITE_SIZE (the 1 GiB device copy of --calibrate-copy 1024),
     root/FETCH_SIZE, root/WRITE_SIZE (the step).  Counters are KiB per
     dispatch; each is scaled by (known bytes of the copy) / (what the same
-    counter reads for the copy kernel)."""
+    counter reads for the copy kernel).  `name`, if given, names the summary
+    file and the traffic entry instead of the workload."""
     stats = list(_csv_rows(os.path.join(root, "trace"), "kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (repository root, rocprofv3 from ROCm 7.2):", ""]
     lines += [f"    {c}" for c in commands.split(";;") if c.strip()] + [""]
@@ -201,14 +202,14 @@ def summarize(root: str, workload: str, commands: str):
                 continue
             traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    name = {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
-            "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
-    with open(os.path.join(ROOT, "profiles", name + ".txt"), "w") as fh:
+    fname = name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
+                     "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
+    with open(os.path.join(ROOT, "profiles", fname + ".txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if traffic:
         path = os.path.join(ROOT, "profiles", "traffic.json")
         data = json.load(open(path)) if os.path.exists(path) else {}
-        data[workload] = traffic
+        data[name or workload] = traffic
         with open(path, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
     print("\n".join(lines))
@@ -374,6 +375,7 @@ def main():
                     help="only summarize the rocprofv3 CSV output under DIR (kernel trace + counter passes) "
                          "into profiles/ and exit; no GPU needed")
     ap.add_argument("--commands", default="", help="with --summarize: the commands that produced DIR")
+    ap.add_argument("--profile-name", default="", help="with --summarize: name of the summary file and traffic entry")
     ap.add_argument("--stress-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--g2p-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="fixed grid density (turns autotuning off)")
@@ -385,7 +387,7 @@ def main():
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.summarize:
-        summarize(args.summarize, args.workload, args.commands)
+        summarize(args.summarize, args.workload, args.commands, args.profile_name)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
