@@ -131,13 +131,13 @@ def _counter_means(root: str) -> dict:
     return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
 
-def summarize(root: str, workload: str, commands: str, name: str = ""):
+def summarize(root: str, workload: str, commands: str, out_name: str = ""):
     """Kernel-trace statistics and HBM traffic per launch from rocprofv3 CSV
     output: root/trace (--kernel-trace --stats), root/copy_FETCH_SIZE,
     root/copy_WRITE_SIZE (the 1 GiB device copy of --calibrate-copy 1024),
     root/FETCH_SIZE, root/WRITE_SIZE (the step).  Counters are KiB per
     dispatch; each is scaled by (known bytes of the copy) / (what the same
-    counter reads for the copy kernel).  `name`, if given, names the summary
+    counter reads for the copy kernel).  `out_name`, if given, names the summary
     file and the traffic entry instead of the workload."""
     stats = list(_csv_rows(os.path.join(root, "trace"), "kernel_stats.csv"))
     lines = [f"# rocprofv3 kernel statistics: {workload}", "", "Commands (repository root, rocprofv3 from ROCm 7.2):", ""]
@@ -202,14 +202,14 @@ def summarize(root: str, workload: str, commands: str, name: str = ""):
                 continue
             traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    fname = name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
+    fname = out_name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
                      "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
     with open(os.path.join(ROOT, "profiles", fname + ".txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if traffic:
         path = os.path.join(ROOT, "profiles", "traffic.json")
         data = json.load(open(path)) if os.path.exists(path) else {}
-        data[name or workload] = traffic
+        data[out_name or workload] = traffic
         with open(path, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
     print("\n".join(lines))
