@@ -2041,6 +2041,11 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
     R4<R> *lvn = la + CAP;
     double (*acc)[CAP] = (double (*)[CAP])(lds + (OVERLAY ? 0 : TILE_BYTES));
     __shared__ int red[6 * (T / 64)];
+    // the accumulators start at zero, and each item's flush leaves them so
+    // (with OVERLAY the tile overwrites them, so every item zeroes them)
+    if constexpr (!OVERLAY)
+        for (int q = threadIdx.x; q < CAP; q += blockDim.x)
+            acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
     for (int64_t g = ir.first; g < ir.end; g += ir.step) {
@@ -2061,9 +2066,6 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         brick_origin(S, item.brick, o);
         const Tile ht = home_tile<SH>(o);
         load_update_tile<R>(S, nb, t, la, lvn);
-        if constexpr (!OVERLAY)
-            for (int q = threadIdx.x; q < CAP; q += blockDim.x)
-                acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
         __syncthreads();
         const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
@@ -2300,18 +2302,30 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 S.ctl[CTL_READY] = 1u;
             }
         }
+        // flush the home-tile entries the moved particles can have touched
+        // (their cells' node box), zeroing them for the next item
         constexpr int HD = kBrick + 2 + ShapeTraits<SH>::lo + ShapeTraits<SH>::hi;   // home tile edge
-        for (int q = threadIdx.x; q < CAP; q += blockDim.x) {
-            const double m = acc[0][q];
-            if (m == 0.0)
-                continue;
-            const int i = ht.lo[0] + q % HD, j = ht.lo[1] + (q / HD) % HD, k = ht.lo[2] + q / (HD * HD);
-            if (!node_in_mesh(S, i, j, k))
-                continue;
-            const uint32_t I = node_id(S, i, j, k);
-            addg(nn.m, I, m);
-            for (int a = 0; a < 3; ++a)
-                addg(nn.p[a], I, (R)acc[1 + a][q]);
+        const Tile nbx = tile_of_cells<SH>(blo, bhi);
+        Tile fb;   // nbx within the home tile, in home-tile coordinates
+        for (int a = 0; a < 3; ++a) {
+            fb.lo[a] = max(nbx.lo[a], ht.lo[a]) - ht.lo[a];
+            fb.dim[a] = max(min(nbx.lo[a] + nbx.dim[a], ht.lo[a] + HD) - ht.lo[a] - fb.lo[a], 0);
+        }
+        const int fv = fb.dim[0] * fb.dim[1] * fb.dim[2];
+        for (int q = threadIdx.x; q < fv; q += blockDim.x) {
+            int a, b, c;
+            tile_node_small(fb, q, a, b, c);
+            const int li = a + HD * (b + HD * c);
+            const double m = acc[0][li];
+            const int i = ht.lo[0] + a, j = ht.lo[1] + b, k = ht.lo[2] + c;
+            if (m != 0.0 && node_in_mesh(S, i, j, k)) {
+                const uint32_t I = node_id(S, i, j, k);
+                addg(nn.m, I, m);
+                for (int e = 0; e < 3; ++e)
+                    addg(nn.p[e], I, (R)acc[1 + e][li]);
+            }
+            if constexpr (!OVERLAY)
+                acc[0][li] = acc[1][li] = acc[2][li] = acc[3][li] = 0.0;
         }
         __syncthreads();
     }
