@@ -422,14 +422,14 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     const int n = (int)list.size();
     const size_t n1 = (size_t)n + 1;
     // layout: scenes[n] | poffs[n+1] | boffs[n+1] | nsteps[n] | ctls[n] | ioffs[n+1] | coffs[n+1] |
-    // flags (128-byte aligned) | scan[4 per reorder workgroup] | bricks[total bricks]
+    // flags (128-byte aligned) | scan[4 per brick chunk] | bricks[total bricks]
     const size_t n8 = 8 * (size_t)std::max(n, 1);
     int64_t nbr = 0;
     for (auto *sc : list)
         nbr += sc->h.nbricks;
     const size_t o_po = n8, o_bo = o_po + 8 * n1, o_ns = o_bo + 8 * n1, o_ct = o_ns + n8, o_io = o_ct + n8,
                  o_co = o_io + 4 * n1, o_fl = (o_co + 4 * n1 + 127) & ~(size_t)127, o_sc = o_fl + 4 * BF_WORDS,
-                 o_br = o_sc + 16 * (size_t)kReorderPerCu * ctx->num_cu, total = o_br + 4 * (size_t)std::max<int64_t>(nbr, 1);
+                 o_br = o_sc + 16 * (size_t)kScanChunks, total = o_br + 4 * (size_t)std::max<int64_t>(nbr, 1);
     std::vector<uint8_t> img(total, 0);
     int64_t maxit = 0, *po = (int64_t *)(img.data() + o_po), *bo = (int64_t *)(img.data() + o_bo);
     SceneDev **sp = (SceneDev **)img.data();
@@ -512,9 +512,8 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
     void *a_bd[] = {&bd};
     const hipStream_t st = ctx->launch_stream ? ctx->launch_stream : ctx->stream;
     // the reorder kernel: enough workgroups for one pass over the particles
-    // and one brick per wavefront, but never more than the device holds at
-    // once (its grid barriers need every workgroup resident); it returns at
-    // once on steps that need no reorder
+    // and one brick per wavefront, at most kReorderPerCu per CU; it returns
+    // at once on steps that need no reorder
     const int64_t rwork = std::max({ceil_div(bd.total_particles, (int64_t)kBlock * kSortU),
                                     ceil_div(bd.total_bricks, kBlock / 64), (int64_t)bd.nscenes, (int64_t)1});
     const dim3 rg((unsigned)std::min<int64_t>(rwork, (int64_t)reorder_per_cu(ctx, b.prec, K.reorder) * ctx->num_cu));

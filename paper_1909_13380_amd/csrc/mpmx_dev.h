@@ -29,6 +29,7 @@ constexpr int kXcds = 8;                  // accelerator dies (one L2 each) of t
 constexpr int kBlock = 1024;              // threads per workgroup of the reorder and control kernel
 constexpr int kSortU = 4;                 // particles per lane in flight in the reorder's particle phases
 constexpr int kReorderPerCu = 1;          // most reorder workgroups per compute unit
+constexpr uint32_t kScanChunks = 4096;     // most chunks of the reorder's brick scan
 // Linear shape functions: per-thread register cache of the gathered support
 // nodes, and per-thread register sums of the scattered values, per kernel
 // (chosen by measurement on the 2M-particle column: the stress kernel is
@@ -134,16 +135,17 @@ struct SceneDev {
 };
 
 // Words of BatchDev::flags (the array is 128-byte aligned; the words that
-// many workgroups update or poll at once sit on 128-byte lines of their own).
+// many workgroups update or poll at once sit on 128-byte lines of their
+// own).  The reorder kernel uses them; the stage kernel after it clears them.
 enum BatchFlag : int {
     BF_ANY_SORT = 0,      // some scene of the batch reorders this step
-    BF_TICKET_MOVE = 1,   // finished reorder workgroups (the last runs the step control)
-    BF_SORT_FAIL = 2,     // a reorder workgroup gave up waiting at a grid barrier
-    BF_NBRICKS = 32,      // non-empty bricks listed by the reorder
-    BF_GRID = 64,         // grid barrier: arrivals of the workgroup groups
-    BF_GROUP = 96,        // + 32 g: arrivals within group g
-    BF_RELEASE = 96 + 32 * kXcds,   // + 32 g: last barrier round released, polled by group g
-    BF_WORDS = 96 + 64 * kXcds
+    BF_SORT_FAIL = 1,     // a reorder workgroup gave up waiting for a phase
+    BF_EXIT = 32,         // reorder workgroups finished (the last runs the step control)
+    BF_NBRICKS = 64,      // non-empty bricks listed by the reorder
+    BF_CLAIM = 96,        // + 32 p: chunks of reorder phase p claimed
+    BF_DONE = 96 + 32 * 5,          // + 32 p: chunks of reorder phase p done
+    BF_RELEASE = 96 + 64 * 5,       // + 32 g: reorder phases complete, polled by group g
+    BF_WORDS = 96 + 64 * 5 + 32 * kXcds
 };
 
 // A launch over several scenes: work is flattened over scenes in order.
@@ -155,7 +157,7 @@ struct BatchDev {
     uint32_t *ioffs;                // this step's item offsets [nscenes+1]
     uint32_t *coffs;                // offsets of the boxes to clear [nscenes+1]
     uint32_t *flags;                // BF_*
-    uint32_t *scan;                 // reorder: per workgroup, 4 words of brick-scan partial sums
+    uint32_t *scan;                 // reorder: per brick chunk, 4 words of brick-scan partial sums [4 kScanChunks]
     uint32_t *bricks;               // reorder: the non-empty bricks (flattened index) [total_bricks]
     int nscenes;
     int pad;

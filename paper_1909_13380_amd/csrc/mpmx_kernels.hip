@@ -952,69 +952,104 @@ __device__ void step_control(const BatchDev &B)
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        B.flags[BF_ANY_SORT] = 0u;
+}
+
+// Clear the batch's reorder words for the next step (run by the first
+// workgroup of the stage kernel after the reorder, when every reorder
+// workgroup has finished).
+__device__ inline void clear_reorder_flags(const BatchDev &B)
+{
+    if (blockIdx.x == 0)
+        for (int w = threadIdx.x; w < BF_WORDS; w += blockDim.x)
+            B.flags[w] = 0u;
 }
 
 // ----------------------------------------------------------------- sort --
 // The reorder runs as one launch of one workgroup per compute unit, in
-// five phases separated by grid-wide barriers: per-cell counts; per-brick
-// cell scan with each workgroup's partial sums of the scan over bricks; the
-// rest of that scan (the carried prefix, every brick's start, the list of
-// non-empty bricks); the permutation; and the move of the non-empty
-// bricks.  Steps that reorder no scene skip straight to the step control,
-// so they pay a single launch.
+// five phases: per-cell counts; per-brick cell scan with each brick range's
+// partial sums of the scan over bricks; the rest of that scan (the carried
+// prefix, every brick's start, the list of non-empty bricks); the
+// permutation; and the move of the non-empty bricks.  Steps that reorder no
+// scene skip straight to the step control, so they pay a single launch.
+//
+// Each phase is split into chunks that workgroups claim from a counter, and
+// a phase is complete when every chunk is done.  A workgroup waits only once
+// no chunk is left to claim, that is for chunks that running workgroups
+// hold, so the reorder completes with any number of its workgroups resident
+// (another kernel may hold part of the device).
 //
 // Every wavefront works on one scene at a time, whose descriptor fields are
 // read through the scalar cache; the particle phases keep kSortU particles
 // per lane in flight, the brick phase kBrickU bricks per wavefront, and the
 // move kMoveLevels levels of a brick (half as many in FP64).  One 1024-thread
-// workgroup per CU: every workgroup's barrier fences write back and
-// invalidate its XCD's L2, so fewer, larger workgroups wait less.
+// workgroup per CU: every workgroup's fences write back and invalidate its
+// XCD's L2, so fewer, larger workgroups wait less.
 
 constexpr int kBrickU = 8;
 constexpr int kMoveLevels = 4;
+constexpr uint32_t kScanBricks = 64;   // fewest bricks per chunk of the brick phases
 
-// Wait until every workgroup of the launch has arrived at barrier `round`
-// (1, 2, ...).  Workgroups form groups by blockIdx mod 8 (the XCD a
-// workgroup runs on): a workgroup arrives on its group's counter, the
-// group's last arrival on the grid counter, and the grid's last arrival
-// releases every group; a workgroup polls its group's release word.  The
-// counters only grow within a launch, so no reset is needed between
-// barriers.  The grid is far below what the device holds at once, so every
-// workgroup is resident and the wait ends; it is bounded all the same
-// (kBarrierTicks of the constant-rate wall clock), and a workgroup that
-// gives up raises BF_SORT_FAIL before it arrives anywhere else.  Returns
-// whether the reorder may go on: the flag is read after the wait, so a
-// workgroup that continues has seen the previous phase complete on every
-// workgroup.
-constexpr uint64_t kBarrierTicks = 100000000ull;   // 1 s at 100 MHz
+// Bound of a phase wait (1 s of the 100 MHz wall clock).  The wait always
+// ends (see above); a workgroup that still gives up raises BF_SORT_FAIL
+// before it reports any later chunk done.
+constexpr uint64_t kBarrierTicks = 100000000ull;
 
-__device__ bool grid_barrier(uint32_t *flags, uint32_t round, int *sh)
+enum ReorderPhase : int { PH_COUNT = 0, PH_BRICKS = 1, PH_SCAN = 2, PH_PERM = 3, PH_MOVE = 4 };
+
+// Claim and run chunks of `phase` until none is left (work(c) runs only if
+// `go`), then publish them and count them done.  A chunk is claimed only
+// once the previous one is finished: claiming ahead would let the first
+// workgroups take two chunks each while others got none.
+template <typename F>
+__device__ void run_chunks(uint32_t *flags, int phase, uint32_t nchunks, bool go, int *sh, F work)
 {
+    uint32_t *claim = &flags[BF_CLAIM + 32 * phase];
+    uint32_t mine = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *sh = (int)atomicAdd(claim, 1u);
+        __syncthreads();
+        const uint32_t c = (uint32_t)*sh;
+        if (c >= nchunks)
+            break;
+        if (go)
+            work(c);
+        ++mine;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t ng = min(gridDim.x, (uint32_t)kXcds);
-        const uint32_t g = blockIdx.x % ng;
-        const uint32_t size = (gridDim.x - g + ng - 1) / ng;   // workgroups in group g
-        __threadfence();   // publish this workgroup's writes of the phase
-        if (atomicAdd(&flags[BF_GROUP + 32 * g], 1u) + 1u == round * size) {
+    if (threadIdx.x == 0 && mine) {
+        __threadfence();   // publish this workgroup's chunks
+        if (atomicAdd(&flags[BF_DONE + 32 * phase], mine) + mine == nchunks) {
+            // the phase's last chunk: release every group of waiting workgroups
             __threadfence();
-            if (atomicAdd(&flags[BF_GRID], 1u) + 1u == round * ng) {
-                __threadfence();
-                for (uint32_t q = 0; q < ng; ++q)
-                    __hip_atomic_store(&flags[BF_RELEASE + 32 * q], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            const uint32_t ng = min(gridDim.x, (uint32_t)kXcds);
+            for (uint32_t q = 0; q < ng; ++q)
+                __hip_atomic_store(&flags[BF_RELEASE + 32 * q], (uint32_t)phase + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
+}
+
+// Wait until every chunk of `phase` is done; returns whether the reorder may
+// go on (no workgroup gave up).  Workgroups poll one release word per group
+// (blockIdx mod 8, the XCD a workgroup runs on), which the workgroup that
+// finished the phase's last chunk writes.  The flag is read after the
+// wait, so a workgroup that goes on has seen every chunk of the phase run.
+__device__ bool phase_done(uint32_t *flags, int phase, int *sh)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t g = blockIdx.x % min(gridDim.x, (uint32_t)kXcds);
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(&flags[BF_RELEASE + 32 * g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
+        while (__hip_atomic_load(&flags[BF_RELEASE + 32 * g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+               (uint32_t)phase) {
             if (wall_clock64() - t0 > kBarrierTicks) {
                 atomicOr(&flags[BF_SORT_FAIL], 1u);
                 break;
             }
-            __builtin_amdgcn_s_sleep(16);
+            __builtin_amdgcn_s_sleep(8);
         }
-        __threadfence();   // see the other workgroups' writes
+        __threadfence();   // see the other workgroups' chunks
         *sh = __hip_atomic_load(&flags[BF_SORT_FAIL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
     }
     __syncthreads();
@@ -1092,18 +1127,22 @@ __device__ inline SortView sort_view(const BatchDev &B, int s)
 __device__ inline uint32_t wave_index() { return uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
 __device__ inline uint32_t wave_count() { return uni((gridDim.x * blockDim.x) >> 6); }
 
-// The particle phases: each wavefront takes 64 * kSortU consecutive
-// particles of the flattened batch per pass and calls
-// f(view, first, lo, hi, off) once per reordering scene the span meets;
-// lane l's particles are first + u * 64 + l (u < kSortU), those in [lo, hi)
-// belong to the scene, whose particle 0 is flattened index off.
+// The particle phases: the flattened batch is cut into spans of 64 * kSortU
+// consecutive particles, and chunk c of n takes spans c, c + n, c + 2n, ...
+// (so the wavefronts running at one time work on distinct bricks, whose
+// count atomics and slot stores then do not meet).  Each wavefront takes
+// one span per pass and calls f(view, first, lo, hi, off) once per
+// reordering scene the span meets; lane l's particles are
+// first + u * 64 + l (u < kSortU), those in [lo, hi) belong to the scene,
+// whose particle 0 is flattened index off.
+constexpr int64_t kSpan = 64 * kSortU;
+
 template <typename F>
-__device__ inline void particle_spans(const BatchDev &B, F f)
+__device__ inline void particle_spans(const BatchDev &B, uint32_t chunk, uint32_t nchunks, F f)
 {
-    constexpr int64_t SPAN = 64 * kSortU;
-    for (int64_t first = (int64_t)wave_index() * SPAN; first < B.total_particles;
-         first += (int64_t)wave_count() * SPAN) {
-        const int64_t end = min(first + SPAN, B.total_particles);
+    const int64_t wave = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    for (int64_t first = (chunk + nchunks * wave) * kSpan; first < B.total_particles; first += nchunks * nw * kSpan) {
+        const int64_t end = min(first + kSpan, B.total_particles);
         int s = find_scene_u(B.poffs, B.nscenes, first);
         for (int64_t lo = first; lo < end; ++s) {
             const int64_t off = cld(&B.poffs[s]), hi = min(end, cld(&B.poffs[s + 1]));
@@ -1118,10 +1157,10 @@ __device__ inline void particle_spans(const BatchDev &B, F f)
 }
 
 // rank[p] = arrival order of p among the particles of its cell.
-__device__ void sort_count(const BatchDev &B)
+__device__ void sort_count(const BatchDev &B, uint32_t chunk, uint32_t nchunks)
 {
     const int lane = threadIdx.x & 63;
-    particle_spans(B, [&](const SortView &v, int64_t first, int64_t lo, int64_t hi, int64_t off) {
+    particle_spans(B, chunk, nchunks, [&](const SortView &v, int64_t first, int64_t lo, int64_t hi, int64_t off) {
         // loads for every lane (an idle lane reads particle 0 of the scene),
         // so all of them are in flight together
         uint32_t p[kSortU], key[kSortU];
@@ -1140,8 +1179,8 @@ __device__ void sort_count(const BatchDev &B)
 }
 
 // --- scan over the bricks of every reordering scene (segmented by scene) --
-// Workgroup j takes a contiguous range of the flattened brick list and each
-// of its threads a contiguous run of that range.
+// Chunk j is a contiguous range of the flattened brick list; each thread of
+// the workgroup running it takes a contiguous run of that range.
 
 // Particle and item sums after the last scene start of a run (f: a scene
 // starts inside the run), and the run's count of non-empty bricks of
@@ -1160,11 +1199,9 @@ struct BrickRun {
     uint32_t lo, hi;   // flattened brick indices [lo, hi)
 };
 
-__device__ inline BrickRun thread_run(const BatchDev &B)
+// A thread's contiguous run of the brick range [b0, b1).
+__device__ inline BrickRun thread_run(uint32_t b0, uint32_t b1)
 {
-    const uint32_t total = (uint32_t)B.total_bricks;
-    const uint32_t per_block = (total + gridDim.x - 1) / gridDim.x;
-    const uint32_t b0 = min(blockIdx.x * per_block, total), b1 = min(b0 + per_block, total);
     const uint32_t per = (b1 - b0 + blockDim.x - 1) / blockDim.x;
     const uint32_t lo = min(b0 + threadIdx.x * per, b1);
     return {lo, min(lo + per, b1)};
@@ -1194,19 +1231,16 @@ __device__ inline void walk_run(const BatchDev &B, const BrickRun &r, F f)
     }
 }
 
-// One wavefront per brick, over a contiguous run of the workgroup's range
+// One wavefront per brick, over a contiguous run of chunk j's range [b0, b1)
 // of the flattened brick list (kBrickU bricks per pass): the brick's
 // particle count, its work-item count and the cell-major start of every
 // cell inside the brick (written for non-empty bricks only: nothing reads
-// the others).  The workgroup then writes its range's partial sums for the
-// brick scan into B.scan.
-__device__ void sort_bricks(const BatchDev &B)
+// the others).  The workgroup then writes the range's partial sums for the
+// brick scan into B.scan[4 j].
+__device__ void sort_bricks(const BatchDev &B, uint32_t j, uint32_t b0, uint32_t b1)
 {
     __shared__ Seg wseg[kBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const uint32_t total = (uint32_t)B.total_bricks;
-    const uint32_t per_block = (total + gridDim.x - 1) / gridDim.x;
-    const uint32_t b0 = min(blockIdx.x * per_block, total), b1 = min(b0 + per_block, total);
     const uint32_t per_wave = (b1 - b0 + nw - 1) / nw;
     const uint32_t w0 = uni(min(b0 + wave * per_wave, b1)), w1 = uni(min(w0 + per_wave, b1));
     Seg acc{0u, 0u, 0u, 0u};
@@ -1260,11 +1294,12 @@ __device__ void sort_bricks(const BatchDev &B)
         Seg agg{0u, 0u, 0u, 0u};
         for (int w = 0; w < nw; ++w)
             agg = seg_join(agg, wseg[w]);
-        gp(B.scan)[4 * blockIdx.x] = agg.p;
-        gp(B.scan)[4 * blockIdx.x + 1] = agg.i;
-        gp(B.scan)[4 * blockIdx.x + 2] = agg.f;
-        gp(B.scan)[4 * blockIdx.x + 3] = agg.n;
+        gp(B.scan)[4 * j] = agg.p;
+        gp(B.scan)[4 * j + 1] = agg.i;
+        gp(B.scan)[4 * j + 2] = agg.f;
+        gp(B.scan)[4 * j + 3] = agg.n;
     }
+    __syncthreads();   // wseg is reused by the workgroup's next chunk
 }
 
 // Workgroup-wide inclusive scan of Seg values with seg_join.
@@ -1287,19 +1322,20 @@ __device__ inline Seg block_seg_scan(Seg v)
     return v;
 }
 
-// Rest of the scan: the carried prefix from the earlier workgroups' sums (back to
-// the last one in which a scene starts; the brick count from all of them),
-// then every brick's exclusive particle and item start, each scene's
-// totals, and the batch's list of non-empty bricks in brick order.
-__device__ void scan_finish(const BatchDev &B)
+// Rest of the scan for chunk j (range [b0, b1)): the carried prefix from the
+// earlier chunks' sums (back to the last one in which a scene starts; the
+// brick count from all of them), then every brick's exclusive particle and
+// item start, each scene's totals, and the batch's list of non-empty bricks
+// in brick order.
+__device__ void scan_finish(const BatchDev &B, uint32_t j, uint32_t b0, uint32_t b1)
 {
     __shared__ uint32_t red[kBlock / 64][3];
     __shared__ uint32_t carry[3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const GLOBAL uint32_t *P = gp(B.scan);
-    // nearest earlier workgroup whose range holds a scene start
+    // nearest earlier chunk whose range holds a scene start
     int k0 = 0;
-    for (int k = threadIdx.x; k < (int)blockIdx.x; k += blockDim.x)
+    for (int k = threadIdx.x; k < (int)j; k += blockDim.x)
         if (P[4 * k + 2])
             k0 = max(k0, k);
     k0 = wave_reduce<true>(k0);
@@ -1311,11 +1347,11 @@ __device__ void scan_finish(const BatchDev &B)
         k0 = max(k0, (int)red[w][0]);
     __syncthreads();
     uint32_t cp = 0, ci = 0, cn = 0;
-    for (int k = k0 + threadIdx.x; k < (int)blockIdx.x; k += blockDim.x) {
+    for (int k = k0 + threadIdx.x; k < (int)j; k += blockDim.x) {
         cp += P[4 * k];
         ci += P[4 * k + 1];
     }
-    for (int k = threadIdx.x; k < (int)blockIdx.x; k += blockDim.x)
+    for (int k = threadIdx.x; k < (int)j; k += blockDim.x)
         cn += P[4 * k + 3];
     for (int o = 32; o > 0; o >>= 1) {
         cp += __shfl_xor(cp, o);
@@ -1341,7 +1377,7 @@ __device__ void scan_finish(const BatchDev &B)
     }
     __syncthreads();
     // this thread's run sums, then its start within the workgroup
-    const BrickRun r = thread_run(B);
+    const BrickRun r = thread_run(b0, b1);
     Seg mine{0u, 0u, 0u, 0u};
     walk_run(B, r, [&](const SceneDev *S, bool sorting, uint32_t, uint32_t b, bool first, bool) {
         if (first)
@@ -1382,15 +1418,16 @@ __device__ void scan_finish(const BatchDev &B)
     });
     if (r.lo < r.hi && r.hi == (uint32_t)B.total_bricks)   // the batch's last brick
         B.flags[BF_NBRICKS] = run.n;
+    __syncthreads();   // shared arrays are reused by the workgroup's next chunk
 }
 
 // perm lists the particles cell-major: slot bstart[brick] + cstart[key] +
 // rank holds p.  The particle that opens a 512-slot chunk of its brick
 // writes that work item.
-__device__ void sort_perm(const BatchDev &B)
+__device__ void sort_perm(const BatchDev &B, uint32_t chunk, uint32_t nchunks)
 {
     const int lane = threadIdx.x & 63;
-    particle_spans(B, [&](const SortView &v, int64_t first, int64_t lo, int64_t hi, int64_t off) {
+    particle_spans(B, chunk, nchunks, [&](const SortView &v, int64_t first, int64_t lo, int64_t hi, int64_t off) {
         // loads for every lane (an idle lane reads particle 0 of the scene),
         // so all of them are in flight together
         uint32_t p[kSortU], key[kSortU], local[kSortU], bs[kSortU];
@@ -1462,13 +1499,14 @@ struct MoveRec {
 // distinct cells, so the scatter kernels' LDS atomics for one node corner do
 // not collide.  Each pass reads kMoveLevels levels before it writes any.
 // Resets the brick's per-cell counts for the next sort.
+// A chunk is the listed bricks [i0, i1).
 template <typename R>
-__device__ void sort_move(const BatchDev &B)
+__device__ void sort_move(const BatchDev &B, uint32_t i0, uint32_t i1)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t nbr = uni(__hip_atomic_load(&B.flags[BF_NBRICKS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    for (uint32_t i = wave_index(); i < nbr; i += wave_count()) {
+    const uint32_t nw = blockDim.x >> 6;
+    for (uint32_t i = i0 + uni(threadIdx.x >> 6); i < i1; i += nw) {
         const uint32_t gb = uni(gp(B.bricks)[i]);
         const int s = find_scene_u(B.boffs, B.nscenes, gb);
         const SortView sv = sort_view(B, s);
@@ -1528,9 +1566,13 @@ __device__ void sort_move(const BatchDev &B)
 }
 
 // Reorder of the flagged scenes, then the step control in the last
-// workgroup to finish.  A phase runs only if no workgroup gave up waiting
-// at the barrier before it; the step control then fails the reordering
-// scenes (ERR_SORT) and keeps their particles where they were.
+// workgroup to leave.  Chunk sizes grow with the batch so that there are
+// about as many chunks in every phase as workgroups.  A phase
+// runs only if no workgroup gave up waiting for the one before; the step
+// control then fails the reordering scenes (ERR_SORT) and keeps their
+// particles where they were.  The counters are cleared by the next stage
+// kernel (and at the start of every call), after every workgroup of this
+// launch has finished.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_reorder(BatchDev B)
 {
@@ -1541,22 +1583,47 @@ __global__ void __launch_bounds__(kBlock) k_reorder(BatchDev B)
             step_control(B);
         return;
     }
-    sort_count(B);
-    if (grid_barrier(B.flags, 1, &sh))
-        sort_bricks(B);
-    if (grid_barrier(B.flags, 2, &sh))
-        scan_finish(B);
-    if (grid_barrier(B.flags, 3, &sh))
-        sort_perm(B);
-    if (grid_barrier(B.flags, 4, &sh))
-        sort_move<R>(B);
-    if (!last_block(&B.flags[BF_TICKET_MOVE], &sh))
-        return;
-    step_control(B);
+    uint32_t *F = B.flags;
+    const int64_t np = B.total_particles;
+    const uint32_t nb = (uint32_t)B.total_bricks;
+    // chunks per phase aimed at: one per workgroup, so that with every
+    // workgroup resident the phases split as evenly as a static assignment
+    const int64_t target = gridDim.x;
+    // particle chunks: about `target` of them, each a whole number of
+    // wavefront passes of the workgroup
+    const int64_t pass = kSpan * (blockDim.x >> 6);
+    const uint32_t npc = (uint32_t)max((int64_t)1, min(target, (np + pass - 1) / pass));
+    // brick chunks of the scan: at most kScanChunks of them
+    const uint32_t bch = max(max(kScanBricks, (nb + kScanChunks - 1) / kScanChunks),
+                             (uint32_t)((nb + gridDim.x - 1) / gridDim.x));
+    const uint32_t nbc = max(1u, (nb + bch - 1) / bch);
+    bool go = true;
+    run_chunks(F, PH_COUNT, npc, go, &sh, [&](uint32_t c) { sort_count(B, c, npc); });
+    go = phase_done(F, PH_COUNT, &sh);
+    run_chunks(F, PH_BRICKS, nbc, go, &sh,
+               [&](uint32_t c) { sort_bricks(B, c, min(c * bch, nb), min((c + 1) * bch, nb)); });
+    go = phase_done(F, PH_BRICKS, &sh);
+    run_chunks(F, PH_SCAN, nbc, go, &sh,
+               [&](uint32_t c) { scan_finish(B, c, min(c * bch, nb), min((c + 1) * bch, nb)); });
+    go = phase_done(F, PH_SCAN, &sh);
+    run_chunks(F, PH_PERM, npc, go, &sh, [&](uint32_t c) { sort_perm(B, c, npc); });
+    go = phase_done(F, PH_PERM, &sh);
+    // move chunks: listed bricks, one per wavefront per pass
+    const uint32_t nbr = uni(__hip_atomic_load(&F[BF_NBRICKS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t mpass = blockDim.x >> 6;
+    const uint32_t mch = max(1u, (nbr + mpass * (uint32_t)target - 1) / (mpass * (uint32_t)target)) * mpass;
+    const uint32_t nmc = max(1u, (nbr + mch - 1) / mch);
+    run_chunks(F, PH_MOVE, nmc, go, &sh, [&](uint32_t c) { sort_move<R>(B, c * mch, min((c + 1) * mch, nbr)); });
+    // the last workgroup to leave runs the step control
+    if (threadIdx.x == 0) {
+        __threadfence();
+        sh = atomicAdd(&F[BF_EXIT], 1u) == gridDim.x - 1 ? 1 : 0;
+    }
     __syncthreads();
-    for (int w = threadIdx.x; w < BF_WORDS; w += blockDim.x)
-        if (w != BF_ANY_SORT)
-            B.flags[w] = 0u;
+    if (!sh)
+        return;
+    __threadfence();
+    step_control(B);
 }
 
 // ------------------------------------------------------- item kernels --
@@ -1605,6 +1672,7 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
     constexpr int NACC = WITH_FORCE ? 7 : 4;
     __shared__ double acc[NACC][CAP];
     __shared__ int red[6 * (T / 64)];
+    clear_reorder_flags(B);
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
     for (int64_t g = ir.first; g < ir.end; g += ir.step) {
@@ -1741,6 +1809,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
     __shared__ R4<R> lv[CAP];
     __shared__ double lf[3][CAP];
     __shared__ int red[6 * (T / 64)];
+    clear_reorder_flags(B);
     clear_previous<R>(B);
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
