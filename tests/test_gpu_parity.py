@@ -612,3 +612,44 @@ def test_device_resident_inputs_and_outputs(ctx, mp):
     ref = oracle.run(sc, 3)
     check_state("device_io", host, ref, sc["x"], 2e-5, 2e-5, 2e-5)
     s.destroy()
+
+
+def test_two_contexts_reordering_at_once(mp):
+    """Two contexts on one device, each with its own stream, stepping scenes
+    that reorder every step, queued back to back so that their reorder
+    launches can run at the same time (a reorder must complete with only
+    part of its workgroups resident): each scene matches the same scene run
+    alone, in FP64, to rounding, with no error."""
+    scs = [scenes.random_block(n_cells=(24, 20, 14), mesh_cells=(40, 32, 24), h=0.05, seed=400 + i,
+                               material=MATERIALS["dp"], vel=3.0, dt=1e-4, stress_scale=2e3) for i in range(2)]
+    nsteps = 20
+    alone = []
+    c = mp.Context(0)
+    try:
+        for sc in scs:
+            s = c.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS)
+            s.step(nsteps)
+            alone.append(s.read())
+            s.destroy()
+    finally:
+        c.close()
+    ctxs = [mp.Context(0), mp.Context(0)]
+    try:
+        ss = [cx.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS) for cx, sc in zip(ctxs, scs)]
+        for rep in range(3):
+            for s in ss:
+                s.step(nsteps)
+        for i, (sc, s) in enumerate(zip(scs, ss)):
+            st = s.stats()
+            assert st["error_bits"] == 0 and st["steps_done"] == 3 * nsteps and st["n_sorts"] == 3 * nsteps, st
+            s.destroy()
+        # the first 20 steps again, queued back to back, against the scene alone
+        ss = [cx.create_scene(sc, precision=mp.FP64, sort_policy=mp.SORT_ALWAYS) for cx, sc in zip(ctxs, scs)]
+        for s in ss:
+            s.step(nsteps)
+        for i, (sc, s, a) in enumerate(zip(scs, ss, alone)):
+            check_state(f"two_ctx/{i}", s.read(), a, sc["x"], 1e-9, 1e-9, 1e-9)
+            s.destroy()
+    finally:
+        for cx in ctxs:
+            cx.close()
