@@ -390,7 +390,7 @@ def main():
         summarize(args.summarize, args.workload, args.commands, args.profile_name)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         raise SystemExit(2)
 
     import torch
