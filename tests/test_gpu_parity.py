@@ -653,3 +653,21 @@ def test_two_contexts_reordering_at_once(mp):
     finally:
         for cx in ctxs:
             cx.close()
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_usl_many_steps_with_reorders(ctx, mp, shape):
+    """USL over 25 steps (graph replays after the first), reordering every
+    step and on demand, against the oracle in FP64."""
+    sc = block(shape=shape, material=MATERIALS["dp"], algo=1, seed=71, vel=4.0, n_cells=(7, 6, 5))
+    sc["scheme"]["dt"] = 1e-4
+    ref = oracle.run(sc, 25)
+    for policy in (mp.SORT_ALWAYS, mp.SORT_ON_DEMAND):
+        s = ctx.create_scene(sc, precision=mp.FP64, sort_policy=policy)
+        s.step(25)
+        st = s.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == 25, st
+        if policy == mp.SORT_ALWAYS:
+            assert st["n_sorts"] == 25, st
+        check_state(f"usl/{'gimp' if shape else 'linear'}/{policy}", s.read(), ref, sc["x"], 1e-9, 1e-9, 1e-9)
+        s.destroy()
