@@ -530,23 +530,6 @@ __device__ inline bool scene_active(const SceneDev &S)
     return uni(S.ctl[CTL_ACTIVE]) != 0u;
 }
 
-// Last workgroup of a grid to arrive (threadfence reduction pattern: every
-// workgroup publishes its writes, then takes a ticket; no workgroup waits).
-__device__ inline bool last_block(uint32_t *ticket, int *flag)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        *flag = (t == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = *flag != 0;
-    if (last)
-        __threadfence();
-    return last;
-}
-
 // Item order of the persistent grids.  Workgroup w runs on XCD w % 8, and
 // each XCD has its own L2; the XCDs get contiguous ranges of the item list,
 // so bricks that share node rows (consecutive items) are processed under one
@@ -994,7 +977,8 @@ constexpr uint32_t kScanBricks = 64;   // fewest bricks per chunk of the brick p
 // before it reports any later chunk done.
 constexpr uint64_t kBarrierTicks = 100000000ull;
 
-enum ReorderPhase : int { PH_COUNT = 0, PH_BRICKS = 1, PH_SCAN = 2, PH_PERM = 3, PH_MOVE = 4 };
+// phases of the reorder, which index the claim and done counters
+enum : int { PH_COUNT = 0, PH_BRICKS = 1, PH_SCAN = 2, PH_PERM = 3, PH_MOVE = 4 };
 
 // Claim and run chunks of `phase` until none is left (work(c) runs only if
 // `go`), then publish them and count them done.  A chunk is claimed only
@@ -1124,8 +1108,6 @@ __device__ inline SortView sort_view(const BatchDev &B, int s)
     return v;
 }
 
-__device__ inline uint32_t wave_index() { return uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
-__device__ inline uint32_t wave_count() { return uni((gridDim.x * blockDim.x) >> 6); }
 
 // The particle phases: the flattened batch is cut into spans of 64 * kSortU
 // consecutive particles, and chunk c of n takes spans c, c + n, c + 2n, ...
