@@ -105,6 +105,29 @@ def cpu_baseline(sc: dict, steps: int) -> dict:
             "seconds": round(dt, 3)}
 
 
+def _oracle_job(job):
+    import oracle
+    sc, steps = job
+    oracle.run(sc, steps)
+    return len(sc["x"]) * steps
+
+
+def cpu_baseline_parallel(scs: list, steps: int, cores: int) -> dict:
+    """The oracle on `cores` host processes at once, one scene per task
+    (scene-parallel), over the given sample; wall time of the whole pool,
+    first touch of each scene's nodal arrays included.  Runs before the
+    process touches the GPU (the workers are forked)."""
+    import multiprocessing as mpr
+    with mpr.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        jobs = sorted(((sc, steps) for sc in scs), key=lambda j: -len(j[0]["x"]))   # largest first
+        pu = sum(pool.map(_oracle_job, jobs, chunksize=1))
+        dt = time.perf_counter() - t0
+    return {"value": pu / dt, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(scs)} scenes of the set spread over its sizes ({sum(len(s['x']) for s in scs)} "
+                      f"particles), {steps} steps each, FP64, scene-parallel", "seconds": round(dt, 3)}
+
+
 def _csv_rows(root: str, suffix: str):
     import csv
     for dirpath, _, files in os.walk(root):
@@ -243,6 +266,13 @@ def run_batch(args):
     scs = scenes.c3(n_sc, nsteps=steps)
     total = int(sum(len(sc["x"]) for sc in scs))
     print(f"# {n_sc} scenes, {total} particles", file=sys.stderr, flush=True)
+    cb_par = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the pool forks
+        cores = max(1, min(16, os.cpu_count() or 1))
+        by_size = sorted(scs, key=lambda sc: len(sc["x"]))
+        sample = by_size[:: max(1, len(by_size) // (2 * cores))][: 2 * cores]
+        cb_par = cpu_baseline_parallel(sample, 10, cores)
     torch.cuda.init()
     stream = torch.cuda.Stream()          # a real stream: the library and torch's events share it
     torch.cuda.set_stream(stream)
@@ -302,6 +332,7 @@ def run_batch(args):
         cb = cpu_baseline(small, min(args.cpu_steps * 20, steps))
         cb["sample"] = f"smallest scene of the set ({len(small['x'])} particles), " + cb["sample"].split(", ", 1)[1]
         out["cpu_baseline"] = cb
+        out["cpu_baseline_parallel"] = cb_par
     print(json.dumps(out), flush=True)
 
 
