@@ -244,6 +244,8 @@ def apply_launch_options(ctx, args):
                      (mpmx.OPT_BLOCKS_PER_CU, args.blocks_per_cu)):
         if val:
             ctx.set_option(opt, val)
+    if args.graph_steps >= 0:
+        ctx.set_option(mpmx.OPT_GRAPH_STEPS, args.graph_steps)
 
 
 def _percentiles(vals):
@@ -350,6 +352,7 @@ def run_serve(args):
     print(f"# {n_req} requests generated, {total_pu:.3e} particle-updates", file=sys.stderr, flush=True)
     torch.cuda.init()
     ctx = mpmx.Context(0)
+    apply_launch_options(ctx, args)
     results = []
     for rate in rates:
         srv = mpmx.Server(ctx, 64 << 30, max_tick_steps=args.tick_steps)
@@ -410,6 +413,7 @@ def main():
     ap.add_argument("--stress-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--g2p-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="fixed grid density (turns autotuning off)")
+    ap.add_argument("--graph-steps", type=int, default=-1, help="steps per recorded HIP graph (0: none; default: the library's)")
     ap.add_argument("--scenes", type=int, default=256, help="--workload batch: number of scenes")
     ap.add_argument("--requests", type=int, default=2000, help="--workload serve: requests per arrival rate")
     ap.add_argument("--rates", default="50,100,150",
