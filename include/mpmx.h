@@ -253,7 +253,8 @@ int mpmx_scene_step(mpmx_ctx *ctx, uint64_t scene, int64_t nsteps);
  * (after copying) if the scene has stopped on that error, and MPMX_E_STATE
  * if it stopped for a reason of the implementation: a work item's particles
  * spread beyond its node tile, or a reorder that gave up waiting (neither
- * is expected; the particles are then those of the last completed step). */
+ * is expected; the scene stops, and its state is what the failing step
+ * left). */
 int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out);
 
 /* Particles per cell (n_x n_y n_z uint32 in linear cell order) for the
