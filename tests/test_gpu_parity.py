@@ -671,3 +671,29 @@ def test_usl_many_steps_with_reorders(ctx, mp, shape):
             assert st["n_sorts"] == 25, st
         check_state(f"usl/{'gimp' if shape else 'linear'}/{policy}", s.read(), ref, sc["x"], 1e-9, 1e-9, 1e-9)
         s.destroy()
+
+
+def test_batch_of_more_scenes_than_a_workgroup_has_threads(ctx, mp):
+    """1,300 tiny scenes in one batch (the step control takes scenes 1,024 at
+    a time and carries its scans across the rounds; the reorder's brick scan
+    meets a scene start in almost every chunk), a third of them reordering
+    every step: every scene completes, and a sample matches the oracle in
+    FP64."""
+    n = 1300
+    scs = [scenes.random_block(n_cells=(1 + i % 3, 1 + (i // 3) % 2, 1), mesh_cells=(6, 5, 4), h=0.05,
+                               seed=1000 + i, material=MATERIALS["le" if i % 2 else "dp"], vel=2.0)
+           for i in range(n)]
+    pol = [mp.SORT_ALWAYS if i % 3 == 0 else mp.SORT_ON_DEMAND for i in range(n)]
+    ss = [ctx.create_scene(sc, precision=mp.FP64, sort_policy=p) for sc, p in zip(scs, pol)]
+    nsteps = [3 + i % 5 for i in range(n)]
+    ctx.batch_step(ss, nsteps)
+    for i, (s, k) in enumerate(zip(ss, nsteps)):
+        st = s.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == k, (i, st)
+        if pol[i] == mp.SORT_ALWAYS:
+            assert st["n_sorts"] == k, (i, st)
+    for i in list(range(0, n, 97)) + [n - 1]:
+        ref = oracle.run(scs[i], nsteps[i])
+        check_state(f"many/{i}", ss[i].read(), ref, scs[i]["x"], 1e-9, 1e-9, 1e-9)
+    for s in ss:
+        s.destroy()
