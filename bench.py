@@ -82,6 +82,10 @@ def make_workload(name: str):
         sc = scenes.c2()
         sc["scheme"]["shape"] = scenes.SHAPE_GIMP
         return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, GIMP"
+    if name == "column_usl":
+        sc = scenes.c2()
+        sc["scheme"]["algo"] = scenes.USL
+        return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, USL"
     if name == "c1":
         return scenes.c1(), "elastic block, 4,096 particles, 16^3 mesh, linear"
     if name == "c5":
@@ -142,6 +146,16 @@ def _short(name: str) -> str:
     return name.strip()
 
 
+def _base(name: str) -> str:
+    """The library's name of a kernel instantiation: k_stress<float, 0, 256>
+    is "stress"; k_p2g with the force (USL) is "p2g_usl"."""
+    base = name.split("<")[0].replace("k_", "")
+    targs = [a.strip() for a in name[len(name.split("<")[0]) + 1:-1].split(",")] if "<" in name else []
+    if base == "p2g" and "true" in targs:
+        return "p2g_usl"
+    return base
+
+
 def _counter_means(root: str) -> dict:
     """Mean counter value per dispatch, per kernel and counter, from the
     counter_collection CSV files under root."""
@@ -184,11 +198,12 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
         # tuned launch shape used
         launch = bench_line.get("config", {}).get("launch", {})
         want = {"stress": launch.get("stress_threads"), "g2p_p2g": launch.get("g2p_threads"),
-                "p2g": launch.get("g2p_threads")}
+                "p2g": launch.get("g2p_threads"), "p2g_usl": launch.get("stress_threads"),
+                "g2p_usl": launch.get("g2p_threads")}
         rp = {}
         for r in stats:
             name = _short(r["Name"])
-            base = name.split("<")[0].replace("k_", "")
+            base = _base(name)
             targs = [a.strip() for a in name[len(name.split("<")[0]) + 1:-1].split(",")] if "<" in name else []
             if base in want and want[base] is not None and (not targs or targs[-1] != str(want[base])):
                 continue
@@ -215,18 +230,20 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
             rd = fm[(k, "FETCH_SIZE")] * 1024.0 * scale["FETCH_SIZE"]
             wr = wm[(k, "WRITE_SIZE")] * 1024.0 * scale["WRITE_SIZE"]
             lines.append(f"{k[:34]:34s} {rd / 1e6:10.2f} {wr / 1e6:10.2f} {(rd + wr) / 1e6:10.2f}")
-            base = k.split("<")[0].replace("k_", "")
+            base = _base(k)
             entry = {"bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr, "source_hash": source_hash(),
                      "instantiation": k}
             # one entry per kernel: the tuned instantiation when there are several
             tw = (bench_line or {}).get("config", {}).get("launch", {})
-            t_use = {"stress": tw.get("stress_threads"), "g2p_p2g": tw.get("g2p_threads")}.get(base)
+            t_use = {"stress": tw.get("stress_threads"), "g2p_p2g": tw.get("g2p_threads"),
+                     "p2g_usl": tw.get("stress_threads"), "g2p_usl": tw.get("g2p_threads")}.get(base)
             if base in traffic and t_use is not None and not k.rstrip(">").endswith(str(t_use)):
                 continue
             traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     fname = out_name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
-                     "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
+                         "column_usl": "step_kernels_column_2m_usl",
+                         "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
     with open(os.path.join(ROOT, "profiles", fname + ".txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if traffic:
@@ -507,7 +524,9 @@ def main():
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "algorithmic_bytes_per_launch": nbytes}
         out["kernels"] = kernels
-        step_bytes = sum(kernel_bytes(k, n, n_nodes) for k in ("stress", "g2p_p2g"))
+        # the kernels every step runs: USF stress + g2p_p2g, USL p2g_usl + g2p_usl
+        step_kernels = ("p2g_usl", "g2p_usl") if sc["scheme"]["algo"] else ("stress", "g2p_p2g")
+        step_bytes = sum(kernel_bytes(k, n, n_nodes) for k in step_kernels)
         out["step_algorithmic_GBs"] = step_bytes / (elapsed / args.steps) / 1e9
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
