@@ -152,6 +152,47 @@ def c5(seed: int = 5, subsample: bool = False, shape: int = SHAPE_GIMP) -> dict:
     return column((256, 128, 96), (512, 256, 128), 0.005, 1e-5, seed, 500, shape, "c5")
 
 
+PLATE = {"h": 0.0625, "radius": 0.5, "half_length": 4.0, "half_width": 2.5, "sigma0": 100.0}
+
+
+def plate_with_hole(load_time: float = 1.0, points_per_axis: int = 4, material=None) -> dict:
+    """The paper's validation strip (benchmark section, Table 1): 5 m wide,
+    8 m long, a centred hole of radius 0.5 m, in uniaxial tension of about
+    100 Pa along its length (x), cells of 0.0625 m.  The quarter x, y >= 0
+    is modelled with symmetry (slip) faces at x = 0 and y = 0, as one layer
+    of cells with 4 x 4 points per cell (all at mid-thickness) and a slip
+    face at z = 0 and a free one at z = h, which leaves sigma_zz free (plane
+    stress).  Points are the sub-cell centres outside the hole: 40,153 of
+    them (the paper has 40,156).
+
+    The end x = 4 m is pulled at the constant velocity that reaches the
+    nominal strain sigma0 / E at `load_time` (per-node velocity constraints
+    on its nodes, in the library's node numbering); the mesh leaves two
+    empty cell columns beyond it.  PIC velocity update, no gravity, explicit
+    USF, linear shape functions, dt at a CFL number of 0.3."""
+    P = PLATE
+    h, a, L, W = P["h"], P["radius"], P["half_length"], P["half_width"]
+    nx, ny = int(round(L / h)), int(round(W / h))
+    mesh = {"n": (nx + 2, ny + 1, 1), "origin": (0.0, 0.0, 0.0), "h": h}
+    g = (np.arange(nx * points_per_axis) + 0.5) * (h / points_per_axis)
+    q = (np.arange(ny * points_per_axis) + 0.5) * (h / points_per_axis)
+    X, Y = np.meshgrid(g, q, indexing="ij")
+    keep = X * X + Y * Y >= a * a
+    x = np.stack([X[keep], Y[keep], np.full(int(keep.sum()), h / 2)], axis=1)
+    mat = material or elastic()
+    dt = 0.3 * h / p_wave_speed(mat)
+    nsteps = int(round(load_time / dt))
+    speed = P["sigma0"] / mat["E"] * L / load_time
+    n0, n1 = mesh["n"][0] + 1, mesh["n"][1] + 1
+    ids = [nx + n0 * (j + n1 * k) for k in range(2) for j in range(n1)]
+    bc = {"face": [SLIP, FREE, SLIP, FREE, SLIP, FREE], "extra": (ids, [0] * len(ids), [speed] * len(ids))}
+    sc = make_scene("plate_with_hole", mesh, mat, bc,
+                    scheme(dt, gravity=(0.0, 0.0, 0.0), velocity_update=PIC), x, None, nsteps=nsteps)
+    sc["vol"] = _f32(np.full(len(x), h ** 3 / points_per_axis ** 2))
+    sc["mass"] = _f32(mat["rho"] * sc["vol"])
+    return sc
+
+
 def c3_scene(index: int, h: float = 0.02, nsteps: int = 500) -> dict:
     """Scene `index` of the batched set: particle count log-uniform in
     [1e3, 2.5e5] (8 per cell), horizontal aspect ratios log-uniform in
