@@ -86,6 +86,9 @@ def make_workload(name: str):
         sc = scenes.c2()
         sc["scheme"]["algo"] = scenes.USL
         return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, USL"
+    if name == "plate":
+        return (scenes.plate_with_hole(),
+                "plate with a hole (quarter strip), 40,153 particles, 66x41x1 mesh, linear, elastic, PIC")
     if name == "c1":
         return scenes.c1(), "elastic block, 4,096 particles, 16^3 mesh, linear"
     if name == "c5":

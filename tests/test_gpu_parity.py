@@ -162,6 +162,29 @@ def test_full_bricks_nodes_and_particles_match_oracle(ctx, mp, prec, vel, jitter
         s.destroy()
 
 
+def test_plate_with_hole_against_oracle_and_table_1(ctx, mp):
+    """The paper's validation problem (benchmark section, Table 1), all 4,612
+    steps of the quarter strip pulled to 100 Pa: FP64 and FP32 particle
+    state against the oracle, and the stress concentration factors of the
+    GPU's own output within 5 % of the largest one Howland and the paper
+    give, and sigma_yy at the hole within 10 % of Howland's."""
+    from plate_analysis import TABLE_1, stress_concentration
+    sc = scenes.plate_with_hole()
+    ref = oracle.run(sc, sc["nsteps"])
+    for prec, p, tol in (("fp64", mp.FP64, (1e-9, 1e-9, 1e-9)), ("fp32", mp.FP32, (U_TOL, S_TOL, 1e-3))):
+        s = ctx.create_scene(sc, precision=p)
+        s.step(sc["nsteps"])
+        got = s.read()
+        assert s.stats()["error_bits"] == 0
+        check_state(f"plate/{prec}", got, ref, sc["x"], *tol)
+        k = stress_concentration(got["x"], got["stress"])
+        print(f"[plate/{prec}]", {key: round(v, 4) for key, v in k.items()}, flush=True)
+        for r in ("howland", "paper"):
+            assert abs(k["max_sxx"] / TABLE_1[r]["max_sxx"] - 1) <= 0.05, (prec, r, k)
+        assert abs(k["min_syy"] / TABLE_1["howland"]["min_syy"] - 1) <= 0.10, (prec, k)
+        s.destroy()
+
+
 def test_bricks_split_into_several_items(ctx, mp):
     """64 particles per cell: 4096 per brick, eight 512-particle work items."""
     h = 0.05
