@@ -245,7 +245,7 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
             traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     fname = out_name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
-                         "column_usl": "step_kernels_column_2m_usl",
+                         "column_usl": "step_kernels_column_2m_usl", "plate": "step_kernels_plate_40k",
                          "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
     with open(os.path.join(ROOT, "profiles", fname + ".txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
