@@ -258,6 +258,48 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
     print("\n".join(lines))
 
 
+def summarize_counters(root: str, workload: str, commands: str, out_name: str):
+    """SQ instruction counters per dispatch from rocprofv3 --pmc passes
+    (root/pmc_*), with the kernel trace of the same command (root/trace):
+    for each item kernel, instructions per particle (wave instructions x 64
+    lanes / particles) and issue rates per CU and cycle (wave instructions /
+    (256 CUs x average duration x 2.4 GHz)).  Counter values are summed over
+    the counter's hardware instances within a dispatch, then averaged over
+    dispatches."""
+    import glob
+    sc, desc = make_workload(workload)
+    n = len(sc["x"])
+    dur = {_short(r["Name"]): float(r["AverageNs"]) for r in _csv_rows(os.path.join(root, "trace"), "kernel_stats.csv")}
+    means: dict = {}
+    for d in sorted(glob.glob(os.path.join(root, "pmc_*"))):
+        means.update(_counter_means(d))
+    kernels = sorted({k for k, _ in means if _base(k) in ("stress", "g2p_p2g", "p2g", "p2g_usl", "g2p_usl")})
+    counters = sorted({c for _, c in means})
+    lines = [f"# rocprofv3 SQ counters: {desc}", "", "Commands (repository root, rocprofv3 from ROCm 7.2):", ""]
+    lines += [f"    {c}" for c in commands.split(";;") if c.strip()] + [""]
+    lines.append("Per dispatch (wave instructions, or cycles for SQ_ACTIVE_* and SQ_BUSY_*):")
+    lines.append("")
+    lines.append(f"{'counter':32s} " + " ".join(f"{k[:26]:>26s}" for k in kernels))
+    for c in counters:
+        lines.append(f"{c:32s} " + " ".join(f"{means.get((k, c), float('nan')):26.4g}" for k in kernels))
+    lines += ["", f"Derived ({n} particles; average durations from the trace):", ""]
+    lines.append(f"{'':32s} " + " ".join(f"{k[:26]:>26s}" for k in kernels))
+    lines.append(f"{'avg duration (us)':32s} " + " ".join(f"{dur.get(k, float('nan')) / 1e3:26.2f}" for k in kernels))
+    for c, label in (("SQ_INSTS_LDS_ATOMIC", "LDS atomics per particle"), ("SQ_INSTS_LDS_LOAD", "LDS loads per particle"),
+                     ("SQ_INSTS_VALU", "VALU instr per particle"), ("SQ_INSTS_SALU", "SALU instr per particle")):
+        if any((k, c) in means for k in kernels):
+            lines.append(f"{label:32s} " + " ".join(f"{means.get((k, c), float('nan')) * 64 / n:26.2f}" for k in kernels))
+    for c, label in (("SQ_INSTS_LDS_ATOMIC", "LDS atomics / CU / cycle"), ("SQ_INSTS_LDS_LOAD", "LDS loads / CU / cycle"),
+                     ("SQ_INSTS_VALU", "VALU instr / CU / cycle")):
+        if any((k, c) in means for k in kernels):
+            lines.append(f"{label:32s} " + " ".join(
+                f"{means.get((k, c), float('nan')) / (256 * dur.get(k, float('nan')) * 2.4):26.4f}" for k in kernels))
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name + ".txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def apply_launch_options(ctx, args):
     from paper_1909_13380_amd import mpmx
     for opt, val in ((mpmx.OPT_STRESS_THREADS, args.stress_threads), (mpmx.OPT_G2P_THREADS, args.g2p_threads),
@@ -430,6 +472,8 @@ def main():
                          "into profiles/ and exit; no GPU needed")
     ap.add_argument("--commands", default="", help="with --summarize: the commands that produced DIR")
     ap.add_argument("--profile-name", default="", help="with --summarize: name of the summary file and traffic entry")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="write the SQ counter summary of rocprofv3 --pmc passes DIR/pmc_* (with DIR/trace) to profiles/")
     ap.add_argument("--stress-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--g2p-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="fixed grid density (turns autotuning off)")
@@ -443,6 +487,10 @@ def main():
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.summarize:
         summarize(args.summarize, args.workload, args.commands, args.profile_name)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload, args.commands,
+                           args.profile_name or "sq_counters_" + args.workload)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
