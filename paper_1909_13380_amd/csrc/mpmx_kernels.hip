@@ -1698,7 +1698,13 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
                 acc[c][q] = 0.0;
         __syncthreads();
         const R gx = cst<R>(S.g[0], S.f_g[0]), gy = cst<R>(S.g[1], S.f_g[1]), gz = cst<R>(S.g[2], S.f_g[2]);
-        for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
+        // a work item holds at most kChunk particles: a fixed trip count the
+        // compiler unrolls, keeping the next particle's loads in flight
+#pragma unroll
+        for (int rr = 0; rr < kChunk / T; ++rr) {
+            const uint32_t q = threadIdx.x + rr * T;
+            if (q >= item.count)
+                break;
             const uint32_t p = item.start + q;
             const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
             int c[3];
