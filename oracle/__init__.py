@@ -7,7 +7,7 @@ the GPU library.
 
 Scene descriptions are plain dicts with the keys produced by the seeded input
 generators: ``mesh`` {n, origin, h}, ``material`` {model, rho, E, nu, phi,
-psi, c, dp_cone}, ``bc`` {face, extra}, ``scheme`` {algo, shape, gravity, dt,
+psi, c, dp_cone}, ``bc`` {face, extra, force}, ``scheme`` {algo, shape, gravity, dt,
 mass_eps_rel, velocity_update}, and particle arrays x (n,3), v (n,3),
 stress (n,6), vol (n,), mass (n,), all float64.
 
@@ -66,7 +66,11 @@ class _Bc(ctypes.Structure):
                 ("n_extra", ctypes.c_int64),
                 ("node", ctypes.POINTER(ctypes.c_int64)),
                 ("axis", ctypes.POINTER(ctypes.c_int32)),
-                ("value", ctypes.POINTER(ctypes.c_double))]
+                ("value", ctypes.POINTER(ctypes.c_double)),
+                ("n_force", ctypes.c_int64),
+                ("force_node", ctypes.POINTER(ctypes.c_int64)),
+                ("force_value", ctypes.POINTER(ctypes.c_double)),
+                ("force_ramp_steps", ctypes.c_int64)]
 
 
 class _Scheme(ctypes.Structure):
@@ -111,7 +115,7 @@ def _load():
     lib.om_dp_coefficients.restype = None
     lib.om_constitutive.argtypes = [P(_Material), P(d), P(d)]
     lib.om_constitutive.restype = ctypes.c_int
-    step_args = [P(_Mesh), P(_Material), P(_Bc), P(_Scheme), i64, P(d), P(d), P(d), P(d), P(d), P(_Grid)]
+    step_args = [P(_Mesh), P(_Material), P(_Bc), P(_Scheme), i64, P(d), P(d), P(d), P(d), P(d), P(_Grid), i64]
     lib.om_step.argtypes = step_args
     lib.om_step.restype = ctypes.c_int
     lib.om_run.argtypes = step_args + [i64]
@@ -169,6 +173,16 @@ class _BcHolder:
             self.c.value = _ptr(self.value)
         else:
             self.c.n_extra = 0
+        force = bc.get("force")
+        if force is not None and len(force[0]) > 0:
+            self.fnode = np.ascontiguousarray(force[0], dtype=np.int64)
+            self.fval = np.ascontiguousarray(np.asarray(force[1], dtype=np.float64).reshape(len(self.fnode), 3))
+            self.c.n_force = len(self.fnode)
+            self.c.force_node = _ptr(self.fnode, ctypes.c_int64)
+            self.c.force_value = _ptr(self.fval)
+            self.c.force_ramp_steps = int(bc.get("force_ramp_steps", 0))
+        else:
+            self.c.n_force = 0
 
 
 def num_nodes(mesh: dict, shape: int = SHAPE_LINEAR) -> int:
@@ -250,9 +264,12 @@ class Grid:
 
 def run(scene: dict, nsteps: int, grid: Grid | None = None, state: dict | None = None) -> dict:
     """Advance a scene by nsteps; returns the particle state (x, v, stress,
-    vol, mass) and the grid of the last step.  ``state`` (if given) replaces
-    the scene's initial particle arrays."""
+    vol, mass), the count of steps done since the scene's start
+    (``steps_done``) and the grid of the last step.  ``state`` (if given,
+    e.g. an earlier return value) replaces the scene's initial particle
+    arrays and continues its step count."""
     src = state if state is not None else scene
+    step0 = int(state.get("steps_done", 0)) if state is not None else 0
     x = np.array(src["x"], dtype=np.float64, order="C").reshape(-1, 3)
     v = np.array(src["v"], dtype=np.float64, order="C").reshape(-1, 3)
     n = len(x)
@@ -266,7 +283,8 @@ def run(scene: dict, nsteps: int, grid: Grid | None = None, state: dict | None =
     bch = _BcHolder(scene["bc"])
     rc = _load().om_run(ctypes.byref(_mesh(scene["mesh"])), ctypes.byref(_material(scene["material"])),
                         ctypes.byref(bch.c), ctypes.byref(sch), n, _ptr(x), _ptr(v), _ptr(sig),
-                        _ptr(vol), _ptr(mass), ctypes.byref(grid.c), int(nsteps))
+                        _ptr(vol), _ptr(mass), ctypes.byref(grid.c), step0, int(nsteps))
     if rc != OK:
         raise OracleError(rc, "run")
-    return {"x": x, "v": v, "stress": sig, "vol": vol, "mass": mass, "grid": grid}
+    return {"x": x, "v": v, "stress": sig, "vol": vol, "mass": mass, "grid": grid,
+            "steps_done": step0 + int(nsteps)}

@@ -344,7 +344,8 @@ static void add_force(const support *s, double vol, const double *sig, double m,
 
 int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
             const om_scheme *scheme, int64_t n, double *x, double *v,
-            double *sig, double *vol, const double *mass, om_grid *grid)
+            double *sig, double *vol, const double *mass, om_grid *grid,
+            int64_t step)
 {
     if (!mesh || !mat || !bc || !scheme || !grid || n < 0 || mesh->h <= 0.0)
         return OM_E_ARG;
@@ -412,11 +413,20 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
         }
     }
 
-    /* 6. P2G: internal and external forces. */
+    /* 6. P2G: internal and external forces, then the external forces given
+     * at nodes (a surface traction in nodal form). */
     for (int64_t p = 0; p < n; ++p) {
         support_of(mesh, shape, &x0[3 * p], &s);
         add_force(&s, vol[p], &sig[6 * p], mass[p], scheme->gravity, grid->f);
     }
+    double ramp = 1.0;
+    if (bc->force_ramp_steps > 0 && step < bc->force_ramp_steps) {
+        double u = (double)step / (double)bc->force_ramp_steps;
+        ramp = u * u * (3.0 - 2.0 * u);
+    }
+    for (int64_t e = 0; e < bc->n_force; ++e)
+        for (int a = 0; a < 3; ++a)
+            grid->f[3 * bc->force_node[e] + a] += ramp * bc->force_value[3 * e + a];
 
     /* 7. Nodal acceleration and updated velocity, with constraints. */
     for (int64_t I = 0; I < nn; ++I)
@@ -476,10 +486,10 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
 int om_run(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
            const om_scheme *scheme, int64_t n, double *x, double *v,
            double *sig, double *vol, const double *mass, om_grid *grid,
-           int64_t nsteps)
+           int64_t step0, int64_t nsteps)
 {
     for (int64_t s = 0; s < nsteps; ++s) {
-        int rc = om_step(mesh, mat, bc, scheme, n, x, v, sig, vol, mass, grid);
+        int rc = om_step(mesh, mat, bc, scheme, n, x, v, sig, vol, mass, grid, step0 + s + 1);
         if (rc != OM_OK)
             return rc;
     }

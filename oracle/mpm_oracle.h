@@ -69,7 +69,13 @@ typedef struct {
 } om_material;
 
 /* Face rules for faces -x,+x,-y,+y,-z,+z plus optional per-node constraints
- * (node id in this library's node numbering, axis 0..2, prescribed velocity). */
+ * (node id in this library's node numbering, axis 0..2, prescribed velocity),
+ * plus optional external nodal forces (node id, force vector force_value[3e+a])
+ * that stand for a traction on the body's surface (benchmark section: uniform
+ * tension applied at the ends of the strip); they join the nodal force of
+ * every step, scaled in the n-th step (n = 1 first) by the smooth ramp
+ * u^2 (3 - 2u), u = n / force_ramp_steps, until n reaches force_ramp_steps
+ * and by 1 after (force_ramp_steps = 0: full from the start). */
 typedef struct {
     int32_t face[6];
     int32_t pad_;
@@ -77,6 +83,10 @@ typedef struct {
     const int64_t *node;
     const int32_t *axis;
     const double *value;
+    int64_t n_force;
+    const int64_t *force_node;
+    const double *force_value;
+    int64_t force_ramp_steps;
 } om_bc;
 
 typedef struct {
@@ -127,17 +137,20 @@ void om_dp_coefficients(const om_material *mat, double out[3]);
  * return to the apex. */
 int om_constitutive(const om_material *mat, const double deps[6], double sig[6]);
 
-/* One time step (algo in scheme) for n particles, updated in place.
- * mass is constant.  Returns OM_OK or an error code. */
+/* Time step number `step` (1 for a scene's first step; it only sets the
+ * ramp of the nodal forces) of the algorithm in scheme, for n particles,
+ * updated in place.  mass is constant.  Returns OM_OK or an error code. */
 int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
             const om_scheme *scheme, int64_t n, double *x, double *v,
-            double *sig, double *vol, const double *mass, om_grid *grid);
+            double *sig, double *vol, const double *mass, om_grid *grid,
+            int64_t step);
 
-/* nsteps calls of om_step; stops at the first error. */
+/* Steps step0 + 1 .. step0 + nsteps through om_step; stops at the first
+ * error. */
 int om_run(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
            const om_scheme *scheme, int64_t n, double *x, double *v,
            double *sig, double *vol, const double *mass, om_grid *grid,
-           int64_t nsteps);
+           int64_t step0, int64_t nsteps);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,8 @@ the oracle, so both can be fed the same arrays.
 A scene is a plain dict:
   mesh     {"n": (nx, ny, nz), "origin": (ox, oy, oz), "h": h}
   material {"model", "dp_cone", "rho", "E", "nu", "phi", "psi", "c"}  (angles in radians)
-  bc       {"face": [-x, +x, -y, +y, -z, +z] rules, "extra": None or (node ids, axes, values)}
+  bc       {"face": [-x, +x, -y, +y, -z, +z] rules, "extra": None or (node ids, axes, values),
+            "force": absent, None or (node ids, forces (k, 3))}
   scheme   {"algo", "shape", "velocity_update", "gravity", "dt", "mass_eps_rel"}
   x (n,3) float64; v (n,3), vol (n,), mass (n,), stress (n,6) float64 holding
   float32-representable values (so an FP32 consumer starts from exactly the
@@ -155,21 +156,44 @@ def c5(seed: int = 5, subsample: bool = False, shape: int = SHAPE_GIMP) -> dict:
 PLATE = {"h": 0.0625, "radius": 0.5, "half_length": 4.0, "half_width": 2.5, "sigma0": 100.0}
 
 
-def plate_with_hole(load_time: float = 1.0, points_per_axis: int = 4, material=None) -> dict:
+def plate_end_forces(mesh: dict, sigma0: float, end_i: int, width_cells: int) -> tuple:
+    """Nodal forces equivalent to a uniform traction sigma0 (along +x) on the
+    strip's end face x = end_i h, which spans width_cells cells in y and the
+    mesh's one cell in z: each bilinear face element of h x h carries
+    sigma0 h^2 / 4 to each of its four corner nodes.  Node ids in the
+    library's numbering (linear shape functions)."""
+    h = mesh["h"]
+    n0, n1 = mesh["n"][0] + 1, mesh["n"][1] + 1
+    f = {}
+    for j in range(width_cells):
+        for k in range(mesh["n"][2]):
+            for dj in (0, 1):
+                for dk in (0, 1):
+                    node = end_i + n0 * ((j + dj) + n1 * (k + dk))
+                    f[node] = f.get(node, 0.0) + sigma0 * h * h / 4.0
+    ids = sorted(f)
+    return ids, np.array([[f[i], 0.0, 0.0] for i in ids])
+
+
+def plate_with_hole(load: str = "traction", load_time: float = 1.0, hold_time: float = 0.0,
+                    points_per_axis: int = 4, material=None) -> dict:
     """The paper's validation strip (benchmark section, Table 1): 5 m wide,
-    8 m long, a centred hole of radius 0.5 m, in uniaxial tension of about
-    100 Pa along its length (x), cells of 0.0625 m.  The quarter x, y >= 0
-    is modelled with symmetry (slip) faces at x = 0 and y = 0, as one layer
-    of cells with 4 x 4 points per cell (all at mid-thickness) and a slip
-    face at z = 0 and a free one at z = h, which leaves sigma_zz free (plane
+    8 m long, a centred hole of radius 0.5 m, in uniaxial tension of 100 Pa
+    along its length (x), cells of 0.0625 m.  The quarter x, y >= 0 is
+    modelled with symmetry (slip) faces at x = 0 and y = 0, as one layer of
+    cells with 4 x 4 points per cell (all at mid-thickness) and a slip face
+    at z = 0 and a free one at z = h, which leaves sigma_zz free (plane
     stress).  Points are the sub-cell centres outside the hole: 40,153 of
     them (the paper has 40,156).
 
-    The end x = 4 m is pulled at the constant velocity that reaches the
-    nominal strain sigma0 / E at `load_time` (per-node velocity constraints
-    on its nodes, in the library's node numbering); the mesh leaves two
-    empty cell columns beyond it.  PIC velocity update, no gravity, explicit
-    USF, linear shape functions, dt at a CFL number of 0.3."""
+    load="traction" (the paper's load): sigma0 = 100 Pa on the end face
+    x = 4 m as nodal forces (plate_end_forces), ramped linearly from zero
+    over `load_time` seconds and then held for `hold_time`.  load="pulled":
+    the end's nodes move along x at the constant velocity that reaches the
+    nominal strain sigma0 / E at `load_time` (per-node velocity
+    constraints).  The mesh leaves two empty cell columns beyond the end.
+    PIC velocity update (it damps the motion), no gravity, explicit USF,
+    linear shape functions, dt at a CFL number of 0.3."""
     P = PLATE
     h, a, L, W = P["h"], P["radius"], P["half_length"], P["half_width"]
     nx, ny = int(round(L / h)), int(round(W / h))
@@ -182,10 +206,17 @@ def plate_with_hole(load_time: float = 1.0, points_per_axis: int = 4, material=N
     mat = material or elastic()
     dt = 0.3 * h / p_wave_speed(mat)
     nsteps = int(round(load_time / dt))
-    speed = P["sigma0"] / mat["E"] * L / load_time
-    n0, n1 = mesh["n"][0] + 1, mesh["n"][1] + 1
-    ids = [nx + n0 * (j + n1 * k) for k in range(2) for j in range(n1)]
-    bc = {"face": [SLIP, FREE, SLIP, FREE, SLIP, FREE], "extra": (ids, [0] * len(ids), [speed] * len(ids))}
+    if load == "traction":
+        bc = {"face": [SLIP, FREE, SLIP, FREE, SLIP, FREE], "extra": None,
+              "force": plate_end_forces(mesh, P["sigma0"], nx, ny), "force_ramp_steps": nsteps}
+        nsteps += int(round(hold_time / dt))
+    elif load == "pulled":
+        speed = P["sigma0"] / mat["E"] * L / load_time
+        n0, n1 = mesh["n"][0] + 1, mesh["n"][1] + 1
+        ids = [nx + n0 * (j + n1 * k) for k in range(2) for j in range(n1)]
+        bc = {"face": [SLIP, FREE, SLIP, FREE, SLIP, FREE], "extra": (ids, [0] * len(ids), [speed] * len(ids))}
+    else:
+        raise ValueError(f"unknown plate load {load!r}")
     sc = make_scene("plate_with_hole", mesh, mat, bc,
                     scheme(dt, gravity=(0.0, 0.0, 0.0), velocity_update=PIC), x, None, nsteps=nsteps)
     sc["vol"] = _f32(np.full(len(x), h ** 3 / points_per_axis ** 2))

@@ -163,3 +163,48 @@ def test_dp_cohesionless_closed_form_cases():
     # pure shear at zero pressure returns to the apex (zero stress)
     new, kind = oracle.constitutive(mat, np.zeros(6), [0, 0, 0, 1e3, 0, 0])
     assert np.allclose(new, 0.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("phi_deg,c", [(30.0, 0.0), (30.0, 4e3), (20.0, 1e3), (40.0, 2e3)])
+def test_dp_plane_strain_cone_reproduces_mohr_coulomb_in_plane_strain(phi_deg, c):
+    """The plane-strain cone is the one whose associated flow, with no plastic
+    strain out of the plane, yields exactly on the Mohr-Coulomb line of the
+    in-plane principal stresses s1 = m + t, s3 = m - t:
+    t = c cos(phi) - m sin(phi) (tension positive).  With the out-of-plane
+    stress z = m + d, sqrt(J2) = sqrt(t^2 + d^2 / 3), and zero out-of-plane
+    flow, d/s_zz-direction: (2/3) d = -(2/3) eta sqrt(J2), which fixes
+    d = -eta t / sqrt(1 - eta^2 / 3).  Such states must sit on the oracle's
+    cone for every m and c: a state a hair inside stays elastic, a hair
+    outside returns.  A wrong coefficient in eta or xi moves f off zero."""
+    rng = np.random.default_rng(7)
+    phi = math.radians(phi_deg)
+    mat = scenes.drucker_prager(phi_deg=phi_deg, psi_deg=phi_deg, c=c, cone=scenes.DP_PLANE_STRAIN)
+    eta, xi, etab = oracle.dp_coefficients(mat)
+    assert etab == pytest.approx(eta, rel=1e-15)          # associated: psi = phi
+    for m in (-8e4, -2e4, -5e3):
+        t = c * math.cos(phi) - m * math.sin(phi)
+        d = -eta * t / math.sqrt(1.0 - eta * eta / 3.0)
+        sig = principal_to_voigt(m + t, m + d, m - t, rng)
+        scale = abs(m) + c
+        assert dp_f(sig, eta, xi, c) == pytest.approx(0.0, abs=1e-10 * scale)
+        # the deviator's out-of-plane component equals the flow condition
+        for f, kind in ((1.0 - 1e-6, 0), (1.0 + 1e-6, 1)):
+            p = sig[:3].mean()
+            trial = sig.copy()
+            trial[:3] -= p
+            trial *= f
+            trial[:3] += p
+            _, got = oracle.constitutive(mat, np.zeros(6), trial)
+            assert got == kind, (m, f)
+
+
+def test_dp_cone_constants_at_thirty_degrees():
+    """At phi = 30 deg: outer eta = 2 sqrt(3)/5 = 0.69282 (M_c = 1.2); inner
+    eta = 6 (1/2) / (sqrt(3) 3.5) = 0.49487; plane strain eta =
+    3 tan(30) / sqrt(13) = 0.48038 (tan^2 = 1/3)."""
+    want = {scenes.DP_OUTER: 0.69282, scenes.DP_INNER: 0.49487, scenes.DP_PLANE_STRAIN: 0.48038}
+    for cone, eta_w in want.items():
+        eta, xi, _ = oracle.dp_coefficients(scenes.drucker_prager(phi_deg=30.0, cone=cone))
+        assert eta == pytest.approx(eta_w, abs=5e-6), cone
+    eta, xi, _ = oracle.dp_coefficients(scenes.drucker_prager(phi_deg=30.0, cone=scenes.DP_PLANE_STRAIN))
+    assert xi == pytest.approx(3.0 / math.sqrt(13.0), rel=1e-14)

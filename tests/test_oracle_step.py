@@ -275,3 +275,36 @@ def test_pic_velocity_is_interpolated_nodal_velocity():
     g = out["grid"]
     _, N, _ = weights_all_nodes(sc["mesh"], oracle.SHAPE_LINEAR, sc["x"])
     np.testing.assert_allclose(out["v"], N.T @ g.vn, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("ramp", [0, 10])
+def test_nodal_forces_change_momentum_by_their_impulse(ramp):
+    """With no gravity and no walls, internal forces sum to zero at the nodes
+    and the FLIP update hands the particles exactly dt times the nodal force
+    sum of every step (every forced node carrying mass), so the particles'
+    total momentum grows by the external forces' impulse:
+    P_N - P_0 = dt sum_n r(n) sum_e F_e, with the ramp r(n) = u^2 (3 - 2u),
+    u = n / ramp, below the ramp's end and 1 from there (or 1 throughout)."""
+    sc = scenes.random_block(n_cells=(4, 4, 3), mesh_cells=(12, 12, 11), gravity=(0, 0, 0),
+                             bc=scenes.walls(floor=scenes.FREE, sides=scenes.FREE), seed=8, vel=0.05)
+    sc["x"] = sc["x"] + np.array([0.0, 0.0, 4 * sc["mesh"]["h"]])
+    # two nodes inside the block (cells 4..7 x, 4..7 y, 4..6 z after the lift)
+    ids = [oracle.node_id(sc["mesh"], 0, 5, 5, 5), oracle.node_id(sc["mesh"], 0, 6, 6, 6)]
+    F = np.array([[0.02, -0.01, 0.03], [-0.005, 0.04, 0.01]])
+    sc["bc"] = dict(sc["bc"], force=(ids, F), force_ramp_steps=ramp)
+    n = 25
+    dt = sc["scheme"]["dt"]
+    P0 = (sc["mass"][:, None] * sc["v"]).sum(axis=0)
+    out = oracle.run(sc, n)
+    assert out["steps_done"] == n
+    P1 = (sc["mass"][:, None] * out["v"]).sum(axis=0)
+    u = np.minimum(np.arange(1, n + 1) / ramp, 1.0) if ramp else np.ones(n)
+    r = u * u * (3 - 2 * u) if ramp else u
+    want = dt * r.sum() * F.sum(axis=0)
+    scale = (sc["mass"][:, None] * np.abs(sc["v"])).sum()
+    np.testing.assert_allclose(P1 - P0, want, atol=1e-12 * scale)
+    assert np.abs(want).max() > 1e3 * 1e-12 * scale
+    # the same run split in two calls continues the ramp
+    half = oracle.run(sc, 11)
+    rest = oracle.run(sc, n - 11, state=half)
+    np.testing.assert_array_equal(rest["v"], out["v"])
