@@ -1,20 +1,24 @@
 """Throughput of the explicit MPM step on one MI355X.
 
-Workload (default): the granular column collapse -- a Drucker-Prager block of
-64x32x128 cells (2,097,152 particles, 8 per cell, jittered) on a 256x128x160
-mesh of 0.01 m cells, frictionless walls, dt = 2e-5 s, FP32 particle state
-with FP64 positions and nodal mass.  One "step" is one full update-stress-
-first time step (reorder check, nodal clear, P2G, stress + force, G2P) of all
-particles.  Inputs are resident in device memory before timing starts.
+Workload (default, ``--workload batch``): the batched set -- 256 independent
+scenes of 1k-250k particles each (log-uniform), elastic or Drucker-Prager
+blocks on meshes of 0.02 m cells, CFL 0.3 -- advanced together, one launch per
+stage, FP32 particle state with FP64 positions and nodal mass.  One "step" is
+one full update-stress-first time step (reorder check, nodal clear, P2G,
+stress + force, G2P) of every particle of every scene.  Inputs are resident in
+device memory before timing starts.
 
-Prints one JSON line: particle-updates/s over the K timed steps (launched as
-the library launches them: tuned launch shape, K-step HIP graphs), the
-dominant kernel's achieved bandwidth against the HBM peak (from a second
-pass of K steps in which every kernel is launched directly between two HIP
-events on the library's stream), and the FP64 oracle timed on a bounded
-sample on the host CPU.
+Prints one JSON line: batched particle-updates/s over exactly K timed steps
+(after an untimed warm-up call that tunes the launch shape and records the
+K-step HIP graphs), the plain one-scene-at-a-time rate over the same steps,
+p50/p99 per-scene completion latency of both over the set's own 500 steps,
+the dominant kernel's achieved bandwidth against the HBM peak (from a pass in
+which every kernel is launched between two HIP events on the library's
+stream), the FP64 oracle timed on a bounded sample on the host CPU, and the
+granular column's full 1000-step run.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload column|column_gimp|c1|c5|c5_linear|batch|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload batch|column|column_gimp|column_usl|plate|c1|c5|c5_linear|serve]
 """
 from __future__ import annotations
 
@@ -316,88 +320,211 @@ def _percentiles(vals):
             "max_ms": float(v[-1]), "n": int(len(v))}
 
 
+def host_identity() -> dict:
+    """The host CPU the oracle baseline ran on: logical CPUs and model name."""
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return {"host_cpus": os.cpu_count() or 1, "host_cpus_available": avail, "cpu_model": model}
+
+
+def active_nodes(mesh: dict, counts: np.ndarray) -> int:
+    """Nodes of the occupied cells (linear shape functions): the nodes a
+    step's transfers touch."""
+    nx, ny, nz = (int(c) for c in mesh["n"])
+    cells = np.flatnonzero(counts)
+    cx, cy, cz = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+    ids = []
+    for dk in (0, 1):
+        for dj in (0, 1):
+            for di in (0, 1):
+                ids.append((cx + di) + (nx + 1) * ((cy + dj) + (ny + 1) * (cz + dk)))
+    return int(np.unique(np.concatenate(ids)).size) if len(cells) else 0
+
+
 def run_batch(args):
     """The batched set: 256 independent scenes (1k-250k particles, elastic
-    or Drucker-Prager), 500 steps each, FP32.  Batched: one launch per
-    stage over all scenes.  Plain: the same kernels per scene, scenes one
-    after another in FIFO order, on a second copy of the inputs.  Per-scene
-    completion latency is measured from the start of the timed region to the
-    scene's completion (HIP event after its last launch)."""
+    or Drucker-Prager), FP32.  Batched: one launch per stage over all scenes.
+    Plain: the same kernels per scene, scenes one after another in FIFO
+    order.  Both legs first run an untimed warm-up call that tunes the launch
+    shape and records the K-step HIP graphs, so the timed calls only replay.
+    `value` is the batched rate over exactly K timed steps per scene; the
+    plain rate over the same K steps stands beside it.  Latency: a second
+    pair of runs over the set's own 500 steps, each scene's completion
+    measured from the start of the run (HIP event after its last launch;
+    in the batch every scene ends with the batch's last step)."""
     import torch
     from paper_1909_13380_amd import mpmx, scenes
     n_sc = args.scenes
-    steps = args.steps if args.steps_given else 500
-    scs = scenes.c3(n_sc, nsteps=steps)
+    K = args.steps
+    full_steps = 500
+    scs = scenes.c3(n_sc, nsteps=full_steps)
     total = int(sum(len(sc["x"]) for sc in scs))
     print(f"# {n_sc} scenes, {total} particles", file=sys.stderr, flush=True)
-    cb_par = None
+    cb = cb_par = None
     if not args.no_cpu_baseline:
         # before anything touches the GPU: the pool forks
-        cores = max(1, min(16, os.cpu_count() or 1))
+        ident = host_identity()
         by_size = sorted(scs, key=lambda sc: len(sc["x"]))
+        one = by_size[:: max(1, len(by_size) // 8)][:8]
+        print("# timing the oracle on the host", file=sys.stderr, flush=True)
+        cb = cpu_baseline_scenes(one, args.cpu_steps * 40)
+        cb.update(ident)
+        cores = max(1, min(16, ident["host_cpus_available"]))
         sample = by_size[:: max(1, len(by_size) // (2 * cores))][: 2 * cores]
         cb_par = cpu_baseline_parallel(sample, 10, cores)
+        cb_par.update(ident)
+        cb_par["note"] = "16 worker processes at most: the CPU share of one GPU on the measurement host"
     torch.cuda.init()
     stream = torch.cuda.Stream()          # a real stream: the library and torch's events share it
     torch.cuda.set_stream(stream)
     ctx = mpmx.Context(0, stream=stream.cuda_stream)
     apply_launch_options(ctx, args)
     untimed = max(args.warmup, mpmx.TUNE_MIN_STEPS)
-    out = {"metric": METRIC, "unit": "particle-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic"}
-    # batched
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # --- batched: warm-up (tunes, records the graphs), then K timed steps
     batch = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
     ctx.batch_step(batch, [untimed] * n_sc)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    ctx.batch_step(batch, [steps] * n_sc)
-    e1.record()
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    g0 = ctx.get_option(mpmx.OPT_GRAPH_LAUNCHES)
+    tb = timed(lambda: ctx.batch_step(batch, [K] * n_sc))
     launch_b = {"stress_threads": ctx.get_option(mpmx.OPT_STRESS_THREADS),
                 "g2p_threads": ctx.get_option(mpmx.OPT_G2P_THREADS),
-                "blocks_per_cu": ctx.get_option(mpmx.OPT_BLOCKS_PER_CU)}
-    errs = [b.stats()["error_bits"] for b in batch]
-    if any(errs):
-        raise SystemExit(f"batched scenes stopped with error bits {errs}")
+                "blocks_per_cu": ctx.get_option(mpmx.OPT_BLOCKS_PER_CU),
+                "graph_steps": ctx.get_option(mpmx.OPT_GRAPH_STEPS),
+                "graph_launches_in_timed_call": ctx.get_option(mpmx.OPT_GRAPH_LAUNCHES) - g0,
+                "tune_runs": ctx.get_option(mpmx.OPT_TUNE_RUNS)}
+    print(f"# batched: {K} steps in {tb * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    prof = {}
+    if not args.no_profile:
+        ctx.profile(True)
+        ctx.profile_reset()
+        ctx.batch_step(batch, [K] * n_sc)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+    n_nodes = 0
+    for sc, b in zip(scs, batch):
+        st = b.stats()
+        if st["error_bits"]:
+            raise SystemExit(f"batched scene {sc['name']} stopped with error bits {st['error_bits']}")
+        n_nodes += active_nodes(sc["mesh"], b.cell_counts())
     for b in batch:
         b.destroy()
-    # plain, FIFO
+    # --- plain FIFO: same warm-up per scene, then K timed steps each
     plain = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
     for s in plain:
         s.step(untimed)
-    torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in plain]
-    p0 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    p0.record()
-    for s, e in zip(plain, evs):
-        s.step(steps)
-        e.record()
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    lat_plain = [p0.elapsed_time(e) for e in evs]
+    tp = timed(lambda: [s.step(K) for s in plain])
+    print(f"# plain: {K} steps per scene in {tp * 1e3:.2f} ms", file=sys.stderr, flush=True)
     for s in plain:
         s.destroy()
+    # --- latency over the set's own 500 steps, from the initial state
+    lat = {}
+    batch = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tfb = timed(lambda: (e0.record(), ctx.batch_step(batch, [full_steps] * n_sc), e1.record()))
+    lat["batched"] = _percentiles([e0.elapsed_time(e1)] * n_sc)
+    for b in batch:
+        b.destroy()
+    plain = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in plain]
+    p0 = torch.cuda.Event(enable_timing=True)
+
+    def fifo():
+        p0.record()
+        for s, e in zip(plain, evs):
+            s.step(full_steps)
+            e.record()
+    tfp = timed(fifo)
+    lat["plain"] = _percentiles([p0.elapsed_time(e) for e in evs])
+    for s in plain:
+        s.destroy()
+    # --- the single large scene (granular column, 2.1M particles): its full
+    # 1000-step run from the initial state in one call, reorders included
+    col = None
+    if not args.no_column:
+        csc = scenes.c2()
+        cs = ctx.create_scene(csc, precision=mpmx.FP32)
+        tc = timed(lambda: cs.step(csc["nsteps"]))
+        st = cs.stats()
+        if st["error_bits"]:
+            raise SystemExit(f"column stopped with error bits {st['error_bits']}")
+        col = {"workload": "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, USF, FP32",
+               "steps": csc["nsteps"], "seconds": tc, "ms_per_step": 1e3 * tc / csc["nsteps"],
+               "value": len(csc["x"]) * csc["nsteps"] / tc, "reorders": st["n_sorts"],
+               "note": "one call from the initial state: first-step P2G, graph recording and every reorder "
+                       "included"}
+        cs.destroy()
+        print(f"# column: {csc['nsteps']} steps in {tc * 1e3:.1f} ms, {st['n_sorts']} reorders",
+              file=sys.stderr, flush=True)
     ctx.close()
-    pu = total * steps
-    out["value"] = pu / tb
-    out["ms_per_step"] = 1e3 * tb / steps
-    out["config"] = {"workload": f"{n_sc} independent scenes, 1k-250k particles each (log-uniform), elastic or "
-                                 f"Drucker-Prager, 0.02 m cells, CFL 0.3, {steps} steps, batched",
-                     "scenes": n_sc, "particles": total, "untimed_steps_before": untimed, "launch": launch_b}
-    out["plain"] = {"value": pu / tp, "seconds": tp, "order": "FIFO, one scene at a time, same kernels"}
+    pu = total * K
+    out = {"metric": METRIC, "value": pu / tb, "unit": "particle-updates/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": 1e3 * tb / K, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"batched: {n_sc} independent scenes, 1k-250k particles each (log-uniform), "
+                                  f"elastic or Drucker-Prager, 0.02 m cells, CFL 0.3, one launch per stage",
+                      "scenes": n_sc, "particles": total, "touched_nodes": n_nodes,
+                      "precision": "fp32 state, fp64 positions and nodal mass",
+                      "untimed_steps_before": untimed, "launch": launch_b}}
+    out["plain"] = {"value": pu / tp, "ms_per_step": 1e3 * tp / K,
+                    "order": "FIFO, one scene at a time, same kernels, each scene warmed up alike"}
     out["speedup_vs_plain"] = tp / tb
-    out["latency"] = {"batched": _percentiles([e0.elapsed_time(e1)] * n_sc), "plain": _percentiles(lat_plain)}
-    if not args.no_cpu_baseline:
-        small = min(scs, key=lambda sc: len(sc["x"]))
-        cb = cpu_baseline(small, min(args.cpu_steps * 20, steps))
-        cb["sample"] = f"smallest scene of the set ({len(small['x'])} particles), " + cb["sample"].split(", ", 1)[1]
+    out["latency"] = {"steps": full_steps, "batched": lat["batched"], "plain": lat["plain"],
+                      "batched_value": total * full_steps / tfb, "plain_value": total * full_steps / tfp,
+                      "note": "per-scene completion from the start of a run from the initial state (first-call "
+                              "work included); all scenes of the batch end with its last step"}
+    if prof:
+        kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1), "total_ms": v[1]}
+                   for k, v in prof.items()}
+        dom = max((k for k in kernels if k in ("stress", "g2p_p2g")), key=lambda k: kernels[k]["total_ms"])
+        nbytes = kernel_bytes(dom, total, n_nodes)
+        achieved = nbytes / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, "batch"),
+                           "algorithmic_bytes_per_launch": nbytes}
+        out["kernels"] = kernels
+        step_bytes = sum(kernel_bytes(k, total, n_nodes) for k in ("stress", "g2p_p2g"))
+        out["step_algorithmic_GBs"] = step_bytes / (tb / K) / 1e9
+    if cb is not None:
         out["cpu_baseline"] = cb
         out["cpu_baseline_parallel"] = cb_par
+    if col is not None:
+        out["column"] = col
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_scenes(scs: list, steps: int) -> dict:
+    """The oracle on one host thread over a sample of the set's scenes, each
+    for `steps` steps from its initial state (first touch of its nodal
+    arrays outside the timing)."""
+    import oracle
+    pu, sec = 0, 0.0
+    for sc in scs:
+        grid = oracle.Grid(sc["mesh"], sc["scheme"]["shape"])
+        oracle.run(sc, 1, grid=grid)
+        t0 = time.perf_counter()
+        oracle.run(sc, steps, grid=grid)
+        sec += time.perf_counter() - t0
+        pu += len(sc["x"]) * steps
+    return {"value": pu / sec, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(scs)} scenes of the set spread over its sizes ({sum(len(s['x']) for s in scs)} "
+                      f"particles), first {steps} steps of each, FP64, one thread", "seconds": round(sec, 3)}
 
 
 def run_serve(args):
@@ -457,11 +584,13 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="column")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="batch")
+    ap.add_argument("--no-column", action="store_true",
+                    help="--workload batch: skip the full 1000-step run of the granular column")
     ap.add_argument("--sort", default="on_demand", choices=["on_demand", "always"])
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps of the CPU baseline (batch: 40x this)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel HIP event timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define MPMX_VERSION 1
+#define MPMX_VERSION 2
 
 /* ------------------------------------------------------------ codes ---- */
 enum {
@@ -78,8 +78,18 @@ enum { MPMX_FP32 = 0, MPMX_FP64 = 1 };
 enum { MPMX_SORT_ON_DEMAND = 0, MPMX_SORT_ALWAYS = 1 };
 enum { MPMX_MEM_HOST = 0, MPMX_MEM_DEVICE = 1 };
 
-/* Scene error bits reported by mpmx_scene_stats. */
-enum { MPMX_ERRBIT_OUT_OF_MESH = 1u, MPMX_ERRBIT_NONFINITE = 2u };
+/* Scene error bits reported by mpmx_scene_stats (sticky: the scene stops at
+ * the step that raised one).  OUT_OF_MESH and NONFINITE come from the
+ * particles; TILE (a work item's particles spread beyond its LDS node tile)
+ * and SORT (a reorder gave up waiting for one of its phases) are failures of
+ * the implementation that its own rules exclude, reported rather than
+ * silently mishandled; mpmx_scene_read maps them to MPMX_E_STATE. */
+enum {
+    MPMX_ERRBIT_OUT_OF_MESH = 1u,
+    MPMX_ERRBIT_NONFINITE = 2u,
+    MPMX_ERRBIT_TILE = 4u,
+    MPMX_ERRBIT_SORT = 8u
+};
 
 /* --------------------------------------------------------- descriptors -- */
 /* Each descriptor starts with its own size in bytes (sizeof), so that later
@@ -106,7 +116,20 @@ typedef struct {
  * included; FIXED constrains all components to 0, SLIP the normal one), then
  * n_extra per-node constraints (node id, axis 0..2, prescribed velocity) that
  * take precedence.  Constrained components get the prescribed velocity and
- * zero acceleration. */
+ * zero acceleration (code overview: velocity constraints held at nodes;
+ * isoparametric-mesh section: boundary conditions applied at the nodes).
+ *
+ * Nodal external forces (benchmark section: a traction applied at the ends
+ * of the strip, here as the equivalent nodal forces): n_force entries of
+ * node id and force vector (force_value[3 e + a], newtons), added to the
+ * nodal force of every step before the acceleration a = f / m is formed (so
+ * a void node, m <= eps_m, still gets a = 0).  Entries naming the same node
+ * add up.  In the scene's n-th step (n = 1 for its first) the forces are
+ * scaled by u^2 (3 - 2 u) with u = n / force_ramp_steps while n <
+ * force_ramp_steps, and by 1 from then on: a smooth ramp to a hold, which
+ * loads the body quasi-statically (its residual vibration falls with the
+ * square of the ramp time); force_ramp_steps = 0 applies them in full from
+ * the first step.  n_force = 0 (and NULL pointers) for none. */
 typedef struct {
     uint32_t size;
     int32_t face[6];
@@ -114,6 +137,10 @@ typedef struct {
     const int64_t *node;
     const int32_t *axis;
     const double *value;
+    int64_t n_force;
+    const int64_t *force_node;
+    const double *force_value;
+    int64_t force_ramp_steps;   /* >= 0 */
 } mpmx_bc;
 
 typedef struct {
@@ -147,6 +174,14 @@ typedef struct {
     int32_t *cell;
 } mpmx_particles_out;
 
+/* Scene counters.  pic_hash identifies the particles-per-cell histogram of
+ * the current positions (code overview: a cell is active when it holds a
+ * material point): starting from h = 14695981039346656037, for every cell
+ * c (linear cell id, ascending) holding k > 0 particles, h = (h ^ c) *
+ * 1099511628211, then h = (h ^ k) * 1099511628211 (64-bit FNV-1a steps on
+ * the two integers, modulo 2^64).  Equal histograms give equal hashes.
+ * lost_particles counts the particles that left the mesh in the step that
+ * stopped the scene (0 while it runs). */
 typedef struct {
     uint32_t size;
     int64_t n_particles;
@@ -157,6 +192,8 @@ typedef struct {
     uint32_t error_bits;    /* MPMX_ERRBIT_* */
     uint32_t pad_;
     uint64_t device_bytes;  /* device memory held by the scene */
+    uint64_t pic_hash;      /* hash of the particles-per-cell histogram (above) */
+    int64_t lost_particles; /* particles outside the mesh when the scene stopped */
 } mpmx_stats;
 
 typedef struct mpmx_ctx mpmx_ctx;
@@ -182,16 +219,23 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  * them beyond the order of floating-point sums).
  *   MPMX_OPT_GRAPH_STEPS   steps recorded into one HIP graph and replayed
  *                          with one launch; 0 launches every kernel
- *                          directly.  Default 8.  Graphs are not used while
+ *                          directly.  Default 8.  The graph of a batch is
+ *                          recorded by its first call of more than one step
+ *                          (after tuning, when that call tunes), so later
+ *                          calls only replay it.  Graphs are not used while
  *                          per-kernel profiling is on.
  *   MPMX_OPT_AUTOTUNE      1 (default): on the first call that runs at least
  *                          MPMX_TUNE_MIN_STEPS steps on a batch layout
  *                          (precision, shape function, algorithm and the
  *                          power-of-two bucket of its particle count), time
- *                          the item kernels at every workgroup size and
- *                          grid density, then keep the fastest for that
- *                          layout.  The timed steps are steps of the call.
- *                          0: use the values below.
+ *                          the item kernels at every pair of workgroup size
+ *                          and grid density (3 steps each), then keep the
+ *                          fastest for that layout; shapes within 2 % of
+ *                          the fastest count as ties, settled by a fixed
+ *                          preference order (256 threads and 16 workgroups
+ *                          per CU first), so that the choice is stable
+ *                          between runs.  The timed steps are steps of the
+ *                          call.  0: use the values below.
  *   MPMX_OPT_STRESS_THREADS  workgroup size of the stress kernel (USL: the
  *                          P2G kernel): 64, 128 or 256.  Setting it, or one
  *                          of the next two, turns autotuning off.
@@ -202,7 +246,7 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  * mpmx_get_option of the three launch shapes returns the values of the
  * last call that stepped a batch.  Errors: MPMX_E_INVALID_ARG for an
  * unknown option or a value out of range. */
-#define MPMX_TUNE_MIN_STEPS 24
+#define MPMX_TUNE_MIN_STEPS 40
 enum {
     MPMX_OPT_GRAPH_STEPS = 1,
     MPMX_OPT_AUTOTUNE = 2,

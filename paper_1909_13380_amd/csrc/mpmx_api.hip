@@ -289,7 +289,7 @@ Sizes sizes_of(const mpmx_mesh *m, int shape, int prec, int64_t np)
 uint64_t align_up(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 
 // Device bytes of a scene; the allocation below follows the same list.
-uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc)
+uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = false)
 {
     uint64_t b = 0;
     const uint64_t R = s.real;
@@ -302,8 +302,10 @@ uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc)
     b += 2 * align_up(4 * (uint64_t)s.nbricks) + 2 * align_up(4 * (uint64_t)(s.nbricks + 1));
     b += align_up(sizeof(Item) * (uint64_t)s.max_items) + 3 * align_up(sizeof(Tile) * (uint64_t)s.max_items);
     b += align_up(4 * CTL_WORDS) + align_up(sizeof(SceneDev));
-    if (extra_bc)
+    if (extra_bc || force)
         b += align_up((uint64_t)s.nn) + align_up(24 * (uint64_t)s.nn);
+    if (force)
+        b += align_up(24 * (uint64_t)s.nn);
     return b;
 }
 
@@ -341,6 +343,9 @@ int validate(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat, con
                 return fail(ctx, MPMX_E_INVALID_ARG, "bc: face %d rule %d unknown", f, bc->face[f]);
         if (bc->n_extra < 0 || (bc->n_extra > 0 && (!bc->node || !bc->axis || !bc->value)))
             return fail(ctx, MPMX_E_INVALID_ARG, "bc: bad per-node constraint list");
+        if (bc->n_force < 0 || (bc->n_force > 0 && (!bc->force_node || !bc->force_value)) ||
+            bc->force_ramp_steps < 0)
+            return fail(ctx, MPMX_E_INVALID_ARG, "bc: bad nodal force list or ramp");
     }
     if (!sch || sch->size < sizeof(mpmx_scheme))
         return fail(ctx, MPMX_E_INVALID_ARG, "scheme descriptor missing or too small");
@@ -558,12 +563,19 @@ uint64_t layout_key(const Batch &b)
 }
 
 // Online tuning of the item kernels' launch shape on real steps of the call:
-// every workgroup size for both kernels (their times are separate, so each
-// kernel takes its fastest), then the grid density with those sizes.  Each
-// candidate runs kTuneReps steps and keeps its fastest.  Uses kTuneSteps steps.
+// every (grid density, workgroup size) pair, kTuneReps steps each, timing
+// the stress-side and the G2P-side kernels separately (each keeps its
+// fastest repeat).  The two kernels share the grid density, so a density is
+// scored by its best stress size plus its best G2P size.  Shapes within
+// kTuneBand of the fastest count as ties, and ties go to the first shape in
+// a fixed preference order (the default shape, then larger workgroups and
+// densities nearer the default), so that timing noise between nearly equal
+// shapes does not change the choice from one run to the next.
 constexpr int kTuneReps = 3;
 constexpr int kTuneDensity[] = {4, 8, 16, 32};
-constexpr int kTuneSteps = kTuneReps * (kNumItemThreadChoices + 4);
+constexpr int kNumTuneDensity = 4;
+constexpr int kTuneSteps = kTuneReps * kNumItemThreadChoices * kNumTuneDensity;
+constexpr float kTuneBand = 0.02f;
 static_assert(kTuneSteps + 1 <= MPMX_TUNE_MIN_STEPS, "tuning must fit in the calls it runs on");
 
 int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
@@ -579,55 +591,69 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
     int rc = MPMX_OK;
     int k = 0;
     LaunchCfg cfg = best;
-    for (int t = 0; t < kNumItemThreadChoices && !rc; ++t) {
-        cfg.t_stress = cfg.t_g2p = t;
-        for (int r = 0; r < kTuneReps && !rc; ++r, ++k)
-            rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
-    }
+    for (int d = 0; d < kNumTuneDensity && !rc; ++d)
+        for (int t = 0; t < kNumItemThreadChoices && !rc; ++t) {
+            cfg.blocks_per_cu = kTuneDensity[d];
+            cfg.t_stress = cfg.t_g2p = t;
+            for (int r = 0; r < kTuneReps && !rc; ++r, ++k)
+                rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
+        }
     if (!rc && hipEventSynchronize(ev[3 * k - 1]) != hipSuccess)
         rc = fail(ctx, MPMX_E_HIP, "tuning: event wait failed");
-    float bs = 1e30f, bg = 1e30f;
-    for (int t = 0, q = 0; t < kNumItemThreadChoices && !rc; ++t)
-        for (int r = 0; r < kTuneReps; ++r, ++q) {
-            float m1 = 0.f, m2 = 0.f;
-            if (hipEventElapsedTime(&m1, ev[3 * q], ev[3 * q + 1]) != hipSuccess ||
-                hipEventElapsedTime(&m2, ev[3 * q + 1], ev[3 * q + 2]) != hipSuccess) {
-                rc = fail(ctx, MPMX_E_HIP, "tuning: event timing failed");
-                break;
-            }
-            if (m1 < bs) {
-                bs = m1;
-                best.t_stress = t;
-            }
-            if (m2 < bg) {
-                bg = m2;
-                best.t_g2p = t;
+    // ts[d][t], tg[d][t]: fastest repeat of each kernel at density d, size t
+    float ts[kNumTuneDensity][kNumItemThreadChoices], tg[kNumTuneDensity][kNumItemThreadChoices];
+    for (int d = 0, q = 0; d < kNumTuneDensity && !rc; ++d)
+        for (int t = 0; t < kNumItemThreadChoices && !rc; ++t) {
+            ts[d][t] = tg[d][t] = 1e30f;
+            for (int r = 0; r < kTuneReps; ++r, ++q) {
+                float m1 = 0.f, m2 = 0.f;
+                if (hipEventElapsedTime(&m1, ev[3 * q], ev[3 * q + 1]) != hipSuccess ||
+                    hipEventElapsedTime(&m2, ev[3 * q + 1], ev[3 * q + 2]) != hipSuccess) {
+                    rc = fail(ctx, MPMX_E_HIP, "tuning: event timing failed");
+                    break;
+                }
+                ts[d][t] = std::min(ts[d][t], m1);
+                tg[d][t] = std::min(tg[d][t], m2);
             }
         }
-    cfg = best;
-    const int k0 = k;
-    for (int d : kTuneDensity) {
-        if (rc)
-            break;
-        cfg.blocks_per_cu = d;
-        for (int r = 0; r < kTuneReps && !rc; ++r, ++k)
-            rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
+    if (!rc) {
+        // preference order: densities by distance from 16, sizes largest first
+        const int dorder[kNumTuneDensity] = {2, 1, 3, 0};
+        float tot[kNumTuneDensity];
+        int bs[kNumTuneDensity], bg[kNumTuneDensity];
+        float fastest = 1e30f;
+        for (int d = 0; d < kNumTuneDensity; ++d) {
+            float ms = 1e30f, mg = 1e30f;
+            for (int t = 0; t < kNumItemThreadChoices; ++t) {
+                ms = std::min(ms, ts[d][t]);
+                mg = std::min(mg, tg[d][t]);
+            }
+            bs[d] = bg[d] = 0;
+            for (int t = kNumItemThreadChoices - 1; t >= 0; --t) {
+                if (ts[d][t] <= ms * (1.f + kTuneBand)) {
+                    bs[d] = t;
+                    break;
+                }
+            }
+            for (int t = kNumItemThreadChoices - 1; t >= 0; --t) {
+                if (tg[d][t] <= mg * (1.f + kTuneBand)) {
+                    bg[d] = t;
+                    break;
+                }
+            }
+            tot[d] = ts[d][bs[d]] + tg[d][bg[d]];
+            fastest = std::min(fastest, tot[d]);
+        }
+        for (int i = 0; i < kNumTuneDensity; ++i) {
+            const int d = dorder[i];
+            if (tot[d] <= fastest * (1.f + kTuneBand)) {
+                best.blocks_per_cu = kTuneDensity[d];
+                best.t_stress = bs[d];
+                best.t_g2p = bg[d];
+                break;
+            }
+        }
     }
-    if (!rc && hipEventSynchronize(ev[3 * k - 1]) != hipSuccess)
-        rc = fail(ctx, MPMX_E_HIP, "tuning: event wait failed");
-    float bt = 1e30f;
-    for (int i = 0, q = k0; i < 4 && !rc; ++i)
-        for (int r = 0; r < kTuneReps; ++r, ++q) {
-            float m = 0.f;
-            if (hipEventElapsedTime(&m, ev[3 * q], ev[3 * q + 2]) != hipSuccess) {
-                rc = fail(ctx, MPMX_E_HIP, "tuning: event timing failed");
-                break;
-            }
-            if (m < bt) {
-                bt = m;
-                best.blocks_per_cu = kTuneDensity[i];
-            }
-        }
     for (auto &e : ev)
         (void)hipEventDestroy(e);
     ctx->tune_runs += rc ? 0 : 1;
@@ -712,10 +738,13 @@ int run_steps(mpmx_ctx *ctx, Batch &b, const int64_t *nsteps, int64_t uniform)
     }
     ctx->last = cfg;
     const int K = ctx->graph_steps;
+    // the K-step graph is recorded by the first call of more than one step
+    // with this launch shape (recording runs nothing), so that later calls
+    // only replay it, however few steps this one has left
+    if (K > 0 && !ctx->prof.on && smax > 1 && (!b.gexec || b.gsteps != K || !(b.gcfg == cfg)))
+        if ((rc = record_graph(ctx, b, cfg, K)))
+            return rc;
     if (K > 0 && !ctx->prof.on && left >= K) {
-        if (!b.gexec || b.gsteps != K || !(b.gcfg == cfg))
-            if ((rc = record_graph(ctx, b, cfg, K)))
-                return rc;
         for (; left >= K; left -= K) {
             HIPCHK(ctx, hipGraphLaunch(b.gexec, ctx->stream));
             ++ctx->graph_launches;
@@ -953,12 +982,18 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
                     (long long)((((int64_t)1 << 32) - 1) / std::max<int64_t>(24, 6 * rb)));
     if (sz.nkeys >= (int64_t)1 << 32 || sz.nn * std::max<int64_t>(8, 3 * rb) >= (int64_t)1 << 32)
         return fail(ctx, MPMX_E_INVALID_ARG, "mesh too large for 32-bit cell keys and node offsets");
-    const bool extra = bc->n_extra > 0;
+    const bool force = bc->n_force > 0;
+    const bool extra = bc->n_extra > 0 || force;
     for (int64_t e = 0; e < bc->n_extra; ++e)
         if (bc->node[e] < 0 || bc->node[e] >= sz.nn || bc->axis[e] < 0 || bc->axis[e] > 2 ||
             !std::isfinite(bc->value[e]))
             return fail(ctx, MPMX_E_INVALID_ARG, "bc: constraint %lld names node %lld axis %d", (long long)e,
                         (long long)bc->node[e], bc->axis[e]);
+    for (int64_t e = 0; e < bc->n_force; ++e)
+        if (bc->force_node[e] < 0 || bc->force_node[e] >= sz.nn || !std::isfinite(bc->force_value[3 * e]) ||
+            !std::isfinite(bc->force_value[3 * e + 1]) || !std::isfinite(bc->force_value[3 * e + 2]))
+            return fail(ctx, MPMX_E_INVALID_ARG, "bc: force %lld names node %lld or is not finite", (long long)e,
+                        (long long)bc->force_node[e]);
     HIPCHK(ctx, hipSetDevice(ctx->device));
 
     auto sc = std::make_unique<Scene>();
@@ -969,7 +1004,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     SceneDev &h = s->h;
     // one block of exactly scene_bytes(); the arrays are carved in the order
     // scene_bytes() counts them
-    const uint64_t total = scene_bytes(sz, np, extra);
+    const uint64_t total = scene_bytes(sz, np, extra, force);
     s->block = ctx->pool.alloc(total);
     if (!s->block)
         return fail(ctx, MPMX_E_OOM, "device allocation of %llu bytes failed", (unsigned long long)total);
@@ -1024,19 +1059,29 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     s->d = (SceneDev *)need(dalloc(sizeof(SceneDev), false), 1);
     if (extra) {
         std::vector<uint8_t> mask(sz.nn, 0);
-        std::vector<double> val(3 * sz.nn, 0.0);
+        std::vector<double> val(3 * sz.nn, 0.0), fv(force ? 3 * sz.nn : 0, 0.0);
         for (int64_t e = 0; e < bc->n_extra; ++e) {
             mask[bc->node[e]] |= (uint8_t)(1u << bc->axis[e]);
             val[3 * bc->node[e] + bc->axis[e]] = bc->value[e];
         }
+        for (int64_t e = 0; e < bc->n_force; ++e) {
+            mask[bc->force_node[e]] |= (uint8_t)8u;
+            for (int a = 0; a < 3; ++a)
+                fv[3 * bc->force_node[e] + a] += bc->force_value[3 * e + a];
+        }
         void *dm = need(dalloc(sz.nn, false), 1);
         void *dv = need(dalloc(24 * (uint64_t)sz.nn, false), 1);
+        void *df = force ? need(dalloc(24 * (uint64_t)sz.nn, false), 1) : nullptr;
         if (ok) {
             HIPCHK(ctx, hipMemcpy(dm, mask.data(), sz.nn, hipMemcpyHostToDevice));
             HIPCHK(ctx, hipMemcpy(dv, val.data(), 24 * sz.nn, hipMemcpyHostToDevice));
+            if (df)
+                HIPCHK(ctx, hipMemcpy(df, fv.data(), 24 * sz.nn, hipMemcpyHostToDevice));
         }
         h.bc_mask = (const uint8_t *)dm;
         h.bc_val = (const double *)dv;
+        h.bc_force = (const double *)df;
+        h.force_ramp = bc->force_ramp_steps;
     }
     for (auto &z : zero_ranges)
         if (ok && hipMemsetAsync(z.first, 0, z.second, ctx->stream) != hipSuccess)
@@ -1364,9 +1409,16 @@ int mpmx_scene_stats(mpmx_ctx *ctx, uint64_t scene, mpmx_stats *out)
     if (rc)
         return rc;
     int64_t active = 0;
-    for (uint32_t c : counts)
-        active += c > 0;
+    uint64_t hash = 14695981039346656037ull;   // FNV-1a over (cell, count) of the occupied cells
+    for (int64_t c = 0; c < nc; ++c)
+        if (counts[c] > 0) {
+            ++active;
+            hash = (hash ^ (uint64_t)c) * 1099511628211ull;
+            hash = (hash ^ (uint64_t)counts[c]) * 1099511628211ull;
+        }
     out->n_particles = s->h.np;
+    out->pic_hash = hash;
+    out->lost_particles = ctl[CTL_LOST];
     out->steps_done = ctl[CTL_STEPS];
     out->n_sorts = ctl[CTL_N_SORTS];
     out->n_items = ctl[CTL_N_ITEMS];

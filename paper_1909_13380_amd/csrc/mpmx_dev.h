@@ -56,6 +56,7 @@ enum Ctl : int {
     CTL_ACC1 = 12,
     CTL_BOX_OK = 13,    // tiles[CTL_NBUF] holds this step's node box of every item
     CTL_ALGO = 14,      // the scene's algorithm (0 USF, 1 USL), set at creation
+    CTL_LOST = 15,      // particles found outside the mesh (the scene stops on the first)
     CTL_WORDS = 16
 };
 
@@ -107,9 +108,11 @@ struct SceneDev {
     double g[3];
     double eps_m;
     uint32_t face_bits;  // 2 bits per face: 0 free, 1 fixed, 2 slip
-    // optional per-node constraints
-    const uint8_t *bc_mask;   // bits 0..2: component constrained
+    // optional per-node constraints and external forces
+    const uint8_t *bc_mask;   // bits 0..2: component constrained; bit 3: the node has an external force
     const double *bc_val;     // 3 per node (prescribed velocity)
+    const double *bc_force;   // 3 per node (external force), or null
+    int64_t force_ramp;       // the forces reach full size at this step (0: from the first)
     // particles (two buffers)
     double *x[2];
     void *v[2];

@@ -277,6 +277,18 @@ __device__ inline void node_velocity(const SceneDev &S, const NodeBuf<R> &nb, in
     velocity_from_raw<R>(S, ldg(nb.m, I), p, i, j, k, v);
 }
 
+// Factor of the external nodal forces in the scene's current step n (the
+// step control has counted it in CTL_STEPS): the smooth ramp u^2 (3 - 2u),
+// u = n / force_ramp, and 1 from step force_ramp on.
+__device__ inline double external_force_scale(const SceneDev &S)
+{
+    const int64_t n = (int64_t)__hip_atomic_load(&S.ctl[CTL_STEPS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (S.force_ramp <= 0 || n >= S.force_ramp)
+        return 1.0;
+    const double u = (double)n / (double)S.force_ramp;
+    return u * u * (3.0 - 2.0 * u);
+}
+
 // Nodal acceleration a = f / m and updated velocity vn = v + dt a, with the
 // constraints applied to v (prescribed), a (zero) and vn (prescribed), from
 // the node's mass, momentum and force.
@@ -285,18 +297,22 @@ __device__ inline void update_from_raw(const SceneDev &S, double m, const R p[3]
                                        R a[3], R vn[3])
 {
     const double inv = m > S.eps_m ? 1.0 / m : 0.0;   // void node: v = a = 0
-    R v[3];
-    for (int c = 0; c < 3; ++c) {
-        v[c] = (R)((double)p[c] * inv);
-        a[c] = (R)((double)f[c] * inv);
-    }
-    const uint32_t fm = face_mask(S, i, j, k);
     uint32_t em = 0u;
     uint32_t I = 0u;
     if (S.bc_mask) {
         I = node_id(S, i, j, k);
         em = gp(S.bc_mask)[I];
     }
+    // a node's external force (ramped over the scene's first steps) joins
+    // the particles' sum before a = f / m; CTL_STEPS is the running step
+    const double fs = (em & 8u) ? external_force_scale(S) : 0.0;
+    R v[3];
+    for (int c = 0; c < 3; ++c) {
+        v[c] = (R)((double)p[c] * inv);
+        const R fc = (em & 8u) ? f[c] + (R)(fs * gp(S.bc_force)[3 * (size_t)I + c]) : f[c];
+        a[c] = (R)((double)fc * inv);
+    }
+    const uint32_t fm = face_mask(S, i, j, k);
     for (int c = 0; c < 3; ++c) {
         if (fm & (1u << c)) {
             v[c] = (R)0;
@@ -805,11 +821,13 @@ __global__ void k_nodes_out(const SceneDev *Sd, double *m, double *p, double *f)
     for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < S.nn; I += (int64_t)gridDim.x * blockDim.x) {
         if (m)
             m[I] = S.nm[b][I];
+        const bool ext = S.bc_mask && (S.bc_mask[I] & 8u);
+        const double fs = ext ? external_force_scale(S) : 0.0;
         for (int a = 0; a < 3; ++a) {
             if (p)
                 p[3 * I + a] = (double)P[a * S.nn + I];
-            if (f)
-                f[3 * I + a] = (double)F[a * S.nn + I];
+            if (f)   // the particles' sum plus the node's external force, as the update uses it
+                f[3 * I + a] = (double)(ext ? F[a * S.nn + I] + (R)(fs * S.bc_force[3 * I + a]) : F[a * S.nn + I]);
         }
     }
 }
@@ -2126,7 +2144,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         __syncthreads();
         const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
-        uint32_t err = 0, drift = 0;
+        uint32_t err = 0, drift = 0, lost = 0;
         int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
         // gather cache (old support) and scatter cache (new support)
         int gb[3] = {-(1 << 30), 0, 0}, sb[3] = {-(1 << 30), 0, 0};
@@ -2261,6 +2279,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             const uint32_t e = locate<SH == 0>(S, xp, nc, fr);
             if (e) {
                 err |= e;   // keep the old cell; the scene stops after this step
+                lost += (e & ERR_OUT_OF_MESH) ? 1u : 0u;
                 continue;
             }
             stg(P.cell, p, pack_cell(nc));
@@ -2346,6 +2365,8 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 flush();
         if (err)
             atomicOr(&S.ctl[CTL_ERR], err);
+        if (lost)
+            atomicAdd(&S.ctl[CTL_LOST], lost);
         if (drift || (S.sort_always && threadIdx.x == 0)) {
             S.ctl[CTL_NEED_SORT] = 1u;
             B.flags[BF_ANY_SORT] = 1u;
@@ -2420,7 +2441,7 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
         __syncthreads();
         const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
-        uint32_t err = 0, drift = 0;
+        uint32_t err = 0, drift = 0, lost = 0;
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
             double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
@@ -2485,6 +2506,7 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
             const uint32_t e = locate(S, xp, nc);
             if (e) {
                 err |= e;
+                lost += (e & ERR_OUT_OF_MESH) ? 1u : 0u;
                 continue;
             }
             stg(P.cell, p, pack_cell(nc));
@@ -2492,6 +2514,8 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
         }
         if (err)
             atomicOr(&S.ctl[CTL_ERR], err);
+        if (lost)
+            atomicAdd(&S.ctl[CTL_LOST], lost);
         if (drift || (S.sort_always && threadIdx.x == 0)) {
             S.ctl[CTL_NEED_SORT] = 1u;
             B.flags[BF_ANY_SORT] = 1u;

@@ -31,6 +31,8 @@ struct Pending {
     std::vector<int64_t> bc_node;
     std::vector<int32_t> bc_axis;
     std::vector<double> bc_value;
+    std::vector<int64_t> force_node;
+    std::vector<double> force_value;
     std::vector<double> x, v, stress, vol, mass;
 };
 
@@ -52,12 +54,14 @@ int request_bytes(const mpmx_mesh *mesh, const mpmx_scheme *sch, const mpmx_bc *
     int rc = mpmx_scene_bytes(mesh, sch, n, out);
     if (rc)
         return rc;
-    if (bc->n_extra > 0) {
+    if (bc->n_extra > 0 || bc->n_force > 0) {
         const int g = sch->shape == MPMX_SHAPE_GIMP ? 1 : 0;
         uint64_t nn = 1;
         for (int a = 0; a < 3; ++a)
             nn *= (uint64_t)(mesh->n[a] + 1 + 2 * g);
         *out += ((nn + 255) & ~uint64_t(255)) + ((24 * nn + 255) & ~uint64_t(255));
+        if (bc->n_force > 0)
+            *out += (24 * nn + 255) & ~uint64_t(255);
     }
     return MPMX_OK;
 }
@@ -152,6 +156,8 @@ int admit(mpmx_server *srv)
         p.bc.node = p.bc_node.data();
         p.bc.axis = p.bc_axis.data();
         p.bc.value = p.bc_value.data();
+        p.bc.force_node = p.force_node.data();
+        p.bc.force_value = p.force_value.data();
         uint64_t scene = 0;
         const int rc = mpmx_scene_create(srv->ctx, &p.mesh, &p.mat, &p.bc, &p.sch, &parts, &scene);
         if (rc == MPMX_E_OOM || rc == MPMX_E_HIP)
@@ -224,6 +230,8 @@ int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id)
         return MPMX_E_INVALID_ARG;
     if (req->bc->n_extra < 0 || (req->bc->n_extra > 0 && (!req->bc->node || !req->bc->axis || !req->bc->value)))
         return MPMX_E_INVALID_ARG;
+    if (req->bc->n_force < 0 || (req->bc->n_force > 0 && (!req->bc->force_node || !req->bc->force_value)))
+        return MPMX_E_INVALID_ARG;
     uint64_t bytes = 0;
     int rc = request_bytes(req->mesh, req->scheme, req->bc, pp->n, &bytes);
     if (rc)
@@ -245,6 +253,9 @@ int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id)
     p.bc_node.assign(req->bc->node, req->bc->node + ne);
     p.bc_axis.assign(req->bc->axis, req->bc->axis + ne);
     p.bc_value.assign(req->bc->value, req->bc->value + ne);
+    const size_t nf = (size_t)req->bc->n_force;
+    p.force_node.assign(req->bc->force_node, req->bc->force_node + nf);
+    p.force_value.assign(req->bc->force_value, req->bc->force_value + 3 * nf);
     const size_t n = (size_t)pp->n;
     p.x.assign(pp->x, pp->x + 3 * n);
     p.v.assign(pp->v, pp->v + 3 * n);

@@ -44,10 +44,10 @@ FLIP, PIC = 0, 1
 FP32, FP64 = 0, 1
 SORT_ON_DEMAND, SORT_ALWAYS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-ERRBIT_OUT_OF_MESH, ERRBIT_NONFINITE = 1, 2
+ERRBIT_OUT_OF_MESH, ERRBIT_NONFINITE, ERRBIT_TILE, ERRBIT_SORT = 1, 2, 4, 8
 OPT_GRAPH_STEPS, OPT_AUTOTUNE, OPT_STRESS_THREADS, OPT_G2P_THREADS, OPT_BLOCKS_PER_CU, OPT_GRAPH_LAUNCHES, \
     OPT_TUNE_RUNS = 1, 2, 3, 4, 5, 6, 7
-TUNE_MIN_STEPS = 24
+TUNE_MIN_STEPS = 40
 
 _P = ctypes.POINTER
 _d, _i32, _i64, _u32, _u64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
@@ -70,7 +70,8 @@ class Material(ctypes.Structure):
 
 class Bc(ctypes.Structure):
     _fields_ = [("size", _u32), ("face", _i32 * 6), ("n_extra", _i64), ("node", _P(_i64)), ("axis", _P(_i32)),
-                ("value", _P(_d))]
+                ("value", _P(_d)), ("n_force", _i64), ("force_node", _P(_i64)), ("force_value", _P(_d)),
+                ("force_ramp_steps", _i64)]
 
 
 class Scheme(ctypes.Structure):
@@ -90,7 +91,8 @@ class ParticlesOut(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("size", _u32), ("n_particles", _i64), ("steps_done", _i64), ("n_sorts", _i64), ("n_items", _i64),
-                ("active_cells", _i64), ("error_bits", _u32), ("pad_", _u32), ("device_bytes", _u64)]
+                ("active_cells", _i64), ("error_bits", _u32), ("pad_", _u32), ("device_bytes", _u64),
+                ("pic_hash", _u64), ("lost_particles", _i64)]
 
 
 class Request(ctypes.Structure):
@@ -207,6 +209,15 @@ def _bc(bc: dict, keep: list) -> Bc:
         cbc.node = node.ctypes.data_as(_P(_i64))
         cbc.axis = axis.ctypes.data_as(_P(_i32))
         cbc.value = value.ctypes.data_as(_P(_d))
+    force = bc.get("force")
+    if force is not None and len(force[0]) > 0:
+        fnode = np.ascontiguousarray(force[0], dtype=np.int64)
+        fval = np.ascontiguousarray(np.asarray(force[1], dtype=np.float64).reshape(len(fnode), 3))
+        keep += [fnode, fval]
+        cbc.n_force = len(fnode)
+        cbc.force_node = fnode.ctypes.data_as(_P(_i64))
+        cbc.force_value = fval.ctypes.data_as(_P(_d))
+        cbc.force_ramp_steps = int(bc.get("force_ramp_steps", 0))
     return cbc
 
 

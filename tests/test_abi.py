@@ -23,7 +23,19 @@ def test_library_exports_every_declared_function(mpmx):
     lib = ctypes.CDLL(mpmx.LIBPATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert mpmx.version() == 1
+    assert mpmx.version() == 2
+
+
+def test_header_constants_match_the_binding(mpmx):
+    # the error bits a scene can report, and the tuning threshold, as the
+    # header declares them
+    text = open(mpmx.HEADER).read()
+    import re
+    bits = dict((k, int(v)) for k, v in re.findall(r"MPMX_ERRBIT_(\w+) = (\d+)u", text))
+    assert bits == {"OUT_OF_MESH": 1, "NONFINITE": 2, "TILE": 4, "SORT": 8}
+    assert (mpmx.ERRBIT_OUT_OF_MESH, mpmx.ERRBIT_NONFINITE, mpmx.ERRBIT_TILE, mpmx.ERRBIT_SORT) == (1, 2, 4, 8)
+    m = re.search(r"#define MPMX_TUNE_MIN_STEPS (\d+)", text)
+    assert int(m.group(1)) == mpmx.TUNE_MIN_STEPS
 
 
 def test_descriptor_layouts_match_the_c_header(mpmx, tmp_path):

@@ -37,12 +37,26 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
 
 
+def max_rel(a, b):
+    """Largest per-particle error of a field, relative to the field's RMS
+    particle magnitude (so near-zero particles do not blow it up)."""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    if len(b) == 0:
+        return 0.0
+    scale = np.sqrt(np.mean(np.sum(b * b, axis=1)))
+    return float(np.max(np.linalg.norm(a - b, axis=1)) / (scale if scale > 0 else 1.0))
+
+
 def check_state(name, got, ref, x0, u_tol, s_tol, v_tol=None):
     eu = rel(got["x"] - x0, ref["x"] - x0)
     es = rel(got["stress"], ref["stress"])
     ev = rel(got["v"], ref["v"])
     evol = rel(got["vol"], ref["vol"])
-    print(f"[{name}] err_u={eu:.3e} err_sigma={es:.3e} err_v={ev:.3e} err_vol={evol:.3e}", flush=True)
+    mu = max_rel(got["x"] - x0, ref["x"] - x0)
+    ms = max_rel(got["stress"], ref["stress"])
+    print(f"[{name}] err_u={eu:.3e} err_sigma={es:.3e} err_v={ev:.3e} err_vol={evol:.3e} "
+          f"max_particle_u={mu:.3e} max_particle_sigma={ms:.3e}", flush=True)
     assert eu <= u_tol, (name, "displacement", eu)
     assert es <= s_tol, (name, "stress", es)
     assert ev <= (v_tol if v_tol is not None else u_tol), (name, "velocity", ev)
@@ -73,7 +87,9 @@ def block(shape=0, material=None, algo=0, seed=21, n_cells=(9, 7, 6), **kw):
     return sc
 
 
-MATERIALS = {"le": scenes.elastic(), "dp": scenes.drucker_prager(), "dpc": scenes.drucker_prager(psi_deg=10, c=2e3)}
+MATERIALS = {"le": scenes.elastic(), "dp": scenes.drucker_prager(), "dpc": scenes.drucker_prager(psi_deg=10, c=2e3),
+             "dpi": scenes.drucker_prager(psi_deg=10, c=2e3, cone=scenes.DP_INNER),
+             "dpps": scenes.drucker_prager(psi_deg=5, c=1e3, cone=scenes.DP_PLANE_STRAIN)}
 
 
 # ------------------------------------------------------------- binning --
@@ -107,7 +123,7 @@ def test_binning_is_bit_exact_on_identical_positions(ctx, mp, which):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [0, 1])
 @pytest.mark.parametrize("algo", [0, 1])
-@pytest.mark.parametrize("mat", ["le", "dp", "dpc"])
+@pytest.mark.parametrize("mat", ["le", "dp", "dpc", "dpi", "dpps"])
 def test_one_step_nodes_and_particles_match_oracle(ctx, mp, prec, shape, algo, mat):
     sc = block(shape=shape, material=MATERIALS[mat], algo=algo)
     if mat != "le":
@@ -163,13 +179,15 @@ def test_full_bricks_nodes_and_particles_match_oracle(ctx, mp, prec, vel, jitter
 
 
 def test_plate_with_hole_against_oracle_and_table_1(ctx, mp):
-    """The paper's validation problem (benchmark section, Table 1), all 4,612
-    steps of the quarter strip pulled to 100 Pa: FP64 and FP32 particle
-    state against the oracle, and the stress concentration factors of the
-    GPU's own output within 5 % of the largest one Howland and the paper
-    give, and sigma_yy at the hole within 10 % of Howland's."""
+    """The paper's validation problem (benchmark section, Table 1): the
+    quarter strip under the 100 Pa end traction as ramped nodal forces, all
+    6,918 steps (ramp over 1 s, hold 0.5 s): FP64 and FP32 particle state
+    against the oracle, and the stress concentration factors of the GPU's
+    own output within the bars of the oracle's Table 1 test (largest
+    sigma_xx within 3 % of 3.14 and 3.13; sigma_yy at the load-axis edge
+    within 5 % of -1.11; sigma_xx there within 0.1 of 0.00)."""
     from plate_analysis import TABLE_1, stress_concentration
-    sc = scenes.plate_with_hole()
+    sc = scenes.plate_with_hole(hold_time=0.5)
     ref = oracle.run(sc, sc["nsteps"])
     for prec, p, tol in (("fp64", mp.FP64, (1e-9, 1e-9, 1e-9)), ("fp32", mp.FP32, (U_TOL, S_TOL, 1e-3))):
         s = ctx.create_scene(sc, precision=p)
@@ -179,9 +197,11 @@ def test_plate_with_hole_against_oracle_and_table_1(ctx, mp):
         check_state(f"plate/{prec}", got, ref, sc["x"], *tol)
         k = stress_concentration(got["x"], got["stress"])
         print(f"[plate/{prec}]", {key: round(v, 4) for key, v in k.items()}, flush=True)
+        assert abs(k["far_sxx"] - 1.0) <= 0.01, (prec, k)
         for r in ("howland", "paper"):
-            assert abs(k["max_sxx"] / TABLE_1[r]["max_sxx"] - 1) <= 0.05, (prec, r, k)
-        assert abs(k["min_syy"] / TABLE_1["howland"]["min_syy"] - 1) <= 0.10, (prec, k)
+            assert abs(k["max_sxx"] / TABLE_1[r]["max_sxx"] - 1) <= 0.03, (prec, r, k)
+        assert abs(k["max_syy"] / TABLE_1["howland"]["max_syy"] - 1) <= 0.05, (prec, k)
+        assert abs(k["min_sxx"] - TABLE_1["howland"]["min_sxx"]) <= 0.1, (prec, k)
         s.destroy()
 
 
@@ -575,30 +595,53 @@ def test_every_launch_shape_matches_oracle(mp, t_stress, t_g2p, blocks):
 
 def test_autotuner_runs_once_per_layout_on_real_steps(mp):
     """The tuner times the launch shapes on steps of the call itself: the
-    result after 40 steps equals the oracle's 40 steps, the chosen shapes
-    are valid, and a second call on the same layout reuses them."""
+    result after the tuning call equals the oracle's state after as many
+    steps, the chosen shapes are valid, and a second call on the same layout
+    reuses them."""
     sc = block(material=MATERIALS["dp"], seed=53, n_cells=(10, 8, 6))
     c = mp.Context(0)
+    T = mp.TUNE_MIN_STEPS
     try:
         assert c.get_option(mp.OPT_AUTOTUNE) == 1
         s = c.create_scene(sc, precision=mp.FP64)
         s.step(10)                       # below the tuning threshold
         assert c.get_option(mp.OPT_TUNE_RUNS) == 0
-        s.step(30)
+        s.step(T)
         assert c.get_option(mp.OPT_TUNE_RUNS) == 1
         assert c.get_option(mp.OPT_STRESS_THREADS) in (64, 128, 256)
         assert c.get_option(mp.OPT_G2P_THREADS) in (64, 128, 256)
         assert c.get_option(mp.OPT_BLOCKS_PER_CU) in (4, 8, 16, 32)
-        check_state("tuned/40", s.read(), oracle.run(sc, 40), sc["x"], 1e-9, 1e-9, 1e-9)
+        check_state(f"tuned/{10 + T}", s.read(), oracle.run(sc, 10 + T), sc["x"], 1e-9, 1e-9, 1e-9)
         s.step(30)
         assert c.get_option(mp.OPT_TUNE_RUNS) == 1
-        assert s.stats()["steps_done"] == 70
+        assert s.stats()["steps_done"] == 40 + T
         with pytest.raises(mp.MpmxError):
             c.set_option(mp.OPT_STRESS_THREADS, 96)
         with pytest.raises(mp.MpmxError):
             c.set_option(mp.OPT_GRAPH_LAUNCHES, 1)
     finally:
         c.close()
+
+
+def test_autotuner_choice_is_stable_between_runs(mp):
+    """Two fresh contexts tune the same layout (the 393k-particle column,
+    FP32) and keep the same launch shape: near-ties settle by the fixed
+    preference order, not by timing noise."""
+    sc = scenes.c5(subsample=True, shape=scenes.SHAPE_LINEAR)
+    picks = []
+    for rep in range(2):
+        c = mp.Context(0)
+        try:
+            s = c.create_scene(sc, precision=mp.FP32)
+            s.step(mp.TUNE_MIN_STEPS)
+            assert c.get_option(mp.OPT_TUNE_RUNS) == 1
+            picks.append(tuple(c.get_option(o) for o in (mp.OPT_STRESS_THREADS, mp.OPT_G2P_THREADS,
+                                                         mp.OPT_BLOCKS_PER_CU)))
+            s.destroy()
+        finally:
+            c.close()
+    print(f"[tuner] picks {picks}", flush=True)
+    assert picks[0] == picks[1], picks
 
 
 def test_out_of_mesh_stops_the_scene(ctx, mp):
@@ -751,3 +794,169 @@ def test_batch_of_more_scenes_than_a_workgroup_has_threads(ctx, mp):
         check_state(f"many/{i}", ss[i].read(), ref, scs[i]["x"], 1e-9, 1e-9, 1e-9)
     for s in ss:
         s.destroy()
+
+
+# ------------------------------------------------- cones, stats, forces --
+
+def admissible(sig, mat):
+    """Largest Drucker-Prager yield value over the particles, relative to the
+    stress scale (<= 0 up to rounding when every particle is admissible)."""
+    eta, xi, _ = oracle.dp_coefficients(mat)
+    p = sig[:, :3].mean(axis=1)
+    dev = sig.copy()
+    dev[:, :3] -= p[:, None]
+    q = np.sqrt(0.5 * (dev[:, :3] ** 2).sum(axis=1) + (dev[:, 3:] ** 2).sum(axis=1))
+    f = q + eta * p - xi * mat["c"]
+    return float(f.max() / max(np.abs(sig).max(), 1.0))
+
+
+@pytest.mark.parametrize("mat", ["dp", "dpi", "dpps"])
+@pytest.mark.parametrize("algo", [0, 1])
+def test_drucker_prager_cones_over_many_steps(ctx, mp, mat, algo):
+    """The outer, inner and plane-strain cones (the Material role of the code
+    overview: Drucker-Prager matched to Mohr-Coulomb three ways) over 25
+    steps of a pre-stressed block in motion, USF and USL: FP64 against the
+    oracle to rounding, FP32 within the bars, and every particle's stress
+    admissible after the run."""
+    m = MATERIALS[mat]
+    sc = block(material=m, algo=algo, seed=88, vel=1.0, stress_scale=4e3)
+    sc["stress"][:, :3] -= 3e3
+    sc["stress"] = sc["stress"].astype(np.float32).astype(np.float64)
+    sc["scheme"]["dt"] = 5e-5
+    ref = oracle.run(sc, 25)
+    assert admissible(ref["stress"], m) < 1e-12
+    for prec, p, tol in (("fp64", mp.FP64, (1e-9, 1e-9, 1e-9)), ("fp32", mp.FP32, (U_TOL, S_TOL, 1e-3))):
+        s = ctx.create_scene(sc, precision=p)
+        s.step(25)
+        got = s.read()
+        name = f"cone/{mat}/{'usl' if algo else 'usf'}/{prec}"
+        check_state(name, got, ref, sc["x"], *tol)
+        f = admissible(got["stress"], m)
+        print(f"[{name}] largest yield value / stress scale {f:.2e}", flush=True)
+        assert f < (1e-12 if p == mp.FP64 else 1e-5)
+        s.destroy()
+
+
+def fnv_histogram_hash(counts):
+    """The particles-per-cell hash that include/mpmx.h defines: 64-bit FNV-1a
+    steps over (cell id, count) of every occupied cell, ascending."""
+    h = 14695981039346656037
+    for c in np.flatnonzero(counts):
+        for v in (int(c), int(counts[c])):
+            h = ((h ^ v) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_stats_report_the_histogram_hash_and_lost_particles(ctx, mp):
+    sc = block(seed=45)
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    st = s.stats()
+    assert st["pic_hash"] == fnv_histogram_hash(oracle.cell_counts(sc["mesh"], sc["x"]))
+    assert st["lost_particles"] == 0
+    s.step(3)
+    got = s.read()
+    ref = oracle.run(sc, 3)
+    if np.array_equal(oracle.cell_counts(sc["mesh"], got["x"]), oracle.cell_counts(sc["mesh"], ref["x"])):
+        assert s.stats()["pic_hash"] == fnv_histogram_hash(oracle.cell_counts(sc["mesh"], ref["x"]))
+    s.destroy()
+    # a column of particles rising out of the open top: every particle that
+    # left the mesh in the stopping step is counted
+    up = block(seed=46)
+    up["v"][:, 2] = 0.0
+    rising = up["x"][:, 2] > 0.15
+    up["v"][rising, 2] = 400.0
+    s = ctx.create_scene(up, precision=mp.FP64)
+    s.step(40)
+    st = s.stats()
+    assert st["error_bits"] & mp.ERRBIT_OUT_OF_MESH
+    got = s.read(raise_on_error=False)
+    top = up["mesh"]["origin"][2] + up["mesh"]["n"][2] * up["mesh"]["h"]
+    outside = int((got["x"][:, 2] >= top).sum())
+    print(f"[lost] steps {st['steps_done']}, lost {st['lost_particles']}, outside {outside}", flush=True)
+    assert st["lost_particles"] == outside > 0
+    s.destroy()
+
+
+@pytest.mark.parametrize("ramp", [0, 7])
+def test_nodal_forces_match_oracle(ctx, mp, ramp):
+    """External nodal forces (the benchmark section's end traction in nodal
+    form), with and without the load ramp, on a block with walls and
+    gravity: nodal force after 1 step and particles after 12 steps (graph
+    replays, the ramp crossing into the hold), FP64 to rounding and FP32
+    within the bars."""
+    sc = block(seed=47, stress_scale=2e3)
+    mesh = sc["mesh"]
+    ids = [oracle.node_id(mesh, 0, i, j, k) for i, j, k in ((4, 3, 1), (5, 3, 1), (7, 6, 3), (4, 3, 1))]
+    F = np.array([[5.0, -1.0, 2.0], [0.0, 3.0, -4.0], [-2.0, 2.0, 6.0], [1.0, 0.0, 0.0]])
+    sc["bc"] = dict(sc["bc"], force=(ids, F), force_ramp_steps=ramp)
+    for n in (1, 12):
+        ref = oracle.run(sc, n)
+        for prec, p, tol in (("fp64", mp.FP64, 1e-9), ("fp32", mp.FP32, 2e-5 if n == 1 else U_TOL)):
+            s = ctx.create_scene(sc, precision=p)
+            s.step(n)
+            got = s.read()
+            name = f"forces/ramp{ramp}/{prec}/{n}"
+            if n == 1:
+                e = rel(s.nodes()["f"], ref["grid"].f)
+                print(f"[{name}] nodal f: {e:.3e}", flush=True)
+                assert e <= tol, (name, e)
+            check_state(name, got, ref, sc["x"], tol, tol if p == mp.FP64 or n == 1 else S_TOL,
+                        tol if p == mp.FP64 or n == 1 else 1e-3)
+            s.destroy()
+
+
+def test_batched_set_largest_scenes_against_stored_oracle_sample(ctx, mp):
+    """The full 256-scene set in one FP32 batch for its 500 steps, with the
+    four largest scenes (200k-250k particles, several work items per brick,
+    the batch's largest particle and brick offsets) compared against the
+    oracle's final state of those scenes, stored for every 97th particle by
+    tests/golden/make_batch_golden.py (which calls only the oracle):
+    displacement and stress bars on the sample, and the histogram of all
+    their particles within the near-face allowance."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "batch_large_500.npz"))
+    scs = scenes.c3()
+    batch = [ctx.create_scene(sc, precision=mp.FP32) for sc in scs]
+    ctx.batch_step(batch, [sc["nsteps"] for sc in scs])
+    for i in gold["scenes"]:
+        sc, b = scs[i], batch[i]
+        idx = gold[f"s{i}_index"]
+        np.testing.assert_array_equal(sc["x"][idx], gold[f"s{i}_x0"])
+        got = b.read()
+        sub = {k: got[k][idx] for k in ("x", "v", "stress", "vol")}
+        ref = {k: gold[f"s{i}_{k}"] for k in ("x", "v", "stress", "vol")}
+        check_state(f"batched_large/{sc['name']}/{len(sc['x'])}", sub, ref, gold[f"s{i}_x0"], U_TOL, S_TOL, 1e-3)
+        hc = b.cell_counts().astype(np.int64)
+        hr = gold[f"s{i}_hist"].astype(np.int64)
+        moved = int(np.abs(hc - hr).sum())
+        print(f"[batched_large/{sc['name']}] histogram L1 difference {moved} of {len(sc['x'])}", flush=True)
+        assert hc.sum() == hr.sum() == len(sc["x"])
+        assert moved <= 1e-4 * len(sc["x"])
+    for sc, b in zip(scs, batch):
+        st = b.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == sc["nsteps"], (sc["name"], st)
+        b.destroy()
+
+
+def test_column_usl_against_stored_oracle_sample(ctx, mp):
+    """200 update-stress-last steps of the 2.1M-particle column in FP32
+    against the oracle's state, stored for every 1024th particle by
+    tests/golden/make_column_usl_golden.py (which calls only the oracle)."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "column_2m_usl_200.npz"))
+    sc = scenes.c2()
+    sc["scheme"]["algo"] = scenes.USL
+    idx = gold["index"]
+    np.testing.assert_array_equal(sc["x"][idx], gold["x0"])
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(int(gold["nsteps"]))
+    got = s.read()
+    sub = {k: got[k][idx] for k in ("x", "v", "stress", "vol")}
+    ref = {k: gold[k] for k in ("x", "v", "stress", "vol")}
+    check_state("column_usl/fp32/200", sub, ref, gold["x0"], U_TOL, S_TOL, 1e-3)
+    hc = s.cell_counts().astype(np.int64)
+    hr = gold["hist"].astype(np.int64)
+    moved = int(np.abs(hc - hr).sum())
+    print(f"[column_usl/fp32/200] histogram L1 difference {moved} of {len(sc['x'])}", flush=True)
+    assert moved <= 1e-4 * len(sc["x"])
+    s.destroy()
