@@ -425,6 +425,18 @@ def run_batch(args):
         n_nodes += active_nodes(sc["mesh"], b.cell_counts())
     for b in batch:
         b.destroy()
+    if args.no_plain:
+        ctx.close()
+        out = {"metric": METRIC, "value": total * K / tb, "unit": "particle-updates/s", "n_gpus": 1, "steps": K,
+               "warmup": args.warmup, "ms_per_step": 1e3 * tb / K, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+               "config": {"workload": f"batched: {n_sc} independent scenes (batched leg only)", "scenes": n_sc,
+                          "particles": total, "touched_nodes": n_nodes, "launch": launch_b}}
+        if prof:
+            out["kernels"] = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1), "total_ms": v[1]}
+                              for k, v in prof.items()}
+        print(json.dumps(out), flush=True)
+        return
     # --- plain FIFO: same warm-up per scene, then K timed steps each
     plain = [ctx.create_scene(sc, precision=mpmx.FP32) for sc in scs]
     for s in plain:
@@ -589,6 +601,8 @@ def main():
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--no-column", action="store_true",
                     help="--workload batch: skip the full 1000-step run of the granular column")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="--workload batch: the batched leg only (no plain leg, latency runs or column), for profiling")
     ap.add_argument("--sort", default="on_demand", choices=["on_demand", "always"])
     ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps of the CPU baseline (batch: 40x this)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
