@@ -52,7 +52,8 @@ def build() -> str:
 
 class _Mesh(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("pad_", ctypes.c_int32),
-                ("origin", ctypes.c_double * 3), ("h", ctypes.c_double)]
+                ("origin", ctypes.c_double * 3), ("h", ctypes.c_double),
+                ("node_x", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Material(ctypes.Structure):
@@ -109,6 +110,8 @@ def _load():
     lib.om_locate.restype = ctypes.c_int
     lib.om_shape.argtypes = [P(_Mesh), i32, P(d), P(i64), P(d), P(d)]
     lib.om_shape.restype = ctypes.c_int
+    lib.om_iso_natural.argtypes = [P(_Mesh), P(i64), P(d), P(d)]
+    lib.om_iso_natural.restype = ctypes.c_int
     lib.om_gimp_1d.argtypes = [d, d, d, P(d)]
     lib.om_gimp_1d.restype = None
     lib.om_dp_coefficients.argtypes = [P(_Material), P(d)]
@@ -129,11 +132,20 @@ def _ptr(a, ctype=ctypes.c_double):
 
 
 def _mesh(mesh: dict) -> _Mesh:
+    """The C mesh descriptor; an isoparametric mesh (``node_x``, (nodes, 3)
+    float64) is referenced, and kept alive by the descriptor."""
     m = _Mesh()
     for a in range(3):
         m.n[a] = int(mesh["n"][a])
         m.origin[a] = float(mesh["origin"][a])
     m.h = float(mesh["h"])
+    if mesh.get("node_x") is not None:
+        nx = np.ascontiguousarray(mesh["node_x"], dtype=np.float64).reshape(-1, 3)
+        want = (m.n[0] + 1) * (m.n[1] + 1) * (m.n[2] + 1)
+        if len(nx) != want:
+            raise ValueError(f"node_x holds {len(nx)} nodes, the mesh has {want}")
+        m._keep = nx
+        m.node_x = _ptr(nx)
     return m
 
 
@@ -224,6 +236,18 @@ def shape(mesh: dict, shape_kind: int, xp) -> tuple[np.ndarray, np.ndarray, np.n
     if q < 0:
         raise OracleError(q, "shape")
     return node[:q].copy(), N[:q].copy(), dN[:3 * q].reshape(q, 3).copy()
+
+
+def iso_natural(mesh: dict, cell, x) -> tuple[np.ndarray, int]:
+    """Natural coordinates of x in cell (cx, cy, cz) of an isoparametric
+    mesh and the Newton iterations taken (raises OracleError on breakdown)."""
+    c = np.ascontiguousarray(cell, dtype=np.int64)
+    xp = np.ascontiguousarray(x, dtype=np.float64)
+    xi = np.empty(3)
+    it = _load().om_iso_natural(ctypes.byref(_mesh(mesh)), _ptr(c, ctypes.c_int64), _ptr(xp), _ptr(xi))
+    if it < 0:
+        raise OracleError(it, "iso_natural")
+    return xi, int(it)
 
 
 def gimp_1d(r: float, h: float, l: float) -> tuple[float, float]:

@@ -39,9 +39,194 @@ int64_t om_node_id(const om_mesh *mesh, int32_t shape, int64_t i, int64_t j, int
 /* Cell index along one axis: half-open cells [o + h c, o + h (c+1)). */
 static int64_t cell_coord(double x, double o, double h) { return (int64_t)floor((x - o) / h); }
 
+/* ------------------------------------------------- isoparametric cells -- */
+
+/* The eight node positions of cell c, node q = i + 2j + 4k at (c + (i,j,k)). */
+static void iso_corners(const om_mesh *mesh, const int64_t c[3], double X[8][3])
+{
+    for (int q = 0; q < 8; ++q) {
+        int64_t I = om_node_id(mesh, OM_SHAPE_LINEAR, c[0] + (q & 1), c[1] + ((q >> 1) & 1), c[2] + (q >> 2));
+        for (int a = 0; a < 3; ++a)
+            X[q][a] = mesh->node_x[3 * I + a];
+    }
+}
+
+/* Trilinear N_q(xi) = 1/8 prod_a (1 + s_qa xi_a), s_qa = -1 or +1, and
+ * dN_q/dxi_a. */
+static void trilinear(const double xi[3], double N[8], double dN[8][3])
+{
+    for (int q = 0; q < 8; ++q) {
+        double s[3] = {(q & 1) ? 1.0 : -1.0, ((q >> 1) & 1) ? 1.0 : -1.0, (q >> 2) ? 1.0 : -1.0};
+        double f[3];
+        for (int a = 0; a < 3; ++a)
+            f[a] = 1.0 + s[a] * xi[a];
+        N[q] = 0.125 * f[0] * f[1] * f[2];
+        dN[q][0] = 0.125 * s[0] * f[1] * f[2];
+        dN[q][1] = 0.125 * f[0] * s[1] * f[2];
+        dN[q][2] = 0.125 * f[0] * f[1] * s[2];
+    }
+}
+
+/* x(xi) = sum_q N_q X_q and J_ab = dx_a/dxi_b = sum_q X_qa dN_q/dxi_b. */
+static void iso_map(const double X[8][3], const double xi[3], double x[3], double J[3][3])
+{
+    double N[8], dN[8][3];
+    trilinear(xi, N, dN);
+    for (int a = 0; a < 3; ++a) {
+        x[a] = 0.0;
+        for (int b = 0; b < 3; ++b)
+            J[a][b] = 0.0;
+        for (int q = 0; q < 8; ++q) {
+            x[a] += N[q] * X[q][a];
+            for (int b = 0; b < 3; ++b)
+                J[a][b] += X[q][a] * dN[q][b];
+        }
+    }
+}
+
+/* Inverse of a 3x3 matrix by cofactors; returns the determinant. */
+static double inverse3(const double M[3][3], double Mi[3][3])
+{
+    double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                 M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                 M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    Mi[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) / det;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / det;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
+    Mi[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / det;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+    Mi[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / det;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+    return det;
+}
+
+int om_iso_natural(const om_mesh *mesh, const int64_t c[3], const double x[3], double xi[3])
+{
+    double X[8][3], xc[3], A[3][3], Ai[3][3];
+    iso_corners(mesh, c, X);
+    /* affine initial guess: the map's value and Jacobian at the centre */
+    const double zero[3] = {0.0, 0.0, 0.0};
+    iso_map(X, zero, xc, A);
+    inverse3(A, Ai);
+    for (int a = 0; a < 3; ++a) {
+        xi[a] = 0.0;
+        for (int b = 0; b < 3; ++b)
+            xi[a] += Ai[a][b] * (x[b] - xc[b]);
+    }
+    for (int it = 1; it <= 50; ++it) {
+        double xm[3], J[3][3], Ji[3][3], r[3], d[3];
+        iso_map(X, xi, xm, J);
+        inverse3(J, Ji);
+        for (int a = 0; a < 3; ++a)
+            r[a] = xm[a] - x[a];
+        double dmax = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = 0.0;
+            for (int b = 0; b < 3; ++b)
+                d[a] += Ji[a][b] * r[b];
+            xi[a] -= d[a];
+            if (!isfinite(xi[a]))
+                return OM_E_NONFINITE;
+            dmax = fmax(dmax, fabs(d[a]));
+        }
+        /* quadratic convergence: what is left after a correction of 1e-12
+         * is of order 1e-24, below the rounding of xi itself */
+        if (dmax <= 1e-12)
+            return it;
+    }
+    return 50;
+}
+
+/* How far xi lies outside the half-open cube [-1, 1)^3 along the worst axis
+ * (<= 0: inside or on a face). */
+static double overshoot(const double xi[3])
+{
+    double o = -1e300;
+    for (int a = 0; a < 3; ++a)
+        o = fmax(o, fmax(-1.0 - xi[a], xi[a] - 1.0));
+    return o;
+}
+
+static int inside(const double xi[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (!(xi[a] >= -1.0 && xi[a] < 1.0))
+            return 0;
+    return 1;
+}
+
+/* Brute-force location in an isoparametric mesh (see om_locate). */
+static int iso_locate_one(const om_mesh *mesh, const double x[3], int64_t c_out[3], double xi_out[3])
+{
+    double best = 1e300;
+    int found = 0;
+    for (int64_t cz = 0; cz < mesh->n[2]; ++cz)
+        for (int64_t cy = 0; cy < mesh->n[1]; ++cy)
+            for (int64_t cx = 0; cx < mesh->n[0]; ++cx) {
+                const int64_t c[3] = {cx, cy, cz};
+                double X[8][3], lo[3], hi[3];
+                iso_corners(mesh, c, X);
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = hi[a] = X[0][a];
+                    for (int q = 1; q < 8; ++q) {
+                        lo[a] = fmin(lo[a], X[q][a]);
+                        hi[a] = fmax(hi[a], X[q][a]);
+                    }
+                    double pad = 1e-9 * (hi[a] - lo[a]);
+                    if (x[a] < lo[a] - pad || x[a] > hi[a] + pad)
+                        goto next;
+                }
+                {
+                    double xi[3];
+                    if (om_iso_natural(mesh, c, x, xi) < 0)
+                        goto next;
+                    if (inside(xi)) {
+                        for (int a = 0; a < 3; ++a) {
+                            c_out[a] = c[a];
+                            xi_out[a] = xi[a];
+                        }
+                        return OM_OK;
+                    }
+                    /* a near miss counts only across a face another cell shares */
+                    double o = overshoot(xi);
+                    int interior = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (xi[a] < -1.0 && c[a] == 0)
+                            interior = 0;
+                        if (xi[a] >= 1.0 && c[a] == mesh->n[a] - 1)
+                            interior = 0;
+                    }
+                    if (interior && o <= 1e-12 && o < best) {
+                        best = o;
+                        found = 1;
+                        for (int a = 0; a < 3; ++a) {
+                            c_out[a] = c[a];
+                            xi_out[a] = xi[a];
+                        }
+                    }
+                }
+            next:;
+            }
+    return found ? OM_OK : OM_E_OUT_OF_MESH;
+}
+
 int om_locate(const om_mesh *mesh, int64_t n, const double *x, int64_t *cell)
 {
     for (int64_t p = 0; p < n; ++p) {
+        if (mesh->node_x) {
+            int64_t c[3];
+            double xi[3];
+            for (int a = 0; a < 3; ++a)
+                if (!isfinite(x[3 * p + a]))
+                    return OM_E_NONFINITE;
+            int rc = iso_locate_one(mesh, &x[3 * p], c, xi);
+            if (rc != OM_OK)
+                return rc;
+            cell[p] = c[0] + (int64_t)mesh->n[0] * (c[1] + (int64_t)mesh->n[1] * c[2]);
+            continue;
+        }
         int64_t c[3];
         for (int a = 0; a < 3; ++a) {
             double xa = x[3 * p + a];
@@ -83,6 +268,35 @@ void om_gimp_1d(double r, double h, double l, double out[2])
 int om_shape(const om_mesh *mesh, int32_t shape, const double x[3],
              int64_t *node, double *N, double *dN)
 {
+    if (mesh->node_x) {
+        /* Isoparametric 8-node hexahedron: N_q(xi) at the particle's natural
+         * coordinates, grad N_q = J^-T dN_q/dxi with J = dx/dxi there. */
+        if (shape != OM_SHAPE_LINEAR)
+            return OM_E_ARG;
+        int64_t c[3];
+        double xi[3], X[8][3], xm[3], J[3][3], Ji[3][3], Nq[8], dNq[8][3];
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(x[a]))
+                return OM_E_NONFINITE;
+        int rc = iso_locate_one(mesh, x, c, xi);
+        if (rc != OM_OK)
+            return rc;
+        iso_corners(mesh, c, X);
+        iso_map(X, xi, xm, J);
+        inverse3(J, Ji);
+        trilinear(xi, Nq, dNq);
+        for (int q = 0; q < 8; ++q) {
+            node[q] = om_node_id(mesh, shape, c[0] + (q & 1), c[1] + ((q >> 1) & 1), c[2] + (q >> 2));
+            N[q] = Nq[q];
+            /* dN/dx_a = sum_b (dxi_b/dx_a) dN/dxi_b = sum_b Ji[b][a] dN/dxi_b */
+            for (int a = 0; a < 3; ++a) {
+                dN[3 * q + a] = 0.0;
+                for (int b = 0; b < 3; ++b)
+                    dN[3 * q + a] += Ji[b][a] * dNq[q][b];
+            }
+        }
+        return 8;
+    }
     const double h = mesh->h;
     int64_t c[3];
     for (int a = 0; a < 3; ++a) {
@@ -347,7 +561,9 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
             double *sig, double *vol, const double *mass, om_grid *grid,
             int64_t step)
 {
-    if (!mesh || !mat || !bc || !scheme || !grid || n < 0 || mesh->h <= 0.0)
+    if (!mesh || !mat || !bc || !scheme || !grid || n < 0 || (!mesh->node_x && mesh->h <= 0.0))
+        return OM_E_ARG;
+    if (mesh->node_x && scheme->shape != OM_SHAPE_LINEAR)
         return OM_E_ARG;
     const int32_t shape = scheme->shape;
     const int64_t nn = om_num_nodes(mesh, shape);

@@ -53,12 +53,18 @@ enum { OM_USF = 0, OM_USL = 1 };
 enum { OM_SHAPE_LINEAR = 0, OM_SHAPE_GIMP = 1 };
 enum { OM_FLIP = 0, OM_PIC = 1 };
 
-/* Uniform mesh: n[a] cells per axis, node (i,j,k) at origin + h*(i,j,k). */
+/* Mesh of n[0] x n[1] x n[2] 8-node hexahedra.  Uniform when node_x is
+ * NULL: node (i,j,k) at origin + h*(i,j,k).  Isoparametric otherwise
+ * (isoparametric-mesh section): the same logically structured cells and
+ * node numbering, node I at node_x[3*I+a], each cell the trilinear image of
+ * the natural cube [-1,1]^3 of its eight nodes; origin and h are then unused
+ * here.  Isoparametric meshes take linear shape functions only. */
 typedef struct {
     int32_t n[3];
     int32_t pad_;
     double origin[3];
     double h;
+    const double *node_x;
 } om_mesh;
 
 typedef struct {
@@ -115,9 +121,24 @@ int64_t om_num_nodes(const om_mesh *mesh, int32_t shape);
 int64_t om_num_cells(const om_mesh *mesh);
 int64_t om_node_id(const om_mesh *mesh, int32_t shape, int64_t i, int64_t j, int64_t k);
 
-/* Cell of each particle: c_a = floor((x_a - o_a)/h), id = cx + nx*(cy + ny*cz).
- * Returns OM_E_OUT_OF_MESH if any particle lies outside [o, o + n h). */
+/* Cell of each particle, id = cx + nx*(cy + ny*cz).  Uniform mesh:
+ * c_a = floor((x_a - o_a)/h); OM_E_OUT_OF_MESH if any particle lies outside
+ * [o, o + n h).  Isoparametric mesh: the cell whose inverse map puts the
+ * particle at natural coordinates -1 <= xi_a < 1 on every axis (the
+ * half-open rule of the uniform mesh), searched over every cell in id
+ * order; a particle that rounding leaves just outside two cells sharing a
+ * face (no more than 1e-12 past it) goes to the one it overshoots least;
+ * OM_E_OUT_OF_MESH if no cell holds it. */
 int om_locate(const om_mesh *mesh, int64_t n, const double *x, int64_t *cell);
+
+/* Natural coordinates of point x in cell (cx, cy, cz) of an isoparametric
+ * mesh by Newton-Raphson on x(xi) = sum_I N_I(xi) X_I, starting from the
+ * affine guess xi0 = A^-1 (x - x_c) (x_c the mean of the eight nodes, A the
+ * Jacobian at the cell's centre) and stopping after a correction of at most
+ * 1e-12 (the error left is then of order its square; at most 50
+ * iterations).  Returns the number of iterations, or
+ * OM_E_NONFINITE if the iteration broke down. */
+int om_iso_natural(const om_mesh *mesh, const int64_t c[3], const double x[3], double xi[3]);
 
 /* Shape functions of one particle.  Writes node ids, weights and
  * x-gradients of every node in the particle's support (8 or 27) and returns

@@ -312,3 +312,116 @@ def random_block(n_cells=(6, 5, 4), mesh_cells=(12, 10, 8), h=0.05, seed=11, mat
     stress = rng.uniform(-stress_scale, stress_scale, size=(len(x), 6)) if stress_scale else None
     return make_scene("random_block", mesh, material or elastic(), bc or walls(floor=FIXED),
                       scheme(dt, shape=shape, gravity=gravity), x, v, nsteps=nsteps, stress=stress)
+
+
+# ------------------------------------------------ isoparametric meshes --
+
+def _smooth_field(mesh: dict, amp: float, seed: int):
+    """A smooth displacement field d(X) of amplitude amp * h over the mesh's
+    box: component a is amp h sin(pi m_a (X_a - o_a) / L_a) times cosines
+    of the other two coordinates with random phases, so it vanishes on the
+    two faces normal to axis a (those faces stay planar).  Returns d and its
+    gradient as functions of positions (k, 3)."""
+    rng = np.random.default_rng(seed)
+    h = mesh["h"]
+    o = np.asarray(mesh["origin"], dtype=np.float64)
+    L = np.asarray(mesh["n"], dtype=np.float64) * h
+    m = rng.integers(1, 3, size=3)
+    ph = rng.uniform(0, 2 * np.pi, size=(3, 3))
+    A = amp * h * rng.uniform(0.5, 1.0, size=3)
+
+    def parts(X):
+        u = (np.asarray(X, dtype=np.float64) - o) / L          # in [0, 1] over the box
+        out = np.zeros_like(u)
+        grad = np.zeros(u.shape + (3,))
+        for a in range(3):
+            b, c = (a + 1) % 3, (a + 2) % 3
+            s = np.sin(np.pi * m[a] * u[:, a])
+            cb = np.cos(2 * np.pi * u[:, b] + ph[a, b])
+            cc = np.cos(2 * np.pi * u[:, c] + ph[a, c])
+            out[:, a] = A[a] * s * cb * cc
+            grad[:, a, a] = A[a] * np.pi * m[a] / L[a] * np.cos(np.pi * m[a] * u[:, a]) * cb * cc
+            grad[:, a, b] = -A[a] * 2 * np.pi / L[b] * s * np.sin(2 * np.pi * u[:, b] + ph[a, b]) * cc
+            grad[:, a, c] = -A[a] * 2 * np.pi / L[c] * s * cb * np.sin(2 * np.pi * u[:, c] + ph[a, c])
+        return out, grad
+    return parts
+
+
+def uniform_nodes(mesh: dict) -> np.ndarray:
+    """Node positions o + h (i, j, k) of a mesh in node-id order (n+1 per axis)."""
+    n = mesh["n"]
+    k, j, i = np.meshgrid(np.arange(n[2] + 1), np.arange(n[1] + 1), np.arange(n[0] + 1), indexing="ij")
+    ijk = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64)
+    return np.asarray(mesh["origin"], dtype=np.float64) + mesh["h"] * ijk
+
+
+def distort(scene: dict, amp: float = 0.25, seed: int = 0) -> dict:
+    """The same scene on an isoparametric mesh: the mesh's nodes and the
+    particles are moved by one smooth displacement field of amplitude amp * h
+    (_smooth_field), each particle's volume and mass scaled by the field's
+    volume change det(I + grad d) at its reference position.  The mesh keeps
+    origin and h (the undistorted grid it came from) beside node_x."""
+    sc = dict(scene)
+    mesh = dict(scene["mesh"])
+    field = _smooth_field(mesh, amp, seed)
+    X = uniform_nodes(mesh)
+    dX, _ = field(X)
+    mesh["node_x"] = X + dX
+    sc["mesh"] = mesh
+    dx, grad = field(scene["x"])
+    sc["x"] = scene["x"] + dx
+    J = np.linalg.det(np.eye(3)[None] + grad)
+    sc["vol"] = _f32(scene["vol"] * J)
+    sc["mass"] = _f32(scene["mass"] * J)
+    return sc
+
+
+def rotate(scene: dict, R, b=(0.0, 0.0, 0.0)) -> dict:
+    """The scene moved rigidly by x -> R x + b: an isoparametric mesh whose
+    nodes are the moved nodes, and moved particles, velocities, stresses and
+    gravity (walls keep their rules on the moved faces, so use it with free
+    faces)."""
+    R = np.asarray(R, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    sc = dict(scene)
+    mesh = dict(scene["mesh"])
+    X = scene["mesh"].get("node_x")
+    X = uniform_nodes(mesh) if X is None else np.asarray(X)
+    mesh["node_x"] = X @ R.T + b
+    sc["mesh"] = mesh
+    sc["x"] = scene["x"] @ R.T + b
+    sc["v"] = scene["v"] @ R.T
+    S = scene["stress"]
+    T = np.zeros((len(S), 3, 3))
+    for (a, c), k in {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (1, 2): 4, (0, 2): 5}.items():
+        T[:, a, c] = T[:, c, a] = S[:, k]
+    T = R[None] @ T @ R.T[None]
+    sc["stress"] = np.stack([T[:, 0, 0], T[:, 1, 1], T[:, 2, 2], T[:, 0, 1], T[:, 1, 2], T[:, 0, 2]], axis=1)
+    sch = dict(scene["scheme"])
+    sch["gravity"] = tuple(R @ np.asarray(scene["scheme"]["gravity"], dtype=np.float64))
+    sc["scheme"] = sch
+    return sc
+
+
+def slope(cells=(24, 8, 10), block=(10, 8, 6), h=0.02, angle_deg=20.0, dt=None, seed=9, material=None,
+          nsteps=200) -> dict:
+    """A granular block on an inclined bed (the non-prismatic boundary an
+    isoparametric mesh follows): a terrain-following mesh whose node (i,j,k)
+    sits at (i h, j h, z_b(i h) + k h) with the bed z_b(x) = x tan(angle),
+    a fixed (no-slip) bed, slip side walls in y, free ends in x and top.  The
+    Drucker-Prager block fills `block` cells at the upslope end (largest x),
+    2x2x2 particles per cell at the sub-cell centres, jittered."""
+    mesh = {"n": tuple(int(c) for c in cells), "origin": (0.0, 0.0, 0.0), "h": h}
+    t = np.tan(np.radians(angle_deg))
+    X = uniform_nodes(mesh)
+    X[:, 2] += X[:, 0] * t
+    mesh["node_x"] = X
+    rng = np.random.default_rng(seed)
+    ref = block_positions((cells[0] - block[0], 0, 0), (cells[0], block[1], block[2]), h, layout="centre",
+                          jitter=0.1, rng=rng)
+    x = ref.copy()
+    x[:, 2] += x[:, 0] * t            # sheared with the mesh (volume-preserving)
+    mat = material or drucker_prager()
+    dt = dt or 0.3 * h / p_wave_speed(mat)
+    bc = {"face": [FREE, FREE, SLIP, SLIP, FIXED, FREE], "extra": None}
+    return make_scene("slope", mesh, mat, bc, scheme(dt), x, None, nsteps=nsteps)
