@@ -95,11 +95,26 @@ enum {
 /* Each descriptor starts with its own size in bytes (sizeof), so that later
  * versions can grow it; a size smaller than this version's is rejected. */
 
+/* Background mesh of n[0] x n[1] x n[2] 8-node hexahedra (code overview:
+ * Mesh, Node, Cell).  Uniform grid when node_x is NULL: node (i, j, k) at
+ * origin + h (i, j, k).  Isoparametric mesh otherwise (isoparametric-mesh
+ * section): the same logically structured cells, node numbering and face
+ * rules, node I at node_x[3 I + a] (host memory, (n0+1)(n1+1)(n2+1) x 3,
+ * copied at scene creation), each cell the trilinear image of the natural
+ * cube [-1,1]^3 of its eight nodes.  A particle belongs to the cell whose
+ * inverse map puts it at natural coordinates -1 <= xi_a < 1 (found by
+ * Newton-Raphson from the cell's affine guess, by a walk across cell faces
+ * from the particle's previous cell); origin and h then name the uniform
+ * grid the mesh was made from, whose cells start the walk at scene
+ * creation.  Isoparametric meshes take MPMX_SHAPE_LINEAR only, and every
+ * cell must have a positive Jacobian at its eight corners
+ * (MPMX_E_INVALID_ARG otherwise). */
 typedef struct {
     uint32_t size;
     int32_t n[3];       /* cells per axis, each >= 1 */
     double origin[3];   /* position of node (0,0,0) */
     double h;           /* cell edge length, > 0 */
+    const double *node_x;   /* NULL, or the isoparametric mesh's node positions */
 } mpmx_mesh;
 
 typedef struct {

@@ -265,37 +265,48 @@ void om_gimp_1d(double r, double h, double l, double out[2])
     }
 }
 
+/* Isoparametric 8-node hexahedron in cell c: N_q(xi) at the point's natural
+ * coordinates xi (Newton-Raphson), grad N_q = J^-T dN_q/dxi with J = dx/dxi
+ * there. */
+static int iso_shape_in_cell(const om_mesh *mesh, const int64_t c[3], const double x[3],
+                             int64_t *node, double *N, double *dN)
+{
+    double xi[3], X[8][3], xm[3], J[3][3], Ji[3][3], Nq[8], dNq[8][3];
+    int rc = om_iso_natural(mesh, c, x, xi);
+    if (rc < 0)
+        return rc;
+    iso_corners(mesh, c, X);
+    iso_map(X, xi, xm, J);
+    inverse3(J, Ji);
+    trilinear(xi, Nq, dNq);
+    for (int q = 0; q < 8; ++q) {
+        node[q] = om_node_id(mesh, OM_SHAPE_LINEAR, c[0] + (q & 1), c[1] + ((q >> 1) & 1), c[2] + (q >> 2));
+        N[q] = Nq[q];
+        /* dN/dx_a = sum_b (dxi_b/dx_a) dN/dxi_b = sum_b Ji[b][a] dN/dxi_b */
+        for (int a = 0; a < 3; ++a) {
+            dN[3 * q + a] = 0.0;
+            for (int b = 0; b < 3; ++b)
+                dN[3 * q + a] += Ji[b][a] * dNq[q][b];
+        }
+    }
+    return 8;
+}
+
 int om_shape(const om_mesh *mesh, int32_t shape, const double x[3],
              int64_t *node, double *N, double *dN)
 {
     if (mesh->node_x) {
-        /* Isoparametric 8-node hexahedron: N_q(xi) at the particle's natural
-         * coordinates, grad N_q = J^-T dN_q/dxi with J = dx/dxi there. */
         if (shape != OM_SHAPE_LINEAR)
             return OM_E_ARG;
         int64_t c[3];
-        double xi[3], X[8][3], xm[3], J[3][3], Ji[3][3], Nq[8], dNq[8][3];
+        double xi[3];
         for (int a = 0; a < 3; ++a)
             if (!isfinite(x[a]))
                 return OM_E_NONFINITE;
         int rc = iso_locate_one(mesh, x, c, xi);
         if (rc != OM_OK)
             return rc;
-        iso_corners(mesh, c, X);
-        iso_map(X, xi, xm, J);
-        inverse3(J, Ji);
-        trilinear(xi, Nq, dNq);
-        for (int q = 0; q < 8; ++q) {
-            node[q] = om_node_id(mesh, shape, c[0] + (q & 1), c[1] + ((q >> 1) & 1), c[2] + (q >> 2));
-            N[q] = Nq[q];
-            /* dN/dx_a = sum_b (dxi_b/dx_a) dN/dxi_b = sum_b Ji[b][a] dN/dxi_b */
-            for (int a = 0; a < 3; ++a) {
-                dN[3 * q + a] = 0.0;
-                for (int b = 0; b < 3; ++b)
-                    dN[3 * q + a] += Ji[b][a] * dNq[q][b];
-            }
-        }
-        return 8;
+        return iso_shape_in_cell(mesh, c, x, node, N, dN);
     }
     const double h = mesh->h;
     int64_t c[3];
@@ -501,9 +512,18 @@ typedef struct {
     int count;
 } support;
 
-static int support_of(const om_mesh *mesh, int32_t shape, const double *x, support *s)
+/* Support of a particle at x; on an isoparametric mesh, in the cell that
+ * step 1 located it in (cell id), on a uniform mesh found from x. */
+static int support_of(const om_mesh *mesh, int32_t shape, const double *x, int64_t cell, support *s)
 {
-    int q = om_shape(mesh, shape, x, s->node, s->N, s->dN);
+    int q;
+    if (mesh->node_x) {
+        const int64_t c[3] = {cell % mesh->n[0], (cell / mesh->n[0]) % mesh->n[1],
+                              cell / ((int64_t)mesh->n[0] * mesh->n[1])};
+        q = iso_shape_in_cell(mesh, c, x, s->node, s->N, s->dN);
+    } else {
+        q = om_shape(mesh, shape, x, s->node, s->N, s->dN);
+    }
     if (q < 0)
         return q;
     s->count = q;
@@ -573,20 +593,26 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
     int rc;
 
     /* 1. Locate every particle; count particles per cell (active cells). */
+    int64_t *pcell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!pcell)
+        return OM_E_NOMEM;
     memset(grid->cell_count, 0, sizeof(uint32_t) * (size_t)nc);
     for (int64_t p = 0; p < n; ++p) {
-        int64_t c;
-        rc = om_locate(mesh, 1, &x[3 * p], &c);
-        if (rc != OM_OK)
+        rc = om_locate(mesh, 1, &x[3 * p], &pcell[p]);
+        if (rc != OM_OK) {
+            free(pcell);
             return rc;
-        grid->cell_count[c] += 1;
+        }
+        grid->cell_count[pcell[p]] += 1;
     }
 
     /* Start-of-step positions: every transfer of the step is evaluated there
      * (USL needs them after the positions have moved). */
     double *x0 = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-    if (!x0)
+    if (!x0) {
+        free(pcell);
         return OM_E_NOMEM;
+    }
     memcpy(x0, x, sizeof(double) * 3 * (size_t)n);
 
     /* 2. Reset every nodal quantity. */
@@ -604,7 +630,7 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
 
     /* 3. P2G: nodal mass and momentum. */
     for (int64_t p = 0; p < n; ++p) {
-        support_of(mesh, shape, &x0[3 * p], &s);
+        support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
         for (int q = 0; q < s.count; ++q) {
             int64_t I = s.node[q];
             grid->m[I] += s.N[q] * mass[p];
@@ -623,7 +649,7 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
     if (scheme->algo == OM_USF) {
         for (int64_t p = 0; p < n; ++p) {
             double deps[6];
-            support_of(mesh, shape, &x0[3 * p], &s);
+            support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
             strain_increment(&s, grid->v, dt, deps);
             update_stress(mat, deps, &vol[p], &sig[6 * p]);
         }
@@ -632,7 +658,7 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
     /* 6. P2G: internal and external forces, then the external forces given
      * at nodes (a surface traction in nodal form). */
     for (int64_t p = 0; p < n; ++p) {
-        support_of(mesh, shape, &x0[3 * p], &s);
+        support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
         add_force(&s, vol[p], &sig[6 * p], mass[p], scheme->gravity, grid->f);
     }
     double ramp = 1.0;
@@ -655,7 +681,7 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
 
     /* 8. G2P: particle velocity (FLIP increment or PIC) and position. */
     for (int64_t p = 0; p < n; ++p) {
-        support_of(mesh, shape, &x0[3 * p], &s);
+        support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
         double dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
         for (int q = 0; q < s.count; ++q) {
             int64_t I = s.node[q];
@@ -678,12 +704,13 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
     if (scheme->algo == OM_USL) {
         for (int64_t p = 0; p < n; ++p) {
             double deps[6];
-            support_of(mesh, shape, &x0[3 * p], &s);
+            support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
             strain_increment(&s, grid->vn, dt, deps);
             update_stress(mat, deps, &vol[p], &sig[6 * p]);
         }
     }
     free(x0);
+    free(pcell);
 
     rc = OM_OK;
     for (int64_t p = 0; p < n && rc == OM_OK; ++p) {

@@ -289,7 +289,7 @@ Sizes sizes_of(const mpmx_mesh *m, int shape, int prec, int64_t np)
 uint64_t align_up(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 
 // Device bytes of a scene; the allocation below follows the same list.
-uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = false)
+uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = false, bool iso = false)
 {
     uint64_t b = 0;
     const uint64_t R = s.real;
@@ -306,6 +306,8 @@ uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = fal
         b += align_up((uint64_t)s.nn) + align_up(24 * (uint64_t)s.nn);
     if (force)
         b += align_up(24 * (uint64_t)s.nn);
+    if (iso)
+        b += align_up(24 * (uint64_t)s.nn);
     return b;
 }
 
@@ -320,6 +322,42 @@ int validate(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat, con
                         kMaxCells[a]);
     if (!(mesh->h > 0.0) || !std::isfinite(mesh->h))
         return fail(ctx, MPMX_E_INVALID_ARG, "mesh: h must be positive and finite");
+    if (mesh->node_x) {
+        if (sch && sch->size >= sizeof(mpmx_scheme) && sch->shape != MPMX_SHAPE_LINEAR)
+            return fail(ctx, MPMX_E_INVALID_ARG, "mesh: an isoparametric mesh takes linear shape functions only");
+        const int64_t N0 = mesh->n[0] + 1, N1 = mesh->n[1] + 1, N2 = mesh->n[2] + 1, nn = N0 * N1 * N2;
+        if (24 * nn >= ((int64_t)1 << 32))
+            return fail(ctx, MPMX_E_INVALID_ARG, "mesh: too many isoparametric nodes for 32-bit offsets");
+        const double *X = mesh->node_x;
+        for (int64_t i = 0; i < 3 * nn; ++i)
+            if (!std::isfinite(X[i]))
+                return fail(ctx, MPMX_E_INVALID_ARG, "mesh: node_x[%lld] not finite", (long long)i);
+        // every cell: positive Jacobian det(dx/dxi) at its eight corners
+        for (int64_t k = 0; k < mesh->n[2]; ++k)
+            for (int64_t j = 0; j < mesh->n[1]; ++j)
+                for (int64_t i = 0; i < mesh->n[0]; ++i)
+                    for (int q = 0; q < 8; ++q) {
+                        const int64_t ci = i + (q & 1), cj = j + ((q >> 1) & 1), ck = k + (q >> 2);
+                        double e[3][3];   // edges from the corner towards its three neighbours in the cell
+                        for (int a = 0; a < 3; ++a) {
+                            const int64_t di = a == 0 ? ((q & 1) ? -1 : 1) : 0;
+                            const int64_t dj = a == 1 ? (((q >> 1) & 1) ? -1 : 1) : 0;
+                            const int64_t dk = a == 2 ? ((q >> 2) ? -1 : 1) : 0;
+                            const double sgn = (di + dj + dk) > 0 ? 1.0 : -1.0;
+                            const int64_t I0 = ci + N0 * (cj + N1 * ck);
+                            const int64_t I1 = (ci + di) + N0 * ((cj + dj) + N1 * (ck + dk));
+                            for (int b = 0; b < 3; ++b)
+                                e[a][b] = sgn * (X[3 * I1 + b] - X[3 * I0 + b]);
+                        }
+                        const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                                           e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                                           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+                        if (!(det > 0.0))
+                            return fail(ctx, MPMX_E_INVALID_ARG,
+                                        "mesh: cell (%lld,%lld,%lld) is inverted or degenerate at corner %d",
+                                        (long long)i, (long long)j, (long long)k, q);
+                    }
+    }
     if (mat) {
         if (mat->size < sizeof(mpmx_material))
             return fail(ctx, MPMX_E_INVALID_ARG, "material descriptor too small");
@@ -952,7 +990,7 @@ int mpmx_scene_bytes(const mpmx_mesh *mesh, const mpmx_scheme *scheme, int64_t n
     if (rc)
         return rc;
     Sizes s = sizes_of(mesh, scheme->shape, scheme->precision, n_particles);
-    *bytes = scene_bytes(s, n_particles, false);
+    *bytes = scene_bytes(s, n_particles, false, false, mesh->node_x != nullptr);
     return MPMX_OK;
 }
 
@@ -996,15 +1034,16 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
                         (long long)bc->force_node[e]);
     HIPCHK(ctx, hipSetDevice(ctx->device));
 
+    const bool iso = mesh->node_x != nullptr;
     auto sc = std::make_unique<Scene>();
     Scene *s = sc.get();
     s->prec = sch->precision;
-    s->shape = sch->shape;
+    s->shape = iso ? 2 : sch->shape;   // kernel shape: 2 is the isoparametric trilinear hexahedron
     s->algo = sch->algo;
     SceneDev &h = s->h;
     // one block of exactly scene_bytes(); the arrays are carved in the order
     // scene_bytes() counts them
-    const uint64_t total = scene_bytes(sz, np, extra, force);
+    const uint64_t total = scene_bytes(sz, np, extra, force, iso);
     s->block = ctx->pool.alloc(total);
     if (!s->block)
         return fail(ctx, MPMX_E_OOM, "device allocation of %llu bytes failed", (unsigned long long)total);
@@ -1082,6 +1121,17 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         h.bc_val = (const double *)dv;
         h.bc_force = (const double *)df;
         h.force_ramp = bc->force_ramp_steps;
+    }
+    if (iso) {
+        // node positions, structure of arrays x[3][nn]
+        std::vector<double> X(3 * sz.nn);
+        for (int64_t I = 0; I < sz.nn; ++I)
+            for (int a = 0; a < 3; ++a)
+                X[a * sz.nn + I] = mesh->node_x[3 * I + a];
+        void *dX = need(dalloc(24 * (uint64_t)sz.nn, false), 1);
+        if (ok)
+            HIPCHK(ctx, hipMemcpy(dX, X.data(), 24 * sz.nn, hipMemcpyHostToDevice));
+        h.X = (const double *)dX;
     }
     for (auto &z : zero_ranges)
         if (ok && hipMemsetAsync(z.first, 0, z.second, ctx->stream) != hipSuccess)

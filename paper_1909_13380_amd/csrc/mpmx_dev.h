@@ -86,6 +86,7 @@ struct SceneDev {
     // mesh
     double origin[3];
     double h, inv_h;
+    const double *X;   // isoparametric mesh: node positions x[3][nn] (FP64); null for the uniform grid
     int n[3];        // cells
     int nb[3];       // bricks
     int N[3];        // nodes per axis incl. ghosts

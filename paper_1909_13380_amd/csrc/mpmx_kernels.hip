@@ -364,13 +364,215 @@ struct ShapeTraits<1> {   // uGIMP, particle half-length h/4, 27 nodes
     static constexpr int hi = 2;
     static constexpr int cap = 729;
 };
+template <>
+struct ShapeTraits<2> {   // isoparametric trilinear 8-node hexahedron
+    static constexpr int NS = 2;
+    static constexpr int lo = 0;
+    static constexpr int hi = 1;
+    static constexpr int cap = 343;
+};
 
+// Shape function values w and one-axis derivatives dw of a particle's
+// support nodes, per axis (tensor-product form).  Uniform linear and GIMP:
+// dw is d/dx.  Isoparametric: the weights are those of the particle's local
+// coordinates r in [0,1)^3 of its cell, dw is d/dr, and Ji = (dx/dr)^-1 at
+// the particle turns d/dr into d/dx: dN/dx_b = sum_c dN/dr_c Ji[c][b].
 template <typename R, int SH>
 struct Support {
     int base[3];
     R w[3][ShapeTraits<SH>::NS];
     R dw[3][ShapeTraits<SH>::NS];
+    R Ji[SH == 2 ? 3 : 1][SH == 2 ? 3 : 1];
 };
+
+// ------------------------------------------------ isoparametric cells --
+// A cell of an isoparametric mesh (isoparametric-mesh section) is the
+// trilinear image of its eight nodes over local coordinates r in [0,1]^3
+// (r = (xi + 1) / 2 of the natural cube [-1,1]^3).  Relative to its first
+// node o, x(r) = b1 r + b2 s + b3 t + b4 rs + b5 st + b6 rt + b7 rst
+// (r, s, t the three local coordinates), in FP64.
+struct IsoCell {
+    double o[3];
+    double b[7][3];
+};
+
+__device__ inline void iso_cell(const SceneDev &S, const int c[3], IsoCell &k)
+{
+    const uint32_t n0 = node_id(S, c[0], c[1], c[2]);
+    const uint32_t ny = (uint32_t)S.N[0], nz = (uint32_t)(S.N[0] * S.N[1]), nn = (uint32_t)S.nn;
+    const GLOBAL double *X = gp(S.X);
+    double P[8][3];
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t I = n0 + (uint32_t)(q & 1) + (uint32_t)((q >> 1) & 1) * ny + (uint32_t)(q >> 2) * nz;
+        for (int a = 0; a < 3; ++a)
+            P[q][a] = ldg(X, a * nn + I);
+    }
+    for (int a = 0; a < 3; ++a) {
+        k.o[a] = P[0][a];
+        const double p1 = P[1][a] - P[0][a], p2 = P[2][a] - P[0][a], p3 = P[3][a] - P[0][a];
+        const double p4 = P[4][a] - P[0][a], p5 = P[5][a] - P[0][a], p6 = P[6][a] - P[0][a];
+        const double p7 = P[7][a] - P[0][a];
+        k.b[0][a] = p1;                       // r
+        k.b[1][a] = p2;                       // s
+        k.b[2][a] = p4;                       // t
+        k.b[3][a] = p3 - p1 - p2;             // rs
+        k.b[4][a] = p6 - p2 - p4;             // st
+        k.b[5][a] = p5 - p1 - p4;             // rt
+        k.b[6][a] = p7 - p3 - p5 - p6 + p1 + p2 + p4;   // rst
+    }
+}
+
+// x(r) - o and the Jacobian J[a][c] = dx_a / dr_c.
+__device__ inline void iso_eval(const IsoCell &k, const double r[3], double x[3], double J[3][3])
+{
+    const double rs = r[0] * r[1], st = r[1] * r[2], rt = r[0] * r[2];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = k.b[0][a] * r[0] + k.b[1][a] * r[1] + k.b[2][a] * r[2] + k.b[3][a] * rs + k.b[4][a] * st +
+               k.b[5][a] * rt + k.b[6][a] * rs * r[2];
+        J[a][0] = k.b[0][a] + k.b[3][a] * r[1] + k.b[5][a] * r[2] + k.b[6][a] * st;
+        J[a][1] = k.b[1][a] + k.b[3][a] * r[0] + k.b[4][a] * r[2] + k.b[6][a] * rt;
+        J[a][2] = k.b[2][a] + k.b[4][a] * r[1] + k.b[5][a] * r[0] + k.b[6][a] * rs;
+    }
+}
+
+__device__ inline void inverse3(const double M[3][3], double Mi[3][3])
+{
+    const double c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    const double c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    const double c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    const double id = 1.0 / (M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02);
+    Mi[0][0] = c00 * id;
+    Mi[1][0] = c01 * id;
+    Mi[2][0] = c02 * id;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) * id;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) * id;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) * id;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) * id;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) * id;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) * id;
+}
+
+// Local coordinates r of the point o + y in the cell: Newton-Raphson on
+// x(r) = y from the affine guess r0 = 1/2 + J(1/2)^-1 (y - x(1/2)), stopping
+// after a correction of at most 5e-13 (1e-12 in natural coordinates; the
+// error left is of the order of its square).  False if it broke down.
+__device__ inline bool iso_local(const IsoCell &k, const double y[3], double r[3])
+{
+    double xm[3], J[3][3], Ji[3][3];
+    const double c[3] = {0.5, 0.5, 0.5};
+    iso_eval(k, c, xm, J);
+    inverse3(J, Ji);
+    for (int a = 0; a < 3; ++a)
+        r[a] = 0.5 + Ji[a][0] * (y[0] - xm[0]) + Ji[a][1] * (y[1] - xm[1]) + Ji[a][2] * (y[2] - xm[2]);
+    for (int it = 0; it < 50; ++it) {
+        iso_eval(k, r, xm, J);
+        inverse3(J, Ji);
+        double dmax = 0.0;
+        double d[3];
+        for (int a = 0; a < 3; ++a)
+            d[a] = Ji[a][0] * (xm[0] - y[0]) + Ji[a][1] * (xm[1] - y[1]) + Ji[a][2] * (xm[2] - y[2]);
+        for (int a = 0; a < 3; ++a) {
+            r[a] -= d[a];
+            dmax = fmax(dmax, fabs(d[a]));
+        }
+        if (!(dmax > 5e-13))   // converged, or not a number (the check below fails)
+            break;
+    }
+    return isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
+}
+
+// Cell of point x on an isoparametric mesh by a walk across cell faces from
+// cell c (updated in place; the particle's previous cell, or a first guess)
+// towards the point, at most `budget` cells: the cell whose local
+// coordinates of x lie in [0,1)^3 (the uniform mesh's half-open rule), its
+// geometry k and the local coordinates r.  A point that rounding leaves
+// just past a face between two cells (by at most 5e-13, never past the
+// mesh's outer faces) goes to the one it overshoots least.  Returns 0 or
+// ERR_OUT_OF_MESH / ERR_NONFINITE.
+__device__ inline uint32_t iso_locate(const SceneDev &S, const double x[3], int c[3], double r[3], IsoCell &k,
+                                      int budget)
+{
+    if (!isfinite(x[0]) || !isfinite(x[1]) || !isfinite(x[2]))
+        return ERR_NONFINITE;
+    int best[3] = {-1, 0, 0}, prev[3] = {-1, -1, -1};
+    double bover = 1.0, br[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < budget; ++m) {
+        iso_cell(S, c, k);
+        const double y[3] = {x[0] - k.o[0], x[1] - k.o[1], x[2] - k.o[2]};
+        if (!iso_local(k, y, r))
+            break;
+        int d[3];
+        bool in = true, outer = false;
+        double over = -1.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = r[a] < 0.0 ? -1 : (r[a] >= 1.0 ? 1 : 0);
+            in = in && d[a] == 0;
+            over = fmax(over, fmax(-r[a], r[a] - 1.0));
+            outer = outer || (unsigned)(c[a] + d[a]) >= (unsigned)S.n[a];
+        }
+        if (in)
+            return 0u;
+        if (!outer && over <= 5e-13 && over < bover) {
+            bover = over;
+            for (int a = 0; a < 3; ++a) {
+                best[a] = c[a];
+                br[a] = r[a];
+            }
+        }
+        if (outer)
+            break;
+        const int nx[3] = {c[0] + d[0], c[1] + d[1], c[2] + d[2]};
+        if (nx[0] == prev[0] && nx[1] == prev[1] && nx[2] == prev[2])
+            break;   // back and forth across one face
+        for (int a = 0; a < 3; ++a) {
+            prev[a] = c[a];
+            c[a] = nx[a];
+        }
+    }
+    if (best[0] < 0)
+        return ERR_OUT_OF_MESH;
+    for (int a = 0; a < 3; ++a) {
+        c[a] = best[a];
+        r[a] = br[a];
+    }
+    iso_cell(S, c, k);
+    return 0u;
+}
+
+// Cells a per-step location walk may visit: a particle moves less than a
+// cell per step (CFL), so it ends in its cell or a neighbour of it.
+constexpr int kIsoWalk = 8;
+
+// Support of a particle at local coordinates r of cell c (geometry k).
+template <typename R>
+__device__ inline void iso_support(const IsoCell &k, const int c[3], const double r[3], Support<R, 2> &sp)
+{
+    for (int a = 0; a < 3; ++a) {
+        sp.base[a] = c[a];
+        sp.w[a][0] = (R)(1.0 - r[a]);
+        sp.w[a][1] = (R)r[a];
+        sp.dw[a][0] = (R)-1;
+        sp.dw[a][1] = (R)1;
+    }
+    double xm[3], J[3][3], Ji[3][3];
+    iso_eval(k, r, xm, J);
+    inverse3(J, Ji);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            sp.Ji[a][b] = (R)Ji[a][b];
+}
+
+// Gradient (d/dx) of a support node's shape function from its d/dr.
+template <typename R, int SH>
+__device__ inline void to_dx(const Support<R, SH> &sp, R &gx, R &gy, R &gz)
+{
+    if constexpr (SH == 2) {
+        const R a = gx, b = gy, c = gz;
+        gx = a * sp.Ji[0][0] + b * sp.Ji[1][0] + c * sp.Ji[2][0];
+        gy = a * sp.Ji[0][1] + b * sp.Ji[1][1] + c * sp.Ji[2][1];
+        gz = a * sp.Ji[0][2] + b * sp.Ji[1][2] + c * sp.Ji[2][2];
+    }
+}
 
 // 1-D uGIMP weight for offset rho = (x_p - X_I)/h with lh = l/h = 1/4: the
 // linear hat averaged over the particle's domain [x_p - l, x_p + l].
@@ -401,7 +603,14 @@ __device__ inline void make_support(const SceneDev &S, const double x[3], const 
 {
     const double h = S.h, ih = S.inv_h;
     const R inv_h = cst<R>(S.inv_h, S.f_inv_h);
-    if constexpr (SH == 0) {
+    if constexpr (SH == 2) {
+        IsoCell k;
+        iso_cell(S, c, k);
+        const double y[3] = {x[0] - k.o[0], x[1] - k.o[1], x[2] - k.o[2]};
+        double r[3];
+        iso_local(k, y, r);
+        iso_support<R>(k, c, r, sp);
+    } else if constexpr (SH == 0) {
         for (int a = 0; a < 3; ++a) {
             const R r = (R)((x[a] - (S.origin[a] + h * (double)c[a])) * ih);
             sp.base[a] = c[a];
@@ -755,7 +964,20 @@ __global__ void k_load(SceneDev *Sd, const double *x, const double *v, const dou
         M[p] = (R)mass[p];
         fin = fin && isfinite(vol[p]) && isfinite(mass[p]);
         int c[3] = {0, 0, 0};
-        uint32_t e = locate(S, xp, c);
+        uint32_t e;
+        if (S.X) {
+            // isoparametric: walk from the cell of the uniform grid (origin,
+            // h) the mesh was made from, clamped to the mesh
+            for (int a = 0; a < 3; ++a) {
+                const double q = floor((xp[a] - S.origin[a]) * S.inv_h);
+                c[a] = q < 0.0 ? 0 : (q >= (double)S.n[a] ? S.n[a] - 1 : (int)q);
+            }
+            double r[3];
+            IsoCell k;
+            e = iso_locate(S, xp, c, r, k, S.n[0] + S.n[1] + S.n[2] + kIsoWalk);
+        } else {
+            e = locate(S, xp, c);
+        }
         if (!fin)
             e |= ERR_NONFINITE;
         if (e) {
@@ -1749,9 +1971,10 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
                         atomicAdd(&acc[2][li], (double)(N * mv[1]));
                         atomicAdd(&acc[3][li], (double)(N * mv[2]));
                         if constexpr (WITH_FORCE) {
-                            const R gxN = sp.dw[0][i] * wyz;
-                            const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
-                            const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
+                            R gxN = sp.dw[0][i] * wyz;
+                            R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
+                            R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
+                            to_dx<R, SH>(sp, gxN, gyN, gzN);
                             const R fx = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mp * gx;
                             const R fy = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mp * gy;
                             const R fz = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mp * gz;
@@ -1790,8 +2013,8 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
 // per particle.
 template <int SH, bool G, bool S>
 struct Cache {
-    static constexpr bool gather = SH == 0 && G;
-    static constexpr bool scatter = SH == 0 && S;
+    static constexpr bool gather = SH != 1 && G;
+    static constexpr bool scatter = SH != 1 && S;
     static constexpr int gnodes = gather ? 8 : 1;
     static constexpr int snodes = scatter ? 8 : 1;
 };
@@ -1926,7 +2149,7 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             // other two axes' weights (pair products below, shared with the
             // force), so the gradient is a weighted sum of nodal differences
             R Pyz[4], Pxz[4], Pxy[4];
-            if constexpr (SH == 0) {
+            if constexpr (SH != 1) {
                 for (int u = 0; u < 2; ++u)
                     for (int w = 0; w < 2; ++w) {
                         Pyz[u + 2 * w] = sp.w[1][u] * sp.w[2][w];
@@ -1955,9 +2178,14 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                             gy += Pxz[u + 2 * w] * (v8[u + 2 + 4 * w][e] - v8[u + 4 * w][e]);
                             gz += Pxy[u + 2 * w] * (v8[u + 2 * w + 4][e] - v8[u + 2 * w][e]);
                         }
-                    L[e][0] = ih * gx;
-                    L[e][1] = ih * gy;
-                    L[e][2] = ih * gz;
+                    if constexpr (SH == 2) {   // d/dr to d/dx through (dx/dr)^-1
+                        for (int b = 0; b < 3; ++b)
+                            L[e][b] = gx * sp.Ji[0][b] + gy * sp.Ji[1][b] + gz * sp.Ji[2][b];
+                    } else {
+                        L[e][0] = ih * gx;
+                        L[e][1] = ih * gy;
+                        L[e][2] = ih * gz;
+                    }
                 }
             } else {
             for (int k = 0; k < NS; ++k)
@@ -2019,11 +2247,27 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                     atomicAdd(&lf[2][li], (double)f2);
                 }
             };
-            if constexpr (SH == 0) {
+            if constexpr (SH != 1) {
                 // f_I = -V sigma . grad N_I + N_I m g with grad N_I = (1/h) (sx Pyz,
-                // sy Pxz, sz Pxy), s = -1 for the lower node of an axis
-                const R c = -vol * cst<R>(S.inv_h, S.f_inv_h);
-                const R A[6] = {c * sg[0], c * sg[1], c * sg[2], c * sg[3], c * sg[4], c * sg[5]};
+                // sy Pxz, sz Pxy), s = -1 for the lower node of an axis; on an
+                // isoparametric cell grad N_I = Ji^T (sx Pyz, sy Pxz, sz Pxy), so
+                // f_Ia = sum_c B_ac dN_I/dr_c with B = -V sigma Ji^T
+                R B[3][3];
+                if constexpr (SH == 2) {
+                    const R sm[3][3] = {{sg[0], sg[3], sg[5]}, {sg[3], sg[1], sg[4]}, {sg[5], sg[4], sg[2]}};
+                    for (int a = 0; a < 3; ++a)
+                        for (int c2 = 0; c2 < 3; ++c2)
+                            B[a][c2] = -vol * (sm[a][0] * sp.Ji[c2][0] + sm[a][1] * sp.Ji[c2][1] +
+                                               sm[a][2] * sp.Ji[c2][2]);
+                } else {
+                    const R c = -vol * cst<R>(S.inv_h, S.f_inv_h);
+                    B[0][0] = c * sg[0];
+                    B[1][1] = c * sg[1];
+                    B[2][2] = c * sg[2];
+                    B[0][1] = B[1][0] = c * sg[3];
+                    B[1][2] = B[2][1] = c * sg[4];
+                    B[0][2] = B[2][0] = c * sg[5];
+                }
                 const R mg0 = mp * gx, mg1 = mp * gy, mg2 = mp * gz;
                 for (int k = 0; k < 2; ++k)
                     for (int j = 0; j < 2; ++j)
@@ -2031,9 +2275,9 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                             const R yz = Pyz[j + 2 * k], xz = Pxz[i + 2 * k], xy = Pxy[i + 2 * j];
                             const R ax = i ? yz : -yz, ay = j ? xz : -xz, az = k ? xy : -xy;
                             const R N = sp.w[0][i] * yz;
-                            deposit(i, j, k, N * mg0 + A[0] * ax + A[3] * ay + A[5] * az,
-                                    N * mg1 + A[3] * ax + A[1] * ay + A[4] * az,
-                                    N * mg2 + A[5] * ax + A[4] * ay + A[2] * az);
+                            deposit(i, j, k, N * mg0 + B[0][0] * ax + B[0][1] * ay + B[0][2] * az,
+                                    N * mg1 + B[1][0] * ax + B[1][1] * ay + B[1][2] * az,
+                                    N * mg2 + B[2][0] * ax + B[2][1] * ay + B[2][2] * az);
                         }
             } else {
             for (int k = 0; k < NS; ++k)
@@ -2276,7 +2520,15 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             }
             int nc[3];
             double fr[3];
-            const uint32_t e = locate<SH == 0>(S, xp, nc, fr);
+            uint32_t e;
+            if constexpr (SH == 2) {   // walk from the old cell; fr: local coordinates in the new one
+                IsoCell k;
+                for (int a = 0; a < 3; ++a)
+                    nc[a] = c[a];
+                e = iso_locate(S, xp, nc, fr, k, kIsoWalk);
+            } else {
+                e = locate<SH == 0>(S, xp, nc, fr);
+            }
             if (e) {
                 err |= e;   // keep the old cell; the scene stops after this step
                 lost += (e & ERR_OUT_OF_MESH) ? 1u : 0u;
@@ -2302,8 +2554,9 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 continue;
             }
             // the next step's P2G from the updated particle (trilinear: the
-            // local coordinate is the cell search's fractional part)
-            if constexpr (SH == 0) {
+            // local coordinate is the cell search's fractional part, or the
+            // isoparametric walk's local coordinates)
+            if constexpr (SH != 1) {
                 const R ih = cst<R>(S.inv_h, S.f_inv_h);
                 for (int a = 0; a < 3; ++a) {
                     const R r = (R)fr[a];
@@ -2457,9 +2710,10 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
                     for (int i = 0; i < NS; ++i) {
                         const R wyz = sp.w[1][j] * sp.w[2][k];
                         const R N = sp.w[0][i] * wyz;
-                        const R gxN = sp.dw[0][i] * wyz;
-                        const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
-                        const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
+                        R gxN = sp.dw[0][i] * wyz;
+                        R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
+                        R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
+                        to_dx<R, SH>(sp, gxN, gyN, gzN);
                         const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
                         const R4<R> a = la[li];
                         const R4<R> u = lvn[li];
@@ -2503,7 +2757,16 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
                     err |= ERR_NONFINITE;
             }
             int nc[3];
-            const uint32_t e = locate(S, xp, nc);
+            uint32_t e;
+            if constexpr (SH == 2) {
+                double rr[3];
+                IsoCell k;
+                for (int a = 0; a < 3; ++a)
+                    nc[a] = c[a];
+                e = iso_locate(S, xp, nc, rr, k, kIsoWalk);
+            } else {
+                e = locate(S, xp, nc);
+            }
             if (e) {
                 err |= e;
                 lost += (e & ERR_OUT_OF_MESH) ? 1u : 0u;
@@ -2559,9 +2822,9 @@ static KernelSet make_set()
 
 const KernelSet &kernel_set(int prec, int shape)
 {
-    static const KernelSet sets[2][2] = {{make_set<float, 0>(), make_set<float, 1>()},
-                                         {make_set<double, 0>(), make_set<double, 1>()}};
-    return sets[prec ? 1 : 0][shape ? 1 : 0];
+    static const KernelSet sets[2][3] = {{make_set<float, 0>(), make_set<float, 1>(), make_set<float, 2>()},
+                                         {make_set<double, 0>(), make_set<double, 1>(), make_set<double, 2>()}};
+    return sets[prec ? 1 : 0][shape < 0 || shape > 2 ? 0 : shape];
 }
 
 const CommonKernels &common_kernels()

@@ -33,6 +33,7 @@ struct Pending {
     std::vector<double> bc_value;
     std::vector<int64_t> force_node;
     std::vector<double> force_value;
+    std::vector<double> node_x;   // isoparametric mesh nodes (empty: uniform)
     std::vector<double> x, v, stress, vol, mass;
 };
 
@@ -158,6 +159,7 @@ int admit(mpmx_server *srv)
         p.bc.value = p.bc_value.data();
         p.bc.force_node = p.force_node.data();
         p.bc.force_value = p.force_value.data();
+        p.mesh.node_x = p.node_x.empty() ? nullptr : p.node_x.data();
         uint64_t scene = 0;
         const int rc = mpmx_scene_create(srv->ctx, &p.mesh, &p.mat, &p.bc, &p.sch, &parts, &scene);
         if (rc == MPMX_E_OOM || rc == MPMX_E_HIP)
@@ -246,6 +248,10 @@ int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id)
     p.bytes = bytes;
     p.t_submit = srv->now();
     p.mesh = *req->mesh;
+    if (req->mesh->node_x) {
+        const size_t nn = (size_t)(req->mesh->n[0] + 1) * (req->mesh->n[1] + 1) * (req->mesh->n[2] + 1);
+        p.node_x.assign(req->mesh->node_x, req->mesh->node_x + 3 * nn);
+    }
     p.mat = *req->material;
     p.bc = *req->bc;
     p.sch = *req->scheme;

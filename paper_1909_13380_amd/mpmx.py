@@ -60,7 +60,7 @@ class MpmxError(RuntimeError):
 
 
 class Mesh(ctypes.Structure):
-    _fields_ = [("size", _u32), ("n", _i32 * 3), ("origin", _d * 3), ("h", _d)]
+    _fields_ = [("size", _u32), ("n", _i32 * 3), ("origin", _d * 3), ("h", _d), ("node_x", _P(_d))]
 
 
 class Material(ctypes.Structure):
@@ -153,12 +153,18 @@ def version() -> int:
 
 
 def _mesh(m: dict) -> Mesh:
+    """The C mesh descriptor; an isoparametric mesh's node positions
+    (``node_x``, (nodes, 3)) are referenced and kept alive by it."""
     out = Mesh()
     out.size = ctypes.sizeof(Mesh)
     for a in range(3):
         out.n[a] = int(m["n"][a])
         out.origin[a] = float(m["origin"][a])
     out.h = float(m["h"])
+    if m.get("node_x") is not None:
+        nx = np.ascontiguousarray(m["node_x"], dtype=np.float64).reshape(-1, 3)
+        out._keep = nx
+        out.node_x = nx.ctypes.data_as(_P(_d))
     return out
 
 

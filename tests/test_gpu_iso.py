@@ -1,0 +1,269 @@
+"""GPU parity on isoparametric (distorted) meshes: the HIP library through
+its C ABI against the FP64 oracle (isoparametric-mesh section: cells that
+are trilinear images of the natural cube, particles located by inverting
+that map with Newton-Raphson from an affine guess, and a walk over
+neighbouring cells in place of the uniform grid's floor()).
+
+Bars as for the uniform mesh: FP64 to rounding (1e-9), FP32 displacement
+and stress within 1e-4 and 1e-3 relative L2.  Cells are compared particle
+by particle; a difference is allowed only for a particle whose oracle
+natural coordinates lie within 1e-9 of its cell's faces (rounding decides
+such a point; both cells then hold it), and those are counted."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_13380_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+U_TOL, S_TOL = 1e-4, 1e-3
+
+
+@pytest.fixture(scope="module")
+def mp():
+    from paper_1909_13380_amd import mpmx
+    return mpmx
+
+
+@pytest.fixture(scope="module")
+def ctx(mp):
+    c = mp.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def check_state(name, got, ref, x0, u_tol, s_tol, v_tol=None):
+    eu = rel(got["x"] - x0, ref["x"] - x0)
+    es = rel(got["stress"], ref["stress"])
+    ev = rel(got["v"], ref["v"])
+    evol = rel(got["vol"], ref["vol"])
+    print(f"[{name}] err_u={eu:.3e} err_sigma={es:.3e} err_v={ev:.3e} err_vol={evol:.3e}", flush=True)
+    assert eu <= u_tol, (name, "displacement", eu)
+    assert es <= s_tol, (name, "stress", es)
+    assert ev <= (v_tol if v_tol is not None else u_tol), (name, "velocity", ev)
+    assert evol <= s_tol, (name, "volume", evol)
+
+
+def cell_ijk(mesh, cid):
+    n0, n1 = mesh["n"][0], mesh["n"][1]
+    return np.stack([cid % n0, (cid // n0) % n1, cid // (n0 * n1)], axis=1)
+
+
+def check_cells(sc, got_cells, x):
+    """GPU cell of every particle against the oracle's location of the same
+    positions; returns the count of face-tied differences."""
+    ref = oracle.locate(sc["mesh"], x)
+    differ = np.flatnonzero(got_cells != ref)
+    for p in differ:
+        c = cell_ijk(sc["mesh"], np.array([ref[p]]))[0]
+        xi, _ = oracle.iso_natural(sc["mesh"], c, x[p])
+        assert np.min(1.0 - np.abs(xi)) < 1e-9, ("cell differs away from a face", p, xi)
+    return len(differ)
+
+
+def distorted_block(seed=21, amp=0.3, material=None, algo=0, vel=0.5, dt=2e-5, stress_scale=3e3):
+    base = scenes.random_block(n_cells=(9, 7, 6), mesh_cells=(14, 11, 9), h=0.05, seed=seed, material=material,
+                               stress_scale=stress_scale, vel=vel, dt=dt)
+    base["scheme"]["algo"] = algo
+    return scenes.distort(base, amp=amp, seed=seed + 100)
+
+
+MATERIALS = {"le": scenes.elastic(), "dp": scenes.drucker_prager(psi_deg=5, c=1e3)}
+
+
+def test_binning_on_a_distorted_mesh(ctx, mp):
+    sc = distorted_block()
+    s = ctx.create_scene(sc, precision=mp.FP64)
+    got = s.read()["cell"]
+    assert check_cells(sc, got, sc["x"]) == 0
+    np.testing.assert_array_equal(s.cell_counts(), oracle.cell_counts(sc["mesh"], sc["x"]))
+    s.destroy()
+    # far from the reference grid: particles made by the forward map of
+    # cells across the whole mesh, located from the (clamped) reference cell
+    rng = np.random.default_rng(5)
+    mesh = sc["mesh"]
+    X = np.asarray(mesh["node_x"])
+    nx, ny = mesh["n"][0] + 1, mesh["n"][1] + 1
+    pts = []
+    for _ in range(2000):
+        c = [int(rng.integers(0, m)) for m in mesh["n"]]
+        r = rng.uniform(0.002, 0.998, size=3)
+        w = [np.array([1 - r[a], r[a]]) for a in range(3)]
+        x = np.zeros(3)
+        for q in range(8):
+            i, j, k = q & 1, (q >> 1) & 1, q >> 2
+            x += w[0][i] * w[1][j] * w[2][k] * X[(c[0] + i) + nx * ((c[1] + j) + ny * (c[2] + k))]
+        pts.append(x)
+    pts = np.array(pts)
+    n = len(pts)
+    sc2 = dict(sc, x=pts, v=np.zeros((n, 3)), stress=np.zeros((n, 6)), vol=np.full(n, 1e-5), mass=np.full(n, 0.02))
+    s = ctx.create_scene(sc2, precision=mp.FP32)
+    assert check_cells(sc2, s.read()["cell"], pts) == 0
+    s.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("mat", ["le", "dp"])
+def test_one_step_on_a_distorted_mesh(ctx, mp, prec, algo, mat):
+    sc = distorted_block(material=MATERIALS[mat], algo=algo)
+    if mat == "dp":
+        sc["stress"][:, :3] -= 2e3
+        sc["stress"] = sc["stress"].astype(np.float32).astype(np.float64)
+    p = mp.FP64 if prec == "fp64" else mp.FP32
+    s = ctx.create_scene(sc, precision=p)
+    s.step(1)
+    got, nodes = s.read(), s.nodes()
+    ref = oracle.run(sc, 1)
+    g = ref["grid"]
+    tol = 1e-9 if prec == "fp64" else 2e-5
+    name = f"iso/{prec}/{'usl' if algo else 'usf'}/{mat}"
+    for k, a, b in (("m", nodes["m"], g.m), ("p", nodes["p"], g.p), ("f", nodes["f"], g.f)):
+        e = rel(a, b)
+        print(f"[{name}] nodal {k}: {e:.3e}", flush=True)
+        assert e <= tol, (name, k, e)
+    check_state(name, got, ref, sc["x"], tol, tol, tol)
+    s.destroy()
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+def test_many_steps_crossing_distorted_cells(ctx, mp, algo):
+    """80 (USF) or 30 (USL) steps of a deforming, pre-stressed body drifting at (6, -4, 2) m/s
+    through a distorted mesh (about half the particles cross cell faces, so
+    the location walk runs), USF and USL, reordering on demand and every
+    step: FP64 to rounding and FP32 within the bars, with cells checked."""
+    b = scenes.free_body(v0=(6.0, -4.0, 2.0), cells=(6, 5, 4), mesh_cells=(14, 12, 10), h=0.05, dt=1e-4,
+                         material=scenes.elastic())
+    rng = np.random.default_rng(3)
+    b["v"] = (b["v"] + rng.uniform(-0.3, 0.3, b["v"].shape)).astype(np.float32).astype(np.float64)
+    b["stress"] = rng.uniform(-2e3, 2e3, b["stress"].shape).astype(np.float32).astype(np.float64)
+    b["scheme"]["algo"] = algo
+    sc = scenes.distort(b, amp=0.3, seed=123)
+    # USL with FLIP grows stress noise on cell crossings at this time step
+    # (on the uniform mesh too), so its run is shorter
+    n = 80 if algo == 0 else 30
+    ref = oracle.run(sc, n)
+    moved = int((oracle.locate(sc["mesh"], ref["x"]) != oracle.locate(sc["mesh"], sc["x"])).sum())
+    print(f"[iso/many] {moved} of {len(sc['x'])} particles changed cell", flush=True)
+    assert moved > len(sc["x"]) // 10
+    for prec, p, tol in (("fp64", mp.FP64, (1e-9, 1e-9, 1e-9)), ("fp32", mp.FP32, (U_TOL, S_TOL, 1e-3))):
+        for policy in (mp.SORT_ON_DEMAND, mp.SORT_ALWAYS):
+            s = ctx.create_scene(sc, precision=p, sort_policy=policy)
+            s.step(n)
+            got = s.read()
+            st = s.stats()
+            assert st["error_bits"] == 0 and st["steps_done"] == n, st
+            name = f"iso/many/{'usl' if algo else 'usf'}/{prec}/{policy}"
+            check_state(name, got, ref, sc["x"], *tol)
+            ties = check_cells(sc, got["cell"], got["x"])
+            print(f"[{name}] face-tied cell differences {ties}", flush=True)
+            s.destroy()
+
+
+def test_free_fall_on_a_distorted_mesh_gpu(ctx, mp):
+    sc = scenes.distort(scenes.free_body(v0=(0.3, -0.2, 0.1), cells=(3, 3, 3), mesh_cells=(9, 9, 9)),
+                        amp=0.25, seed=70)
+    sc["scheme"]["mass_eps_rel"] = 0.0
+    v0 = sc["v"][0]
+    g = np.array(scenes.GRAVITY)
+    dt = sc["scheme"]["dt"]
+    n = 30
+    for prec, tol in ((mp.FP64, 1e-11), (mp.FP32, 2e-6)):
+        s = ctx.create_scene(sc, precision=prec)
+        s.step(n)
+        got = s.read()
+        assert rel(got["v"], np.broadcast_to(v0 + n * g * dt, got["v"].shape)) < tol
+        uref = n * dt * v0 + g * dt * dt * n * (n + 1) / 2
+        assert rel(got["x"] - sc["x"], np.broadcast_to(uref, sc["x"].shape)) < tol
+        s.destroy()
+
+
+def test_rotated_free_body_gpu(ctx, mp):
+    """A free body on a rigidly rotated mesh (every cell a rotated cube):
+    the GPU against the oracle, and against the unrotated run's image."""
+    sc = scenes.free_body(v0=(0.3, -0.2, 0.1), cells=(3, 3, 2), mesh_cells=(9, 9, 8))
+    rng = np.random.default_rng(68)
+    sc["v"] = (sc["v"] + rng.uniform(-0.05, 0.05, size=sc["v"].shape)).astype(np.float32).astype(np.float64)
+    sc["stress"] = rng.uniform(-1e3, 1e3, size=sc["stress"].shape).astype(np.float32).astype(np.float64)
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    R = Q if np.linalg.det(Q) > 0 else -Q
+    rot = scenes.rotate(sc, R, (1.3, -0.7, 2.1))
+    n = 12
+    ref = oracle.run(rot, n)
+    s = ctx.create_scene(rot, precision=mp.FP64)
+    s.step(n)
+    got = s.read()
+    check_state("iso/rotated", got, ref, rot["x"], 1e-9, 1e-9, 1e-9)
+    s.destroy()
+    plain = oracle.run(sc, n)
+    np.testing.assert_allclose(got["x"], plain["x"] @ R.T + np.array([1.3, -0.7, 2.1]), rtol=0, atol=1e-11)
+
+
+def test_uniform_grid_as_node_list_matches_the_uniform_path(ctx, mp):
+    base = scenes.random_block(n_cells=(7, 6, 5), mesh_cells=(12, 10, 8), seed=91, stress_scale=2e3,
+                               material=MATERIALS["dp"])
+    iso = dict(base, mesh=dict(base["mesh"], node_x=scenes.uniform_nodes(base["mesh"])))
+    a = ctx.create_scene(base, precision=mp.FP64)
+    b = ctx.create_scene(iso, precision=mp.FP64)
+    a.step(20)
+    b.step(20)
+    ra, rb = a.read(), b.read()
+    np.testing.assert_array_equal(ra["cell"], rb["cell"])
+    check_state("iso/uniform_nodes", rb, ra, base["x"], 1e-10, 1e-10, 1e-10)
+    a.destroy()
+    b.destroy()
+
+
+def test_slope_on_a_terrain_following_mesh(ctx, mp):
+    """A Drucker-Prager block on a 20 degree bed (a non-prismatic boundary
+    the mesh follows), fixed bed: 150 steps in FP32 against the oracle."""
+    sc = scenes.slope(cells=(16, 6, 8), block=(8, 6, 5), nsteps=150)
+    ref = oracle.run(sc, sc["nsteps"])
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(sc["nsteps"])
+    got = s.read()
+    check_state("iso/slope/fp32", got, ref, sc["x"], U_TOL, S_TOL, 1e-3)
+    print(f"[iso/slope] face-tied cell differences {check_cells(sc, got['cell'], got['x'])}", flush=True)
+    s.destroy()
+
+
+def test_batch_of_isoparametric_scenes_equals_alone(ctx, mp):
+    scs = [distorted_block(seed=30 + i, vel=2.0, dt=1e-4, material=MATERIALS["le" if i % 2 else "dp"])
+           for i in range(5)]
+    alone = []
+    for sc in scs:
+        s = ctx.create_scene(sc, precision=mp.FP64)
+        s.step(15)
+        alone.append(s.read())
+        s.destroy()
+    ss = [ctx.create_scene(sc, precision=mp.FP64) for sc in scs]
+    ctx.batch_step(ss, [15] * len(ss))
+    for i, (sc, s, a) in enumerate(zip(scs, ss, alone)):
+        check_state(f"iso/batch/{i}", s.read(), a, sc["x"], 1e-10, 1e-10, 1e-10)
+        s.destroy()
+
+
+def test_isoparametric_inputs_are_validated(ctx, mp):
+    sc = distorted_block()
+    bad = dict(sc, mesh=dict(sc["mesh"]))
+    X = np.array(sc["mesh"]["node_x"])
+    X[0], X[1] = X[1].copy(), X[0].copy()        # node 0 and 1 swapped: the first cell is inverted
+    bad["mesh"]["node_x"] = X
+    with pytest.raises(mp.MpmxError) as e:
+        ctx.create_scene(bad)
+    assert e.value.code == mp.E_INVALID_ARG
+    gimp = dict(sc, scheme=dict(sc["scheme"], shape=scenes.SHAPE_GIMP))
+    with pytest.raises(mp.MpmxError) as e:
+        ctx.create_scene(gimp)
+    assert e.value.code == mp.E_INVALID_ARG
+    out = dict(sc, x=sc["x"].copy())
+    out["x"][0] = [-5.0, 0.1, 0.1]
+    with pytest.raises(mp.MpmxError) as e:
+        ctx.create_scene(out)
+    assert e.value.code == mp.E_OUT_OF_MESH
