@@ -18,7 +18,7 @@ stream), the FP64 oracle timed on a bounded sample on the host CPU, and the
 granular column's full 1000-step run.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload batch|column|column_gimp|column_usl|plate|c1|c5|c5_linear|serve]
+                    [--workload batch|column|column_gimp|column_usl|column_iso|plate|c1|c5|c5_linear|serve]
 """
 from __future__ import annotations
 
@@ -90,6 +90,10 @@ def make_workload(name: str):
         sc = scenes.c2()
         sc["scheme"]["algo"] = scenes.USL
         return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, USL"
+    if name == "column_iso":
+        return (scenes.distort(scenes.c2(), amp=0.25, seed=2),
+                "granular column, DP, 2,097,152 particles, 256x128x160 isoparametric mesh (uniform grid moved by a "
+                "smooth field of 0.25 h), linear")
     if name == "plate":
         return (scenes.plate_with_hole(),
                 "plate with a hole (quarter strip), 40,153 particles, 66x41x1 mesh, linear, elastic, PIC")
@@ -724,7 +728,16 @@ def main():
         out["step_algorithmic_GBs"] = step_bytes / (elapsed / args.steps) / 1e9
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        if args.workload in ("c5", "c5_linear"):
+        if args.workload == "column_iso":
+            # the oracle locates isoparametric particles by searching every
+            # cell: a small distorted block stands in
+            from paper_1909_13380_amd import scenes as _sc
+            sub = _sc.distort(_sc.random_block(n_cells=(9, 7, 6), mesh_cells=(14, 11, 9), h=0.05, seed=21,
+                                               material=_sc.drucker_prager()), amp=0.25, seed=2)
+            cb = cpu_baseline(sub, args.cpu_steps * 4)
+            cb["sample"] = (f"first {args.cpu_steps * 4} steps of a distorted Drucker-Prager block "
+                            f"({len(sub['x'])} particles, 14x11x9 isoparametric mesh), FP64, one thread")
+        elif args.workload in ("c5", "c5_linear"):
             from paper_1909_13380_amd import scenes as _sc
             sub = _sc.c5(subsample=True, shape=sc["scheme"]["shape"])
             cb = cpu_baseline(sub, args.cpu_steps)
