@@ -340,6 +340,24 @@ int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene);
  * sums. */
 int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * steps as mpmx_batch_step on scenes created beforehand, with every device
+ * array of the call (scene list, offsets, step counts, reorder flags and
+ * brick-scan partial sums, list of non-empty bricks) in a fixed 4 MiB
+ * scratch array that each GPU holds for the life of the process.  It calls
+ * no hipMalloc or hipFree and creates no graph or event: every step is
+ * launched directly, with the launch shape the context has already tuned
+ * for this batch layout, else the fixed one (mpmx_set_option).  Limits: at
+ * most 4096 scenes, and about one million 4x4x4-cell bricks over all the
+ * scenes' meshes (a brick is counted over the whole mesh, occupied or not);
+ * larger batches fail with MPMX_E_INVALID_ARG and run nothing.  The array
+ * is shared by every call on one GPU and keeps the last call's contents:
+ * calls on the same context are ordered by its stream, but calls from
+ * different contexts on one GPU whose work overlaps race on it.  Other
+ * errors as mpmx_batch_step.  Asynchronous. */
+int mpmx_batch_step_noalloc(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n);
+
 /* ------------------------------------------------------------- serving -- */
 
 /* A request loop over one context: independent scenes arrive at any time,

@@ -136,6 +136,7 @@ struct DevicePool {
 
 struct Scene {
     uint64_t id = 0;
+    uint64_t stamp = 0;      // last allocation-free batch call that listed the scene
     SceneDev h{};
     SceneDev *d = nullptr;
     void *block = nullptr;   // every device array of the scene, from the pool
@@ -169,7 +170,23 @@ struct mpmx_ctx {
     DevicePool pool;
     void *staging = nullptr;               // device staging of host inputs/outputs
     uint64_t staging_cap = 0;
+    // mpmx_batch_step_noalloc: this device's address of the file-scope
+    // scratch array, the host image of its per-call part (sized at creation)
+    // and the call counter that marks the scenes of a call
+    void *scratch = nullptr;
+    std::vector<uint8_t> scratch_img;
+    uint64_t scratch_calls = 0;
 };
+
+// ---------------------------------------------- allocation-free batches --
+// mpmx_batch_step_noalloc keeps the per-call arrays of a batch (scene list,
+// offsets, step counts, reorder flags, brick-scan partial sums, brick list)
+// in this array instead of a block the library allocates.  Each GPU holds
+// its own copy for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns (mpmx_ctx::scratch).
+constexpr size_t kScratchBytes = 4u << 20;
+constexpr int kNoAllocMaxScenes = 4096;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 namespace {
 
@@ -846,6 +863,18 @@ int mpmx_create(mpmx_ctx **out, int device, void *stream)
         }
         ctx->own_stream = true;
     }
+    // this device's copy of the allocation-free scratch array (the device
+    // is current); the host image of its per-call part is sized here, so the
+    // allocation-free call allocates nothing
+    void *sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+        if (ctx->own_stream)
+            (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return MPMX_E_HIP;
+    }
+    ctx->scratch = sp;
+    ctx->scratch_img.assign(40 * (size_t)kNoAllocMaxScenes + 16, 0);
     *out = ctx;
     return MPMX_OK;
 }
@@ -1315,6 +1344,108 @@ int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps
             return rc;
     }
     return run_steps(ctx, ctx->cached_batch, nsteps, 0);
+}
+
+int mpmx_batch_step_noalloc(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n)
+{
+    if (!ctx || n < 0 || (n > 0 && (!scenes || !nsteps)))
+        return MPMX_E_INVALID_ARG;
+    if (n == 0)
+        return MPMX_OK;
+    if (n > kNoAllocMaxScenes)
+        return fail(ctx, MPMX_E_INVALID_ARG, "allocation-free batch: %d scenes, at most %d", n, kNoAllocMaxScenes);
+    const uint64_t stamp = ++ctx->scratch_calls;
+    Scene *first = nullptr;
+    int64_t nbr = 0, np = 0, smax = 0;
+    for (int i = 0; i < n; ++i) {
+        auto it = ctx->scenes.find(scenes[i]);
+        if (it == ctx->scenes.end())
+            return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scenes[i]);
+        Scene *s = it->second.get();
+        if (nsteps[i] < 0)
+            return fail(ctx, MPMX_E_INVALID_ARG, "nsteps[%d] < 0", i);
+        if (s->stamp == stamp)
+            return fail(ctx, MPMX_E_INVALID_ARG, "scene %llu listed twice", (unsigned long long)scenes[i]);
+        s->stamp = stamp;
+        if (first && (s->prec != first->prec || s->shape != first->shape || s->algo != first->algo))
+            return fail(ctx, MPMX_E_INVALID_ARG, "batched scenes must share precision, shape and algorithm");
+        if (!first)
+            first = s;
+        nbr += s->h.nbricks;
+        np += s->h.np;
+        smax = std::max(smax, nsteps[i]);
+    }
+    // the layout of mpmx_batch_step's block, inside the scratch array
+    const size_t n1 = (size_t)n + 1, n8 = 8 * (size_t)n;
+    const size_t o_po = n8, o_bo = o_po + 8 * n1, o_ns = o_bo + 8 * n1, o_ct = o_ns + n8, o_io = o_ct + n8,
+                 o_co = o_io + 4 * n1, o_fl = (o_co + 4 * n1 + 127) & ~(size_t)127, o_sc = o_fl + 4 * BF_WORDS,
+                 o_br = o_sc + 16 * (size_t)kScanChunks, total = o_br + 4 * (size_t)std::max<int64_t>(nbr, 1);
+    if (total > kScratchBytes)
+        return fail(ctx, MPMX_E_INVALID_ARG,
+                    "allocation-free batch: %lld bricks need %zu bytes of scratch, at most %zu (about %zu bricks)",
+                    (long long)nbr, total, kScratchBytes, (kScratchBytes - o_br) / 4);
+    if (smax == 0)
+        return MPMX_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    // the part the host writes: scene descriptors, particle and brick
+    // offsets, step counts, control blocks (the flags are cleared by the
+    // first kernel, the rest is written by the kernels)
+    uint8_t *img = ctx->scratch_img.data();
+    SceneDev **sp = (SceneDev **)img;
+    int64_t *po = (int64_t *)(img + o_po), *bo = (int64_t *)(img + o_bo), *ns = (int64_t *)(img + o_ns);
+    uint32_t **cp = (uint32_t **)(img + o_ct);
+    po[0] = bo[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        Scene *s = ctx->scenes.find(scenes[i])->second.get();
+        sp[i] = s->d;
+        cp[i] = s->h.ctl;
+        ns[i] = nsteps[i];
+        po[i + 1] = po[i] + s->h.np;
+        bo[i + 1] = bo[i] + s->h.nbricks;
+    }
+    uint8_t *base = (uint8_t *)ctx->scratch;
+    HIPCHK(ctx, hipMemcpyAsync(base, img, o_io, hipMemcpyHostToDevice, ctx->stream));
+    Batch b;
+    b.bd.scenes = (SceneDev **)base;
+    b.bd.ctls = (uint32_t *const *)(base + o_ct);
+    b.bd.poffs = (const int64_t *)(base + o_po);
+    b.bd.boffs = (const int64_t *)(base + o_bo);
+    b.bd.ioffs = (uint32_t *)(base + o_io);
+    b.bd.coffs = (uint32_t *)(base + o_co);
+    b.bd.flags = (uint32_t *)(base + o_fl);
+    b.bd.scan = (uint32_t *)(base + o_sc);
+    b.bd.bricks = (uint32_t *)(base + o_br);
+    b.bd.nscenes = n;
+    b.bd.total_particles = np;
+    b.bd.total_bricks = nbr;
+    int64_t maxit = 0;
+    for (int i = 0; i < n; ++i)
+        maxit += ctx->scenes.find(scenes[i])->second->h.max_items;
+    b.bd.max_items = maxit;
+    b.prec = first->prec;
+    b.shape = first->shape;
+    b.algo = first->algo;
+    // a launch shape the context already tuned for this layout, else the
+    // fixed one; no tuning, no graphs, no per-launch events
+    LaunchCfg cfg = ctx->fixed;
+    if (ctx->autotune) {
+        auto it = ctx->tuned.find(layout_key(b));
+        if (it != ctx->tuned.end())
+            cfg = it->second;
+    }
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    ctx->launch_stream = nullptr;
+    BatchDev bd = b.bd;
+    const int64_t *dns = (const int64_t *)(base + o_ns);
+    void *a_begin[] = {&bd, &dns};
+    int rc = launch(ctx, "begin", common_kernels().begin, dim3(1), dim3(1024), a_begin);
+    for (int64_t k = 0; k < smax && !rc; ++k)
+        rc = enqueue_step(ctx, b, cfg, k == 0, nullptr);
+    ctx->prof.on = prof;
+    if (!rc)
+        ctx->last = cfg;
+    return rc;
 }
 
 int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out)

@@ -128,6 +128,7 @@ _SIGNATURES = {
     "mpmx_scene_stats": ([_vp, _u64, _P(Stats)], ctypes.c_int),
     "mpmx_scene_destroy": ([_vp, _u64], ctypes.c_int),
     "mpmx_batch_step": ([_vp, _P(_u64), _P(_i64), ctypes.c_int], ctypes.c_int),
+    "mpmx_batch_step_noalloc": ([_vp, _P(_u64), _P(_i64), ctypes.c_int], ctypes.c_int),
     "mpmx_server_create": ([_vp, _u64, _i64, _P(_vp)], ctypes.c_int),
     "mpmx_server_submit": ([_vp, _P(Request), _P(_u64)], ctypes.c_int),
     "mpmx_server_tick": ([_vp, _P(ctypes.c_int), _P(ctypes.c_int)], ctypes.c_int),
@@ -316,6 +317,15 @@ class Context:
             nsteps = [int(nsteps)] * n
         ns = (_i64 * n)(*[int(k) for k in nsteps])
         self._check(_lib.mpmx_batch_step(self._h, ids, ns, n), "batch_step")
+
+    def batch_step_noalloc(self, scenes: list, nsteps):
+        """mpmx_batch_step_noalloc: the same steps, with no device allocation."""
+        n = len(scenes)
+        ids = (_u64 * n)(*[s.id for s in scenes])
+        if np.isscalar(nsteps):
+            nsteps = [int(nsteps)] * n
+        ns = (_i64 * n)(*[int(k) for k in nsteps])
+        self._check(_lib.mpmx_batch_step_noalloc(self._h, ids, ns, n), "batch_step_noalloc")
 
     # -- profiling
     def set_option(self, option: int, value: int):
