@@ -539,6 +539,36 @@ __device__ inline uint32_t iso_locate(const SceneDev &S, const double x[3], int 
     return 0u;
 }
 
+// ---------------------------------------- anchored GIMP scatter layout --
+// A GIMP particle's 3-node support per axis starts at its cell c - 1 or c.
+// Scattered as it stands, two lanes of a wavefront in neighbouring cells can
+// add to the same node in the same LDS atomic (whenever one support starts
+// at c and the other at c' - 1 = c), and the LDS unit serializes them.  The
+// anchored form gives every particle the 4 nodes c - 1 .. c + 2 per axis
+// (4^3 = 64 slots), with weight 0 at the end its support does not reach:
+// the lanes of a level-major wavefront hold distinct cells, so for one slot
+// they add to distinct nodes.  With the accumulators laid out at row and
+// plane pitches of 12 and 108 entries (FP64) the adds are also free of bank
+// conflicts.  Measured on a probe of this pattern: 8.3 cycles per
+// wavefront-wide FP64 LDS add (2121 per 64 particles) against 31.5 (3407)
+// for the 27-slot form.
+constexpr int kAnchPX = 12, kAnchPXY = 108, kAnchCap = 972;   // 12 x 9 x 9 entries
+
+// The 4 anchored weights (and their derivatives) of one axis from a 3-node
+// support that starts at cell c (d = 1) or c - 1 (d = 0).
+template <typename R>
+__device__ inline void anchor4(const R w[3], const R dw[3], int d, R w4[4], R dw4[4])
+{
+    w4[0] = d ? (R)0 : w[0];
+    w4[1] = d ? w[0] : w[1];
+    w4[2] = d ? w[1] : w[2];
+    w4[3] = d ? w[2] : (R)0;
+    dw4[0] = d ? (R)0 : dw[0];
+    dw4[1] = d ? dw[0] : dw[1];
+    dw4[2] = d ? dw[1] : dw[2];
+    dw4[3] = d ? dw[2] : (R)0;
+}
+
 // Cells a per-step location walk may visit: a particle moves less than a
 // cell per step (CFL), so it ends in its cell or a neighbour of it.
 constexpr int kIsoWalk = 8;
@@ -2035,8 +2065,11 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
     using C = Cache<SH, kStressCacheGather, kStressCacheScatter>;
     constexpr bool GC = C::gather, SC = C::scatter;
     constexpr int GN = C::gnodes, SN = C::snodes;
+    // GIMP force accumulators in the anchored layout (12 x 9 x 9) when the
+    // item's node box fits it, else in the box's own layout
+    constexpr int FCAP = SH == 1 ? kAnchCap : CAP;
     __shared__ R4<R> lv[CAP];
-    __shared__ double lf[3][CAP];
+    __shared__ double lf[3][FCAP];
     __shared__ int red[6 * (T / 64)];
     clear_reorder_flags(B);
     clear_previous<R>(B);
@@ -2086,13 +2119,21 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             continue;
         }
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+        // anchored GIMP scatter: every anchored node of the item's particles
+        // (cells lo..hi, nodes lo - 1 .. hi + 2) lies in the box, whose edges
+        // must fit the anchored layout
+        const bool anch = SH == 1 && t.dim[0] <= kAnchPX && t.dim[1] <= 9 && t.dim[2] <= 9;
+        auto fidx = [&](int q, int i, int j, int k) {
+            return anch ? (i - t.lo[0]) + kAnchPX * (j - t.lo[1]) + kAnchPXY * (k - t.lo[2]) : q;
+        };
         for (int q = threadIdx.x; q < tv; q += blockDim.x) {
             int i, j, k;
             tile_node_small(t, q, i, j, k);
             R v[3];
             node_velocity<R>(S, nb, i, j, k, v);
             lv[q] = R4<R>{v[0], v[1], v[2], (R)0};
-            lf[0][q] = lf[1][q] = lf[2][q] = 0.0;
+            const int fq = fidx(q, i, j, k);
+            lf[0][fq] = lf[1][fq] = lf[2][fq] = 0.0;
         }
         __syncthreads();
         const R dt = cst<R>(S.dt, S.f_dt);
@@ -2279,6 +2320,29 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                                     N * mg1 + B[1][0] * ax + B[1][1] * ay + B[1][2] * az,
                                     N * mg2 + B[2][0] * ax + B[2][1] * ay + B[2][2] * az);
                         }
+            } else if (anch) {
+                // anchored 4 x 4 x 4 slots (see kAnchPX)
+                R w4[3][4], dw4[3][4];
+                for (int a = 0; a < 3; ++a)
+                    anchor4<R>(sp.w[a], sp.dw[a], sp.base[a] == c[a] ? 1 : 0, w4[a], dw4[a]);
+                const int a0 = (c[0] - 1 - t.lo[0]) + kAnchPX * (c[1] - 1 - t.lo[1]) + kAnchPXY * (c[2] - 1 - t.lo[2]);
+                const R mg0 = mp * gx, mg1 = mp * gy, mg2 = mp * gz;
+                for (int k = 0; k < 4; ++k)
+                    for (int j = 0; j < 4; ++j) {
+                        const R wyz = w4[1][j] * w4[2][k], dyz = dw4[1][j] * w4[2][k], ydz = w4[1][j] * dw4[2][k];
+                        for (int i = 0; i < 4; ++i) {
+                            const R N = w4[0][i] * wyz;
+                            const R gxN = dw4[0][i] * wyz, gyN = w4[0][i] * dyz, gzN = w4[0][i] * ydz;
+                            const R f0 = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mg0;
+                            const R f1 = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mg1;
+                            const R f2 = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mg2;
+                            const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
+                            atomicAdd(&lf[0][li], (double)f0);
+                            atomicAdd(&lf[1][li], (double)f1);
+                            atomicAdd(&lf[2][li], (double)f2);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                    }
             } else {
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
@@ -2305,11 +2369,12 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
             atomicOr(&S.ctl[CTL_ERR], bad);
         __syncthreads();
         for (int q = threadIdx.x; q < tv; q += blockDim.x) {
-            const R f0 = (R)lf[0][q], f1 = (R)lf[1][q], f2 = (R)lf[2][q];
-            if (f0 == (R)0 && f1 == (R)0 && f2 == (R)0)
-                continue;
             int i, j, k;
             tile_node_small(t, q, i, j, k);
+            const int fq = fidx(q, i, j, k);
+            const R f0 = (R)lf[0][fq], f1 = (R)lf[1][fq], f2 = (R)lf[2][fq];
+            if (f0 == (R)0 && f1 == (R)0 && f2 == (R)0)
+                continue;
             const uint32_t I = node_id(S, i, j, k);
             addg(nb.f[0], I, f0);
             addg(nb.f[1], I, f1);
@@ -2353,17 +2418,23 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
     // particles are updated before the scatter starts), which admits one
     // more workgroup per CU
     constexpr bool OVERLAY = SH == 1;
-    constexpr int TILE_BYTES = 2 * CAP * (int)sizeof(R4<R>), ACC_BYTES = 4 * CAP * (int)sizeof(double);
+    // home-tile accumulators: edge HD, at row and plane pitches APX, APXY
+    // (GIMP: the anchored layout, see kAnchPX)
+    constexpr int HD = kBrick + 2 + ShapeTraits<SH>::lo + ShapeTraits<SH>::hi;   // home tile edge
+    constexpr int APX = SH == 1 ? kAnchPX : HD, APXY = SH == 1 ? kAnchPXY : HD * HD;
+    constexpr int ACAP = APXY * HD;
+    static_assert(SH != 1 || (HD == 9 && ACAP == kAnchCap), "anchored layout holds the GIMP home tile");
+    constexpr int TILE_BYTES = 2 * CAP * (int)sizeof(R4<R>), ACC_BYTES = 4 * ACAP * (int)sizeof(double);
     __shared__ __attribute__((aligned(16))) char lds[OVERLAY ? (TILE_BYTES > ACC_BYTES ? TILE_BYTES : ACC_BYTES)
                                                              : TILE_BYTES + ACC_BYTES];
     R4<R> *la = (R4<R> *)lds;
     R4<R> *lvn = la + CAP;
-    double (*acc)[CAP] = (double (*)[CAP])(lds + (OVERLAY ? 0 : TILE_BYTES));
+    double (*acc)[ACAP] = (double (*)[ACAP])(lds + (OVERLAY ? 0 : TILE_BYTES));
     __shared__ int red[6 * (T / 64)];
     // the accumulators start at zero, and each item's flush leaves them so
     // (with OVERLAY the tile overwrites them, so every item zeroes them)
     if constexpr (!OVERLAY)
-        for (int q = threadIdx.x; q < CAP; q += blockDim.x)
+        for (int q = threadIdx.x; q < ACAP; q += blockDim.x)
             acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
@@ -2408,9 +2479,29 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 mvd[rr].ok = false;
         // next step's mass and momentum of one particle with support sp:
         // into the home tile's accumulators, or (drifted) global memory
-        auto scatter = [&](const Support<R, SH> &sq, bool inh, R m, const R mvq[3]) {
+        auto scatter = [&](const Support<R, SH> &sq, const int cq[3], bool inh, R m, const R mvq[3]) {
             const Corners hq = corners(S, ht, sq.base);
-            if (inh) {
+            if (SH == 1 && inh) {
+                // anchored 4 x 4 x 4 slots (see kAnchPX); home-tile coordinates
+                // of node c - 1 are c - o + 1 in [0, 5] for a cell in the home region
+                R w4[3][4], dw4[3][4];
+                for (int a = 0; a < 3; ++a)
+                    anchor4<R>(sq.w[a], sq.dw[a], sq.base[a] == cq[a] ? 1 : 0, w4[a], dw4[a]);
+                const int a0 = (cq[0] - 1 - ht.lo[0]) + APX * (cq[1] - 1 - ht.lo[1]) + APXY * (cq[2] - 1 - ht.lo[2]);
+                for (int k = 0; k < 4; ++k)
+                    for (int j = 0; j < 4; ++j) {
+                        const R wyz = w4[1][j] * w4[2][k];
+                        for (int i = 0; i < 4; ++i) {
+                            const R N = w4[0][i] * wyz;
+                            const int li = a0 + i + APX * j + APXY * k;
+                            atomicAdd(&acc[0][li], (double)(N * m));
+                            atomicAdd(&acc[1][li], (double)(N * mvq[0]));
+                            atomicAdd(&acc[2][li], (double)(N * mvq[1]));
+                            atomicAdd(&acc[3][li], (double)(N * mvq[2]));
+                        }
+                        __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                    }
+            } else if (inh) {
                 for (int k = 0; k < NS; ++k)
                     for (int j = 0; j < NS; ++j)
                         for (int i = 0; i < NS; ++i) {
@@ -2596,13 +2687,13 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                                 sp_[n][a] += N * mv[a];
                         }
             } else {
-                scatter(sp, in, mp, mv);
+                scatter(sp, nc, in, mp, mv);
             }
         }
         if constexpr (OVERLAY) {
             // every gather from the tile is done: the same LDS now accumulates
             __syncthreads();
-            for (int q = threadIdx.x; q < CAP; q += blockDim.x)
+            for (int q = threadIdx.x; q < ACAP; q += blockDim.x)
                 acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
             __syncthreads();
 #pragma unroll
@@ -2610,7 +2701,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                 if (mvd[rr].ok) {
                     Support<R, SH> sq;
                     make_support<R, SH>(S, mvd[rr].x, mvd[rr].c, sq);
-                    scatter(sq, mvd[rr].in, mvd[rr].m, mvd[rr].mv);
+                    scatter(sq, mvd[rr].c, mvd[rr].in, mvd[rr].m, mvd[rr].mv);
                 }
         }
         if constexpr (SC)
@@ -2635,7 +2726,6 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         }
         // flush the home-tile entries the moved particles can have touched
         // (their cells' node box), zeroing them for the next item
-        constexpr int HD = kBrick + 2 + ShapeTraits<SH>::lo + ShapeTraits<SH>::hi;   // home tile edge
         const Tile nbx = tile_of_cells<SH>(blo, bhi);
         Tile fb;   // nbx within the home tile, in home-tile coordinates
         for (int a = 0; a < 3; ++a) {
@@ -2646,7 +2736,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         for (int q = threadIdx.x; q < fv; q += blockDim.x) {
             int a, b, c;
             tile_node_small(fb, q, a, b, c);
-            const int li = a + HD * (b + HD * c);
+            const int li = a + APX * b + APXY * c;
             const double m = acc[0][li];
             const int i = ht.lo[0] + a, j = ht.lo[1] + b, k = ht.lo[2] + c;
             if (m != 0.0 && node_in_mesh(S, i, j, k)) {
