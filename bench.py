@@ -543,11 +543,67 @@ def cpu_baseline_scenes(scs: list, steps: int) -> dict:
                       f"particles), first {steps} steps of each, FP64, one thread", "seconds": round(sec, 3)}
 
 
+def _serve_batched(mpmx, ctx, reqs, rate, tick_steps, budget):
+    """The request loop (continuous batching) on one arrival stream: submit
+    each request at its arrival, tick, collect completions.  Returns the
+    latencies (arrival -> result on the host, ms), particle-updates and the
+    span in seconds."""
+    srv = mpmx.Server(ctx, budget, max_tick_steps=tick_steps)
+    n_req = len(reqs)
+    arrivals = [t / rate for t, _, _ in reqs]
+    lat, pu, i, ticks = [], 0, 0, 0
+    t0 = srv.clock()
+    while len(lat) < n_req:
+        now = srv.clock() - t0
+        while i < n_req and arrivals[i] <= now:
+            _, sc, k = reqs[i]
+            srv.submit(sc, k, precision=mpmx.FP32, tag=i)
+            i += 1
+        r, q = srv.tick()
+        ticks += 1
+        for c in srv.poll(256, copy_state=False):
+            if c["status"] != mpmx.OK:
+                raise SystemExit(f"request {c['tag']} failed with status {c['status']}")
+            lat.append(1e3 * (c["t_done"] - t0 - arrivals[c["tag"]]))
+            pu += c["n"] * c["steps_done"]
+        if r == 0 and q == 0 and i < n_req:
+            time.sleep(max(0.0, min(0.002, arrivals[i] - (srv.clock() - t0))))
+    span = srv.clock() - t0
+    srv.close()
+    return lat, pu, span, ticks
+
+
+def _serve_plain(mpmx, ctx, reqs, rate):
+    """The plain path on the same arrivals: one request at a time in arrival
+    order, alone on the GPU (create, step, read back, free)."""
+    import torch
+    n_req = len(reqs)
+    arrivals = [t / rate for t, _, _ in reqs]
+    lat, pu = [], 0
+    t0 = time.perf_counter()
+    for i, (_, sc, k) in enumerate(reqs):
+        wait = arrivals[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        s = ctx.create_scene(sc, precision=mpmx.FP32)
+        s.step(k)
+        s.read()
+        s.destroy()
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t0 - arrivals[i]))
+        pu += len(sc["x"]) * k
+    return lat, pu, time.perf_counter() - t0
+
+
 def run_serve(args):
     """Serving: a Poisson stream of requests from the batched-scene
     generator (seed 4), steps uniform in 100..2000, admitted against a 64 GiB
-    device budget by the library's request loop, final particle state
-    returned to host memory.  Latency is arrival -> result on the host."""
+    device budget by the library's request loop (continuous batching: uploads
+    and read-backs overlap the running steps), final particle state returned
+    to host memory; latency is arrival -> result on the host.  Beside it at
+    every rate, the plain path on the same arrivals (one request at a time,
+    alone on the GPU).  Then one rate of the stream of 2.1M-particle column
+    requests, batched and plain."""
     import torch
     from paper_1909_13380_amd import mpmx, scenes
     n_req = args.requests
@@ -558,33 +614,30 @@ def run_serve(args):
     torch.cuda.init()
     ctx = mpmx.Context(0)
     apply_launch_options(ctx, args)
+    budget = 64 << 30
     results = []
     for rate in rates:
-        srv = mpmx.Server(ctx, 64 << 30, max_tick_steps=args.tick_steps)
-        arrivals = [t / rate for t, _, _ in base]
-        lat, pu, i, ticks = [], 0, 0, 0
-        t0 = srv.clock()
-        while len(lat) < n_req:
-            now = srv.clock() - t0
-            while i < n_req and arrivals[i] <= now:
-                _, sc, k = base[i]
-                srv.submit(sc, k, precision=mpmx.FP32, tag=i)
-                i += 1
-            r, q = srv.tick()
-            ticks += 1
-            for c in srv.poll(256, copy_state=False):
-                if c["status"] != mpmx.OK:
-                    raise SystemExit(f"request {c['tag']} failed with status {c['status']}")
-                lat.append(1e3 * (c["t_done"] - t0 - arrivals[c["tag"]]))
-                pu += c["n"] * c["steps_done"]
-            if r == 0 and q == 0 and i < n_req:
-                time.sleep(max(0.0, min(0.002, arrivals[i] - (srv.clock() - t0))))
-        span = srv.clock() - t0
-        srv.close()
+        lat, pu, span, ticks = _serve_batched(mpmx, ctx, base, rate, args.tick_steps, budget)
         row = {"rate_per_s": rate, "requests": n_req, "seconds": span, "value": pu / span, "ticks": ticks,
                **_percentiles(lat)}
+        if not args.no_plain:
+            plat, ppu, pspan = _serve_plain(mpmx, ctx, base, rate)
+            row["plain"] = {"seconds": pspan, "value": ppu / pspan, **_percentiles(plat)}
         print(f"# rate {rate}/s: {json.dumps(row)}", file=sys.stderr, flush=True)
         results.append(row)
+    col = None
+    if args.column_rate > 0:
+        creqs = scenes.column_requests(1.0, args.column_requests)
+        cpu_total = int(sum(len(sc["x"]) * k for _, sc, k in creqs))
+        lat, pu, span, ticks = _serve_batched(mpmx, ctx, creqs, args.column_rate, args.tick_steps, budget)
+        col = {"workload": f"serving: Poisson stream of {len(creqs)} granular-column requests (2,097,152 particles "
+                           f"each, own jitter seed), 100-2000 steps each, 64 GiB budget",
+               "rate_per_s": args.column_rate, "requests": len(creqs), "seconds": span, "value": pu / span,
+               "ticks": ticks, "particle_updates": cpu_total, **_percentiles(lat)}
+        if not args.no_plain:
+            plat, ppu, pspan = _serve_plain(mpmx, ctx, creqs, args.column_rate)
+            col["plain"] = {"seconds": pspan, "value": ppu / pspan, **_percentiles(plat)}
+        print(f"# column stream: {json.dumps(col)}", file=sys.stderr, flush=True)
     ctx.close()
     best = max(results, key=lambda r: r["value"])
     out = {"metric": METRIC, "value": best["value"], "unit": "particle-updates/s", "n_gpus": 1, "steps": None,
@@ -594,6 +647,8 @@ def run_serve(args):
                                   f"generator (seed 4), 1k-250k particles, 100-2000 steps each, 64 GiB budget",
                       "max_tick_steps": args.tick_steps, "particle_updates_per_rate": total_pu},
            "rates": results}
+    if col is not None:
+        out["column_stream"] = col
     print(json.dumps(out), flush=True)
 
 
@@ -606,7 +661,8 @@ def main():
     ap.add_argument("--no-column", action="store_true",
                     help="--workload batch: skip the full 1000-step run of the granular column")
     ap.add_argument("--no-plain", action="store_true",
-                    help="--workload batch: the batched leg only (no plain leg, latency runs or column), for profiling")
+                    help="--workload batch: the batched leg only (no plain leg, latency runs or column), for profiling; "
+                         "--workload serve: no plain path beside the request loop")
     ap.add_argument("--sort", default="on_demand", choices=["on_demand", "always"])
     ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps of the CPU baseline (batch: 40x this)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -630,6 +686,9 @@ def main():
     ap.add_argument("--rates", default="50,100,150",
                     help="--workload serve: arrival rates (requests/s); about 0.3, 0.6 and 0.9 of the saturated rate")
     ap.add_argument("--tick-steps", type=int, default=64, help="--workload serve: most steps per server tick")
+    ap.add_argument("--column-rate", type=float, default=0.0,
+                    help="--workload serve: also run the stream of 2.1M-particle column requests at this rate (req/s)")
+    ap.add_argument("--column-requests", type=int, default=40, help="--workload serve: column requests")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.summarize:

@@ -292,7 +292,9 @@ int mpmx_scene_bytes(const mpmx_mesh *mesh, const mpmx_scheme *scheme, int64_t n
                      uint64_t *bytes);
 
 /* Create a scene: validate and copy the descriptors, upload the particles,
- * bin them into cells.  *scene receives an id > 0.  A particle outside the
+ * bin them into cells (on the context's second stream, so that the upload
+ * overlaps steps already queued on the context stream; returns when it is
+ * done).  *scene receives an id > 0.  A particle outside the
  * mesh or a non-finite input fails with MPMX_E_OUT_OF_MESH /
  * MPMX_E_NONFINITE and creates nothing.  The kernels address each particle
  * and node field with 32-bit byte offsets, so a scene holds fewer than
@@ -308,7 +310,8 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
 int mpmx_scene_step(mpmx_ctx *ctx, uint64_t scene, int64_t nsteps);
 
 /* Copy the particle state, in the original particle order, to the caller's
- * buffers (synchronises).  Returns MPMX_E_OUT_OF_MESH / MPMX_E_NONFINITE
+ * buffers.  Waits for this scene's queued steps only (steps queued for
+ * other scenes keep running), and returns with the copies done.  Returns MPMX_E_OUT_OF_MESH / MPMX_E_NONFINITE
  * (after copying) if the scene has stopped on that error, and MPMX_E_STATE
  * if it stopped for a reason of the implementation: a work item's particles
  * spread beyond its node tile, or a reorder that gave up waiting (neither
@@ -328,7 +331,7 @@ int mpmx_scene_nodes(mpmx_ctx *ctx, uint64_t scene, double *mass, double *moment
 /* Counters and error bits of a scene (synchronises). */
 int mpmx_scene_stats(mpmx_ctx *ctx, uint64_t scene, mpmx_stats *out);
 
-/* Free a scene (waits for its queued work). */
+/* Free a scene (waits for its own queued work only). */
 int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene);
 
 /* ------------------------------------------------------------- batches -- */
@@ -404,12 +407,17 @@ int mpmx_server_create(mpmx_ctx *ctx, uint64_t budget_bytes, int64_t max_tick_st
  * mpmx_scene_create. */
 int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id);
 
-/* One scheduling round: admit queued requests in arrival order while they
- * fit; advance every resident scene, one batch per (precision, shape,
- * algorithm) group, by the number of steps until the first of them
- * completes (at most max_tick_steps); copy finished scenes to host memory,
- * free them and record their completions.  Synchronises.  Optional outputs:
- * resident and queued request counts after the round. */
+/* One scheduling round, continuous batching: admit queued requests in
+ * arrival order while they fit (their uploads overlap the steps queued by
+ * the previous round); queue the steps of every resident scene, one batch
+ * per (precision, shape, algorithm) group, by the number of steps until the
+ * first of them completes (at least 16, at most max_tick_steps); then copy
+ * to host memory, free and record as complete the scenes whose last steps
+ * the previous round queued (each read waits for that scene's own steps,
+ * while this round's run), or this round's when it queued nothing.
+ * Returns once those reads are done; this round's steps may still run.
+ * Optional outputs: requests resident (not yet complete) and queued after
+ * the round. */
 int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued);
 
 /* Move up to max completions (oldest first) into out[]; *n gets the count.

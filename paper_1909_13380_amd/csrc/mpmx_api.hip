@@ -43,6 +43,17 @@ struct Profiler {
     std::map<std::string, std::pair<int64_t, double>> totals;
 };
 
+// An event recorded on the context stream after a batch's queued steps;
+// shared by the batch and its scenes, destroyed with its last holder.
+struct StepEvent {
+    hipEvent_t e = nullptr;
+    ~StepEvent()
+    {
+        if (e)
+            (void)hipEventDestroy(e);
+    }
+};
+
 // Launch shape of the item kernels: workgroup size (index into
 // kItemThreadChoices) of the stress-side and G2P-side kernels, and
 // workgroups per compute unit of their persistent grid.
@@ -64,6 +75,10 @@ struct Batch {
     uint32_t *d_ioffs = nullptr, *d_coffs = nullptr, *d_flags = nullptr;
     BatchDev bd{};
     int prec = 0, shape = 0, algo = 0;
+    // the last queued steps of this batch (its image is free to rewrite
+    // once they are done)
+    std::shared_ptr<StepEvent> last_use;
+    uint64_t used_at = 0;   // call counter of its last use (the older of two cached batches is rebuilt)
     // executable graph of `gsteps` steps recorded with launch shape gcfg
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
@@ -75,17 +90,21 @@ struct Batch {
         gexec = nullptr;
         gsteps = 0;
     }
-    void release()
+    // the image goes back to the context's device pool (no hipFree, which
+    // would wait for the whole device)
+    template <typename Pool>
+    void release(Pool &pool)
     {
         drop_graph();
         if (dmem)
-            (void)hipFree(dmem);
+            pool.release(dmem);
         dmem = nullptr;
         dcap = 0;
         d_scenes = nullptr;
         d_poffs = d_boffs = d_nsteps = nullptr;
         d_ioffs = d_coffs = d_flags = nullptr;
         ids.clear();
+        last_use.reset();
     }
 };
 
@@ -143,6 +162,11 @@ struct Scene {
     uint64_t bytes = 0;
     int prec = 0, shape = 0, algo = 0;
     Batch single;
+    // the last queued steps of the scene; main_sync: it was last stepped
+    // without an event (the allocation-free call), so waiting for it means
+    // waiting for the whole context stream
+    std::shared_ptr<StepEvent> last;
+    bool main_sync = false;
 };
 
 }  // namespace
@@ -156,7 +180,11 @@ struct mpmx_ctx {
     std::string err;
     uint64_t next_id = 1;
     std::map<uint64_t, std::unique_ptr<Scene>> scenes;
-    Batch cached_batch;
+    Batch cached_batch[2];                 // the two most recent batches of mpmx_batch_step
+    uint64_t batch_calls = 0;
+    // second stream of the context: scene uploads and read-backs, which then
+    // overlap the steps queued on the context stream (default priority)
+    hipStream_t aux = nullptr;
     Profiler prof;
     // launch options
     int graph_steps = 8;
@@ -449,7 +477,7 @@ Scene *find(mpmx_ctx *ctx, uint64_t id)
 
 void free_scene(mpmx_ctx *ctx, Scene *s)
 {
-    s->single.release();
+    s->single.release(ctx->pool);
     ctx->pool.release(s->block);
     s->block = nullptr;
 }
@@ -478,6 +506,10 @@ void *staging(mpmx_ctx *ctx, uint64_t bytes)
 
 int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
 {
+    // the previous image may still be read by this batch's queued steps
+    if (b.last_use)
+        HIPCHK(ctx, hipEventSynchronize(b.last_use->e));
+    b.last_use.reset();
     b.drop_graph();
     const int n = (int)list.size();
     const size_t n1 = (size_t)n + 1;
@@ -503,15 +535,14 @@ int build_batch(mpmx_ctx *ctx, Batch &b, const std::vector<Scene *> &list)
     }
     if (total > b.dcap) {
         if (b.dmem)
-            (void)hipFree(b.dmem);
-        b.dmem = nullptr;
+            ctx->pool.release(b.dmem);
+        b.dmem = ctx->pool.alloc(2 * total);
         b.dcap = 0;
-        HIPCHK(ctx, hipMalloc(&b.dmem, 2 * total));
+        if (!b.dmem)
+            return fail(ctx, MPMX_E_OOM, "batch image of %zu bytes", 2 * total);
         b.dcap = 2 * total;
     }
     uint8_t *base = (uint8_t *)b.dmem;
-    // the previous contents may still be read by queued steps of this batch
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(base, img.data(), total, hipMemcpyHostToDevice));
     b.d_scenes = (SceneDev **)base;
     b.d_poffs = (int64_t *)(base + o_po);
@@ -747,6 +778,53 @@ int record_graph(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, int steps)
     return MPMX_OK;
 }
 
+// Record an event after the steps just queued for b; the batch and each of
+// its scenes keep it, so that reading or freeing a scene waits for its own
+// steps only.
+int mark_queued(mpmx_ctx *ctx, Batch &b)
+{
+    auto ev = std::make_shared<StepEvent>();
+    HIPCHK(ctx, hipEventCreateWithFlags(&ev->e, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventRecord(ev->e, ctx->stream));
+    b.last_use = ev;
+    for (uint64_t id : b.ids) {
+        auto it = ctx->scenes.find(id);
+        if (it != ctx->scenes.end()) {
+            it->second->last = ev;
+            it->second->main_sync = false;
+        }
+    }
+    return MPMX_OK;
+}
+
+// Make stream st wait for the queued steps of scene s.
+int wait_for_scene(mpmx_ctx *ctx, Scene *s, hipStream_t st)
+{
+    if (s->main_sync) {
+        hipEvent_t e = nullptr;
+        HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        hipError_t r = hipEventRecord(e, ctx->stream);
+        if (r == hipSuccess)
+            r = hipStreamWaitEvent(st, e, 0);
+        (void)hipEventDestroy(e);
+        if (r != hipSuccess)
+            return fail(ctx, MPMX_E_HIP, "stream wait: %s", hipGetErrorString(r));
+    } else if (s->last) {
+        HIPCHK(ctx, hipStreamWaitEvent(st, s->last->e, 0));
+    }
+    return MPMX_OK;
+}
+
+// Block the host until the queued steps of scene s are done.
+int host_wait_for_scene(mpmx_ctx *ctx, Scene *s)
+{
+    if (s->main_sync)
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    else if (s->last)
+        HIPCHK(ctx, hipEventSynchronize(s->last->e));
+    return MPMX_OK;
+}
+
 // Queue `steps` steps of every scene of b (scene i: nsteps[i], or `uniform`
 // for all when nsteps is null).  The host never waits on the GPU, except
 // once per batch layout while tuning.
@@ -808,7 +886,7 @@ int run_steps(mpmx_ctx *ctx, Batch &b, const int64_t *nsteps, int64_t uniform)
     for (; left > 0; --left)
         if ((rc = enqueue_step(ctx, b, cfg, false, nullptr)))
             return rc;
-    return MPMX_OK;
+    return mark_queued(ctx, b);
 }
 
 int read_ctl(mpmx_ctx *ctx, Scene *s, uint32_t *ctl)
@@ -863,11 +941,18 @@ int mpmx_create(mpmx_ctx **out, int device, void *stream)
         }
         ctx->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
+        if (ctx->own_stream)
+            (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return MPMX_E_HIP;
+    }
     // this device's copy of the allocation-free scratch array (the device
     // is current); the host image of its per-call part is sized here, so the
     // allocation-free call allocates nothing
     void *sp = nullptr;
     if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+        (void)hipStreamDestroy(ctx->aux);
         if (ctx->own_stream)
             (void)hipStreamDestroy(ctx->stream);
         delete ctx;
@@ -885,10 +970,12 @@ void mpmx_destroy(mpmx_ctx *ctx)
         return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->aux);
     for (auto &kv : ctx->scenes)
         free_scene(ctx, kv.second.get());
     ctx->scenes.clear();
-    ctx->cached_batch.release();
+    for (auto &cb : ctx->cached_batch)
+        cb.release(ctx->pool);
     if (ctx->staging)
         (void)hipFree(ctx->staging);
     ctx->pool.clear();
@@ -900,6 +987,8 @@ void mpmx_destroy(mpmx_ctx *ctx)
         (void)hipEventDestroy(e);
     if (ctx->capture)
         (void)hipStreamDestroy(ctx->capture);
+    if (ctx->aux)
+        (void)hipStreamDestroy(ctx->aux);
     if (ctx->own_stream)
         (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1162,12 +1251,14 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
             HIPCHK(ctx, hipMemcpy(dX, X.data(), 24 * sz.nn, hipMemcpyHostToDevice));
         h.X = (const double *)dX;
     }
+    // uploads go through the second stream, so that they overlap steps
+    // already queued on the context stream
     for (auto &z : zero_ranges)
-        if (ok && hipMemsetAsync(z.first, 0, z.second, ctx->stream) != hipSuccess)
+        if (ok && hipMemsetAsync(z.first, 0, z.second, ctx->aux) != hipSuccess)
             ok = false;
     // the control words below are written with blocking copies: the zeroing
     // must be complete first
-    if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
+    if (ok && hipStreamSynchronize(ctx->aux) != hipSuccess)
         ok = false;
     if (!ok) {
         free_scene(ctx, s);
@@ -1273,10 +1364,10 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         const KernelSet &K = kernel_set(s->prec, s->shape);
         SceneDev *d = s->d;
         void *args[] = {&d, &dx, &dv, &dsig, &dvol, &dmass};
-        if (hipLaunchKernel(K.load, particle_grid(np), dim3(kParticleBlock), args, 0, ctx->stream) != hipSuccess)
+        if (hipLaunchKernel(K.load, particle_grid(np), dim3(kParticleBlock), args, 0, ctx->aux) != hipSuccess)
             ok = false;
     }
-    if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
+    if (ok && hipStreamSynchronize(ctx->aux) != hipSuccess)
         ok = false;
     if (!ok) {
         free_scene(ctx, s);
@@ -1298,6 +1389,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         return rc;
     }
     s->id = ctx->next_id++;
+    s->single.ids.assign(1, s->id);
     *scene_out = s->id;
     ctx->scenes[s->id] = std::move(sc);
     return MPMX_OK;
@@ -1337,13 +1429,19 @@ int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps
         list.push_back(s);
     }
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if (ctx->cached_batch.ids != ids) {
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        int rc = build_batch(ctx, ctx->cached_batch, list);
+    // the two most recent batches stay built: a caller alternating between
+    // batch compositions (the request loop) rebuilds the older one, whose
+    // image its queued steps have most likely finished reading
+    const uint64_t call = ++ctx->batch_calls;
+    int slot = ctx->cached_batch[0].ids == ids ? 0 : (ctx->cached_batch[1].ids == ids ? 1 : -1);
+    if (slot < 0) {
+        slot = ctx->cached_batch[0].used_at <= ctx->cached_batch[1].used_at ? 0 : 1;
+        int rc = build_batch(ctx, ctx->cached_batch[slot], list);
         if (rc)
             return rc;
     }
-    return run_steps(ctx, ctx->cached_batch, nsteps, 0);
+    ctx->cached_batch[slot].used_at = call;
+    return run_steps(ctx, ctx->cached_batch[slot], nsteps, 0);
 }
 
 int mpmx_batch_step_noalloc(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n)
@@ -1443,6 +1541,10 @@ int mpmx_batch_step_noalloc(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t
     for (int64_t k = 0; k < smax && !rc; ++k)
         rc = enqueue_step(ctx, b, cfg, k == 0, nullptr);
     ctx->prof.on = prof;
+    // no event (that would allocate): reading or freeing these scenes waits
+    // for the whole context stream
+    for (int i = 0; i < n; ++i)
+        ctx->scenes.find(scenes[i])->second->main_sync = true;
     if (!rc)
         ctx->last = cfg;
     return rc;
@@ -1457,6 +1559,11 @@ int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out
     if (!s)
         return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
     HIPCHK(ctx, hipSetDevice(ctx->device));
+    // the read runs on the second stream once the scene's own queued steps
+    // are done; later steps of other scenes keep running meanwhile
+    int rc = wait_for_scene(ctx, s, ctx->aux);
+    if (rc)
+        return rc;
     const int64_t np = s->h.np;
     if (np > 0) {
         double *x = out->x, *v = out->v, *sg = out->stress, *vol = out->vol;
@@ -1482,10 +1589,10 @@ int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out
         const KernelSet &K = kernel_set(s->prec, s->shape);
         SceneDev *d = s->d;
         void *args[] = {&d, &dx, &dv, &ds, &dvo, &dc};
-        if (ok && hipLaunchKernel(K.read_out, particle_grid(np), dim3(kParticleBlock), args, 0, ctx->stream) !=
+        if (ok && hipLaunchKernel(K.read_out, particle_grid(np), dim3(kParticleBlock), args, 0, ctx->aux) !=
                       hipSuccess)
             ok = false;
-        if (ok && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        if (ok && hipStreamSynchronize(ctx->aux) != hipSuccess)
             ok = false;
         if (ok && out->mem == MPMX_MEM_HOST) {
             if (x && hipMemcpy(x, dx, 24 * np, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
@@ -1497,10 +1604,9 @@ int mpmx_scene_read(mpmx_ctx *ctx, uint64_t scene, const mpmx_particles_out *out
         if (!ok)
             return fail(ctx, MPMX_E_HIP, "particle read failed");
     }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->aux));
     uint32_t ctl[CTL_WORDS];
-    int rc = read_ctl(ctx, s, ctl);
-    if (rc)
-        return rc;
+    HIPCHK(ctx, hipMemcpy(ctl, s->h.ctl, sizeof(uint32_t) * CTL_WORDS, hipMemcpyDeviceToHost));
     if (ctl[CTL_ERR])
         return fail(ctx, err_code(ctl[CTL_ERR]), "scene stopped on error bits %u", ctl[CTL_ERR]);
     return MPMX_OK;
@@ -1617,11 +1723,17 @@ int mpmx_scene_destroy(mpmx_ctx *ctx, uint64_t scene)
     if (it == ctx->scenes.end())
         return fail(ctx, MPMX_E_NOT_FOUND, "unknown scene %llu", (unsigned long long)scene);
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    if (std::find(ctx->cached_batch.ids.begin(), ctx->cached_batch.ids.end(), scene) != ctx->cached_batch.ids.end()) {
-        ctx->cached_batch.drop_graph();
-        ctx->cached_batch.ids.clear();
-    }
+    // its own queued steps, and reads of its buffers on the second stream
+    int rc = host_wait_for_scene(ctx, it->second.get());
+    if (rc)
+        return rc;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->aux));
+    for (auto &cb : ctx->cached_batch)
+        if (std::find(cb.ids.begin(), cb.ids.end(), scene) != cb.ids.end()) {
+            // keep the image until its queued steps are done (a rebuild waits)
+            cb.drop_graph();
+            cb.ids.clear();
+        }
     free_scene(ctx, it->second.get());
     ctx->scenes.erase(it);
     return MPMX_OK;

@@ -76,7 +76,8 @@ struct mpmx_server {
     uint64_t next_id = 1;
     std::chrono::steady_clock::time_point t0;
     std::deque<Pending> queue;
-    std::vector<Resident> resident;
+    std::vector<Resident> resident;      // scenes with steps still to queue
+    std::vector<Resident> pending;       // every step queued, read back by the next tick
     std::deque<uint64_t> ready;          // completed, not yet polled
     std::map<uint64_t, Done> done;       // completed, not yet released
     double now() const
@@ -278,10 +279,14 @@ int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued)
 {
     if (!srv)
         return MPMX_E_INVALID_ARG;
+    // admission uploads on the context's second stream, overlapping the
+    // steps the previous tick queued
     int rc = admit(srv);
     if (rc)
         return rc;
-    // requests of zero steps complete without stepping
+    // queue this tick's steps: every resident scene, as a batch per group,
+    // by the steps until the first of them completes (at least
+    // kMinTickSteps, at most max_tick)
     int64_t k = srv->max_tick;
     for (auto &r : srv->resident)
         if (r.remaining > 0)
@@ -301,19 +306,27 @@ int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued)
     }
     for (auto &r : srv->resident)
         r.remaining -= std::min(r.remaining, k);
+    // read back the scenes the previous tick finished queuing: each read
+    // waits for that scene's own steps only, while this tick's run
+    std::vector<Resident> done;
+    done.swap(srv->pending);
+    for (auto &r : done)
+        if ((rc = finish(srv, r)))
+            return rc;
     std::vector<Resident> keep;
-    for (auto &r : srv->resident) {
-        if (r.remaining == 0) {
-            rc = finish(srv, r);
-            if (rc)
-                return rc;
-        } else {
-            keep.push_back(r);
-        }
-    }
+    for (auto &r : srv->resident)
+        (r.remaining == 0 ? srv->pending : keep).push_back(r);
     srv->resident.swap(keep);
+    // nothing queued this tick: no later tick to overlap the reads with
+    if (groups.empty() && !srv->pending.empty()) {
+        done.clear();
+        done.swap(srv->pending);
+        for (auto &r : done)
+            if ((rc = finish(srv, r)))
+                return rc;
+    }
     if (n_resident)
-        *n_resident = (int)srv->resident.size();
+        *n_resident = (int)(srv->resident.size() + srv->pending.size());
     if (n_queued)
         *n_queued = (int)srv->queue.size();
     return MPMX_OK;
@@ -349,6 +362,8 @@ void mpmx_server_destroy(mpmx_server *srv)
     if (!srv)
         return;
     for (auto &r : srv->resident)
+        (void)mpmx_scene_destroy(srv->ctx, r.scene);
+    for (auto &r : srv->pending)
         (void)mpmx_scene_destroy(srv->ctx, r.scene);
     delete srv;
 }

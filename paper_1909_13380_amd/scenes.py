@@ -268,6 +268,27 @@ def c4_requests(rate_hz: float, n_requests: int, seed: int = 4, scene_offset: in
     return out
 
 
+def column_requests(rate_hz: float, n_requests: int, seed: int = 4, scene_offset: int = 5000) -> list:
+    """Poisson request stream drawn from the granular column generator (C2's
+    2,097,152-particle Drucker-Prager column): each request is (arrival time
+    in s, scene, step count uniform in 100..2000), every scene with its own
+    jitter seed (scene_offset + request index).  The scenes share every
+    array but the positions."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_requests))
+    steps = rng.integers(100, 2001, size=n_requests)
+    base = c2()
+    h = base["mesh"]["h"]
+    centres = block_positions((0, 48, 0), (64, 80, 128), h, layout="centre")
+    out = []
+    for i in range(n_requests):
+        jr = np.random.default_rng(scene_offset + i)
+        x = centres + jr.uniform(-0.1 * 0.5 * h, 0.1 * 0.5 * h, size=centres.shape)
+        sc = dict(base, x=x, name=f"column_{i}", nsteps=int(steps[i]))
+        out.append((float(t[i]), sc, int(steps[i])))
+    return out
+
+
 # ------------------------------------------------ closed-form test scenes --
 
 def free_body(v0=(0.3, -0.2, 0.1), gravity=GRAVITY, cells=(4, 3, 5), mesh_cells=(16, 16, 16), h=0.1,
