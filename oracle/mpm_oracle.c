@@ -585,6 +585,8 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
         return OM_E_ARG;
     if (mesh->node_x && scheme->shape != OM_SHAPE_LINEAR)
         return OM_E_ARG;
+    if (scheme->algo != OM_USF && scheme->algo != OM_USL && scheme->algo != OM_MUSL)
+        return OM_E_ARG;
     const int32_t shape = scheme->shape;
     const int64_t nn = om_num_nodes(mesh, shape);
     const int64_t nc = om_num_cells(mesh);
@@ -708,6 +710,34 @@ int om_step(const om_mesh *mesh, const om_material *mat, const om_bc *bc,
             strain_increment(&s, grid->vn, dt, deps);
             update_stress(mat, deps, &vol[p], &sig[6 * p]);
         }
+    }
+    /* 9'. MUSL: the updated particle momenta back to the nodes with the
+     * start-of-step shape functions, the nodal velocity of that momentum
+     * under the velocity constraints, and the stress update from it. */
+    if (scheme->algo == OM_MUSL) {
+        double *vr = (double *)calloc(3 * (size_t)nn, sizeof(double));
+        if (!vr) {
+            free(x0);
+            free(pcell);
+            return OM_E_NOMEM;
+        }
+        for (int64_t p = 0; p < n; ++p) {
+            support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
+            for (int q = 0; q < s.count; ++q)
+                for (int a = 0; a < 3; ++a)
+                    vr[3 * s.node[q] + a] += s.N[q] * mass[p] * v[3 * p + a];
+        }
+        for (int64_t I = 0; I < nn; ++I)
+            for (int a = 0; a < 3; ++a)
+                vr[3 * I + a] = grid->m[I] > eps_m ? vr[3 * I + a] / grid->m[I] : 0.0;
+        apply_constraints(mesh, shape, bc, vr, 0);
+        for (int64_t p = 0; p < n; ++p) {
+            double deps[6];
+            support_of(mesh, shape, &x0[3 * p], pcell[p], &s);
+            strain_increment(&s, vr, dt, deps);
+            update_stress(mat, deps, &vol[p], &sig[6 * p]);
+        }
+        free(vr);
     }
     free(x0);
     free(pcell);

@@ -17,6 +17,9 @@
  *     and its nodes are active iff the cell holds a material point; Material
  *     returns the updated stress for a strain increment; the explicit
  *     algorithms are update-stress-first (USF) and update-stress-last (USL);
+ *     the modified USL (MUSL), which strains with the nodal velocity of the
+ *     updated particle momenta mapped back to the nodes, is not in the paper
+ *     and follows Sulsky, Zhou & Schreyer (1995) and Buzzi et al. (2008);
  *     shape functions are linear or GIMP.
  *   - Data structures: 6-component Voigt stress.
  * The paper prints no MPM equations.  The steps are the textbook explicit MPM
@@ -49,7 +52,7 @@ enum {
 enum { OM_LINEAR_ELASTIC = 0, OM_DRUCKER_PRAGER = 1 };
 enum { OM_DP_OUTER = 0, OM_DP_INNER = 1, OM_DP_PLANE_STRAIN = 2 };
 enum { OM_FREE = 0, OM_FIXED = 1, OM_SLIP = 2 };
-enum { OM_USF = 0, OM_USL = 1 };
+enum { OM_USF = 0, OM_USL = 1, OM_MUSL = 2 };
 enum { OM_SHAPE_LINEAR = 0, OM_SHAPE_GIMP = 1 };
 enum { OM_FLIP = 0, OM_PIC = 1 };
 
@@ -96,7 +99,7 @@ typedef struct {
 } om_bc;
 
 typedef struct {
-    int32_t algo;            /* OM_USF or OM_USL */
+    int32_t algo;            /* OM_USF, OM_USL or OM_MUSL */
     int32_t shape;           /* OM_SHAPE_LINEAR or OM_SHAPE_GIMP */
     int32_t velocity_update; /* OM_FLIP or OM_PIC */
     int32_t pad_;

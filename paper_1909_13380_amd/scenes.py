@@ -29,7 +29,7 @@ import numpy as np
 LINEAR_ELASTIC, DRUCKER_PRAGER = 0, 1
 DP_OUTER, DP_INNER, DP_PLANE_STRAIN = 0, 1, 2
 FREE, FIXED, SLIP = 0, 1, 2
-USF, USL = 0, 1
+USF, USL, MUSL = 0, 1, 2
 SHAPE_LINEAR, SHAPE_GIMP = 0, 1
 FLIP, PIC = 0, 1
 

@@ -9,8 +9,11 @@
 * Closed forms: discrete free fall under gravity, rigid translation, FLIP
   momentum invariance, and the fundamental period of a fixed-free elastic
   bar (4L/c; lumped-mass dispersion (2c/h) sin(pi h / 4L)).
-* Algorithm order (code overview: USF vs USL), nodal velocity constraints,
-  cell counts (active cells) and the out-of-mesh error.
+* Algorithm order (code overview: USF vs USL; the modified USL, MUSL, of
+  Sulsky, Zhou & Schreyer 1995), nodal velocity constraints, cell counts
+  (active cells) and the out-of-mesh error.
+* MUSL closed forms: a lone particle's remapped nodal velocity is the same
+  at every node of its support, so it never strains; the bar's period.
 """
 import math
 
@@ -81,7 +84,7 @@ def stiffness(E, nu):
 
 
 @pytest.mark.parametrize("shape", [oracle.SHAPE_LINEAR, oracle.SHAPE_GIMP])
-@pytest.mark.parametrize("algo", [oracle.USF, oracle.USL])
+@pytest.mark.parametrize("algo", [oracle.USF, oracle.USL, oracle.MUSL])
 def test_one_step_equals_brute_force_global_definition(shape, algo):
     sc = scenes.random_block(n_cells=(2, 2, 2), mesh_cells=(5, 4, 4), shape=shape, stress_scale=2e3, seed=5)
     sc["scheme"]["algo"] = algo
@@ -132,6 +135,15 @@ def test_one_step_equals_brute_force_global_definition(shape, algo):
     np.testing.assert_allclose(out["x"], x0 + dt * (N.T @ vn), rtol=0, atol=1e-15)
     if algo == oracle.USL:
         s1, V1 = stress_update(vn)
+    if algo == oracle.MUSL:
+        # the updated particle momenta back to the nodes (same weights), the
+        # nodal velocity of that momentum, then the constraints
+        v1 = v0 + dt * (N.T @ aI)
+        PR = N @ (m[:, None] * v1)
+        vR = np.where(live[:, None], PR / np.where(live, mI, 1.0)[:, None], 0.0)
+        vR[mask] = 0.0
+        s1, V1 = stress_update(vR)
+        assert np.abs(vR - vn).max() > 1e-6 * np.abs(vn).max()    # a different field from USL's
     np.testing.assert_allclose(out["stress"], s1, rtol=1e-9, atol=1e-9 * np.abs(s1).max())
     np.testing.assert_allclose(out["vol"], V1, rtol=1e-13)
 
@@ -225,6 +237,64 @@ def test_elastic_bar_fundamental_period():
     T_h = 2 * np.pi / ((2 * c / h) * np.sin(np.pi * h / (4 * L)))
     assert abs(period / T_h - 1) < 0.005
     assert np.abs(state["v"][:, 1:]).max() < 1e-12     # rollers keep it one-dimensional
+
+
+@pytest.mark.parametrize("shape", [oracle.SHAPE_LINEAR, oracle.SHAPE_GIMP])
+def test_musl_lone_particle_never_strains(shape):
+    """One particle, clear of every wall: its momentum mapped back to the
+    nodes gives each node of its support the particle's own velocity (the
+    weights cancel between momentum and mass), and the gradients of a
+    partition of unity sum to zero, so MUSL leaves its stress and volume
+    unchanged whatever the stress, velocity and gravity, and FLIP moves its
+    velocity by dt g exactly (the internal forces sum to zero over the
+    support).  USL strains the same particle: its nodal accelerations
+    -V sigma grad N_I / (N_I m) differ from node to node."""
+    sc = scenes.random_block(n_cells=(1, 1, 1), mesh_cells=(6, 6, 6), shape=shape, stress_scale=4e3, seed=21,
+                             vel=0.3, bc=scenes.walls(floor=scenes.FREE, sides=scenes.FREE))
+    for k in ("x", "v", "stress", "vol", "mass"):
+        sc[k] = sc[k][:1].copy()
+    sc["x"] = sc["x"] + 2.3 * sc["mesh"]["h"]
+    sc["scheme"]["mass_eps_rel"] = 0.0
+    sc["scheme"]["algo"] = oracle.MUSL
+    dt, g = sc["scheme"]["dt"], np.asarray(sc["scheme"]["gravity"])
+    for n in (1, 5):
+        out = oracle.run(sc, n)
+        np.testing.assert_allclose(out["stress"], sc["stress"], rtol=1e-12, atol=1e-9)
+        np.testing.assert_allclose(out["vol"], sc["vol"], rtol=1e-13)
+        np.testing.assert_allclose(out["v"], sc["v"] + n * dt * g, rtol=1e-12, atol=1e-14)
+    sc["scheme"]["algo"] = oracle.USL
+    out = oracle.run(sc, 1)
+    assert np.abs(out["stress"] - sc["stress"]).max() > 1e-3 * np.abs(sc["stress"]).max()
+
+
+def test_musl_elastic_bar_fundamental_period():
+    """MUSL on the fixed-free bar: the same period as the continuum (4L/c)
+    and the lumped-mass dispersion relation, within the USF bounds."""
+    sc = scenes.elastic_bar(n_cells=20)
+    sc["scheme"]["algo"] = oracle.MUSL
+    L = 20 * sc["mesh"]["h"]
+    c = math.sqrt(sc["material"]["E"] / sc["material"]["rho"])
+    dt = sc["scheme"]["dt"]
+    T = 4 * L / c
+    steps = int(1.3 * T / dt)
+    state = {k: sc[k] for k in ("x", "v", "stress", "vol", "mass")}
+    grid = oracle.Grid(sc["mesh"], oracle.SHAPE_LINEAR)
+    mode = np.sin(np.pi * sc["x"][:, 0] / (2 * L))
+    amp = []
+    for _ in range(steps):
+        state = oracle.run(sc, 1, grid=grid, state=state)
+        amp.append((sc["mass"] * state["v"][:, 0] * mode).sum())
+    amp = np.array(amp)
+    t = dt * np.arange(1, steps + 1)
+    z = [t[i] - amp[i] * (t[i + 1] - t[i]) / (amp[i + 1] - amp[i]) for i in range(steps - 1)
+         if amp[i] > 0 >= amp[i + 1] or amp[i] < 0 <= amp[i + 1]]
+    assert len(z) >= 2
+    period = 2 * (z[1] - z[0])
+    print(f"MUSL period / (4L/c) = {period / T:.5f}", flush=True)
+    assert abs(period / T - 1) < 0.01
+    h = sc["mesh"]["h"]
+    T_h = 2 * np.pi / ((2 * c / h) * np.sin(np.pi * h / (4 * L)))
+    assert abs(period / T_h - 1) < 0.005
 
 
 def test_usf_stress_uses_velocity_before_forces():
