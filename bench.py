@@ -18,7 +18,7 @@ stream), the FP64 oracle timed on a bounded sample on the host CPU, and the
 granular column's full 1000-step run.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload batch|column|column_gimp|column_usl|column_iso|plate|c1|c5|c5_linear|serve]
+                    [--workload batch|column|column_gimp|column_usl|column_musl|column_iso|plate|c1|c5|c5_linear|serve]
 """
 from __future__ import annotations
 
@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ITEM_KERNELS = ("p2g", "stress", "g2p_p2g", "p2g_usl", "g2p_usl", "p2g_musl", "musl_g2p", "musl_stress")
 METRIC = "particle-updates/s (FP32 batched vs plain) at stated error; p50/p99 scene latency"
 
 
@@ -49,8 +50,14 @@ def kernel_bytes(kernel: str, n_particles: int, n_nodes: int) -> int:
         "g2p_p2g": (24 + 12 + 4 + 4) + (24 + 12 + 4),      # read x, v, cell, mass; write x, v, cell
         "p2g_usl": 24 + 12 + 4 + 4 + 24 + 4,
         "g2p_usl": (24 + 12 + 4 + 24 + 4) + (24 + 12 + 4 + 24 + 4),
+        "p2g_musl": 24 + 12 + 4 + 4 + 24 + 4,
+        "musl_g2p": (24 + 12 + 4 + 4) + 12,                 # read x, v, cell, mass; write v
+        "musl_stress": (24 + 4 + 4 + 24) + (24 + 4 + 24 + 4),   # read x, cell, vol, sigma; write x, vol, sigma, cell
     }
-    per_node = {"p2g": 20, "stress": 20 + 12 + 32, "g2p_p2g": 32 + 20, "p2g_usl": 32, "g2p_usl": 32 + 32}
+    # MUSL nodes also carry the remapped momentum r (12 B): cleared by
+    # p2g_musl, written by musl_g2p, read by musl_stress
+    per_node = {"p2g": 20, "stress": 20 + 12 + 32, "g2p_p2g": 32 + 20, "p2g_usl": 32, "g2p_usl": 32 + 32,
+                "p2g_musl": 32 + 12, "musl_g2p": 32 + 12, "musl_stress": 32 + 12 + 32}
     return per_particle.get(kernel, 0) * n_particles + per_node.get(kernel, 0) * n_nodes
 
 
@@ -90,6 +97,10 @@ def make_workload(name: str):
         sc = scenes.c2()
         sc["scheme"]["algo"] = scenes.USL
         return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, USL"
+    if name == "column_musl":
+        sc = scenes.c2()
+        sc["scheme"]["algo"] = scenes.MUSL
+        return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, MUSL"
     if name == "column_iso":
         return (scenes.distort(scenes.c2(), amp=0.25, seed=2),
                 "granular column, DP, 2,097,152 particles, 256x128x160 isoparametric mesh (uniform grid moved by a "
@@ -159,11 +170,12 @@ def _short(name: str) -> str:
 
 def _base(name: str) -> str:
     """The library's name of a kernel instantiation: k_stress<float, 0, 256>
-    is "stress"; k_p2g with the force (USL) is "p2g_usl"."""
+    is "stress"; k_p2g with the force (USL) is "p2g_usl", and with the force
+    and the remap clear (MUSL) "p2g_musl"."""
     base = name.split("<")[0].replace("k_", "")
     targs = [a.strip() for a in name[len(name.split("<")[0]) + 1:-1].split(",")] if "<" in name else []
-    if base == "p2g" and "true" in targs:
-        return "p2g_usl"
+    if base == "p2g" and len(targs) > 2 and targs[2] == "true":
+        return "p2g_musl" if len(targs) > 4 and targs[4] == "true" else "p2g_usl"
     return base
 
 
@@ -210,13 +222,15 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
         launch = bench_line.get("config", {}).get("launch", {})
         want = {"stress": launch.get("stress_threads"), "g2p_p2g": launch.get("g2p_threads"),
                 "p2g": launch.get("g2p_threads"), "p2g_usl": launch.get("stress_threads"),
-                "g2p_usl": launch.get("g2p_threads")}
+                "g2p_usl": launch.get("g2p_threads"), "p2g_musl": launch.get("stress_threads"),
+                "musl_g2p": launch.get("g2p_threads"), "musl_stress": launch.get("g2p_threads")}
         rp = {}
         for r in stats:
             name = _short(r["Name"])
             base = _base(name)
             targs = [a.strip() for a in name[len(name.split("<")[0]) + 1:-1].split(",")] if "<" in name else []
-            if base in want and want[base] is not None and (not targs or targs[-1] != str(want[base])):
+            threads = targs[3] if base in ("p2g", "p2g_usl", "p2g_musl") and len(targs) > 3 else (targs[-1] if targs else "")
+            if base in want and want[base] is not None and threads != str(want[base]):
                 continue
             rp[base] = (float(r["AverageNs"]) / 1e3, name)
         for k, v in sorted(bench_line["kernels"].items()):
@@ -247,13 +261,18 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
             # one entry per kernel: the tuned instantiation when there are several
             tw = (bench_line or {}).get("config", {}).get("launch", {})
             t_use = {"stress": tw.get("stress_threads"), "g2p_p2g": tw.get("g2p_threads"),
-                     "p2g_usl": tw.get("stress_threads"), "g2p_usl": tw.get("g2p_threads")}.get(base)
-            if base in traffic and t_use is not None and not k.rstrip(">").endswith(str(t_use)):
+                     "p2g_usl": tw.get("stress_threads"), "g2p_usl": tw.get("g2p_threads"),
+                     "p2g_musl": tw.get("stress_threads"), "musl_g2p": tw.get("g2p_threads"),
+                     "musl_stress": tw.get("g2p_threads")}.get(base)
+            targs = [a.strip() for a in k[len(k.split("<")[0]) + 1:-1].split(",")] if "<" in k else []
+            threads = targs[3] if base in ("p2g", "p2g_usl", "p2g_musl") and len(targs) > 3 else (targs[-1] if targs else "")
+            if base in traffic and t_use is not None and threads != str(t_use):
                 continue
             traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     fname = out_name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
-                         "column_usl": "step_kernels_column_2m_usl", "plate": "step_kernels_plate_40k",
+                         "column_usl": "step_kernels_column_2m_usl", "column_musl": "step_kernels_column_2m_musl",
+                         "plate": "step_kernels_plate_40k",
                          "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
     with open(os.path.join(ROOT, "profiles", fname + ".txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -281,7 +300,7 @@ def summarize_counters(root: str, workload: str, commands: str, out_name: str):
     means: dict = {}
     for d in sorted(glob.glob(os.path.join(root, "pmc_*"))):
         means.update(_counter_means(d))
-    kernels = sorted({k for k, _ in means if _base(k) in ("stress", "g2p_p2g", "p2g", "p2g_usl", "g2p_usl")})
+    kernels = sorted({k for k, _ in means if _base(k) in ITEM_KERNELS})
     counters = sorted({c for _, c in means})
     lines = [f"# rocprofv3 SQ counters: {desc}", "", "Commands (repository root, rocprofv3 from ROCm 7.2):", ""]
     lines += [f"    {c}" for c in commands.split(";;") if c.strip()] + [""]
@@ -543,12 +562,14 @@ def cpu_baseline_scenes(scs: list, steps: int) -> dict:
                       f"particles), first {steps} steps of each, FP64, one thread", "seconds": round(sec, 3)}
 
 
-def _serve_batched(mpmx, ctx, reqs, rate, tick_steps, budget):
+def _serve_batched(mpmx, ctx, reqs, rate, tick_steps, budget, fill=0):
     """The request loop (continuous batching) on one arrival stream: submit
-    each request at its arrival, tick, collect completions.  Returns the
+    each request at its arrival (particle arrays borrowed, results written to
+    arrays allocated at submit, as the plain path's read allocates them),
+    tick, collect completions.  Returns the
     latencies (arrival -> result on the host, ms), particle-updates and the
-    span in seconds."""
-    srv = mpmx.Server(ctx, budget, max_tick_steps=tick_steps)
+    span in seconds.  fill: the server's occupancy limit (particles; 0 off)."""
+    srv = mpmx.Server(ctx, budget, max_tick_steps=tick_steps, fill_particles=fill)
     n_req = len(reqs)
     arrivals = [t / rate for t, _, _ in reqs]
     lat, pu, i, ticks = [], 0, 0, 0
@@ -557,7 +578,7 @@ def _serve_batched(mpmx, ctx, reqs, rate, tick_steps, budget):
         now = srv.clock() - t0
         while i < n_req and arrivals[i] <= now:
             _, sc, k = reqs[i]
-            srv.submit(sc, k, precision=mpmx.FP32, tag=i)
+            srv.submit(sc, k, precision=mpmx.FP32, tag=i, borrow=True, out=True)
             i += 1
         r, q = srv.tick()
         ticks += 1
@@ -603,7 +624,7 @@ def run_serve(args):
     to host memory; latency is arrival -> result on the host.  Beside it at
     every rate, the plain path on the same arrivals (one request at a time,
     alone on the GPU).  Then one rate of the stream of 2.1M-particle column
-    requests, batched and plain."""
+    requests, batched (without and with the occupancy limit) and plain."""
     import torch
     from paper_1909_13380_amd import mpmx, scenes
     n_req = args.requests
@@ -617,7 +638,7 @@ def run_serve(args):
     budget = 64 << 30
     results = []
     for rate in rates:
-        lat, pu, span, ticks = _serve_batched(mpmx, ctx, base, rate, args.tick_steps, budget)
+        lat, pu, span, ticks = _serve_batched(mpmx, ctx, base, rate, args.tick_steps, budget, args.fill_particles)
         row = {"rate_per_s": rate, "requests": n_req, "seconds": span, "value": pu / span, "ticks": ticks,
                **_percentiles(lat)}
         if not args.no_plain:
@@ -634,6 +655,11 @@ def run_serve(args):
                            f"each, own jitter seed), 100-2000 steps each, 64 GiB budget",
                "rate_per_s": args.column_rate, "requests": len(creqs), "seconds": span, "value": pu / span,
                "ticks": ticks, "particle_updates": cpu_total, **_percentiles(lat)}
+        if args.column_fill > 0:
+            lat, pu, span, ticks = _serve_batched(mpmx, ctx, creqs, args.column_rate, args.tick_steps, budget,
+                                                  args.column_fill)
+            col["filled"] = {"fill_particles": args.column_fill, "seconds": span, "value": pu / span,
+                             "ticks": ticks, **_percentiles(lat)}
         if not args.no_plain:
             plat, ppu, pspan = _serve_plain(mpmx, ctx, creqs, args.column_rate)
             col["plain"] = {"seconds": pspan, "value": ppu / pspan, **_percentiles(plat)}
@@ -645,7 +671,8 @@ def run_serve(args):
            "data": "synthetic",
            "config": {"workload": f"serving: Poisson stream of {n_req} requests per rate from the batched-scene "
                                   f"generator (seed 4), 1k-250k particles, 100-2000 steps each, 64 GiB budget",
-                      "max_tick_steps": args.tick_steps, "particle_updates_per_rate": total_pu},
+                      "max_tick_steps": args.tick_steps, "fill_particles": args.fill_particles,
+                      "particle_updates_per_rate": total_pu},
            "rates": results}
     if col is not None:
         out["column_stream"] = col
@@ -689,6 +716,10 @@ def main():
     ap.add_argument("--column-rate", type=float, default=0.0,
                     help="--workload serve: also run the stream of 2.1M-particle column requests at this rate (req/s)")
     ap.add_argument("--column-requests", type=int, default=40, help="--workload serve: column requests")
+    ap.add_argument("--fill-particles", type=int, default=0,
+                    help="--workload serve: the server's occupancy limit for the batched-scene stream (0: off)")
+    ap.add_argument("--column-fill", type=int, default=2000000,
+                    help="--workload serve: the column stream again with this occupancy limit (0: skip)")
     args = ap.parse_args()
     args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
     if args.summarize:
@@ -771,8 +802,7 @@ def main():
     if prof:
         kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1), "total_ms": v[1]}
                    for k, v in prof.items()}
-        dom = max((k for k in kernels if k in ("p2g", "stress", "g2p_p2g", "p2g_usl", "g2p_usl")),
-                  key=lambda k: kernels[k]["total_ms"])
+        dom = max((k for k in kernels if k in ITEM_KERNELS), key=lambda k: kernels[k]["total_ms"])
         avg_s = kernels[dom]["avg_us"] * 1e-6
         nbytes = kernel_bytes(dom, n, n_nodes)
         achieved = nbytes / avg_s / 1e9
@@ -781,8 +811,10 @@ def main():
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "algorithmic_bytes_per_launch": nbytes}
         out["kernels"] = kernels
-        # the kernels every step runs: USF stress + g2p_p2g, USL p2g_usl + g2p_usl
-        step_kernels = ("p2g_usl", "g2p_usl") if sc["scheme"]["algo"] else ("stress", "g2p_p2g")
+        # the kernels every step runs: USF stress + g2p_p2g, USL p2g_usl +
+        # g2p_usl, MUSL p2g_musl + musl_g2p + musl_stress
+        step_kernels = {0: ("stress", "g2p_p2g"), 1: ("p2g_usl", "g2p_usl"),
+                        2: ("p2g_musl", "musl_g2p", "musl_stress")}[sc["scheme"]["algo"]]
         step_bytes = sum(kernel_bytes(k, n, n_nodes) for k in step_kernels)
         out["step_algorithmic_GBs"] = step_bytes / (elapsed / args.steps) / 1e9
     if not args.no_cpu_baseline:

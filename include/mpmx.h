@@ -14,7 +14,10 @@
  *   - velocity constraints held at nodes (code overview; isoparametric-mesh
  *     section: boundary conditions are applied at the nodes),
  *   - an explicit algorithm, update-stress-first or update-stress-last, and
- *     linear or GIMP shape functions (code overview),
+ *     linear or GIMP shape functions (code overview); beyond the paper, the
+ *     modified update-stress-last (MUSL: the strain increment comes from
+ *     the updated particle momenta mapped back to the nodes; Sulsky, Zhou
+ *     & Schreyer 1995),
  *   - a time step and a step count (benchmark section: 1000 explicit USF
  *     steps);
  * in, and the updated particle state out.
@@ -46,7 +49,7 @@
 extern "C" {
 #endif
 
-#define MPMX_VERSION 2
+#define MPMX_VERSION 3
 
 /* ------------------------------------------------------------ codes ---- */
 enum {
@@ -68,7 +71,7 @@ enum { MPMX_LINEAR_ELASTIC = 0, MPMX_DRUCKER_PRAGER = 1 };
  * plane-strain match. */
 enum { MPMX_DP_OUTER = 0, MPMX_DP_INNER = 1, MPMX_DP_PLANE_STRAIN = 2 };
 enum { MPMX_BC_FREE = 0, MPMX_BC_FIXED = 1, MPMX_BC_SLIP = 2 };
-enum { MPMX_USF = 0, MPMX_USL = 1 };
+enum { MPMX_USF = 0, MPMX_USL = 1, MPMX_MUSL = 2 };
 enum { MPMX_SHAPE_LINEAR = 0, MPMX_SHAPE_GIMP = 1 };
 enum { MPMX_FLIP = 0, MPMX_PIC = 1 };
 enum { MPMX_FP32 = 0, MPMX_FP64 = 1 };
@@ -160,7 +163,7 @@ typedef struct {
 
 typedef struct {
     uint32_t size;
-    int32_t algo;            /* MPMX_USF or MPMX_USL */
+    int32_t algo;            /* MPMX_USF, MPMX_USL or MPMX_MUSL */
     int32_t shape;           /* MPMX_SHAPE_LINEAR or MPMX_SHAPE_GIMP */
     int32_t velocity_update; /* MPMX_FLIP or MPMX_PIC */
     int32_t precision;       /* MPMX_FP32 (x and nodal mass FP64) or MPMX_FP64 */
@@ -251,10 +254,11 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  *                          per CU first), so that the choice is stable
  *                          between runs.  The timed steps are steps of the
  *                          call.  0: use the values below.
- *   MPMX_OPT_STRESS_THREADS  workgroup size of the stress kernel (USL: the
- *                          P2G kernel): 64, 128 or 256.  Setting it, or one
- *                          of the next two, turns autotuning off.
- *   MPMX_OPT_G2P_THREADS   same for the G2P(+P2G) kernel.
+ *   MPMX_OPT_STRESS_THREADS  workgroup size of the stress kernel (USL and
+ *                          MUSL: the P2G kernel): 64, 128 or 256.  Setting
+ *                          it, or one of the next two, turns autotuning off.
+ *   MPMX_OPT_G2P_THREADS   same for the G2P(+P2G) kernel (MUSL: both G2P
+ *                          kernels).
  *   MPMX_OPT_BLOCKS_PER_CU item-kernel workgroups per compute unit, 1..64.
  *   MPMX_OPT_GRAPH_LAUNCHES  read-only: graph launches so far.
  *   MPMX_OPT_TUNE_RUNS     read-only: tuning passes so far.
@@ -361,6 +365,27 @@ int mpmx_batch_step(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps
  * errors as mpmx_batch_step.  Asynchronous. */
 int mpmx_batch_step_noalloc(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t *nsteps, int n);
 
+/* -------------------------------------------------------------- fences -- */
+
+/* A fence marks the work queued so far on the context stream (the steps of
+ * every batch and scene; uploads and read-backs run on the context's second
+ * stream and are not covered).  Not a method of the paper: it lets a host
+ * loop keep a bounded amount of work queued ahead of the GPU and learn,
+ * without blocking, which of it has finished.
+ * mpmx_fence_record: *fence gets the new fence's id.  Errors:
+ * MPMX_E_INVALID_ARG, MPMX_E_HIP. */
+int mpmx_fence_record(mpmx_ctx *ctx, uint64_t *fence);
+
+/* Whether the fence's work has finished.  block = 0: *done = 1 or 0 at once;
+ * block != 0: waits, then *done = 1.  A fence reported done is freed and its
+ * id is no longer valid.  Errors: MPMX_E_INVALID_ARG, MPMX_E_NOT_FOUND
+ * (unknown or already freed id), MPMX_E_HIP. */
+int mpmx_fence_wait(mpmx_ctx *ctx, uint64_t fence, int block, int *done);
+
+/* Free a fence without waiting.  Errors: MPMX_E_INVALID_ARG,
+ * MPMX_E_NOT_FOUND. */
+int mpmx_fence_release(mpmx_ctx *ctx, uint64_t fence);
+
 /* ------------------------------------------------------------- serving -- */
 
 /* A request loop over one context: independent scenes arrive at any time,
@@ -373,9 +398,16 @@ int mpmx_batch_step_noalloc(mpmx_ctx *ctx, const uint64_t *scenes, const int64_t
  * caller creates on the same context are not touched by it. */
 typedef struct mpmx_server mpmx_server;
 
+/* mpmx_request.flags: MPMX_REQ_BORROW keeps the particle arrays (x, v,
+ * stress, vol, mass) by pointer instead of copying them at submit; they must
+ * stay valid and unchanged until the request's completion has been polled.
+ * Descriptors, constraint and force lists and node positions are always
+ * copied. */
+enum { MPMX_REQ_BORROW = 1 };
+
 typedef struct mpmx_request {
     uint32_t size;                       /* sizeof(mpmx_request) */
-    int32_t pad_;
+    uint32_t flags;                      /* MPMX_REQ_* */
     const mpmx_mesh *mesh;
     const mpmx_material *material;
     const mpmx_bc *bc;
@@ -383,6 +415,11 @@ typedef struct mpmx_request {
     const mpmx_particles *particles;     /* MPMX_MEM_HOST */
     int64_t nsteps;                      /* >= 0 */
     uint64_t tag;                        /* returned in the completion */
+    /* optional caller-owned host buffers (MPMX_MEM_HOST; x, v, stress, vol
+     * required, cell optional) that receive the final state; they must stay
+     * valid until the completion has been polled.  NULL: the server holds
+     * the state until mpmx_server_release. */
+    const mpmx_particles_out *out;
 } mpmx_request;
 
 typedef struct mpmx_completion {
@@ -392,8 +429,9 @@ typedef struct mpmx_completion {
     uint64_t tag;
     int64_t n;                           /* particles */
     int64_t steps_done;
-    /* final state in the original particle order, host memory owned by the
-     * server until mpmx_server_release: x, v (n x 3), stress (n x 6), vol */
+    /* final state in the original particle order: x, v (n x 3), stress
+     * (n x 6), vol; the request's output buffers, or host memory owned by the
+     * server until mpmx_server_release */
     const double *x, *v, *stress, *vol;
     double t_submit, t_admit, t_done;    /* seconds, mpmx_server_clock */
 } mpmx_completion;
@@ -402,20 +440,31 @@ typedef struct mpmx_completion {
  * steps one tick runs.  Errors: MPMX_E_INVALID_ARG. */
 int mpmx_server_create(mpmx_ctx *ctx, uint64_t budget_bytes, int64_t max_tick_steps, mpmx_server **out);
 
-/* Queue a request; its inputs are copied before return.  *id identifies it.
+/* Admission by occupancy: while the resident scenes that still have steps
+ * to run hold at least `particles` particles, tick admits nothing more, so
+ * requests wait in arrival order instead of sharing the GPU with scenes
+ * that already fill it (sharing slows each of them and lengthens every
+ * latency).  A request is admitted whatever its size when no such scene is
+ * resident.  0 (the default) turns the limit off.  Errors:
+ * MPMX_E_INVALID_ARG (srv NULL or particles < 0). */
+int mpmx_server_set_fill(mpmx_server *srv, int64_t particles);
+
+/* Queue a request; its inputs are copied before return (the particle
+ * arrays are only kept by pointer with MPMX_REQ_BORROW).  *id identifies it.
  * MPMX_E_BUDGET if the scene alone exceeds the budget; descriptor errors as
  * mpmx_scene_create. */
 int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id);
 
 /* One scheduling round, continuous batching: admit queued requests in
- * arrival order while they fit (their uploads overlap the steps queued by
- * the previous round); queue the steps of every resident scene, one batch
- * per (precision, shape, algorithm) group, by the number of steps until the
- * first of them completes (at least 16, at most max_tick_steps); then copy
- * to host memory, free and record as complete the scenes whose last steps
- * the previous round queued (each read waits for that scene's own steps,
- * while this round's run), or this round's when it queued nothing.
- * Returns once those reads are done; this round's steps may still run.
+ * arrival order while they fit the budget and the fill limit (their uploads
+ * overlap the steps already queued); queue the steps of every resident
+ * scene, one batch per (precision, shape, algorithm) group, by the number of
+ * steps until the first of them completes (at least 16, at most
+ * max_tick_steps), and record a fence after them; then, oldest round first,
+ * copy to host memory, free and record as complete the scenes whose last
+ * steps a finished round queued.  The host stays at most two rounds ahead
+ * of the GPU: a round that leaves three unfinished waits for the oldest, and
+ * a round that queues nothing waits for the oldest unfinished one.
  * Optional outputs: requests resident (not yet complete) and queued after
  * the round. */
 int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued);

@@ -5,6 +5,7 @@
 // is a fixed sequence of launches over a BatchDev (one scene, or many):
 //   reorder (its last workgroup runs the step control) -> stress -> g2p_p2g   (USF)
 //   reorder -> p2g_usl -> g2p_usl                                              (USL)
+//   reorder -> p2g_musl -> musl_g2p -> musl_stress                             (MUSL)
 // plus one p2g at the start of a USF call for scenes whose node buffer is
 // not yet filled.  The reorder kernel goes straight to the step control
 // unless a scene flagged a reorder; all counts the kernels need live in
@@ -204,6 +205,9 @@ struct mpmx_ctx {
     void *scratch = nullptr;
     std::vector<uint8_t> scratch_img;
     uint64_t scratch_calls = 0;
+    // fences (mpmx_fence_*): events on the context stream, by id
+    std::map<uint64_t, hipEvent_t> fences;
+    uint64_t next_fence = 1;
 };
 
 // ---------------------------------------------- allocation-free batches --
@@ -334,7 +338,8 @@ Sizes sizes_of(const mpmx_mesh *m, int shape, int prec, int64_t np)
 uint64_t align_up(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 
 // Device bytes of a scene; the allocation below follows the same list.
-uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = false, bool iso = false)
+uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = false, bool iso = false,
+                     bool remap = false)
 {
     uint64_t b = 0;
     const uint64_t R = s.real;
@@ -353,6 +358,8 @@ uint64_t scene_bytes(const Sizes &s, int64_t np, bool extra_bc, bool force = fal
         b += align_up(24 * (uint64_t)s.nn);
     if (iso)
         b += align_up(24 * (uint64_t)s.nn);
+    if (remap)
+        b += align_up(3 * R * s.nn);
     return b;
 }
 
@@ -432,7 +439,7 @@ int validate(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material *mat, con
     }
     if (!sch || sch->size < sizeof(mpmx_scheme))
         return fail(ctx, MPMX_E_INVALID_ARG, "scheme descriptor missing or too small");
-    if ((sch->algo != MPMX_USF && sch->algo != MPMX_USL) ||
+    if ((sch->algo != MPMX_USF && sch->algo != MPMX_USL && sch->algo != MPMX_MUSL) ||
         (sch->shape != MPMX_SHAPE_LINEAR && sch->shape != MPMX_SHAPE_GIMP) ||
         (sch->velocity_update != MPMX_FLIP && sch->velocity_update != MPMX_PIC) ||
         (sch->precision != MPMX_FP32 && sch->precision != MPMX_FP64) ||
@@ -623,16 +630,20 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
         HIPCHK(ctx, hipEventRecord(ev[0], st));
     if (b.algo == MPMX_USF)
         rc = launch(ctx, "stress", K.stress[cfg.t_stress], ig, ts, a_bd);
-    else
+    else if (b.algo == MPMX_USL)
         rc = launch(ctx, "p2g_usl", K.p2g_usl[cfg.t_stress], ig, ts, a_bd);
+    else
+        rc = launch(ctx, "p2g_musl", K.p2g_musl[cfg.t_stress], ig, ts, a_bd);
     if (rc)
         return rc;
     if (ev)
         HIPCHK(ctx, hipEventRecord(ev[1], st));
     if (b.algo == MPMX_USF)
         rc = launch(ctx, "g2p_p2g", K.g2p_p2g[cfg.t_g2p], ig, tg, a_bd);
-    else
+    else if (b.algo == MPMX_USL)
         rc = launch(ctx, "g2p_usl", K.g2p_usl[cfg.t_g2p], ig, tg, a_bd);
+    else if (!(rc = launch(ctx, "musl_g2p", K.musl_g2p[cfg.t_g2p], ig, tg, a_bd)))
+        rc = launch(ctx, "musl_stress", K.musl_stress[cfg.t_g2p], ig, tg, a_bd);
     if (rc)
         return rc;
     if (ev)
@@ -976,6 +987,9 @@ void mpmx_destroy(mpmx_ctx *ctx)
     ctx->scenes.clear();
     for (auto &cb : ctx->cached_batch)
         cb.release(ctx->pool);
+    for (auto &kv : ctx->fences)
+        (void)hipEventDestroy(kv.second);
+    ctx->fences.clear();
     if (ctx->staging)
         (void)hipFree(ctx->staging);
     ctx->pool.clear();
@@ -1108,7 +1122,7 @@ int mpmx_scene_bytes(const mpmx_mesh *mesh, const mpmx_scheme *scheme, int64_t n
     if (rc)
         return rc;
     Sizes s = sizes_of(mesh, scheme->shape, scheme->precision, n_particles);
-    *bytes = scene_bytes(s, n_particles, false, false, mesh->node_x != nullptr);
+    *bytes = scene_bytes(s, n_particles, false, false, mesh->node_x != nullptr, scheme->algo == MPMX_MUSL);
     return MPMX_OK;
 }
 
@@ -1161,7 +1175,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     SceneDev &h = s->h;
     // one block of exactly scene_bytes(); the arrays are carved in the order
     // scene_bytes() counts them
-    const uint64_t total = scene_bytes(sz, np, extra, force, iso);
+    const uint64_t total = scene_bytes(sz, np, extra, force, iso, sch->algo == MPMX_MUSL);
     s->block = ctx->pool.alloc(total);
     if (!s->block)
         return fail(ctx, MPMX_E_OOM, "device allocation of %llu bytes failed", (unsigned long long)total);
@@ -1214,6 +1228,8 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
     h.tstep = (Tile *)need(dalloc(sizeof(Tile) * (uint64_t)sz.max_items, true), 1);
     h.ctl = (uint32_t *)need(dalloc(4 * CTL_WORDS, true), 1);
     s->d = (SceneDev *)need(dalloc(sizeof(SceneDev), false), 1);
+    if (sch->algo == MPMX_MUSL)   // zero at creation; each step clears what the previous one wrote
+        h.nr = need(dalloc(3 * R * sz.nn, true), 1);
     if (extra) {
         std::vector<uint8_t> mask(sz.nn, 0);
         std::vector<double> val(3 * sz.nn, 0.0), fv(force ? 3 * sz.nn : 0, 0.0);
@@ -1712,6 +1728,60 @@ int mpmx_scene_stats(mpmx_ctx *ctx, uint64_t scene, mpmx_stats *out)
     out->active_cells = active;
     out->error_bits = ctl[CTL_ERR];
     out->device_bytes = s->bytes;
+    return MPMX_OK;
+}
+
+int mpmx_fence_record(mpmx_ctx *ctx, uint64_t *fence)
+{
+    if (!ctx || !fence)
+        return MPMX_E_INVALID_ARG;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipEvent_t e = nullptr;
+    HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const hipError_t r = hipEventRecord(e, ctx->stream);
+    if (r != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return fail(ctx, MPMX_E_HIP, "fence record: %s", hipGetErrorString(r));
+    }
+    *fence = ctx->next_fence++;
+    ctx->fences[*fence] = e;
+    return MPMX_OK;
+}
+
+int mpmx_fence_wait(mpmx_ctx *ctx, uint64_t fence, int block, int *done)
+{
+    if (!ctx || !done)
+        return MPMX_E_INVALID_ARG;
+    auto it = ctx->fences.find(fence);
+    if (it == ctx->fences.end())
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown fence %llu", (unsigned long long)fence);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (block) {
+        HIPCHK(ctx, hipEventSynchronize(it->second));
+    } else {
+        const hipError_t r = hipEventQuery(it->second);
+        if (r == hipErrorNotReady) {
+            *done = 0;
+            return MPMX_OK;
+        }
+        if (r != hipSuccess)
+            return fail(ctx, MPMX_E_HIP, "fence query: %s", hipGetErrorString(r));
+    }
+    (void)hipEventDestroy(it->second);
+    ctx->fences.erase(it);
+    *done = 1;
+    return MPMX_OK;
+}
+
+int mpmx_fence_release(mpmx_ctx *ctx, uint64_t fence)
+{
+    if (!ctx)
+        return MPMX_E_INVALID_ARG;
+    auto it = ctx->fences.find(fence);
+    if (it == ctx->fences.end())
+        return fail(ctx, MPMX_E_NOT_FOUND, "unknown fence %llu", (unsigned long long)fence);
+    (void)hipEventDestroy(it->second);
+    ctx->fences.erase(it);
     return MPMX_OK;
 }
 

@@ -126,6 +126,7 @@ struct SceneDev {
     double *nm[2];
     void *np_[2];   // momentum p[3][nn]
     void *nf[2];    // force f[3][nn]
+    void *nr;       // MUSL: the updated particle momenta mapped back, r[3][nn]; null otherwise
     // sort scratch
     uint32_t *cnt, *cstart, *rank, *perm;
     uint32_t *bcnt, *bitem, *bstart, *istart;

@@ -961,6 +961,37 @@ __device__ inline void clear_previous(const BatchDev &B)
     }
 }
 
+// MUSL: zero the remap array of every active MUSL scene over the boxes of
+// the other node buffer's items, the only nodes the previous step's remap
+// wrote.
+template <typename R>
+__device__ inline void clear_remap_previous(const BatchDev &B)
+{
+    const int64_t total = B.coffs[B.nscenes];
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
+        const ItemRef r = item_ref(B.coffs, B, g);
+        const SceneDev S = load_scene(r.S);
+        if (!scene_active(S) || !S.nr)
+            continue;
+        const int other = (int)uni(S.ctl[CTL_NBUF]) ^ 1;
+        const Tile t = pick(S.tiles, other)[r.it];
+        GLOBAL R *NR = gp((R *)S.nr);
+        const uint32_t nn = (uint32_t)S.nn;
+        const int vol = t.dim[0] * t.dim[1] * t.dim[2];
+        for (int q = threadIdx.x; q < vol; q += blockDim.x) {
+            int i, j, k;
+            if (t.fits)
+                tile_node_small(t, q, i, j, k);
+            else
+                tile_node(t, q, i, j, k);
+            const uint32_t I = node_id(S, i, j, k);
+            for (int a = 0; a < 3; ++a)
+                stg(NR, a * nn + I, (R)0);
+        }
+    }
+}
+
 // ----------------------------------------------------- load / read out --
 
 // Inputs are row-major doubles (n x 3, n x 6, n); fills particle buffer 0,
@@ -1915,8 +1946,9 @@ __device__ inline Parts<R> parts(const SceneDev &S, int cur)
 
 // Nodal mass and momentum into the step's node buffer (first step of a call;
 // USF scenes whose buffer is already filled skip it); with WITH_FORCE also
-// the nodal force from the current stress and volume (USL, every step).
-template <typename R, int SH, bool WITH_FORCE, int T>
+// the nodal force from the current stress and volume (USL and MUSL, every
+// step); with REMAP (MUSL) it also zeroes the previous step's remap.
+template <typename R, int SH, bool WITH_FORCE, int T, bool REMAP = false>
 __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
@@ -1925,6 +1957,8 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
     __shared__ double acc[NACC][CAP];
     __shared__ int red[6 * (T / 64)];
     clear_reorder_flags(B);
+    if constexpr (REMAP)
+        clear_remap_previous<R>(B);
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
     for (int64_t g = ir.first; g < ir.end; g += ir.step) {
@@ -2877,6 +2911,241 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
     }
 }
 
+// MUSL, after p2g_usl: particle velocity (FLIP or PIC) from the nodal
+// acceleration and updated velocity, then the updated particle momenta back
+// to the nodes through the same start-of-step shape functions, summed in the
+// scene's remap array.  Positions move in k_musl_stress, which evaluates
+// the same shape functions again.
+template <typename R, int SH, int T>
+__global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
+{
+    constexpr int NS = ShapeTraits<SH>::NS;
+    constexpr int CAP = ShapeTraits<SH>::cap;
+    __shared__ R4<R> la[CAP];
+    __shared__ R4<R> lvn[CAP];
+    __shared__ double acc[3][CAP];
+    const int64_t total = B.ioffs[B.nscenes];
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
+        const ItemRef r = item_ref(B.ioffs, B, g);
+        const SceneDev S = load_scene(r.S);
+        if (!scene_active(S))
+            continue;
+        const Item item = uni_struct(S.items[r.it]);
+        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Tile t = pick(S.tiles, buf)[r.it];
+        if (!t.fits)
+            continue;
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const Parts<R> P = parts<R>(S, cur);
+        const NodeBuf<R> nb = node_buf<R>(S, buf);
+        const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+        load_update_tile<R>(S, nb, t, la, lvn);
+        for (int q = threadIdx.x; q < tv; q += blockDim.x)
+            acc[0][q] = acc[1][q] = acc[2][q] = 0.0;
+        __syncthreads();
+        const R dt = cst<R>(S.dt, S.f_dt);
+        const int pic = S.vel_update == 1;
+        uint32_t err = 0;
+        for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
+            const uint32_t p = item.start + q;
+            const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            int c[3];
+            unpack_cell(ldg(P.cell, p), c);
+            Support<R, SH> sp;
+            make_support<R, SH>(S, xp, c, sp);
+            const Corners cn = corners(S, t, sp.base);
+            R dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+            for (int k = 0; k < NS; ++k)
+                for (int j = 0; j < NS; ++j)
+                    for (int i = 0; i < NS; ++i) {
+                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                        const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                        const R4<R> a = la[li];
+                        const R4<R> u = lvn[li];
+                        dv[0] += N * a.x;
+                        dv[1] += N * a.y;
+                        dv[2] += N * a.z;
+                        vp[0] += N * u.x;
+                        vp[1] += N * u.y;
+                        vp[2] += N * u.z;
+                        if constexpr (SH == 1)
+                            if (i == NS - 1)
+                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
+                    }
+            const R mp = ldg(P.mass, p);
+            R mv[3];
+            for (int a = 0; a < 3; ++a) {
+                const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
+                stg(P.v[a], p, nva);
+                mv[a] = mp * nva;
+                if (!isfinite(nva))
+                    err |= ERR_NONFINITE;
+            }
+            for (int k = 0; k < NS; ++k)
+                for (int j = 0; j < NS; ++j)
+                    for (int i = 0; i < NS; ++i) {
+                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                        const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                        atomicAdd(&acc[0][li], (double)(N * mv[0]));
+                        atomicAdd(&acc[1][li], (double)(N * mv[1]));
+                        atomicAdd(&acc[2][li], (double)(N * mv[2]));
+                    }
+        }
+        if (err)
+            atomicOr(&S.ctl[CTL_ERR], err);
+        __syncthreads();
+        GLOBAL R *NR = gp((R *)S.nr);
+        const uint32_t nn = (uint32_t)S.nn;
+        for (int q = threadIdx.x; q < tv; q += blockDim.x) {
+            const double r0 = acc[0][q], r1 = acc[1][q], r2 = acc[2][q];
+            if (r0 == 0.0 && r1 == 0.0 && r2 == 0.0)
+                continue;
+            int i, j, k;
+            tile_node_small(t, q, i, j, k);
+            const uint32_t I = node_id(S, i, j, k);
+            addg(NR, I, (R)r0);
+            addg(NR, nn + I, (R)r1);
+            addg(NR, 2 * nn + I, (R)r2);
+        }
+        __syncthreads();
+    }
+}
+
+// MUSL, after k_musl_g2p: the nodal velocity of the remapped momenta (over
+// the step's nodal mass, with the velocity constraints) gives the strain
+// increment, volume and stress update; the position moves by the
+// interpolated updated nodal velocity of the grid update; new cell, error
+// and reorder flags.  Zeroes the previous step's node buffer.
+template <typename R, int SH, int T>
+__global__ void __launch_bounds__(T) k_musl_stress(BatchDev B)
+{
+    constexpr int NS = ShapeTraits<SH>::NS;
+    constexpr int CAP = ShapeTraits<SH>::cap;
+    __shared__ R4<R> lvn[CAP];
+    __shared__ R4<R> lvr[CAP];
+    clear_previous<R>(B);
+    const int64_t total = B.ioffs[B.nscenes];
+    const ItemRange ir = item_range(total);
+    for (int64_t g = ir.first; g < ir.end; g += ir.step) {
+        const ItemRef r = item_ref(B.ioffs, B, g);
+        const SceneDev S = load_scene(r.S);
+        if (!scene_active(S))
+            continue;
+        const Item item = uni_struct(S.items[r.it]);
+        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Tile t = pick(S.tiles, buf)[r.it];
+        if (!t.fits)
+            continue;
+        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const Parts<R> P = parts<R>(S, cur);
+        const NodeBuf<R> nb = node_buf<R>(S, buf);
+        int o[3];
+        brick_origin(S, item.brick, o);
+        {
+            const GLOBAL R *NR = gp((const R *)S.nr);
+            const uint32_t nn = (uint32_t)S.nn;
+            const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+            for (int q = threadIdx.x; q < tv; q += blockDim.x) {
+                int i, j, k;
+                tile_node_small(t, q, i, j, k);
+                const uint32_t I = node_id(S, i, j, k);
+                R a[3], vn[3], vr[3];
+                node_update<R>(S, nb, i, j, k, a, vn);
+                const R pr[3] = {ldg(NR, I), ldg(NR, nn + I), ldg(NR, 2 * nn + I)};
+                velocity_from_raw<R>(S, ldg(nb.m, I), pr, i, j, k, vr);
+                lvn[q] = R4<R>{vn[0], vn[1], vn[2], (R)0};
+                lvr[q] = R4<R>{vr[0], vr[1], vr[2], (R)0};
+            }
+        }
+        __syncthreads();
+        const R dt = cst<R>(S.dt, S.f_dt);
+        uint32_t err = 0, drift = 0, lost = 0;
+        for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
+            const uint32_t p = item.start + q;
+            double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            int c[3];
+            unpack_cell(ldg(P.cell, p), c);
+            Support<R, SH> sp;
+            make_support<R, SH>(S, xp, c, sp);
+            const Corners cn = corners(S, t, sp.base);
+            R vp[3] = {0, 0, 0};
+            R L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int k = 0; k < NS; ++k)
+                for (int j = 0; j < NS; ++j)
+                    for (int i = 0; i < NS; ++i) {
+                        const R wyz = sp.w[1][j] * sp.w[2][k];
+                        const R N = sp.w[0][i] * wyz;
+                        R gxN = sp.dw[0][i] * wyz;
+                        R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
+                        R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
+                        to_dx<R, SH>(sp, gxN, gyN, gzN);
+                        const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                        const R4<R> u = lvn[li];
+                        const R4<R> w = lvr[li];
+                        vp[0] += N * u.x;
+                        vp[1] += N * u.y;
+                        vp[2] += N * u.z;
+                        L[0][0] += w.x * gxN;
+                        L[0][1] += w.x * gyN;
+                        L[0][2] += w.x * gzN;
+                        L[1][0] += w.y * gxN;
+                        L[1][1] += w.y * gyN;
+                        L[1][2] += w.y * gzN;
+                        L[2][0] += w.z * gxN;
+                        L[2][1] += w.z * gyN;
+                        L[2][2] += w.z * gzN;
+                        if constexpr (SH == 1)
+                            if (i == NS - 1)
+                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
+                    }
+            for (int a = 0; a < 3; ++a) {
+                xp[a] += S.dt * (double)vp[a];
+                stg(P.x[a], p, xp[a]);
+            }
+            const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
+                             dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
+            stg(P.vol, p, ldg(P.vol, p) * ((R)1 + de[0] + de[1] + de[2]));
+            R sg[6];
+            for (int k = 0; k < 6; ++k)
+                sg[k] = ldg(P.sig[k], p);
+            constitutive<R>(S, de, sg);
+            for (int k = 0; k < 6; ++k) {
+                stg(P.sig[k], p, sg[k]);
+                if (!isfinite(sg[k]))
+                    err |= ERR_NONFINITE;
+            }
+            int nc[3];
+            uint32_t e;
+            if constexpr (SH == 2) {
+                double rr[3];
+                IsoCell k;
+                for (int a = 0; a < 3; ++a)
+                    nc[a] = c[a];
+                e = iso_locate(S, xp, nc, rr, k, kIsoWalk);
+            } else {
+                e = locate(S, xp, nc);
+            }
+            if (e) {
+                err |= e;
+                lost += (e & ERR_OUT_OF_MESH) ? 1u : 0u;
+                continue;
+            }
+            stg(P.cell, p, pack_cell(nc));
+            drift |= in_home(nc, o) ? 0u : 1u;
+        }
+        if (err)
+            atomicOr(&S.ctl[CTL_ERR], err);
+        if (lost)
+            atomicAdd(&S.ctl[CTL_LOST], lost);
+        if (drift || (S.sort_always && threadIdx.x == 0)) {
+            S.ctl[CTL_NEED_SORT] = 1u;
+            B.flags[BF_ANY_SORT] = 1u;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace mpmx
 
 // --------------------------------------------------- host launch table --
@@ -2894,6 +3163,9 @@ static void set_items(KernelSet &k)
     k.g2p_p2g[TI] = (const void *)&k_g2p_p2g<R, SH, T>;
     k.p2g_usl[TI] = (const void *)&k_p2g<R, SH, true, T>;
     k.g2p_usl[TI] = (const void *)&k_g2p_usl<R, SH, T>;
+    k.p2g_musl[TI] = (const void *)&k_p2g<R, SH, true, T, true>;
+    k.musl_g2p[TI] = (const void *)&k_musl_g2p<R, SH, T>;
+    k.musl_stress[TI] = (const void *)&k_musl_stress<R, SH, T>;
 }
 
 template <typename R, int SH>

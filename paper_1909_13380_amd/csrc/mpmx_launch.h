@@ -21,6 +21,9 @@ struct KernelSet {
     const void *g2p_p2g[kNumItemThreadChoices];  // (BatchDev)
     const void *p2g_usl[kNumItemThreadChoices];  // (BatchDev)
     const void *g2p_usl[kNumItemThreadChoices];  // (BatchDev)
+    const void *p2g_musl[kNumItemThreadChoices];     // (BatchDev)
+    const void *musl_g2p[kNumItemThreadChoices];     // (BatchDev)
+    const void *musl_stress[kNumItemThreadChoices];  // (BatchDev)
 };
 
 struct CommonKernels {

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -35,6 +36,9 @@ struct Pending {
     std::vector<double> force_value;
     std::vector<double> node_x;   // isoparametric mesh nodes (empty: uniform)
     std::vector<double> x, v, stress, vol, mass;
+    mpmx_particles borrowed{};    // MPMX_REQ_BORROW: the caller's arrays
+    bool borrow = false;
+    mpmx_particles_out out{};     // caller's output buffers (out.size == 0: none)
 };
 
 struct Resident {
@@ -42,11 +46,12 @@ struct Resident {
     int64_t n = 0, nsteps = 0, remaining = 0;
     double t_submit = 0.0, t_admit = 0.0;
     std::tuple<int, int, int> group;
+    mpmx_particles_out out{};     // caller's output buffers (out.size == 0: none)
 };
 
 struct Done {
     mpmx_completion c{};
-    std::vector<double> x, v, stress, vol;
+    std::unique_ptr<double[]> x, v, stress, vol;   // unless the request gave output buffers
 };
 
 // Device bytes a request occupies once admitted.
@@ -73,11 +78,16 @@ struct mpmx_server {
     mpmx_ctx *ctx = nullptr;
     uint64_t budget = 0, used = 0;
     int64_t max_tick = 0;
+    int64_t fill = 0;                    // admission stops at this many active particles (0: off)
     uint64_t next_id = 1;
     std::chrono::steady_clock::time_point t0;
     std::deque<Pending> queue;
     std::vector<Resident> resident;      // scenes with steps still to queue
-    std::vector<Resident> pending;       // every step queued, read back by the next tick
+    struct Round {
+        uint64_t fence = 0;              // after the round's steps
+        std::vector<Resident> last;      // scenes whose last steps the round queued
+    };
+    std::deque<Round> rounds;            // queued rounds not yet known finished, oldest first
     std::deque<uint64_t> ready;          // completed, not yet polled
     std::map<uint64_t, Done> done;       // completed, not yet released
     double now() const
@@ -93,21 +103,30 @@ namespace {
 // single steps when completions are close together.
 constexpr int64_t kMinTickSteps = 16;
 
+// Rounds the host may keep queued ahead of the GPU: enough that the GPU
+// never waits for the host between rounds, few enough that a request
+// arriving now joins the batch within a couple of rounds.
+constexpr size_t kMaxAhead = 2;
+
 int finish(mpmx_server *srv, Resident &r)
 {
     Done d;
     const size_t n = (size_t)r.n;
-    d.x.resize(3 * n);
-    d.v.resize(3 * n);
-    d.stress.resize(6 * n);
-    d.vol.resize(n);
-    mpmx_particles_out out{};
-    out.size = sizeof out;
-    out.mem = MPMX_MEM_HOST;
-    out.x = d.x.data();
-    out.v = d.v.data();
-    out.stress = d.stress.data();
-    out.vol = d.vol.data();
+    mpmx_particles_out out = r.out;
+    if (!out.size) {   // the server's own arrays (never zero-filled: the read writes every element)
+        d.x.reset(new (std::nothrow) double[3 * n]);
+        d.v.reset(new (std::nothrow) double[3 * n]);
+        d.stress.reset(new (std::nothrow) double[6 * n]);
+        d.vol.reset(new (std::nothrow) double[n]);
+        if (n && (!d.x || !d.v || !d.stress || !d.vol))
+            return MPMX_E_OOM;
+        out.size = sizeof out;
+        out.mem = MPMX_MEM_HOST;
+        out.x = d.x.get();
+        out.v = d.v.get();
+        out.stress = d.stress.get();
+        out.vol = d.vol.get();
+    }
     const int status = mpmx_scene_read(srv->ctx, r.scene, &out);
     if (status == MPMX_E_HIP || status == MPMX_E_INVALID_ARG || status == MPMX_E_NOT_FOUND)
         return status;
@@ -129,32 +148,41 @@ int finish(mpmx_server *srv, Resident &r)
     d.c.t_submit = r.t_submit;
     d.c.t_admit = r.t_admit;
     d.c.t_done = srv->now();
+    d.c.x = out.x;
+    d.c.v = out.v;
+    d.c.stress = out.stress;
+    d.c.vol = out.vol;
     srv->ready.push_back(r.id);
     srv->done[r.id] = std::move(d);
-    Done &k = srv->done[r.id];
-    k.c.x = k.x.data();
-    k.c.v = k.v.data();
-    k.c.stress = k.stress.data();
-    k.c.vol = k.vol.data();
     return MPMX_OK;
 }
 
-// Admit from the head of the queue while the next request fits.
+// Admit from the head of the queue while the next request fits the budget
+// and the scenes still stepping hold fewer particles than the fill limit.
 int admit(mpmx_server *srv)
 {
+    int64_t active = 0;
+    for (const auto &r : srv->resident)
+        active += r.n;
     while (!srv->queue.empty()) {
         Pending &p = srv->queue.front();
         if (srv->used + p.bytes > srv->budget)
             break;
+        if (srv->fill > 0 && !srv->resident.empty() && active >= srv->fill)
+            break;
         mpmx_particles parts{};
-        parts.size = sizeof parts;
-        parts.mem = MPMX_MEM_HOST;
-        parts.n = p.n;
-        parts.x = p.x.data();
-        parts.v = p.v.data();
-        parts.stress = p.stress.empty() ? nullptr : p.stress.data();
-        parts.vol = p.vol.data();
-        parts.mass = p.mass.data();
+        if (p.borrow) {
+            parts = p.borrowed;
+        } else {
+            parts.size = sizeof parts;
+            parts.mem = MPMX_MEM_HOST;
+            parts.n = p.n;
+            parts.x = p.x.data();
+            parts.v = p.v.data();
+            parts.stress = p.stress.empty() ? nullptr : p.stress.data();
+            parts.vol = p.vol.data();
+            parts.mass = p.mass.data();
+        }
         p.bc.node = p.bc_node.data();
         p.bc.axis = p.bc_axis.data();
         p.bc.value = p.bc_value.data();
@@ -191,7 +219,9 @@ int admit(mpmx_server *srv)
         r.t_submit = p.t_submit;
         r.t_admit = srv->now();
         r.group = std::make_tuple(p.sch.precision, p.sch.shape, p.sch.algo);
+        r.out = p.out;
         srv->used += p.bytes;
+        active += p.n;
         srv->resident.push_back(r);
         srv->queue.pop_front();
     }
@@ -217,6 +247,14 @@ int mpmx_server_create(mpmx_ctx *ctx, uint64_t budget_bytes, int64_t max_tick_st
     return MPMX_OK;
 }
 
+int mpmx_server_set_fill(mpmx_server *srv, int64_t particles)
+{
+    if (!srv || particles < 0)
+        return MPMX_E_INVALID_ARG;
+    srv->fill = particles;
+    return MPMX_OK;
+}
+
 double mpmx_server_clock(const mpmx_server *srv) { return srv ? srv->now() : 0.0; }
 
 int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id)
@@ -234,6 +272,12 @@ int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id)
     if (req->bc->n_extra < 0 || (req->bc->n_extra > 0 && (!req->bc->node || !req->bc->axis || !req->bc->value)))
         return MPMX_E_INVALID_ARG;
     if (req->bc->n_force < 0 || (req->bc->n_force > 0 && (!req->bc->force_node || !req->bc->force_value)))
+        return MPMX_E_INVALID_ARG;
+    if ((req->flags & ~(uint32_t)MPMX_REQ_BORROW) != 0)
+        return MPMX_E_INVALID_ARG;
+    const mpmx_particles_out *o = req->out;
+    if (o && (o->size < sizeof(mpmx_particles_out) || o->mem != MPMX_MEM_HOST ||
+              (pp->n > 0 && (!o->x || !o->v || !o->stress || !o->vol))))
         return MPMX_E_INVALID_ARG;
     uint64_t bytes = 0;
     int rc = request_bytes(req->mesh, req->scheme, req->bc, pp->n, &bytes);
@@ -264,12 +308,20 @@ int mpmx_server_submit(mpmx_server *srv, const mpmx_request *req, uint64_t *id)
     p.force_node.assign(req->bc->force_node, req->bc->force_node + nf);
     p.force_value.assign(req->bc->force_value, req->bc->force_value + 3 * nf);
     const size_t n = (size_t)pp->n;
-    p.x.assign(pp->x, pp->x + 3 * n);
-    p.v.assign(pp->v, pp->v + 3 * n);
-    if (pp->stress)
-        p.stress.assign(pp->stress, pp->stress + 6 * n);
-    p.vol.assign(pp->vol, pp->vol + n);
-    p.mass.assign(pp->mass, pp->mass + n);
+    if (req->flags & MPMX_REQ_BORROW) {
+        p.borrow = true;
+        p.borrowed = *pp;
+        p.borrowed.size = sizeof(mpmx_particles);
+    } else {
+        p.x.assign(pp->x, pp->x + 3 * n);
+        p.v.assign(pp->v, pp->v + 3 * n);
+        if (pp->stress)
+            p.stress.assign(pp->stress, pp->stress + 6 * n);
+        p.vol.assign(pp->vol, pp->vol + n);
+        p.mass.assign(pp->mass, pp->mass + n);
+    }
+    if (o)
+        p.out = *o;
     srv->queue.push_back(std::move(p));
     *id = srv->queue.back().id;
     return MPMX_OK;
@@ -280,11 +332,11 @@ int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued)
     if (!srv)
         return MPMX_E_INVALID_ARG;
     // admission uploads on the context's second stream, overlapping the
-    // steps the previous tick queued
+    // steps already queued
     int rc = admit(srv);
     if (rc)
         return rc;
-    // queue this tick's steps: every resident scene, as a batch per group,
+    // queue this round's steps: every resident scene, as a batch per group,
     // by the steps until the first of them completes (at least
     // kMinTickSteps, at most max_tick)
     int64_t k = srv->max_tick;
@@ -304,29 +356,42 @@ int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued)
         if (rc)
             return rc;
     }
-    for (auto &r : srv->resident)
-        r.remaining -= std::min(r.remaining, k);
-    // read back the scenes the previous tick finished queuing: each read
-    // waits for that scene's own steps only, while this tick's run
-    std::vector<Resident> done;
-    done.swap(srv->pending);
-    for (auto &r : done)
-        if ((rc = finish(srv, r)))
+    if (!groups.empty()) {
+        mpmx_server::Round round;
+        if ((rc = mpmx_fence_record(srv->ctx, &round.fence)))
             return rc;
-    std::vector<Resident> keep;
-    for (auto &r : srv->resident)
-        (r.remaining == 0 ? srv->pending : keep).push_back(r);
-    srv->resident.swap(keep);
-    // nothing queued this tick: no later tick to overlap the reads with
-    if (groups.empty() && !srv->pending.empty()) {
-        done.clear();
-        done.swap(srv->pending);
-        for (auto &r : done)
+        std::vector<Resident> keep;
+        for (auto &r : srv->resident) {
+            r.remaining -= std::min(r.remaining, k);
+            (r.remaining == 0 ? round.last : keep).push_back(r);
+        }
+        srv->resident.swap(keep);
+        srv->rounds.push_back(std::move(round));
+    }
+    // finish rounds oldest first: those already finished, after waiting for
+    // the oldest while more than kMaxAhead are queued or when this round
+    // queued nothing
+    bool wait = groups.empty();
+    while (!srv->rounds.empty()) {
+        const bool block = wait || srv->rounds.size() > kMaxAhead;
+        int done = 0;
+        if ((rc = mpmx_fence_wait(srv->ctx, srv->rounds.front().fence, block ? 1 : 0, &done)))
+            return rc;
+        if (!done)
+            break;
+        wait = false;
+        mpmx_server::Round round = std::move(srv->rounds.front());
+        srv->rounds.pop_front();
+        for (auto &r : round.last)
             if ((rc = finish(srv, r)))
                 return rc;
     }
-    if (n_resident)
-        *n_resident = (int)(srv->resident.size() + srv->pending.size());
+    if (n_resident) {
+        size_t waiting = 0;
+        for (auto &rd : srv->rounds)
+            waiting += rd.last.size();
+        *n_resident = (int)(srv->resident.size() + waiting);
+    }
     if (n_queued)
         *n_queued = (int)srv->queue.size();
     return MPMX_OK;
@@ -363,8 +428,11 @@ void mpmx_server_destroy(mpmx_server *srv)
         return;
     for (auto &r : srv->resident)
         (void)mpmx_scene_destroy(srv->ctx, r.scene);
-    for (auto &r : srv->pending)
-        (void)mpmx_scene_destroy(srv->ctx, r.scene);
+    for (auto &rd : srv->rounds) {
+        for (auto &r : rd.last)
+            (void)mpmx_scene_destroy(srv->ctx, r.scene);
+        (void)mpmx_fence_release(srv->ctx, rd.fence);
+    }
     delete srv;
 }
 

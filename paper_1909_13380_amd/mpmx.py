@@ -38,7 +38,7 @@ OK = 0
 E_INVALID_ARG, E_OOM, E_BUDGET, E_OUT_OF_MESH, E_NONFINITE, E_HIP, E_AGAIN, E_NOT_FOUND, E_STATE = \
     -1, -2, -3, -4, -5, -6, -7, -8, -9
 LINEAR_ELASTIC, DRUCKER_PRAGER = 0, 1
-USF, USL = 0, 1
+USF, USL, MUSL = 0, 1, 2
 SHAPE_LINEAR, SHAPE_GIMP = 0, 1
 FLIP, PIC = 0, 1
 FP32, FP64 = 0, 1
@@ -96,8 +96,12 @@ class Stats(ctypes.Structure):
 
 
 class Request(ctypes.Structure):
-    _fields_ = [("size", _u32), ("pad_", _i32), ("mesh", _P(Mesh)), ("material", _P(Material)), ("bc", _P(Bc)),
-                ("scheme", _P(Scheme)), ("particles", _P(Particles)), ("nsteps", _i64), ("tag", _u64)]
+    _fields_ = [("size", _u32), ("flags", _u32), ("mesh", _P(Mesh)), ("material", _P(Material)), ("bc", _P(Bc)),
+                ("scheme", _P(Scheme)), ("particles", _P(Particles)), ("nsteps", _i64), ("tag", _u64),
+                ("out", _P(ParticlesOut))]
+
+
+REQ_BORROW = 1
 
 
 class Completion(ctypes.Structure):
@@ -135,6 +139,10 @@ _SIGNATURES = {
     "mpmx_server_poll": ([_vp, _P(Completion), ctypes.c_int, _P(ctypes.c_int)], ctypes.c_int),
     "mpmx_server_release": ([_vp, _u64], ctypes.c_int),
     "mpmx_server_clock": ([_vp], _d),
+    "mpmx_server_set_fill": ([_vp, _i64], ctypes.c_int),
+    "mpmx_fence_record": ([_vp, _P(_u64)], ctypes.c_int),
+    "mpmx_fence_wait": ([_vp, _u64, ctypes.c_int, _P(ctypes.c_int)], ctypes.c_int),
+    "mpmx_fence_release": ([_vp, _u64], ctypes.c_int),
     "mpmx_server_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGNATURES.items():
@@ -318,6 +326,19 @@ class Context:
         ns = (_i64 * n)(*[int(k) for k in nsteps])
         self._check(_lib.mpmx_batch_step(self._h, ids, ns, n), "batch_step")
 
+    def fence(self) -> int:
+        """mpmx_fence_record: a fence after the steps queued so far."""
+        f = _u64()
+        self._check(_lib.mpmx_fence_record(self._h, ctypes.byref(f)), "fence_record")
+        return int(f.value)
+
+    def fence_done(self, fence: int, block: bool = False) -> bool:
+        """mpmx_fence_wait: True once the fence's work has finished (the fence
+        is then freed); with block, waits for it."""
+        d = ctypes.c_int(0)
+        self._check(_lib.mpmx_fence_wait(self._h, int(fence), 1 if block else 0, ctypes.byref(d)), "fence_wait")
+        return bool(d.value)
+
     def batch_step_noalloc(self, scenes: list, nsteps):
         """mpmx_batch_step_noalloc: the same steps, with no device allocation."""
         n = len(scenes)
@@ -419,12 +440,21 @@ class Server:
     """Request loop over a context (mpmx_server_*): submit scenes at any
     time, call tick() to admit and advance them, poll() for finished ones."""
 
-    def __init__(self, ctx: Context, budget_bytes: int, max_tick_steps: int = 256):
+    def __init__(self, ctx: Context, budget_bytes: int, max_tick_steps: int = 256, fill_particles: int = 0):
         self.ctx = ctx
         self._h = _vp()
         rc = _lib.mpmx_server_create(ctx._h, int(budget_bytes), int(max_tick_steps), ctypes.byref(self._h))
         if rc != OK:
             raise MpmxError(rc, "server_create")
+        self._held = {}   # request id -> (borrowed inputs, output arrays) until polled
+        if fill_particles:
+            self.set_fill(fill_particles)
+
+    def set_fill(self, particles: int):
+        """Admission waits while scenes still stepping hold >= particles (0: off)."""
+        rc = _lib.mpmx_server_set_fill(self._h, int(particles))
+        if rc != OK:
+            raise MpmxError(rc, "server_set_fill")
 
     def _check(self, rc: int, what: str):
         if rc != OK:
@@ -434,7 +464,12 @@ class Server:
     def clock(self) -> float:
         return float(_lib.mpmx_server_clock(self._h))
 
-    def submit(self, scene: dict, nsteps: int, precision: int = FP32, tag: int = 0) -> int:
+    def submit(self, scene: dict, nsteps: int, precision: int = FP32, tag: int = 0, borrow: bool = False,
+               out: bool = False) -> int:
+        """Queue a request.  borrow: the server keeps the particle arrays by
+        pointer (this object holds them until the completion is polled); out:
+        the final state goes to arrays allocated here (returned by poll)
+        instead of the server's own."""
         keep = []
         n = len(scene["x"])
         arrs = [_host_f64(scene["x"], (n, 3)), _host_f64(scene["v"], (n, 3)),
@@ -450,10 +485,22 @@ class Server:
         mat = _material(scene["material"])
         cbc = _bc(scene["bc"], keep)
         sch = _scheme(scene["scheme"], precision, SORT_ON_DEMAND)
-        req = Request(ctypes.sizeof(Request), 0, ctypes.pointer(mesh), ctypes.pointer(mat), ctypes.pointer(cbc),
-                      ctypes.pointer(sch), ctypes.pointer(parts), int(nsteps), int(tag))
+        outs, pout = None, None
+        if out:
+            outs = {"x": np.empty((n, 3)), "v": np.empty((n, 3)), "stress": np.empty((n, 6)), "vol": np.empty(n)}
+            po = ParticlesOut()
+            po.size = ctypes.sizeof(ParticlesOut)
+            po.mem = MEM_HOST
+            po.x, po.v, po.stress, po.vol = [outs[k].ctypes.data for k in ("x", "v", "stress", "vol")]
+            po.cell = None
+            pout = ctypes.pointer(po)
+        req = Request(ctypes.sizeof(Request), REQ_BORROW if borrow else 0, ctypes.pointer(mesh),
+                      ctypes.pointer(mat), ctypes.pointer(cbc), ctypes.pointer(sch), ctypes.pointer(parts),
+                      int(nsteps), int(tag), pout)
         rid = _u64()
         self._check(_lib.mpmx_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)), "server_submit")
+        if borrow or out:
+            self._held[int(rid.value)] = (arrs if borrow else None, outs)
         return int(rid.value)
 
     def tick(self) -> tuple[int, int]:
@@ -472,7 +519,10 @@ class Server:
             d = {"request": int(c.request), "tag": int(c.tag), "status": int(c.status), "n": int(c.n),
                  "steps_done": int(c.steps_done), "t_submit": c.t_submit, "t_admit": c.t_admit,
                  "t_done": c.t_done}
-            if copy_state and c.n > 0 and c.x:
+            _, outs = self._held.pop(int(c.request), (None, None))
+            if copy_state and outs is not None and c.status == OK:
+                d.update(outs)
+            elif copy_state and c.n > 0 and c.x:
                 k = int(c.n)
                 d["x"] = np.ctypeslib.as_array(c.x, shape=(k, 3)).copy()
                 d["v"] = np.ctypeslib.as_array(c.v, shape=(k, 3)).copy()
@@ -486,6 +536,7 @@ class Server:
         if self._h:
             _lib.mpmx_server_destroy(self._h)
             self._h = _vp()
+        getattr(self, "_held", {}).clear()
 
     def __del__(self):
         try:

@@ -23,7 +23,7 @@ def test_library_exports_every_declared_function(mpmx):
     lib = ctypes.CDLL(mpmx.LIBPATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert mpmx.version() == 2
+    assert mpmx.version() == 3
 
 
 def test_header_constants_match_the_binding(mpmx):
@@ -75,6 +75,15 @@ def test_scene_bytes_is_pure_and_grows_with_size(mpmx):
     col = {"mesh": {"n": (256, 128, 160), "origin": (0, 0, 0), "h": 0.01}, "scheme": scenes.scheme(2e-5)}
     b = mpmx.scene_bytes(col, mpmx.FP32, n_particles=2_097_152)
     assert 500e6 < b < 900e6
+    # MUSL scenes add one array of remapped nodal momenta (3 components)
+    nn = 257 * 129 * 161
+    for prec, R in ((mpmx.FP32, 4), (mpmx.FP64, 8)):
+        usl = dict(col, scheme=dict(col["scheme"], algo=mpmx.USL))
+        musl = dict(col, scheme=dict(col["scheme"], algo=mpmx.MUSL))
+        extra = mpmx.scene_bytes(musl, prec, n_particles=1000) - mpmx.scene_bytes(usl, prec, n_particles=1000)
+        assert extra == (3 * R * nn + 255) // 256 * 256
+    with pytest.raises(mpmx.MpmxError):
+        mpmx.scene_bytes(dict(col, scheme=dict(col["scheme"], algo=3)), mpmx.FP32, n_particles=10)
 
 
 def test_invalid_descriptors_are_rejected(mpmx):
@@ -114,6 +123,13 @@ def test_server_queue_without_a_gpu(mpmx):
     assert mpmx._lib.mpmx_server_create(placeholder, 0, 16, ctypes.byref(h)) == mpmx.E_INVALID_ARG
     assert mpmx._lib.mpmx_server_create(placeholder, need, 0, ctypes.byref(h)) == mpmx.E_INVALID_ARG
     assert mpmx._lib.mpmx_server_create(placeholder, need, 16, ctypes.byref(h)) == mpmx.OK
+    assert mpmx._lib.mpmx_server_set_fill(h, -1) == mpmx.E_INVALID_ARG
+    assert mpmx._lib.mpmx_server_set_fill(None, 100) == mpmx.E_INVALID_ARG
+    assert mpmx._lib.mpmx_server_set_fill(h, 0) == mpmx.OK
+    f, d = ctypes.c_uint64(0), ctypes.c_int(0)
+    assert mpmx._lib.mpmx_fence_record(None, ctypes.byref(f)) == mpmx.E_INVALID_ARG
+    assert mpmx._lib.mpmx_fence_wait(None, 1, 0, ctypes.byref(d)) == mpmx.E_INVALID_ARG
+    assert mpmx._lib.mpmx_fence_release(None, 1) == mpmx.E_INVALID_ARG
 
     class _Ctx:
         _h = placeholder

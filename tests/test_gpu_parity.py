@@ -92,6 +92,9 @@ MATERIALS = {"le": scenes.elastic(), "dp": scenes.drucker_prager(), "dpc": scene
              "dpps": scenes.drucker_prager(psi_deg=5, c=1e3, cone=scenes.DP_PLANE_STRAIN)}
 
 
+ALGO_NAMES = {0: "usf", 1: "usl", 2: "musl"}
+
+
 # ------------------------------------------------------------- binning --
 
 @pytest.mark.parametrize("which", ["c1", "column_small", "ragged"])
@@ -122,7 +125,7 @@ def test_binning_is_bit_exact_on_identical_positions(ctx, mp, which):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [0, 1])
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 @pytest.mark.parametrize("mat", ["le", "dp", "dpc", "dpi", "dpps"])
 def test_one_step_nodes_and_particles_match_oracle(ctx, mp, prec, shape, algo, mat):
     sc = block(shape=shape, material=MATERIALS[mat], algo=algo)
@@ -138,7 +141,7 @@ def test_one_step_nodes_and_particles_match_oracle(ctx, mp, prec, shape, algo, m
     ref = oracle.run(sc, 1)
     g = ref["grid"]
     tol = 1e-9 if prec == "fp64" else 2e-5
-    name = f"{prec}/{'gimp' if shape else 'linear'}/{'usl' if algo else 'usf'}/{mat}"
+    name = f"{prec}/{'gimp' if shape else 'linear'}/{ALGO_NAMES[algo]}/{mat}"
     for k, a, b in (("m", nodes["m"], g.m), ("p", nodes["p"], g.p), ("f", nodes["f"], g.f)):
         e = rel(a, b)
         print(f"[{name}] nodal {k}: {e:.3e}", flush=True)
@@ -753,10 +756,11 @@ def test_two_contexts_reordering_at_once(mp):
 
 
 @pytest.mark.parametrize("shape", [0, 1])
-def test_usl_many_steps_with_reorders(ctx, mp, shape):
-    """USL over 25 steps (graph replays after the first), reordering every
-    step and on demand, against the oracle in FP64."""
-    sc = block(shape=shape, material=MATERIALS["dp"], algo=1, seed=71, vel=4.0, n_cells=(7, 6, 5))
+@pytest.mark.parametrize("algo", [1, 2])
+def test_usl_many_steps_with_reorders(ctx, mp, shape, algo):
+    """USL and MUSL over 25 steps (graph replays after the first), reordering
+    every step and on demand, against the oracle in FP64."""
+    sc = block(shape=shape, material=MATERIALS["dp"], algo=algo, seed=71, vel=4.0, n_cells=(7, 6, 5))
     sc["scheme"]["dt"] = 1e-4
     ref = oracle.run(sc, 25)
     for policy in (mp.SORT_ALWAYS, mp.SORT_ON_DEMAND):
@@ -766,7 +770,8 @@ def test_usl_many_steps_with_reorders(ctx, mp, shape):
         assert st["error_bits"] == 0 and st["steps_done"] == 25, st
         if policy == mp.SORT_ALWAYS:
             assert st["n_sorts"] == 25, st
-        check_state(f"usl/{'gimp' if shape else 'linear'}/{policy}", s.read(), ref, sc["x"], 1e-9, 1e-9, 1e-9)
+        check_state(f"{ALGO_NAMES[algo]}/{'gimp' if shape else 'linear'}/{policy}", s.read(), ref, sc["x"],
+                    1e-9, 1e-9, 1e-9)
         s.destroy()
 
 
@@ -811,7 +816,7 @@ def admissible(sig, mat):
 
 
 @pytest.mark.parametrize("mat", ["dp", "dpi", "dpps"])
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_drucker_prager_cones_over_many_steps(ctx, mp, mat, algo):
     """The outer, inner and plane-strain cones (the Material role of the code
     overview: Drucker-Prager matched to Mohr-Coulomb three ways) over 25
@@ -829,7 +834,7 @@ def test_drucker_prager_cones_over_many_steps(ctx, mp, mat, algo):
         s = ctx.create_scene(sc, precision=p)
         s.step(25)
         got = s.read()
-        name = f"cone/{mat}/{'usl' if algo else 'usf'}/{prec}"
+        name = f"cone/{mat}/{ALGO_NAMES[algo]}/{prec}"
         check_state(name, got, ref, sc["x"], *tol)
         f = admissible(got["stress"], m)
         print(f"[{name}] largest yield value / stress scale {f:.2e}", flush=True)
@@ -958,5 +963,51 @@ def test_column_usl_against_stored_oracle_sample(ctx, mp):
     hr = gold["hist"].astype(np.int64)
     moved = int(np.abs(hc - hr).sum())
     print(f"[column_usl/fp32/200] histogram L1 difference {moved} of {len(sc['x'])}", flush=True)
+    assert moved <= 1e-4 * len(sc["x"])
+    s.destroy()
+
+
+def test_musl_batch_with_reorders_matches_oracle(ctx, mp):
+    """Several MUSL scenes of uneven size in one batch with different step
+    counts (each step also zeroes the remap array the previous step wrote,
+    over that step's boxes), reordering on demand: FP64 against the oracle,
+    then a second call continuing from the first."""
+    scs = [block(material=MATERIALS["dp"], algo=2, seed=150 + i, vel=3.0, n_cells=n, stress_scale=2e3)
+           for i, n in enumerate([(7, 6, 5), (3, 3, 2), (9, 7, 6), (1, 1, 1)])]
+    for sc in scs:
+        sc["scheme"]["dt"] = 1e-4
+    ss = [ctx.create_scene(sc, precision=mp.FP64) for sc in scs]
+    first, second = [12, 7, 20, 3], [9, 14, 5, 11]
+    ctx.batch_step(ss, first)
+    ctx.batch_step(ss, second)
+    for i, (sc, s) in enumerate(zip(scs, ss)):
+        k = first[i] + second[i]
+        st = s.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == k, (i, st)
+        check_state(f"musl/batch/{i}", s.read(), oracle.run(sc, k), sc["x"], 1e-9, 1e-9, 1e-9)
+        s.destroy()
+
+
+def test_column_musl_against_stored_oracle_sample(ctx, mp):
+    """200 modified-USL steps of the 2.1M-particle column in FP32 against
+    the oracle's state, stored for every 1024th particle by
+    tests/golden/make_column_usl_golden.py 200 musl (which calls only the
+    oracle)."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "column_2m_musl_200.npz"))
+    sc = scenes.c2()
+    sc["scheme"]["algo"] = scenes.MUSL
+    idx = gold["index"]
+    np.testing.assert_array_equal(sc["x"][idx], gold["x0"])
+    s = ctx.create_scene(sc, precision=mp.FP32)
+    s.step(int(gold["nsteps"]))
+    got = s.read()
+    sub = {k: got[k][idx] for k in ("x", "v", "stress", "vol")}
+    ref = {k: gold[k] for k in ("x", "v", "stress", "vol")}
+    check_state("column_musl/fp32/200", sub, ref, gold["x0"], U_TOL, S_TOL, 1e-3)
+    hc = s.cell_counts().astype(np.int64)
+    hr = gold["hist"].astype(np.int64)
+    moved = int(np.abs(hc - hr).sum())
+    print(f"[column_musl/fp32/200] histogram L1 difference {moved} of {len(sc['x'])}", flush=True)
     assert moved <= 1e-4 * len(sc["x"])
     s.destroy()

@@ -1,6 +1,8 @@
 """GPU tests of the request loop (mpmx_server_* through the C ABI): scenes
 admitted in arrival order within the device-memory budget, advanced in
 shared batches, and returned with the oracle's final state."""
+import time
+
 import numpy as np
 import pytest
 
@@ -102,4 +104,119 @@ def test_server_results_in_the_mix_equal_each_scene_alone():
             assert eu <= 1e-5 and es <= 1e-5 and ev <= 1e-5
     finally:
         srv.close()
+        ctx.close()
+
+
+def test_server_fill_limit_admits_one_filling_scene_at_a_time():
+    """With the fill limit at one scene's particle count, a resident scene
+    that still has steps to run holds back admission: the queue shrinks by
+    at most one request per tick, at most two requests are resident (one
+    stepping, one being read back), and results still equal each scene run
+    alone."""
+    from paper_1909_13380_amd import mpmx
+    plan = [((6, 5, 4), 30), ((6, 5, 4), 20), ((6, 5, 4), 25), ((6, 5, 4), 17)]
+    scs = [scenes.random_block(n_cells=cells, mesh_cells=(12, 10, 8), h=0.05, seed=120 + i,
+                               material=scenes.drucker_prager(), stress_scale=2e3) for i, (cells, _) in enumerate(plan)]
+    ctx = mpmx.Context(0)
+    srv = mpmx.Server(ctx, 8 << 30, max_tick_steps=8, fill_particles=len(scs[0]["x"]))
+    try:
+        ids = [srv.submit(sc, k, tag=i) for i, (sc, (_, k)) in enumerate(zip(scs, plan))]
+        done, last_q = {}, len(ids)
+        for _ in range(400):
+            r, q = srv.tick()
+            assert r <= 2 and last_q - q <= 1, (r, q, last_q)
+            last_q = q
+            for c in srv.poll():
+                done[c["request"]] = c
+            if len(done) == len(plan):
+                break
+        assert len(done) == len(plan)
+        admits = [done[i]["t_admit"] for i in ids]
+        assert admits == sorted(admits)
+        for i, (sc, (_, k)) in enumerate(zip(scs, plan)):
+            c = done[ids[i]]
+            assert c["status"] == mpmx.OK and c["steps_done"] == k
+            s = ctx.create_scene(sc, precision=mpmx.FP32)
+            s.step(k)
+            alone = s.read()
+            s.destroy()
+            eu = _rel(c["x"] - sc["x"], alone["x"] - sc["x"])
+            es = _rel(c["stress"], alone["stress"])
+            print(f"[fill/{i}/{k}] err_u={eu:.3e} err_sigma={es:.3e}", flush=True)
+            assert eu <= 1e-5 and es <= 1e-5
+    finally:
+        srv.close()
+        ctx.close()
+
+
+def test_fences_report_queued_steps_finished():
+    """mpmx_fence_*: a fence recorded after queued steps reports finished
+    once they are (a blocking wait returns done, the id is then freed), and
+    a non-blocking query never claims done before the steps' results are
+    readable."""
+    from paper_1909_13380_amd import mpmx
+    sc = scenes.random_block(n_cells=(6, 5, 4), mesh_cells=(12, 10, 8), h=0.05, seed=140, stress_scale=2e3)
+    ctx = mpmx.Context(0)
+    try:
+        s = ctx.create_scene(sc, precision=mpmx.FP32)
+        s.step(50)
+        f = ctx.fence()
+        t0 = time.monotonic()
+        while not ctx.fence_done(f):
+            assert time.monotonic() - t0 < 60.0, "fence never reported done"
+            time.sleep(0.001)
+        with pytest.raises(mpmx.MpmxError) as e:
+            ctx.fence_done(f)
+        assert e.value.code == mpmx.E_NOT_FOUND
+        assert s.stats()["steps_done"] == 50
+        s.step(20)
+        g = ctx.fence()
+        assert ctx.fence_done(g, block=True)
+        h = ctx.fence()
+        assert mpmx._lib.mpmx_fence_release(ctx._h, h) == mpmx.OK
+        assert mpmx._lib.mpmx_fence_release(ctx._h, h) == mpmx.E_NOT_FOUND
+        assert s.stats()["steps_done"] == 70
+        s.destroy()
+    finally:
+        ctx.close()
+
+
+def test_borrowed_inputs_and_caller_outputs_give_the_same_results():
+    """MPMX_REQ_BORROW (the particle arrays kept by pointer) and caller-owned
+    output buffers: the same final state as a copying request, written into
+    the caller's arrays."""
+    from paper_1909_13380_amd import mpmx
+    scs = [scenes.random_block(n_cells=(5, 4, 4), mesh_cells=(12, 10, 8), h=0.05, seed=160 + i,
+                               material=scenes.drucker_prager(), stress_scale=2e3) for i in range(3)]
+    steps = [21, 9, 30]
+    ctx = mpmx.Context(0)
+    results = {}
+    try:
+        for mode in ("copy", "borrow_out", "borrow"):
+            srv = mpmx.Server(ctx, 8 << 30, max_tick_steps=8)
+            ids = [srv.submit(sc, k, tag=i, borrow=mode != "copy", out=mode == "borrow_out")
+                   for i, (sc, k) in enumerate(zip(scs, steps))]
+            done = {}
+            for _ in range(200):
+                srv.tick()
+                for c in srv.poll():
+                    done[c["tag"]] = c
+                if len(done) == len(ids):
+                    break
+            srv.close()
+            assert len(done) == len(ids)
+            results[mode] = done
+        for i, (sc, k) in enumerate(zip(scs, steps)):
+            ref = results["copy"][i]
+            assert ref["status"] == mpmx.OK and ref["steps_done"] == k
+            for mode in ("borrow_out", "borrow"):
+                got = results[mode][i]
+                assert got["status"] == mpmx.OK and got["steps_done"] == k
+                for f in ("x", "v", "stress", "vol"):
+                    e = _rel(got[f], ref[f])
+                    assert e <= 1e-5, (mode, i, f, e)
+            np.testing.assert_array_equal(scs[i]["x"], scenes.random_block(
+                n_cells=(5, 4, 4), mesh_cells=(12, 10, 8), h=0.05, seed=160 + i, material=scenes.drucker_prager(),
+                stress_scale=2e3)["x"])   # borrowed inputs are read, never written
+    finally:
         ctx.close()
