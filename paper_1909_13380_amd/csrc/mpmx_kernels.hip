@@ -2177,6 +2177,62 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
         int fb[3] = {-(1 << 30), 0, 0};   // support base of the force accumulators
         Corners kc{};
         R cv[GN][3], fa[SN][3];
+        // anchored GIMP: the updated stress and volume of each of the
+        // thread's particles, for the paired force scatter after the loop
+        R dsg[SH == 1 ? KP : 1][6], dvol[SH == 1 ? KP : 1];
+        bool dok[SH == 1 ? KP : 1];
+        for (int rr = 0; rr < (SH == 1 ? KP : 1); ++rr)
+            dok[rr] = false;
+        // internal and external force of particle ra, and of particle rb (>= 0)
+        // in the same cell, into the anchored slots of that cell
+        auto anchored_forces = [&](int ra, int rb) {
+            if constexpr (SH == 1) {
+                R w4[2][3][4], dw4[2][3][4], A[2][6], mg[2][3];
+                int c[3];
+                unpack_cell(pcell[ra], c);
+                const int np_ = rb >= 0 ? 2 : 1;
+                for (int u = 0; u < np_; ++u) {
+                    const int rq = u ? rb : ra;
+                    const uint32_t p = item.start + threadIdx.x + rq * T;
+                    const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+                    Support<R, SH> sq;
+                    make_support<R, SH>(S, xp, c, sq);
+                    for (int a = 0; a < 3; ++a)
+                        anchor4<R>(sq.w[a], sq.dw[a], sq.base[a] == c[a] ? 1 : 0, w4[u][a], dw4[u][a]);
+                    const R mq = ldg(P.mass, p);
+                    for (int k = 0; k < 6; ++k)
+                        A[u][k] = -dvol[rq] * dsg[rq][k];
+                    mg[u][0] = mq * gx;
+                    mg[u][1] = mq * gy;
+                    mg[u][2] = mq * gz;
+                }
+                const int a0 = (c[0] - 1 - t.lo[0]) + kAnchPX * (c[1] - 1 - t.lo[1]) + kAnchPXY * (c[2] - 1 - t.lo[2]);
+                for (int k = 0; k < 4; ++k)
+                    for (int j = 0; j < 4; ++j) {
+                        R f[4][3];
+                        for (int i = 0; i < 4; ++i)
+                            f[i][0] = f[i][1] = f[i][2] = (R)0;
+                        for (int u = 0; u < np_; ++u) {
+                            const R wyz = w4[u][1][j] * w4[u][2][k], dyz = dw4[u][1][j] * w4[u][2][k],
+                                    ydz = w4[u][1][j] * dw4[u][2][k];
+                            for (int i = 0; i < 4; ++i) {
+                                const R N = w4[u][0][i] * wyz;
+                                const R gxN = dw4[u][0][i] * wyz, gyN = w4[u][0][i] * dyz, gzN = w4[u][0][i] * ydz;
+                                f[i][0] += A[u][0] * gxN + A[u][3] * gyN + A[u][5] * gzN + N * mg[u][0];
+                                f[i][1] += A[u][3] * gxN + A[u][1] * gyN + A[u][4] * gzN + N * mg[u][1];
+                                f[i][2] += A[u][5] * gxN + A[u][4] * gyN + A[u][2] * gzN + N * mg[u][2];
+                            }
+                        }
+                        for (int i = 0; i < 4; ++i) {
+                            const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
+                            atomicAdd(&lf[0][li], (double)f[i][0]);
+                            atomicAdd(&lf[1][li], (double)f[i][1]);
+                            atomicAdd(&lf[2][li], (double)f[i][2]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                    }
+            }
+        };
         auto flush = [&]() {
             for (int n = 0; n < SN; ++n) {
                 const int li = kc.t0 + (n & 1) + ((n >> 1) & 1) * kc.ty + (n >> 2) * kc.tz;
@@ -2355,28 +2411,11 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                                     N * mg2 + B[2][0] * ax + B[2][1] * ay + B[2][2] * az);
                         }
             } else if (anch) {
-                // anchored 4 x 4 x 4 slots (see kAnchPX)
-                R w4[3][4], dw4[3][4];
-                for (int a = 0; a < 3; ++a)
-                    anchor4<R>(sp.w[a], sp.dw[a], sp.base[a] == c[a] ? 1 : 0, w4[a], dw4[a]);
-                const int a0 = (c[0] - 1 - t.lo[0]) + kAnchPX * (c[1] - 1 - t.lo[1]) + kAnchPXY * (c[2] - 1 - t.lo[2]);
-                const R mg0 = mp * gx, mg1 = mp * gy, mg2 = mp * gz;
-                for (int k = 0; k < 4; ++k)
-                    for (int j = 0; j < 4; ++j) {
-                        const R wyz = w4[1][j] * w4[2][k], dyz = dw4[1][j] * w4[2][k], ydz = w4[1][j] * dw4[2][k];
-                        for (int i = 0; i < 4; ++i) {
-                            const R N = w4[0][i] * wyz;
-                            const R gxN = dw4[0][i] * wyz, gyN = w4[0][i] * dyz, gzN = w4[0][i] * ydz;
-                            const R f0 = -vol * (sg[0] * gxN + sg[3] * gyN + sg[5] * gzN) + N * mg0;
-                            const R f1 = -vol * (sg[3] * gxN + sg[1] * gyN + sg[4] * gzN) + N * mg1;
-                            const R f2 = -vol * (sg[5] * gxN + sg[4] * gyN + sg[2] * gzN) + N * mg2;
-                            const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
-                            atomicAdd(&lf[0][li], (double)f0);
-                            atomicAdd(&lf[1][li], (double)f1);
-                            atomicAdd(&lf[2][li], (double)f2);
-                        }
-                        __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
-                    }
+                // after the particle loop, in pairs (anchored_forces)
+                for (int k = 0; k < 6; ++k)
+                    dsg[rr][k] = sg[k];
+                dvol[rr] = vol;
+                dok[rr] = true;
             } else {
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
@@ -2394,6 +2433,26 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                             if (i == NS - 1)
                                 __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
+            }
+        }
+        if constexpr (SH == 1) {
+            if (anch) {
+                // particles rr and rr + 1 of a thread are successive particles
+                // of one cell in level-major order: such a pair shares one set
+                // of anchored adds (half the LDS atomics); positions and masses
+                // are loaded again (cache hits), the stress and volume kept
+#pragma unroll
+                for (int rr = 0; rr < KP; rr += 2) {
+                    const bool two = rr + 1 < KP && dok[rr] && dok[rr + 1] && pcell[rr] == pcell[rr + 1];
+                    if (two) {
+                        anchored_forces(rr, rr + 1);
+                        continue;
+                    }
+#pragma unroll
+                    for (int r2 = rr; r2 < rr + 2 && r2 < KP; ++r2)
+                        if (dok[r2])
+                            anchored_forces(r2, -1);
+                }
             }
         }
         if constexpr (SC)
@@ -2557,6 +2616,30 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                                 addg(nn.p[a], I, N * mvq[a]);
                         }
             }
+        };
+        // two particles in one home cell (GIMP): one set of anchored adds
+        // carries the sum of their contributions
+        auto scatter_pair = [&](const Support<R, SH> &sa, const Support<R, SH> &sb, const int cq[3], R ma,
+                                const R mva[3], R mb, const R mvb[3]) {
+            R wa[3][4], wb[3][4], unused[4];
+            for (int a = 0; a < 3; ++a) {
+                anchor4<R>(sa.w[a], sa.dw[a], sa.base[a] == cq[a] ? 1 : 0, wa[a], unused);
+                anchor4<R>(sb.w[a], sb.dw[a], sb.base[a] == cq[a] ? 1 : 0, wb[a], unused);
+            }
+            const int a0 = (cq[0] - 1 - ht.lo[0]) + APX * (cq[1] - 1 - ht.lo[1]) + APXY * (cq[2] - 1 - ht.lo[2]);
+            for (int k = 0; k < 4; ++k)
+                for (int j = 0; j < 4; ++j) {
+                    const R ya = wa[1][j] * wa[2][k], yb = wb[1][j] * wb[2][k];
+                    for (int i = 0; i < 4; ++i) {
+                        const R Na = wa[0][i] * ya, Nb = wb[0][i] * yb;
+                        const int li = a0 + i + APX * j + APXY * k;
+                        atomicAdd(&acc[0][li], (double)(Na * ma + Nb * mb));
+                        atomicAdd(&acc[1][li], (double)(Na * mva[0] + Nb * mvb[0]));
+                        atomicAdd(&acc[2][li], (double)(Na * mva[1] + Nb * mvb[1]));
+                        atomicAdd(&acc[3][li], (double)(Na * mva[2] + Nb * mvb[2]));
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                }
         };
         auto flush = [&]() {
             for (int n = 0; n < SN; ++n) {
@@ -2730,13 +2813,27 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             for (int q = threadIdx.x; q < ACAP; q += blockDim.x)
                 acc[0][q] = acc[1][q] = acc[2][q] = acc[3][q] = 0.0;
             __syncthreads();
+            // particles rr and rr + 1 of a thread are successive particles of
+            // one cell in level-major order, and most stay in it: such a pair
+            // shares one set of anchored adds (half the LDS atomics)
 #pragma unroll
-            for (int rr = 0; rr < KP; ++rr)
-                if (mvd[rr].ok) {
-                    Support<R, SH> sq;
-                    make_support<R, SH>(S, mvd[rr].x, mvd[rr].c, sq);
-                    scatter(sq, mvd[rr].c, mvd[rr].in, mvd[rr].m, mvd[rr].mv);
+            for (int rr = 0; rr < KP; rr += 2) {
+                if (rr + 1 < KP && mvd[rr].ok && mvd[rr + 1].ok && mvd[rr].in && mvd[rr + 1].in &&
+                    same_base(mvd[rr].c, mvd[rr + 1].c)) {
+                    Support<R, SH> sa, sb;
+                    make_support<R, SH>(S, mvd[rr].x, mvd[rr].c, sa);
+                    make_support<R, SH>(S, mvd[rr + 1].x, mvd[rr + 1].c, sb);
+                    scatter_pair(sa, sb, mvd[rr].c, mvd[rr].m, mvd[rr].mv, mvd[rr + 1].m, mvd[rr + 1].mv);
+                    continue;
                 }
+#pragma unroll
+                for (int r2 = rr; r2 < rr + 2 && r2 < KP; ++r2)
+                    if (mvd[r2].ok) {
+                        Support<R, SH> sq;
+                        make_support<R, SH>(S, mvd[r2].x, mvd[r2].c, sq);
+                        scatter(sq, mvd[r2].c, mvd[r2].in, mvd[r2].m, mvd[r2].mv);
+                    }
+            }
         }
         if constexpr (SC)
             if (sb[0] != -(1 << 30))
