@@ -2091,7 +2091,7 @@ __device__ inline bool same_base(const int a[3], const int b[3])
 // USF: zero the previous step's node buffer; nodal velocity, strain
 // increment, volume and stress update, nodal internal + external force.
 template <typename R, int SH, int T>
-__global__ void __launch_bounds__(T) k_stress(BatchDev B)
+__global__ void __launch_bounds__(T, (SH == 1 && T == 256 && sizeof(R) == 4) ? 4 : 1) k_stress(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
@@ -2213,15 +2213,18 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                         for (int i = 0; i < 4; ++i)
                             f[i][0] = f[i][1] = f[i][2] = (R)0;
                         for (int u = 0; u < np_; ++u) {
-                            const R wyz = w4[u][1][j] * w4[u][2][k], dyz = dw4[u][1][j] * w4[u][2][k],
-                                    ydz = w4[u][1][j] * dw4[u][2][k];
-                            for (int i = 0; i < 4; ++i) {
-                                const R N = w4[u][0][i] * wyz;
-                                const R gxN = dw4[u][0][i] * wyz, gyN = w4[u][0][i] * dyz, gzN = w4[u][0][i] * ydz;
-                                f[i][0] += A[u][0] * gxN + A[u][3] * gyN + A[u][5] * gzN + N * mg[u][0];
-                                f[i][1] += A[u][3] * gxN + A[u][1] * gyN + A[u][4] * gzN + N * mg[u][1];
-                                f[i][2] += A[u][5] * gxN + A[u][4] * gyN + A[u][2] * gzN + N * mg[u][2];
-                            }
+                            // f_a = A_a0 dN/dx + A_a1 dN/dy + A_a2 dN/dz + N m g_a with
+                            // dN/dx = dw_i P1, dN/dy = w_i P2, dN/dz = w_i P3, N = w_i P1:
+                            // the row's (j, k) factors once, then two terms per slot
+                            const R P1 = w4[u][1][j] * w4[u][2][k], P2 = dw4[u][1][j] * w4[u][2][k],
+                                    P3 = w4[u][1][j] * dw4[u][2][k];
+                            const R X[3] = {A[u][0] * P1, A[u][3] * P1, A[u][5] * P1};
+                            const R Y[3] = {A[u][3] * P2 + A[u][5] * P3 + mg[u][0] * P1,
+                                            A[u][1] * P2 + A[u][4] * P3 + mg[u][1] * P1,
+                                            A[u][4] * P2 + A[u][2] * P3 + mg[u][2] * P1};
+                            for (int i = 0; i < 4; ++i)
+                                for (int a = 0; a < 3; ++a)
+                                    f[i][a] += dw4[u][0][i] * X[a] + w4[u][0][i] * Y[a];
                         }
                         for (int i = 0; i < 4; ++i) {
                             const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
@@ -2319,37 +2322,29 @@ __global__ void __launch_bounds__(T) k_stress(BatchDev B)
                     }
                 }
             } else {
+            // GIMP, row by row of the support: dN/dx = dw_i P1, dN/dy = w_i P2,
+            // dN/dz = w_i P3 with the row's (j, k) factors, so each row sums
+            // v dw_i and v w_i over i first
             for (int k = 0; k < NS; ++k)
-                for (int j = 0; j < NS; ++j)
+                for (int j = 0; j < NS; ++j) {
+                    const R P1 = sp.w[1][j] * sp.w[2][k], P2 = sp.dw[1][j] * sp.w[2][k],
+                            P3 = sp.w[1][j] * sp.dw[2][k];
+                    R Sx[3] = {0, 0, 0}, Sw[3] = {0, 0, 0};
                     for (int i = 0; i < NS; ++i) {
-                        const R gxN = sp.dw[0][i] * sp.w[1][j] * sp.w[2][k];
-                        const R gyN = sp.w[0][i] * sp.dw[1][j] * sp.w[2][k];
-                        const R gzN = sp.w[0][i] * sp.w[1][j] * sp.dw[2][k];
-                        R v[3];
-                        if constexpr (GC) {
-                            const int n = i + 2 * j + 4 * k;
-                            v[0] = cv[n][0];
-                            v[1] = cv[n][1];
-                            v[2] = cv[n][2];
-                        } else {
-                            const R4<R> w = lv[cn.t0 + i + j * cn.ty + k * cn.tz];
-                            v[0] = w.x;
-                            v[1] = w.y;
-                            v[2] = w.z;
+                        const R4<R> w = lv[cn.t0 + i + j * cn.ty + k * cn.tz];
+                        const R v[3] = {w.x, w.y, w.z};
+                        for (int e = 0; e < 3; ++e) {
+                            Sx[e] += v[e] * sp.dw[0][i];
+                            Sw[e] += v[e] * sp.w[0][i];
                         }
-                        L[0][0] += v[0] * gxN;
-                        L[0][1] += v[0] * gyN;
-                        L[0][2] += v[0] * gzN;
-                        L[1][0] += v[1] * gxN;
-                        L[1][1] += v[1] * gyN;
-                        L[1][2] += v[1] * gzN;
-                        L[2][0] += v[2] * gxN;
-                        L[2][1] += v[2] * gyN;
-                        L[2][2] += v[2] * gzN;
-                        if constexpr (SH == 1)
-                            if (i == NS - 1)
-                                __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
+                    for (int e = 0; e < 3; ++e) {
+                        L[e][0] += Sx[e] * P1;
+                        L[e][1] += Sw[e] * P2;
+                        L[e][2] += Sw[e] * P3;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one support row of LDS reads in flight
+                }
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
