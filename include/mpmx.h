@@ -248,7 +248,7 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  *                          power-of-two bucket of its particle count), time
  *                          the item kernels at every pair of workgroup size
  *                          and grid density (3 steps each), then keep the
- *                          fastest for that layout; shapes within 2 % of
+ *                          fastest for that layout; shapes within 4 % of
  *                          the fastest count as ties, settled by a fixed
  *                          preference order (256 threads and 16 workgroups
  *                          per CU first), so that the choice is stable

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <string>
@@ -324,7 +325,7 @@ Sizes sizes_of(const mpmx_mesh *m, int shape, int prec, int64_t np)
     s.real = prec == MPMX_FP64 ? 8 : 4;
     s.ncells = 1;
     for (int a = 0; a < 3; ++a) {
-        s.nb[a] = ceil_div(m->n[a], kBrick);
+        s.nb[a] = ceil_div(m->n[a] + kBrick - 1, kBrick);   // any brick shift 0..3
         s.N[a] = m->n[a] + 1 + 2 * s.ghost;
         s.ncells *= m->n[a];
     }
@@ -672,7 +673,7 @@ constexpr int kTuneReps = 3;
 constexpr int kTuneDensity[] = {4, 8, 16, 32};
 constexpr int kNumTuneDensity = 4;
 constexpr int kTuneSteps = kTuneReps * kNumItemThreadChoices * kNumTuneDensity;
-constexpr float kTuneBand = 0.02f;
+constexpr float kTuneBand = 0.04f;
 static_assert(kTuneSteps + 1 <= MPMX_TUNE_MIN_STEPS, "tuning must fit in the calls it runs on");
 
 int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
@@ -688,21 +689,25 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
     int rc = MPMX_OK;
     int k = 0;
     LaunchCfg cfg = best;
-    for (int d = 0; d < kNumTuneDensity && !rc; ++d)
-        for (int t = 0; t < kNumItemThreadChoices && !rc; ++t) {
-            cfg.blocks_per_cu = kTuneDensity[d];
-            cfg.t_stress = cfg.t_g2p = t;
-            for (int r = 0; r < kTuneReps && !rc; ++r, ++k)
+    // repeats in the outer loop: a drift over the tuning steps (clocks, the
+    // scene's own evolution) then weighs on every shape alike
+    constexpr int kShapes = kNumTuneDensity * kNumItemThreadChoices;
+    for (int r = 0; r < kTuneReps && !rc; ++r)
+        for (int d = 0; d < kNumTuneDensity && !rc; ++d)
+            for (int t = 0; t < kNumItemThreadChoices && !rc; ++t, ++k) {
+                cfg.blocks_per_cu = kTuneDensity[d];
+                cfg.t_stress = cfg.t_g2p = t;
                 rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
-        }
+            }
     if (!rc && hipEventSynchronize(ev[3 * k - 1]) != hipSuccess)
         rc = fail(ctx, MPMX_E_HIP, "tuning: event wait failed");
     // ts[d][t], tg[d][t]: fastest repeat of each kernel at density d, size t
     float ts[kNumTuneDensity][kNumItemThreadChoices], tg[kNumTuneDensity][kNumItemThreadChoices];
-    for (int d = 0, q = 0; d < kNumTuneDensity && !rc; ++d)
+    for (int d = 0; d < kNumTuneDensity && !rc; ++d)
         for (int t = 0; t < kNumItemThreadChoices && !rc; ++t) {
             ts[d][t] = tg[d][t] = 1e30f;
-            for (int r = 0; r < kTuneReps; ++r, ++q) {
+            for (int r = 0; r < kTuneReps; ++r) {
+                const int q = r * kShapes + d * kNumItemThreadChoices + t;
                 float m1 = 0.f, m2 = 0.f;
                 if (hipEventElapsedTime(&m1, ev[3 * q], ev[3 * q + 1]) != hipSuccess ||
                     hipEventElapsedTime(&m2, ev[3 * q + 1], ev[3 * q + 2]) != hipSuccess) {
@@ -1286,6 +1291,7 @@ int mpmx_scene_create(mpmx_ctx *ctx, const mpmx_mesh *mesh, const mpmx_material 
         h.origin[a] = mesh->origin[a];
         h.n[a] = mesh->n[a];
         h.nb[a] = (int)sz.nb[a];
+        h.cmin[a] = std::numeric_limits<int>::max();   // k_load takes the particles' minimum
         h.N[a] = (int)sz.N[a];
         h.g[a] = sch->gravity[a];
     }

@@ -88,7 +88,8 @@ struct SceneDev {
     double h, inv_h;
     const double *X;   // isoparametric mesh: node positions x[3][nn] (FP64); null for the uniform grid
     int n[3];        // cells
-    int nb[3];       // bricks
+    int nb[3];       // bricks per axis: room for every brick shift
+    int cmin[3];     // smallest cell of the particles at creation (sets the brick shift)
     int N[3];        // nodes per axis incl. ghosts
     int ghost;       // 0 linear, 1 GIMP
     int64_t nn;      // nodes

@@ -135,11 +135,18 @@ __device__ inline void unpack_cell(uint32_t p, int c[3])
     c[2] = (int)(p >> 22);
 }
 
+// Cells are grouped into bricks of 4^3 after a per-scene shift: brick
+// coordinate (c + s) >> 2 per axis with s = (-cmin) & 3, cmin the smallest
+// cell of the particles at creation, so that a block of particles starts a
+// brick on its lower faces instead of leaving a row of underfilled bricks
+// there.
+__device__ inline int brick_shift(int cmin) { return (-cmin) & 3; }
+
 __device__ inline void brick_origin(const SceneDev &S, uint32_t b, int o[3])
 {
-    o[0] = (int)(b % (uint32_t)S.nb[0]) * kBrick;
-    o[1] = (int)((b / (uint32_t)S.nb[0]) % (uint32_t)S.nb[1]) * kBrick;
-    o[2] = (int)(b / ((uint32_t)S.nb[0] * (uint32_t)S.nb[1])) * kBrick;
+    o[0] = (int)(b % (uint32_t)S.nb[0]) * kBrick - brick_shift(S.cmin[0]);
+    o[1] = (int)((b / (uint32_t)S.nb[0]) % (uint32_t)S.nb[1]) * kBrick - brick_shift(S.cmin[1]);
+    o[2] = (int)(b / ((uint32_t)S.nb[0] * (uint32_t)S.nb[1])) * kBrick - brick_shift(S.cmin[2]);
 }
 
 // A per-scene constant in the state precision: the FP32 copy the host
@@ -1007,6 +1014,7 @@ __global__ void k_load(SceneDev *Sd, const double *x, const double *v, const dou
     R *SG = (R *)S.sig[0];
     R *VO = (R *)S.vol[0];
     R *M = (R *)S.mass[0];
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX};
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         double xp[3];
         bool fin = true;
@@ -1047,6 +1055,15 @@ __global__ void k_load(SceneDev *Sd, const double *x, const double *v, const dou
         }
         S.cell[0][p] = pack_cell(c);
         S.pid[0][p] = (uint32_t)p;
+        if (!e)
+            for (int a = 0; a < 3; ++a)
+                mn[a] = min(mn[a], c[a]);
+    }
+    // the smallest cell per axis (sets the brick shift): one atomic per wave
+    for (int a = 0; a < 3; ++a) {
+        const int w = wave_reduce<false>(mn[a]);
+        if ((threadIdx.x & 63) == 0 && w != INT_MAX)
+            atomicMin(&Sd->cmin[a], w);
     }
 }
 
@@ -1372,6 +1389,7 @@ struct SortView {
     GLOBAL Item *items;
     GLOBAL uint32_t *ctl;
     uint32_t nb0, nb1;
+    int sh[3];      // brick shift per axis
     uint32_t bo;    // flattened index of the scene's brick 0
     int cur;
     bool sorting;   // the scene reorders in the coming step
@@ -1379,6 +1397,8 @@ struct SortView {
     {
         int c[3];
         unpack_cell(packed, c);
+        for (int a = 0; a < 3; ++a)
+            c[a] += sh[a];
         const uint32_t b = (uint32_t)(c[0] >> 2) + nb0 * ((uint32_t)(c[1] >> 2) + nb1 * (uint32_t)(c[2] >> 2));
         return b * 64u + (uint32_t)((c[0] & 3) + 4 * ((c[1] & 3) + 4 * (c[2] & 3)));
     }
@@ -1405,6 +1425,8 @@ __device__ inline SortView sort_view(const BatchDev &B, int s)
     v.items = gp(cld(&S->items));
     v.nb0 = (uint32_t)cld(&S->nb[0]);
     v.nb1 = (uint32_t)cld(&S->nb[1]);
+    for (int a = 0; a < 3; ++a)
+        v.sh[a] = brick_shift(cld(&S->cmin[a]));
     v.bo = (uint32_t)cld(&B.boffs[s]);
     return v;
 }

@@ -209,7 +209,10 @@ def test_plate_with_hole_against_oracle_and_table_1(ctx, mp):
 
 
 def test_bricks_split_into_several_items(ctx, mp):
-    """64 particles per cell: 4096 per brick, eight 512-particle work items."""
+    """64 particles per cell: 4096 per brick, eight 512-particle work items.
+    The block starts at cell (2, 2, 0), so the bricks are shifted by
+    (-cmin) & 3 = (2, 2, 0) cells: x cells 2..9 make two full bricks (three
+    without the shift)."""
     h = 0.05
     x = scenes.block_positions((2, 2, 0), (10, 9, 6), h, layout="centre")
     off = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)]) * (h / 4) - h / 8
@@ -222,9 +225,12 @@ def test_bricks_split_into_several_items(ctx, mp):
     s = ctx.create_scene(sc, precision=mp.FP64)
     s.step(3)
     got = s.read()
-    # work items: ceil(particles of the brick / 512) per 4x4x4-cell brick
+    # work items: ceil(particles of the brick / 512) per 4x4x4-cell brick,
+    # bricks shifted so that the particles' smallest cell starts one
     c = np.floor(sc["x"] / h).astype(int)
-    bricks = c // 4
+    shift = (-c.min(axis=0)) & 3
+    assert list(shift) == [2, 2, 0]
+    bricks = (c + shift) // 4
     _, per_brick = np.unique(bricks[:, 0] + 100 * (bricks[:, 1] + 100 * bricks[:, 2]), return_counts=True)
     assert per_brick.max() == 4096
     assert s.stats()["n_items"] == int(np.sum((per_brick + 511) // 512))
