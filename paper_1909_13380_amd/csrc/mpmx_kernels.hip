@@ -2110,10 +2110,21 @@ __device__ inline bool same_base(const int a[3], const int b[3])
     return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
 }
 
+// Register caps of k_stress, as wavefronts per SIMD (1: none), where
+// measurement showed more waves in flight to pay: FP32 GIMP at 256 threads
+// (4: 128 VGPRs, 28 bytes of spills; 1874 -> 1618 us on the 25.2M-particle
+// column) and FP32 linear at 128 threads (6: 79 VGPRs, no spills; 344 ->
+// 324 us on the 256-scene batch).
+template <typename R, int SH, int T>
+constexpr int stress_waves()
+{
+    return sizeof(R) != 4 ? 1 : (SH == 1 && T == 256) ? 4 : (SH == 0 && T == 128) ? 6 : 1;
+}
+
 // USF: zero the previous step's node buffer; nodal velocity, strain
 // increment, volume and stress update, nodal internal + external force.
 template <typename R, int SH, int T>
-__global__ void __launch_bounds__(T, (SH == 1 && T == 256 && sizeof(R) == 4) ? 4 : 1) k_stress(BatchDev B)
+__global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
