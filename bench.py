@@ -294,8 +294,13 @@ def summarize_counters(root: str, workload: str, commands: str, out_name: str):
     the counter's hardware instances within a dispatch, then averaged over
     dispatches."""
     import glob
-    sc, desc = make_workload(workload)
-    n = len(sc["x"])
+    if workload == "batch":
+        from paper_1909_13380_amd import scenes
+        n = sum(len(sc["x"]) for sc in scenes.c3())
+        desc = f"the batched set: 256 scenes, {n} particles"
+    else:
+        sc, desc = make_workload(workload)
+        n = len(sc["x"])
     dur = {_short(r["Name"]): float(r["AverageNs"]) for r in _csv_rows(os.path.join(root, "trace"), "kernel_stats.csv")}
     means: dict = {}
     for d in sorted(glob.glob(os.path.join(root, "pmc_*"))):
