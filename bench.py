@@ -270,16 +270,19 @@ def summarize(root: str, workload: str, commands: str, out_name: str = ""):
                 continue
             traffic[base] = entry
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    fname = out_name or {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
-                         "column_usl": "step_kernels_column_2m_usl", "column_musl": "step_kernels_column_2m_musl",
-                         "plate": "step_kernels_plate_40k",
-                         "c1": "step_kernels_block_4k"}.get(workload, "step_kernels_" + workload)
+    default = {"column": "step_kernels_column_2m", "column_gimp": "step_kernels_column_2m_gimp",
+               "column_usl": "step_kernels_column_2m_usl", "column_musl": "step_kernels_column_2m_musl",
+               "plate": "step_kernels_plate_40k", "c1": "step_kernels_block_4k", "batch": "step_kernels_batch_256",
+               "c5": "step_kernels_column_25m_gimp"}.get(workload, "step_kernels_" + workload)
+    fname = out_name or default
     with open(os.path.join(ROOT, "profiles", fname + ".txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     if traffic:
         path = os.path.join(ROOT, "profiles", "traffic.json")
         data = json.load(open(path)) if os.path.exists(path) else {}
-        data[out_name or workload] = traffic
+        # the workload's own profile is what its bench line reads; other
+        # profiles of it (e.g. a forced reorder every step) keep their name
+        data[workload if fname == default else fname] = traffic
         with open(path, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
     print("\n".join(lines))
