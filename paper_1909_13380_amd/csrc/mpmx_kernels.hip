@@ -2256,8 +2256,10 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                                             A[u][1] * P2 + A[u][4] * P3 + mg[u][1] * P1,
                                             A[u][4] * P2 + A[u][2] * P3 + mg[u][2] * P1};
                             for (int i = 0; i < 4; ++i)
-                                for (int a = 0; a < 3; ++a)
-                                    f[i][a] += dw4[u][0][i] * X[a] + w4[u][0][i] * Y[a];
+                                for (int a = 0; a < 3; ++a) {   // two fused multiply-adds
+                                    f[i][a] += dw4[u][0][i] * X[a];
+                                    f[i][a] += w4[u][0][i] * Y[a];
+                                }
                         }
                         for (int i = 0; i < 4; ++i) {
                             const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
