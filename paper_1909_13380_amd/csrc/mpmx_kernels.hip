@@ -233,6 +233,11 @@ struct alignas(4 * sizeof(R)) R4 {
     R x, y, z, w;
 };
 
+template <typename R>
+struct alignas(2 * sizeof(R)) R2 {
+    R y, z;
+};
+
 // Component arrays of one node buffer.
 template <typename R>
 struct NodeBuf {
@@ -2523,6 +2528,23 @@ __device__ inline void load_update_tile(const SceneDev &S, const NodeBuf<R> &nb,
     }
 }
 
+// Load the acceleration and updated velocity of the item's node tile into
+// 24 bytes per node (FP32): a and vn.x in la, vn.y and vn.z in lyz.
+template <typename R>
+__device__ inline void load_update_tile_packed(const SceneDev &S, const NodeBuf<R> &nb, const Tile &t, R4<R> *la,
+                                               R2<R> *lyz)
+{
+    const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+    for (int q = threadIdx.x; q < tv; q += blockDim.x) {
+        int i, j, k;
+        tile_node_small(t, q, i, j, k);
+        R a[3], vn[3];
+        node_update<R>(S, nb, i, j, k, a, vn);
+        la[q] = R4<R>{a[0], a[1], a[2], vn[0]};
+        lyz[q] = R2<R>{vn[1], vn[2]};
+    }
+}
+
 // USF: particle velocity (FLIP/PIC) and position from the nodal acceleration
 // and updated velocity; new cell, error and reorder flags; then the next
 // step's nodal mass and momentum from the updated particle into the other
@@ -2547,11 +2569,14 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
     constexpr int APX = SH == 1 ? kAnchPX : HD, APXY = SH == 1 ? kAnchPXY : HD * HD;
     constexpr int ACAP = APXY * HD;
     static_assert(SH != 1 || (HD == 9 && ACAP == kAnchCap), "anchored layout holds the GIMP home tile");
-    constexpr int TILE_BYTES = 2 * CAP * (int)sizeof(R4<R>), ACC_BYTES = 4 * ACAP * (int)sizeof(double);
+    // the gather tile packs a node's acceleration and updated velocity in
+    // 24 bytes (FP32), which leaves room for one more workgroup per CU
+    constexpr int TILE_BYTES = CAP * (int)(sizeof(R4<R>) + sizeof(R2<R>)), ACC_BYTES = 4 * ACAP * (int)sizeof(double);
+    static_assert((CAP * sizeof(R4<R>)) % alignof(R2<R>) == 0 && TILE_BYTES % alignof(double) == 0, "tile alignment");
     __shared__ __attribute__((aligned(16))) char lds[OVERLAY ? (TILE_BYTES > ACC_BYTES ? TILE_BYTES : ACC_BYTES)
                                                              : TILE_BYTES + ACC_BYTES];
     R4<R> *la = (R4<R> *)lds;
-    R4<R> *lvn = la + CAP;
+    R2<R> *lyz = (R2<R> *)(lds + CAP * sizeof(R4<R>));
     double (*acc)[ACAP] = (double (*)[ACAP])(lds + (OVERLAY ? 0 : TILE_BYTES));
     __shared__ int red[6 * (T / 64)];
     // the accumulators start at zero, and each item's flush leaves them so
@@ -2578,7 +2603,7 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         int o[3];
         brick_origin(S, item.brick, o);
         const Tile ht = home_tile<SH>(o);
-        load_update_tile<R>(S, nb, t, la, lvn);
+        load_update_tile_packed<R>(S, nb, t, la, lyz);
         __syncthreads();
         const R dt = cst<R>(S.dt, S.f_dt);
         const int pic = S.vel_update == 1;
@@ -2707,13 +2732,14 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                         gb[a] = sp.base[a];
                     for (int n = 0; n < GN; ++n) {
                         const int li = cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz;
-                        const R4<R> a4 = la[li], u4 = lvn[li];
+                        const R4<R> a4 = la[li];
+                        const R2<R> u2 = lyz[li];
                         ca[n][0] = a4.x;
                         ca[n][1] = a4.y;
                         ca[n][2] = a4.z;
-                        cu[n][0] = u4.x;
-                        cu[n][1] = u4.y;
-                        cu[n][2] = u4.z;
+                        cu[n][0] = a4.w;
+                        cu[n][1] = u2.y;
+                        cu[n][2] = u2.z;
                     }
                 }
             }
@@ -2731,13 +2757,14 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                             }
                         } else {
                             const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
-                            const R4<R> a4 = la[li], u4 = lvn[li];
+                            const R4<R> a4 = la[li];
+                            const R2<R> u2 = lyz[li];
                             a[0] = a4.x;
                             a[1] = a4.y;
                             a[2] = a4.z;
-                            u[0] = u4.x;
-                            u[1] = u4.y;
-                            u[2] = u4.z;
+                            u[0] = a4.w;
+                            u[1] = u2.y;
+                            u[2] = u2.z;
                         }
                         for (int e = 0; e < 3; ++e) {
                             dv[e] += N * a[e];
