@@ -235,7 +235,7 @@ struct alignas(4 * sizeof(R)) R4 {
 
 template <typename R>
 struct alignas(2 * sizeof(R)) R2 {
-    R y, z;
+    R s, t;
 };
 
 // Component arrays of one node buffer.
@@ -2140,7 +2140,9 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
     // GIMP force accumulators in the anchored layout (12 x 9 x 9) when the
     // item's node box fits it, else in the box's own layout
     constexpr int FCAP = SH == 1 ? kAnchCap : CAP;
-    __shared__ R4<R> lv[CAP];
+    // nodal velocity tile, 12 bytes per node (FP32): x, y in lvxy, z in lvz
+    __shared__ R2<R> lvxy[CAP];
+    __shared__ R lvz[CAP];
     __shared__ double lf[3][FCAP];
     __shared__ int red[6 * (T / 64)];
     clear_reorder_flags(B);
@@ -2203,7 +2205,8 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
             tile_node_small(t, q, i, j, k);
             R v[3];
             node_velocity<R>(S, nb, i, j, k, v);
-            lv[q] = R4<R>{v[0], v[1], v[2], (R)0};
+            lvxy[q] = R2<R>{v[0], v[1]};
+            lvz[q] = v[2];
             const int fq = fidx(q, i, j, k);
             lf[0][fq] = lf[1][fq] = lf[2][fq] = 0.0;
         }
@@ -2300,10 +2303,11 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                     for (int a = 0; a < 3; ++a)
                         kb[a] = sp.base[a];
                     for (int n = 0; n < GN; ++n) {
-                        const R4<R> v = lv[cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz];
-                        cv[n][0] = v.x;
-                        cv[n][1] = v.y;
-                        cv[n][2] = v.z;
+                        const int li = cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz;
+                        const R2<R> v = lvxy[li];
+                        cv[n][0] = v.s;
+                        cv[n][1] = v.t;
+                        cv[n][2] = lvz[li];
                     }
                 }
             }
@@ -2337,10 +2341,11 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                         v8[n][1] = cv[n][1];
                         v8[n][2] = cv[n][2];
                     } else {
-                        const R4<R> w = lv[cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz];
-                        v8[n][0] = w.x;
-                        v8[n][1] = w.y;
-                        v8[n][2] = w.z;
+                        const int li = cn.t0 + (n & 1) + ((n >> 1) & 1) * cn.ty + (n >> 2) * cn.tz;
+                        const R2<R> w = lvxy[li];
+                        v8[n][0] = w.s;
+                        v8[n][1] = w.t;
+                        v8[n][2] = lvz[li];
                     }
                 }
                 const R ih = cst<R>(S.inv_h, S.f_inv_h);
@@ -2371,8 +2376,9 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                             P3 = sp.w[1][j] * sp.dw[2][k];
                     R Sx[3] = {0, 0, 0}, Sw[3] = {0, 0, 0};
                     for (int i = 0; i < NS; ++i) {
-                        const R4<R> w = lv[cn.t0 + i + j * cn.ty + k * cn.tz];
-                        const R v[3] = {w.x, w.y, w.z};
+                        const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                        const R2<R> w = lvxy[li];
+                        const R v[3] = {w.s, w.t, lvz[li]};
                         for (int e = 0; e < 3; ++e) {
                             Sx[e] += v[e] * sp.dw[0][i];
                             Sw[e] += v[e] * sp.w[0][i];
@@ -2738,8 +2744,8 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                         ca[n][1] = a4.y;
                         ca[n][2] = a4.z;
                         cu[n][0] = a4.w;
-                        cu[n][1] = u2.y;
-                        cu[n][2] = u2.z;
+                        cu[n][1] = u2.s;
+                        cu[n][2] = u2.t;
                     }
                 }
             }
@@ -2763,8 +2769,8 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
                             a[1] = a4.y;
                             a[2] = a4.z;
                             u[0] = a4.w;
-                            u[1] = u2.y;
-                            u[2] = u2.z;
+                            u[1] = u2.s;
+                            u[2] = u2.t;
                         }
                         for (int e = 0; e < 3; ++e) {
                             dv[e] += N * a[e];
