@@ -18,7 +18,7 @@ stream), the FP64 oracle timed on a bounded sample on the host CPU, and the
 granular column's full 1000-step run.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload batch|column|column_gimp|column_usl|column_musl|column_iso|plate|c1|c5|c5_linear|serve]
+                    [--workload batch|column|column_gimp|column_usl|column_musl|column_iso|plate|c1|c5|c5_linear|c5_compare|serve]
 """
 from __future__ import annotations
 
@@ -687,6 +687,97 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def _shape_metrics(x0, x, v, mass, h):
+    """Outcome measures of a column run: displacement, runout (front along x,
+    the direction the column collapses), final height, kinetic energy."""
+    u = x - x0
+    return {"runout_m": float(x[:, 0].max() - x0[:, 0].max()), "height_m": float(x[:, 2].max()),
+            "mean_settlement_m": float(-u[:, 2].mean()), "kinetic_energy_J": float(0.5 * (mass * (v * v).sum(1)).sum()),
+            "moved_over_h": float((np.linalg.norm(u, axis=1) > h).mean())}
+
+
+def run_c5_compare(args):
+    """The large column with GIMP and with linear shape functions on the same
+    inputs, all 500 steps each in FP32: throughput of each, and how the two
+    results differ (relative L2 of the displacement difference, runout,
+    height, settlement, kinetic energy).  Beside it, the same comparison on
+    the 1/64 subsample scene: the GPU's GIMP and linear runs against the
+    FP64 oracle's stored samples of both (tests/golden/c5sub_*_500.npz, made
+    by tests/golden/make_c5sub_golden.py, which calls only the oracle)."""
+    import torch
+    from paper_1909_13380_amd import mpmx, scenes
+    torch.cuda.init()
+    ctx = mpmx.Context(0)
+    apply_launch_options(ctx, args)
+    out_runs = {}
+    for name, shape in (("gimp", scenes.SHAPE_GIMP), ("linear", scenes.SHAPE_LINEAR)):
+        sc = scenes.c5(shape=shape)
+        k = sc["nsteps"]
+        s = ctx.create_scene(sc, precision=mpmx.FP32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(k)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        got = s.read()
+        st = s.stats()
+        s.destroy()
+        if st["error_bits"]:
+            raise SystemExit(f"c5 {name} stopped with error bits {st['error_bits']}")
+        out_runs[name] = {"x0": sc["x"], "x": got["x"], "v": got["v"], "mass": sc["mass"], "h": sc["mesh"]["h"],
+                          "steps": k, "seconds": sec, "value": len(sc["x"]) * k / sec, "reorders": st["n_sorts"]}
+        print(f"# c5 {name}: {k} steps in {sec:.3f} s", file=sys.stderr, flush=True)
+    g, l = out_runs["gimp"], out_runs["linear"]
+    ug, ul = g["x"] - g["x0"], l["x"] - l["x0"]
+    full = {"particles": len(g["x0"]), "steps": g["steps"],
+            "gimp": {"value": g["value"], "seconds": g["seconds"], "reorders": g["reorders"],
+                     **_shape_metrics(g["x0"], g["x"], g["v"], g["mass"], g["h"])},
+            "linear": {"value": l["value"], "seconds": l["seconds"], "reorders": l["reorders"],
+                       **_shape_metrics(l["x0"], l["x"], l["v"], l["mass"], l["h"])},
+            "displacement_difference_rel_l2": float(np.linalg.norm(ug - ul) / np.linalg.norm(ul))}
+    # the 1/64 subsample: GPU runs of both shapes against the oracle's samples
+    sub = {}
+    gold_dir = os.path.join(ROOT, "tests", "golden")
+    for name, shape in (("gimp", scenes.SHAPE_GIMP), ("linear", scenes.SHAPE_LINEAR)):
+        path = os.path.join(gold_dir, f"c5sub_{name}_500.npz")
+        if not os.path.exists(path):
+            continue
+        gold = np.load(path)
+        sc = scenes.c5(subsample=True, shape=shape)
+        s = ctx.create_scene(sc, precision=mpmx.FP32)
+        s.step(int(gold["nsteps"]))
+        got = s.read()
+        s.destroy()
+        idx = gold["index"]
+        u_gpu, u_or = got["x"][idx] - gold["x0"], gold["x"] - gold["x0"]
+        sub[name] = {"u_gpu": u_gpu, "u_oracle": u_or,
+                     "err_u_vs_oracle": float(np.linalg.norm(u_gpu - u_or) / np.linalg.norm(u_or)),
+                     "err_sigma_vs_oracle": float(np.linalg.norm(got["stress"][idx] - gold["stress"])
+                                                  / np.linalg.norm(gold["stress"]))}
+    ctx.close()
+    subsample = None
+    if len(sub) == 2:
+        dg = sub["gimp"]["u_gpu"] - sub["linear"]["u_gpu"]
+        do = sub["gimp"]["u_oracle"] - sub["linear"]["u_oracle"]
+        subsample = {"sample": "every 64th of the 393,216 particles, 500 steps",
+                     "gimp_err_u_vs_oracle": sub["gimp"]["err_u_vs_oracle"],
+                     "linear_err_u_vs_oracle": sub["linear"]["err_u_vs_oracle"],
+                     "gimp_err_sigma_vs_oracle": sub["gimp"]["err_sigma_vs_oracle"],
+                     "linear_err_sigma_vs_oracle": sub["linear"]["err_sigma_vs_oracle"],
+                     "oracle_displacement_difference_rel_l2": float(np.linalg.norm(do) /
+                                                                    np.linalg.norm(sub["linear"]["u_oracle"])),
+                     "gpu_displacement_difference_rel_l2": float(np.linalg.norm(dg) /
+                                                                 np.linalg.norm(sub["linear"]["u_gpu"])),
+                     "difference_of_differences_rel_l2": float(np.linalg.norm(dg - do) / np.linalg.norm(do))}
+    line = {"metric": METRIC, "value": full["gimp"]["value"], "unit": "particle-updates/s", "n_gpus": 1,
+            "steps": full["steps"], "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "fp32", "data": "synthetic",
+            "config": {"workload": "large granular column, DP, 25,165,824 particles, 512x256x128 mesh, GIMP against "
+                                   "linear on the same inputs, all 500 steps each, FP32"},
+            "full_size": full, "subsample_vs_oracle": subsample}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -756,6 +847,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "c5_compare":
+        run_c5_compare(args)
         return
     from paper_1909_13380_amd import mpmx
 

@@ -418,6 +418,35 @@ def test_column_subsample_full_run_against_stored_oracle_sample(ctx, mp, shape):
     s.destroy()
 
 
+def test_gimp_against_linear_on_the_same_inputs_matches_the_oracle(ctx, mp):
+    """The large column's comparison of GIMP with linear shape functions on
+    the same inputs, reproduced on the 1/64 subsample: the GPU's
+    GIMP-minus-linear displacement field after 500 steps equals the oracle's
+    (stored samples of both runs) within what the per-run displacement bar
+    allows (each run off by at most U_TOL of |u|, so the difference by at
+    most 2 U_TOL |u|), and the difference is itself well above that bar, so
+    the comparison measures the shape functions, not rounding."""
+    import os
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    gold = {n: np.load(os.path.join(gdir, f"c5sub_{n}_500.npz")) for n in ("gimp", "linear")}
+    np.testing.assert_array_equal(gold["gimp"]["x0"], gold["linear"]["x0"])
+    u = {}
+    for n, shape in (("gimp", mp.SHAPE_GIMP), ("linear", mp.SHAPE_LINEAR)):
+        sc = scenes.c5(subsample=True, shape=shape)
+        s = ctx.create_scene(sc, precision=mp.FP32)
+        s.step(int(gold[n]["nsteps"]))
+        u[n] = s.read()["x"][gold[n]["index"]] - gold[n]["x0"]
+        s.destroy()
+    d_gpu = u["gimp"] - u["linear"]
+    d_or = (gold["gimp"]["x"] - gold["gimp"]["x0"]) - (gold["linear"]["x"] - gold["linear"]["x0"])
+    size = np.linalg.norm(d_or) / np.linalg.norm(gold["linear"]["x"] - gold["linear"]["x0"])
+    e = rel(d_gpu, d_or)
+    print(f"[gimp_vs_linear] oracle difference {size:.3e} of the displacement; GPU against it {e:.3e} "
+          f"(bar {2 * U_TOL / size:.3e})", flush=True)
+    assert size > 10 * U_TOL
+    assert e <= 2 * U_TOL / size
+
+
 def test_large_gimp_column_full_size_properties(ctx, mp):
     """The 25M-particle GIMP column at full size in the benchmark's
     configuration, 20 steps: no error, every particle inside the mesh and on
