@@ -118,8 +118,24 @@ int finish(mpmx_server *srv, Resident &r)
         d.v.reset(new (std::nothrow) double[3 * n]);
         d.stress.reset(new (std::nothrow) double[6 * n]);
         d.vol.reset(new (std::nothrow) double[n]);
-        if (n && (!d.x || !d.v || !d.stress || !d.vol))
-            return MPMX_E_OOM;
+        if (n && (!d.x || !d.v || !d.stress || !d.vol)) {
+            // no host memory for the result: free the scene and report it
+            if (int rc = mpmx_scene_destroy(srv->ctx, r.scene))
+                return rc;
+            srv->used -= r.bytes;
+            Done f;
+            f.c.size = sizeof(mpmx_completion);
+            f.c.status = MPMX_E_OOM;
+            f.c.request = r.id;
+            f.c.tag = r.tag;
+            f.c.n = r.n;
+            f.c.t_submit = r.t_submit;
+            f.c.t_admit = r.t_admit;
+            f.c.t_done = srv->now();
+            srv->ready.push_back(r.id);
+            srv->done[r.id] = std::move(f);
+            return MPMX_OK;
+        }
         out.size = sizeof out;
         out.mem = MPMX_MEM_HOST;
         out.x = d.x.get();
@@ -351,31 +367,44 @@ int mpmx_server_tick(mpmx_server *srv, int *n_resident, int *n_queued)
             g.first.push_back(r.scene);
             g.second.push_back(std::min(r.remaining, k));
         }
+    // the groups whose steps were queued: a failure part-way leaves the
+    // bookkeeping of the queued groups right, then reports the error
+    std::vector<std::tuple<int, int, int>> queued;
+    int launch_rc = MPMX_OK;
     for (auto &kv : groups) {
-        rc = mpmx_batch_step(srv->ctx, kv.second.first.data(), kv.second.second.data(), (int)kv.second.first.size());
-        if (rc)
-            return rc;
+        launch_rc = mpmx_batch_step(srv->ctx, kv.second.first.data(), kv.second.second.data(),
+                                    (int)kv.second.first.size());
+        if (launch_rc)
+            break;
+        queued.push_back(kv.first);
     }
-    if (!groups.empty()) {
+    {
         mpmx_server::Round round;
-        if ((rc = mpmx_fence_record(srv->ctx, &round.fence)))
-            return rc;
         std::vector<Resident> keep;
         for (auto &r : srv->resident) {
-            r.remaining -= std::min(r.remaining, k);
-            (r.remaining == 0 ? round.last : keep).push_back(r);
+            if (r.remaining > 0 && std::find(queued.begin(), queued.end(), r.group) != queued.end())
+                r.remaining -= std::min(r.remaining, k);
+            (r.remaining == 0 ? round.last : keep).push_back(r);   // (requests of 0 steps too)
         }
         srv->resident.swap(keep);
-        srv->rounds.push_back(std::move(round));
+        // without a fence (0) the round counts as finished: each read below
+        // still waits for its own scene's steps
+        if (!queued.empty() && mpmx_fence_record(srv->ctx, &round.fence) != MPMX_OK)
+            round.fence = 0;
+        if (!queued.empty() || !round.last.empty())
+            srv->rounds.push_back(std::move(round));
     }
+    if (launch_rc)
+        return launch_rc;
     // finish rounds oldest first: those already finished, after waiting for
     // the oldest while more than kMaxAhead are queued or when this round
     // queued nothing
-    bool wait = groups.empty();
+    bool wait = queued.empty();
     while (!srv->rounds.empty()) {
         const bool block = wait || srv->rounds.size() > kMaxAhead;
-        int done = 0;
-        if ((rc = mpmx_fence_wait(srv->ctx, srv->rounds.front().fence, block ? 1 : 0, &done)))
+        int done = 1;
+        if (srv->rounds.front().fence &&
+            (rc = mpmx_fence_wait(srv->ctx, srv->rounds.front().fence, block ? 1 : 0, &done)))
             return rc;
         if (!done)
             break;
@@ -431,7 +460,8 @@ void mpmx_server_destroy(mpmx_server *srv)
     for (auto &rd : srv->rounds) {
         for (auto &r : rd.last)
             (void)mpmx_scene_destroy(srv->ctx, r.scene);
-        (void)mpmx_fence_release(srv->ctx, rd.fence);
+        if (rd.fence)
+            (void)mpmx_fence_release(srv->ctx, rd.fence);
     }
     delete srv;
 }

@@ -220,3 +220,28 @@ def test_borrowed_inputs_and_caller_outputs_give_the_same_results():
                 stress_scale=2e3)["x"])   # borrowed inputs are read, never written
     finally:
         ctx.close()
+
+
+def test_a_lone_request_of_zero_steps_completes():
+    """A request of 0 steps, alone in the server (no round queues any GPU
+    work), completes on the next tick with its input state."""
+    from paper_1909_13380_amd import mpmx
+    sc = scenes.random_block(n_cells=(3, 3, 2), mesh_cells=(8, 8, 6), h=0.05, seed=170, stress_scale=1e3)
+    ctx = mpmx.Context(0)
+    srv = mpmx.Server(ctx, 1 << 30, max_tick_steps=8)
+    try:
+        rid = srv.submit(sc, 0, precision=mpmx.FP64)
+        done = []
+        for _ in range(5):
+            srv.tick()
+            done += srv.poll()
+            if done:
+                break
+        assert len(done) == 1 and done[0]["request"] == rid
+        c = done[0]
+        assert c["status"] == mpmx.OK and c["steps_done"] == 0
+        np.testing.assert_array_equal(c["x"], sc["x"])
+        assert srv.tick() == (0, 0)
+    finally:
+        srv.close()
+        ctx.close()
