@@ -18,7 +18,7 @@ stream), the FP64 oracle timed on a bounded sample on the host CPU, and the
 granular column's full 1000-step run.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload batch|column|column_gimp|column_usl|column_musl|column_iso|plate|c1|c5|c5_linear|c5_compare|serve]
+                    [--workload batch|column|column_gimp|column_usl|column_musl|column_gimp_usl|column_gimp_musl|column_iso|plate|c1|c5|c5_linear|c5_compare|serve]
 """
 from __future__ import annotations
 
@@ -97,6 +97,12 @@ def make_workload(name: str):
         sc = scenes.c2()
         sc["scheme"]["algo"] = scenes.USL
         return sc, "granular column, DP, 2,097,152 particles, 256x128x160 mesh, linear, USL"
+    if name in ("column_gimp_usl", "column_gimp_musl"):
+        sc = scenes.c2()
+        sc["scheme"]["shape"] = scenes.SHAPE_GIMP
+        sc["scheme"]["algo"] = scenes.USL if name == "column_gimp_usl" else scenes.MUSL
+        return sc, ("granular column, DP, 2,097,152 particles, 256x128x160 mesh, GIMP, "
+                    + ("USL" if name == "column_gimp_usl" else "MUSL"))
     if name == "column_musl":
         sc = scenes.c2()
         sc["scheme"]["algo"] = scenes.MUSL

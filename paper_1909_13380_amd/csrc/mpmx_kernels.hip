@@ -2110,6 +2110,24 @@ struct Cache {
     static constexpr int snodes = scatter ? 8 : 1;
 };
 
+// Make the compiler produce the G2P sums where they are written: without
+// this it sinks a sum into the branch that needs it (the PIC/FLIP choice,
+// the stress update after the position), which keeps every gathered node
+// value live to the end of the support (the GIMP g2p_usl and musl_g2p took
+// 238-256 VGPRs; 113 and 92 with it).  An empty statement, no code.
+template <typename R>
+__device__ inline void pin_sums(R (&a)[3], R (&b)[3])
+{
+    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(b[0]), "+v"(b[1]), "+v"(b[2]));
+}
+
+template <typename R>
+__device__ inline void pin_grad(R (&L)[3][3])
+{
+    asm volatile("" : "+v"(L[0][0]), "+v"(L[0][1]), "+v"(L[0][2]), "+v"(L[1][0]), "+v"(L[1][1]), "+v"(L[1][2]),
+                 "+v"(L[2][0]), "+v"(L[2][1]), "+v"(L[2][2]));
+}
+
 __device__ inline bool same_base(const int a[3], const int b[3])
 {
     return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
@@ -3020,6 +3038,8 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
                             if (i == NS - 1)
                                 __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
+            pin_sums<R>(dv, vp);
+            pin_grad<R>(L);
             for (int a = 0; a < 3; ++a) {
                 const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
                 stg(P.v[a], p, nva);
@@ -3133,6 +3153,7 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
                             if (i == NS - 1)
                                 __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
+            pin_sums<R>(dv, vp);
             const R mp = ldg(P.mass, p);
             R mv[3];
             for (int a = 0; a < 3; ++a) {
@@ -3259,6 +3280,7 @@ __global__ void __launch_bounds__(T) k_musl_stress(BatchDev B)
                             if (i == NS - 1)
                                 __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
+            pin_grad<R>(L);
             for (int a = 0; a < 3; ++a) {
                 xp[a] += S.dt * (double)vp[a];
                 stg(P.x[a], p, xp[a]);
