@@ -344,7 +344,9 @@ def summarize_counters(root: str, workload: str, commands: str, out_name: str):
 def apply_launch_options(ctx, args):
     from paper_1909_13380_amd import mpmx
     for opt, val in ((mpmx.OPT_STRESS_THREADS, args.stress_threads), (mpmx.OPT_G2P_THREADS, args.g2p_threads),
-                     (mpmx.OPT_BLOCKS_PER_CU, args.blocks_per_cu)):
+                     (mpmx.OPT_BLOCKS_PER_CU, args.blocks_per_cu),
+                     (mpmx.OPT_STRESS_BLOCKS_PER_CU, args.stress_blocks_per_cu),
+                     (mpmx.OPT_G2P_BLOCKS_PER_CU, args.g2p_blocks_per_cu)):
         if val:
             ctx.set_option(opt, val)
     if args.graph_steps >= 0:
@@ -442,7 +444,8 @@ def run_batch(args):
     tb = timed(lambda: ctx.batch_step(batch, [K] * n_sc))
     launch_b = {"stress_threads": ctx.get_option(mpmx.OPT_STRESS_THREADS),
                 "g2p_threads": ctx.get_option(mpmx.OPT_G2P_THREADS),
-                "blocks_per_cu": ctx.get_option(mpmx.OPT_BLOCKS_PER_CU),
+                "stress_blocks_per_cu": ctx.get_option(mpmx.OPT_STRESS_BLOCKS_PER_CU),
+                "g2p_blocks_per_cu": ctx.get_option(mpmx.OPT_G2P_BLOCKS_PER_CU),
                 "graph_steps": ctx.get_option(mpmx.OPT_GRAPH_STEPS),
                 "graph_launches_in_timed_call": ctx.get_option(mpmx.OPT_GRAPH_LAUNCHES) - g0,
                 "tune_runs": ctx.get_option(mpmx.OPT_TUNE_RUNS)}
@@ -811,7 +814,12 @@ def main():
                     help="write the SQ counter summary of rocprofv3 --pmc passes DIR/pmc_* (with DIR/trace) to profiles/")
     ap.add_argument("--stress-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
     ap.add_argument("--g2p-threads", type=int, default=0, help="fixed workgroup size (turns autotuning off)")
-    ap.add_argument("--blocks-per-cu", type=int, default=0, help="fixed grid density (turns autotuning off)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="fixed grid density of both item kernels (turns autotuning off)")
+    ap.add_argument("--stress-blocks-per-cu", type=int, default=0,
+                    help="fixed grid density of the stress-side kernel (turns autotuning off)")
+    ap.add_argument("--g2p-blocks-per-cu", type=int, default=0,
+                    help="fixed grid density of the G2P-side kernel (turns autotuning off)")
     ap.add_argument("--graph-steps", type=int, default=-1, help="steps per recorded HIP graph (0: none; default: the library's)")
     ap.add_argument("--scenes", type=int, default=256, help="--workload batch: number of scenes")
     ap.add_argument("--requests", type=int, default=2000, help="--workload serve: requests per arrival rate")
@@ -883,7 +891,8 @@ def main():
     print(f"# timed {args.steps} steps: {1e3 * (t1 - t0) / args.steps:.4f} ms/step", file=sys.stderr, flush=True)
     launch = {"stress_threads": ctx.get_option(mpmx.OPT_STRESS_THREADS),
               "g2p_threads": ctx.get_option(mpmx.OPT_G2P_THREADS),
-              "blocks_per_cu": ctx.get_option(mpmx.OPT_BLOCKS_PER_CU),
+              "stress_blocks_per_cu": ctx.get_option(mpmx.OPT_STRESS_BLOCKS_PER_CU),
+              "g2p_blocks_per_cu": ctx.get_option(mpmx.OPT_G2P_BLOCKS_PER_CU),
               "graph_steps": ctx.get_option(mpmx.OPT_GRAPH_STEPS),
               "graph_launches": ctx.get_option(mpmx.OPT_GRAPH_LAUNCHES)}
     prof = {}

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define MPMX_VERSION 3
+#define MPMX_VERSION 4
 
 /* ------------------------------------------------------------ codes ---- */
 enum {
@@ -247,24 +247,30 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  *                          (precision, shape function, algorithm and the
  *                          power-of-two bucket of its particle count), time
  *                          the item kernels at every pair of workgroup size
- *                          and grid density (3 steps each), then keep the
- *                          fastest for that layout; shapes within 4 % of
- *                          the fastest count as ties, settled by a fixed
- *                          preference order (256 threads and 16 workgroups
- *                          per CU first), so that the choice is stable
- *                          between runs.  The timed steps are steps of the
- *                          call.  0: use the values below.
+ *                          and grid density (3 steps each), then keep, for
+ *                          each of the two kernels, its fastest pair for
+ *                          that layout; pairs within 4 % of the fastest
+ *                          count as ties, settled by a fixed preference
+ *                          order (16 workgroups per CU and 256 threads
+ *                          first), so that the choice is stable between
+ *                          runs.  The timed steps are steps of the call.
+ *                          0: use the values below.
  *   MPMX_OPT_STRESS_THREADS  workgroup size of the stress kernel (USL and
  *                          MUSL: the P2G kernel): 64, 128 or 256.  Setting
- *                          it, or one of the next two, turns autotuning off.
+ *                          it, or any launch shape below, turns autotuning
+ *                          off.
  *   MPMX_OPT_G2P_THREADS   same for the G2P(+P2G) kernel (MUSL: both G2P
  *                          kernels).
- *   MPMX_OPT_BLOCKS_PER_CU item-kernel workgroups per compute unit, 1..64.
+ *   MPMX_OPT_BLOCKS_PER_CU workgroups per compute unit of both item
+ *                          kernels' persistent grids, 1..64 (reads back
+ *                          the stress kernel's).
+ *   MPMX_OPT_STRESS_BLOCKS_PER_CU, MPMX_OPT_G2P_BLOCKS_PER_CU  the same for
+ *                          one of the two kernels.
  *   MPMX_OPT_GRAPH_LAUNCHES  read-only: graph launches so far.
  *   MPMX_OPT_TUNE_RUNS     read-only: tuning passes so far.
- * mpmx_get_option of the three launch shapes returns the values of the
- * last call that stepped a batch.  Errors: MPMX_E_INVALID_ARG for an
- * unknown option or a value out of range. */
+ * mpmx_get_option of the launch shapes returns the values of the last call
+ * that stepped a batch.  Errors: MPMX_E_INVALID_ARG for an unknown option
+ * or a value out of range. */
 #define MPMX_TUNE_MIN_STEPS 40
 enum {
     MPMX_OPT_GRAPH_STEPS = 1,
@@ -273,7 +279,9 @@ enum {
     MPMX_OPT_G2P_THREADS = 4,
     MPMX_OPT_BLOCKS_PER_CU = 5,
     MPMX_OPT_GRAPH_LAUNCHES = 6,
-    MPMX_OPT_TUNE_RUNS = 7
+    MPMX_OPT_TUNE_RUNS = 7,
+    MPMX_OPT_STRESS_BLOCKS_PER_CU = 8,
+    MPMX_OPT_G2P_BLOCKS_PER_CU = 9
 };
 int mpmx_set_option(mpmx_ctx *ctx, int option, int64_t value);
 int mpmx_get_option(mpmx_ctx *ctx, int option, int64_t *value);

@@ -57,14 +57,14 @@ struct StepEvent {
 };
 
 // Launch shape of the item kernels: workgroup size (index into
-// kItemThreadChoices) of the stress-side and G2P-side kernels, and
-// workgroups per compute unit of their persistent grid.
+// kItemThreadChoices) and workgroups per compute unit of the persistent
+// grid, of the stress-side and of the G2P-side kernels.
 struct LaunchCfg {
     int t_stress = 1, t_g2p = 1;
-    int blocks_per_cu = 16;
+    int bpc_stress = 16, bpc_g2p = 16;
     bool operator==(const LaunchCfg &o) const
     {
-        return t_stress == o.t_stress && t_g2p == o.t_g2p && blocks_per_cu == o.blocks_per_cu;
+        return t_stress == o.t_stress && t_g2p == o.t_g2p && bpc_stress == o.bpc_stress && bpc_g2p == o.bpc_g2p;
     }
 };
 
@@ -617,34 +617,37 @@ int enqueue_step(mpmx_ctx *ctx, Batch &b, const LaunchCfg &cfg, bool first, hipE
                                     ceil_div(bd.total_bricks, kBlock / 64), (int64_t)bd.nscenes, (int64_t)1});
     const dim3 rg((unsigned)std::min<int64_t>(rwork, (int64_t)reorder_per_cu(ctx, b.prec, K.reorder) * ctx->num_cu));
     // item grids: a multiple of the XCD count unless there are fewer items
-    int64_t ign = std::min<int64_t>(bd.max_items, (int64_t)cfg.blocks_per_cu * ctx->num_cu);
-    if (ign >= kXcds)
-        ign -= ign % kXcds;
-    const dim3 ig((unsigned)std::max<int64_t>(1, ign));
+    auto item_grid = [&](int per_cu) {
+        int64_t n = std::min<int64_t>(bd.max_items, (int64_t)per_cu * ctx->num_cu);
+        if (n >= kXcds)
+            n -= n % kXcds;
+        return dim3((unsigned)std::max<int64_t>(1, n));
+    };
+    const dim3 igs = item_grid(cfg.bpc_stress), igg = item_grid(cfg.bpc_g2p);
     const dim3 ts(kItemThreadChoices[cfg.t_stress]), tg(kItemThreadChoices[cfg.t_g2p]);
     int rc;
     if ((rc = launch(ctx, "reorder", K.reorder, rg, dim3(kBlock), a_bd)))
         return rc;
-    if (b.algo == MPMX_USF && first && (rc = launch(ctx, "p2g", K.p2g[cfg.t_g2p], ig, tg, a_bd)))
+    if (b.algo == MPMX_USF && first && (rc = launch(ctx, "p2g", K.p2g[cfg.t_g2p], igg, tg, a_bd)))
         return rc;
     if (ev)
         HIPCHK(ctx, hipEventRecord(ev[0], st));
     if (b.algo == MPMX_USF)
-        rc = launch(ctx, "stress", K.stress[cfg.t_stress], ig, ts, a_bd);
+        rc = launch(ctx, "stress", K.stress[cfg.t_stress], igs, ts, a_bd);
     else if (b.algo == MPMX_USL)
-        rc = launch(ctx, "p2g_usl", K.p2g_usl[cfg.t_stress], ig, ts, a_bd);
+        rc = launch(ctx, "p2g_usl", K.p2g_usl[cfg.t_stress], igs, ts, a_bd);
     else
-        rc = launch(ctx, "p2g_musl", K.p2g_musl[cfg.t_stress], ig, ts, a_bd);
+        rc = launch(ctx, "p2g_musl", K.p2g_musl[cfg.t_stress], igs, ts, a_bd);
     if (rc)
         return rc;
     if (ev)
         HIPCHK(ctx, hipEventRecord(ev[1], st));
     if (b.algo == MPMX_USF)
-        rc = launch(ctx, "g2p_p2g", K.g2p_p2g[cfg.t_g2p], ig, tg, a_bd);
+        rc = launch(ctx, "g2p_p2g", K.g2p_p2g[cfg.t_g2p], igg, tg, a_bd);
     else if (b.algo == MPMX_USL)
-        rc = launch(ctx, "g2p_usl", K.g2p_usl[cfg.t_g2p], ig, tg, a_bd);
-    else if (!(rc = launch(ctx, "musl_g2p", K.musl_g2p[cfg.t_g2p], ig, tg, a_bd)))
-        rc = launch(ctx, "musl_stress", K.musl_stress[cfg.t_g2p], ig, tg, a_bd);
+        rc = launch(ctx, "g2p_usl", K.g2p_usl[cfg.t_g2p], igg, tg, a_bd);
+    else if (!(rc = launch(ctx, "musl_g2p", K.musl_g2p[cfg.t_g2p], igg, tg, a_bd)))
+        rc = launch(ctx, "musl_stress", K.musl_stress[cfg.t_g2p], igg, tg, a_bd);
     if (rc)
         return rc;
     if (ev)
@@ -663,11 +666,10 @@ uint64_t layout_key(const Batch &b)
 // Online tuning of the item kernels' launch shape on real steps of the call:
 // every (grid density, workgroup size) pair, kTuneReps steps each, timing
 // the stress-side and the G2P-side kernels separately (each keeps its
-// fastest repeat).  The two kernels share the grid density, so a density is
-// scored by its best stress size plus its best G2P size.  Shapes within
-// kTuneBand of the fastest count as ties, and ties go to the first shape in
-// a fixed preference order (the default shape, then larger workgroups and
-// densities nearer the default), so that timing noise between nearly equal
+// fastest repeat), and each kernel keeps its own fastest pair.  Pairs within
+// kTuneBand of the fastest count as ties, and ties go to the first pair in a
+// fixed preference order (the default shape, then densities nearer the
+// default and larger workgroups), so that timing noise between nearly equal
 // shapes does not change the choice from one run to the next.
 constexpr int kTuneReps = 3;
 constexpr int kTuneDensity[] = {4, 8, 16, 32};
@@ -695,7 +697,7 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
     for (int r = 0; r < kTuneReps && !rc; ++r)
         for (int d = 0; d < kNumTuneDensity && !rc; ++d)
             for (int t = 0; t < kNumItemThreadChoices && !rc; ++t, ++k) {
-                cfg.blocks_per_cu = kTuneDensity[d];
+                cfg.bpc_stress = cfg.bpc_g2p = kTuneDensity[d];
                 cfg.t_stress = cfg.t_g2p = t;
                 rc = enqueue_step(ctx, b, cfg, false, &ev[3 * k]);
             }
@@ -719,42 +721,24 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
             }
         }
     if (!rc) {
-        // preference order: densities by distance from 16, sizes largest first
+        // preference order: densities by distance from 16, then sizes
+        // largest first
         const int dorder[kNumTuneDensity] = {2, 1, 3, 0};
-        float tot[kNumTuneDensity];
-        int bs[kNumTuneDensity], bg[kNumTuneDensity];
-        float fastest = 1e30f;
-        for (int d = 0; d < kNumTuneDensity; ++d) {
-            float ms = 1e30f, mg = 1e30f;
-            for (int t = 0; t < kNumItemThreadChoices; ++t) {
-                ms = std::min(ms, ts[d][t]);
-                mg = std::min(mg, tg[d][t]);
-            }
-            bs[d] = bg[d] = 0;
-            for (int t = kNumItemThreadChoices - 1; t >= 0; --t) {
-                if (ts[d][t] <= ms * (1.f + kTuneBand)) {
-                    bs[d] = t;
-                    break;
-                }
-            }
-            for (int t = kNumItemThreadChoices - 1; t >= 0; --t) {
-                if (tg[d][t] <= mg * (1.f + kTuneBand)) {
-                    bg[d] = t;
-                    break;
-                }
-            }
-            tot[d] = ts[d][bs[d]] + tg[d][bg[d]];
-            fastest = std::min(fastest, tot[d]);
-        }
-        for (int i = 0; i < kNumTuneDensity; ++i) {
-            const int d = dorder[i];
-            if (tot[d] <= fastest * (1.f + kTuneBand)) {
-                best.blocks_per_cu = kTuneDensity[d];
-                best.t_stress = bs[d];
-                best.t_g2p = bg[d];
-                break;
-            }
-        }
+        auto choose = [&](const float (&tm)[kNumTuneDensity][kNumItemThreadChoices], int &bpc, int &t_out) {
+            float fastest = 1e30f;
+            for (int d = 0; d < kNumTuneDensity; ++d)
+                for (int t = 0; t < kNumItemThreadChoices; ++t)
+                    fastest = std::min(fastest, tm[d][t]);
+            for (int i = 0; i < kNumTuneDensity; ++i)
+                for (int t = kNumItemThreadChoices - 1; t >= 0; --t)
+                    if (tm[dorder[i]][t] <= fastest * (1.f + kTuneBand)) {
+                        bpc = kTuneDensity[dorder[i]];
+                        t_out = t;
+                        return;
+                    }
+        };
+        choose(ts, best.bpc_stress, best.t_stress);
+        choose(tg, best.bpc_g2p, best.t_g2p);
     }
     for (auto &e : ev)
         (void)hipEventDestroy(e);
@@ -1046,9 +1030,14 @@ int mpmx_set_option(mpmx_ctx *ctx, int option, int64_t value)
         return MPMX_OK;
     }
     case MPMX_OPT_BLOCKS_PER_CU:
+    case MPMX_OPT_STRESS_BLOCKS_PER_CU:
+    case MPMX_OPT_G2P_BLOCKS_PER_CU:
         if (value < 1 || value > 64)
             return fail(ctx, MPMX_E_INVALID_ARG, "blocks per CU must be 1..64");
-        ctx->fixed.blocks_per_cu = (int)value;
+        if (option != MPMX_OPT_G2P_BLOCKS_PER_CU)
+            ctx->fixed.bpc_stress = (int)value;
+        if (option != MPMX_OPT_STRESS_BLOCKS_PER_CU)
+            ctx->fixed.bpc_g2p = (int)value;
         ctx->autotune = false;
         return MPMX_OK;
     default:
@@ -1065,7 +1054,9 @@ int mpmx_get_option(mpmx_ctx *ctx, int option, int64_t *value)
     case MPMX_OPT_AUTOTUNE: *value = ctx->autotune ? 1 : 0; return MPMX_OK;
     case MPMX_OPT_STRESS_THREADS: *value = kItemThreadChoices[ctx->last.t_stress]; return MPMX_OK;
     case MPMX_OPT_G2P_THREADS: *value = kItemThreadChoices[ctx->last.t_g2p]; return MPMX_OK;
-    case MPMX_OPT_BLOCKS_PER_CU: *value = ctx->last.blocks_per_cu; return MPMX_OK;
+    case MPMX_OPT_BLOCKS_PER_CU:
+    case MPMX_OPT_STRESS_BLOCKS_PER_CU: *value = ctx->last.bpc_stress; return MPMX_OK;
+    case MPMX_OPT_G2P_BLOCKS_PER_CU: *value = ctx->last.bpc_g2p; return MPMX_OK;
     case MPMX_OPT_GRAPH_LAUNCHES: *value = ctx->graph_launches; return MPMX_OK;
     case MPMX_OPT_TUNE_RUNS: *value = ctx->tune_runs; return MPMX_OK;
     default: return fail(ctx, MPMX_E_INVALID_ARG, "unknown option %d", option);

@@ -46,7 +46,7 @@ SORT_ON_DEMAND, SORT_ALWAYS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 ERRBIT_OUT_OF_MESH, ERRBIT_NONFINITE, ERRBIT_TILE, ERRBIT_SORT = 1, 2, 4, 8
 OPT_GRAPH_STEPS, OPT_AUTOTUNE, OPT_STRESS_THREADS, OPT_G2P_THREADS, OPT_BLOCKS_PER_CU, OPT_GRAPH_LAUNCHES, \
-    OPT_TUNE_RUNS = 1, 2, 3, 4, 5, 6, 7
+    OPT_TUNE_RUNS, OPT_STRESS_BLOCKS_PER_CU, OPT_G2P_BLOCKS_PER_CU = 1, 2, 3, 4, 5, 6, 7, 8, 9
 TUNE_MIN_STEPS = 40
 
 _P = ctypes.POINTER

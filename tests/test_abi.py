@@ -23,7 +23,7 @@ def test_library_exports_every_declared_function(mpmx):
     lib = ctypes.CDLL(mpmx.LIBPATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert mpmx.version() == 3
+    assert mpmx.version() == 4
 
 
 def test_header_constants_match_the_binding(mpmx):

@@ -611,12 +611,16 @@ def test_graph_replays_match_direct_launches(mp):
         ce.close()
 
 
-@pytest.mark.parametrize("t_stress,t_g2p,blocks", [(64, 256, 1), (256, 64, 3), (128, 128, 40)])
+@pytest.mark.parametrize("t_stress,t_g2p,blocks", [(64, 256, 1), (256, 64, 3), (128, 128, 40), (128, 256, (2, 24))])
 def test_every_launch_shape_matches_oracle(mp, t_stress, t_g2p, blocks):
+    """Workgroup sizes and grid densities, the same for both item kernels or
+    (a pair) one density each."""
     sc = block(material=MATERIALS["dpc"], seed=52, n_cells=(12, 9, 7))
     c = mp.Context(0)
     try:
-        _fixed(c, mp, 0, t_stress, t_g2p, blocks)
+        bs, bg = blocks if isinstance(blocks, tuple) else (blocks, blocks)
+        _fixed(c, mp, 0, t_stress, t_g2p, bs)
+        c.set_option(mp.OPT_G2P_BLOCKS_PER_CU, bg)
         for shape in (0, 1):
             sc["scheme"]["shape"] = shape
             s = c.create_scene(sc, precision=mp.FP64)
@@ -625,7 +629,8 @@ def test_every_launch_shape_matches_oracle(mp, t_stress, t_g2p, blocks):
                         1e-9, 1e-9)
             assert c.get_option(mp.OPT_STRESS_THREADS) == t_stress
             assert c.get_option(mp.OPT_G2P_THREADS) == t_g2p
-            assert c.get_option(mp.OPT_BLOCKS_PER_CU) == blocks
+            assert c.get_option(mp.OPT_BLOCKS_PER_CU) == c.get_option(mp.OPT_STRESS_BLOCKS_PER_CU) == bs
+            assert c.get_option(mp.OPT_G2P_BLOCKS_PER_CU) == bg
             s.destroy()
     finally:
         c.close()
@@ -648,7 +653,9 @@ def test_autotuner_runs_once_per_layout_on_real_steps(mp):
         assert c.get_option(mp.OPT_TUNE_RUNS) == 1
         assert c.get_option(mp.OPT_STRESS_THREADS) in (64, 128, 256)
         assert c.get_option(mp.OPT_G2P_THREADS) in (64, 128, 256)
-        assert c.get_option(mp.OPT_BLOCKS_PER_CU) in (4, 8, 16, 32)
+        for o in (mp.OPT_BLOCKS_PER_CU, mp.OPT_STRESS_BLOCKS_PER_CU, mp.OPT_G2P_BLOCKS_PER_CU):
+            assert c.get_option(o) in (4, 8, 16, 32)
+        assert c.get_option(mp.OPT_BLOCKS_PER_CU) == c.get_option(mp.OPT_STRESS_BLOCKS_PER_CU)
         check_state(f"tuned/{10 + T}", s.read(), oracle.run(sc, 10 + T), sc["x"], 1e-9, 1e-9, 1e-9)
         s.step(30)
         assert c.get_option(mp.OPT_TUNE_RUNS) == 1
@@ -674,7 +681,7 @@ def test_autotuner_choice_is_stable_between_runs(mp):
             s.step(mp.TUNE_MIN_STEPS)
             assert c.get_option(mp.OPT_TUNE_RUNS) == 1
             picks.append(tuple(c.get_option(o) for o in (mp.OPT_STRESS_THREADS, mp.OPT_G2P_THREADS,
-                                                         mp.OPT_BLOCKS_PER_CU)))
+                                                         mp.OPT_STRESS_BLOCKS_PER_CU, mp.OPT_G2P_BLOCKS_PER_CU)))
             s.destroy()
         finally:
             c.close()
