@@ -249,11 +249,12 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  *                          the item kernels at every pair of workgroup size
  *                          and grid density (3 steps each), then keep, for
  *                          each of the two kernels, its fastest pair for
- *                          that layout; pairs within 4 % of the fastest
- *                          count as ties, settled by a fixed preference
- *                          order (16 workgroups per CU and 256 threads
- *                          first), so that the choice is stable between
- *                          runs.  The timed steps are steps of the call.
+ *                          that layout; pairs at most 4 % plus 2 us
+ *                          slower than the fastest count as ties, settled
+ *                          by a fixed preference order (16 workgroups per
+ *                          CU and 256 threads first), so that the choice is
+ *                          stable between runs.  The timed steps are steps
+ *                          of the call.
  *                          0: use the values below.
  *   MPMX_OPT_STRESS_THREADS  workgroup size of the stress kernel (USL and
  *                          MUSL: the P2G kernel): 64, 128 or 256.  Setting

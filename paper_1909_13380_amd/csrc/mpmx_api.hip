@@ -667,15 +667,17 @@ uint64_t layout_key(const Batch &b)
 // every (grid density, workgroup size) pair, kTuneReps steps each, timing
 // the stress-side and the G2P-side kernels separately (each keeps its
 // fastest repeat), and each kernel keeps its own fastest pair.  Pairs within
-// kTuneBand of the fastest count as ties, and ties go to the first pair in a
+// kTuneBand plus kTuneSlackMs of the fastest count as ties (the slack covers
+// the timing jitter of short kernels), and ties go to the first pair in a
 // fixed preference order (the default shape, then densities nearer the
 // default and larger workgroups), so that timing noise between nearly equal
 // shapes does not change the choice from one run to the next.
 constexpr int kTuneReps = 3;
-constexpr int kTuneDensity[] = {4, 8, 16, 32};
+constexpr int kTuneDensity[] = {8, 16, 32, 64};
 constexpr int kNumTuneDensity = 4;
 constexpr int kTuneSteps = kTuneReps * kNumItemThreadChoices * kNumTuneDensity;
 constexpr float kTuneBand = 0.04f;
+constexpr float kTuneSlackMs = 0.002f;
 static_assert(kTuneSteps + 1 <= MPMX_TUNE_MIN_STEPS, "tuning must fit in the calls it runs on");
 
 int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
@@ -723,7 +725,7 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
     if (!rc) {
         // preference order: densities by distance from 16, then sizes
         // largest first
-        const int dorder[kNumTuneDensity] = {2, 1, 3, 0};
+        const int dorder[kNumTuneDensity] = {1, 0, 2, 3};
         auto choose = [&](const float (&tm)[kNumTuneDensity][kNumItemThreadChoices], int &bpc, int &t_out) {
             float fastest = 1e30f;
             for (int d = 0; d < kNumTuneDensity; ++d)
@@ -731,7 +733,7 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
                     fastest = std::min(fastest, tm[d][t]);
             for (int i = 0; i < kNumTuneDensity; ++i)
                 for (int t = kNumItemThreadChoices - 1; t >= 0; --t)
-                    if (tm[dorder[i]][t] <= fastest * (1.f + kTuneBand)) {
+                    if (tm[dorder[i]][t] <= fastest * (1.f + kTuneBand) + kTuneSlackMs) {
                         bpc = kTuneDensity[dorder[i]];
                         t_out = t;
                         return;

@@ -654,7 +654,7 @@ def test_autotuner_runs_once_per_layout_on_real_steps(mp):
         assert c.get_option(mp.OPT_STRESS_THREADS) in (64, 128, 256)
         assert c.get_option(mp.OPT_G2P_THREADS) in (64, 128, 256)
         for o in (mp.OPT_BLOCKS_PER_CU, mp.OPT_STRESS_BLOCKS_PER_CU, mp.OPT_G2P_BLOCKS_PER_CU):
-            assert c.get_option(o) in (4, 8, 16, 32)
+            assert c.get_option(o) in (8, 16, 32, 64)
         assert c.get_option(mp.OPT_BLOCKS_PER_CU) == c.get_option(mp.OPT_STRESS_BLOCKS_PER_CU)
         check_state(f"tuned/{10 + T}", s.read(), oracle.run(sc, 10 + T), sc["x"], 1e-9, 1e-9, 1e-9)
         s.step(30)
