@@ -723,9 +723,9 @@ int tune(mpmx_ctx *ctx, Batch &b, LaunchCfg &best)
             }
         }
     if (!rc) {
-        // preference order: densities by distance from 16, then sizes
+        // preference order: 16 workgroups per CU, then 32, 8, 64; sizes
         // largest first
-        const int dorder[kNumTuneDensity] = {1, 0, 2, 3};
+        const int dorder[kNumTuneDensity] = {1, 2, 0, 3};
         auto choose = [&](const float (&tm)[kNumTuneDensity][kNumItemThreadChoices], int &bpc, int &t_out) {
             float fastest = 1e30f;
             for (int d = 0; d < kNumTuneDensity; ++d)

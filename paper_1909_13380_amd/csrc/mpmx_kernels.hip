@@ -750,17 +750,44 @@ __device__ inline T *uni(T *p)
     return (T *)(((uint64_t)uni((uint32_t)(v >> 32)) << 32) | (uint64_t)uni((uint32_t)v));
 }
 
-// Copy of a plain struct with every 32-bit word made wave-uniform.
+// Load through the scalar cache: the address is wave-uniform and the data
+// does not change during the kernel (written at creation or by an earlier
+// kernel).
 template <typename T>
-__device__ inline T uni_struct(const T &v)
+__device__ inline T cld(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)uni(p);
+}
+
+// The same for a plain struct, word by word.
+template <typename T>
+__device__ inline T cld_struct(const T *p)
 {
     static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+    typedef const __attribute__((address_space(4))) uint32_t CWord;
+    CWord *src = (CWord *)uni(p);
     T out;
-    const uint32_t *src = (const uint32_t *)&v;
     uint32_t *dst = (uint32_t *)&out;
     for (int w = 0; w < (int)(sizeof(T) / 4); ++w)
-        dst[w] = uni(src[w]);
+        dst[w] = src[w];
     return out;
+}
+
+// Largest s with offs[s] <= g for a wave-uniform g (offs non-decreasing),
+// through the scalar cache: a work item's scene is found in a few scalar
+// loads, not a chain of vector memory round trips.
+template <typename T>
+__device__ inline int find_scene_u(const T *offs, int nscenes, int64_t g)
+{
+    int lo = 0, hi = nscenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)cld(&offs[mid]) <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // Scene descriptor through the scalar cache: it is written once at creation
@@ -784,8 +811,8 @@ struct ItemRef {
 
 __device__ inline ItemRef item_ref(const uint32_t *offs, const BatchDev &B, int64_t g)
 {
-    const int s = (int)uni((uint32_t)find_scene(offs, B.nscenes, g));
-    return {uni(B.scenes[s]), (int)uni((uint32_t)(g - (int64_t)offs[s]))};
+    const int s = find_scene_u(offs, B.nscenes, g);
+    return {cld(&B.scenes[s]), (int)(uint32_t)(g - (int64_t)cld(&offs[s]))};
 }
 
 // The stage kernels after the step control test CTL_ACTIVE only: it is fixed
@@ -794,7 +821,7 @@ __device__ inline ItemRef item_ref(const uint32_t *offs, const BatchDev &B, int6
 // around its barriers.
 __device__ inline bool scene_active(const SceneDev &S)
 {
-    return uni(S.ctl[CTL_ACTIVE]) != 0u;
+    return cld(&S.ctl[CTL_ACTIVE]) != 0u;
 }
 
 // Item order of the persistent grids.  Workgroup w runs on XCD w % 8, and
@@ -968,8 +995,8 @@ __device__ inline void clear_previous(const BatchDev &B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const int other = (int)uni(S.ctl[CTL_NBUF]) ^ 1;
-        clear_box<R>(S, node_buf<R>(S, other), pick(S.tiles, other)[r.it]);
+        const int other = (int)cld(&S.ctl[CTL_NBUF]) ^ 1;
+        clear_box<R>(S, node_buf<R>(S, other), cld_struct(&pick(S.tiles, other)[r.it]));
     }
 }
 
@@ -986,8 +1013,8 @@ __device__ inline void clear_remap_previous(const BatchDev &B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S) || !S.nr)
             continue;
-        const int other = (int)uni(S.ctl[CTL_NBUF]) ^ 1;
-        const Tile t = pick(S.tiles, other)[r.it];
+        const int other = (int)cld(&S.ctl[CTL_NBUF]) ^ 1;
+        const Tile t = cld_struct(&pick(S.tiles, other)[r.it]);
         GLOBAL R *NR = gp((R *)S.nr);
         const uint32_t nn = (uint32_t)S.nn;
         const int vol = t.dim[0] * t.dim[1] * t.dim[2];
@@ -1078,7 +1105,7 @@ __global__ void k_read_out(const SceneDev *Sd, double *x, double *v, double *sig
 {
     const SceneDev &S = *Sd;
     const int64_t n = S.np;
-    const int cur = (int)uni(S.ctl[CTL_CUR]);
+    const int cur = (int)cld(&S.ctl[CTL_CUR]);
     const double *X = S.x[cur];
     const R *V = (const R *)S.v[cur];
     const R *SG = (const R *)S.sig[cur];
@@ -1107,7 +1134,7 @@ __global__ void k_read_out(const SceneDev *Sd, double *x, double *v, double *sig
 __global__ void k_cell_counts(const SceneDev *Sd, uint32_t *counts)
 {
     const SceneDev &S = *Sd;
-    const int cur = (int)uni(S.ctl[CTL_CUR]);
+    const int cur = (int)cld(&S.ctl[CTL_CUR]);
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < S.np; p += (int64_t)gridDim.x * blockDim.x) {
         int c[3];
         unpack_cell(S.cell[cur][p], c);
@@ -1120,7 +1147,7 @@ template <typename R>
 __global__ void k_nodes_out(const SceneDev *Sd, double *m, double *p, double *f)
 {
     const SceneDev &S = *Sd;
-    const int b = (int)uni(S.ctl[CTL_NBUF]);
+    const int b = (int)cld(&S.ctl[CTL_NBUF]);
     const R *P = (const R *)S.np_[b];
     const R *F = (const R *)S.nf[b];
     for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < S.nn; I += (int64_t)gridDim.x * blockDim.x) {
@@ -1363,27 +1390,6 @@ __device__ bool phase_done(uint32_t *flags, int phase, int *sh)
     return *sh != 0;
 }
 
-// Load through the scalar cache: the address is wave-uniform and the data
-// does not change during the kernel.
-template <typename T>
-__device__ inline T cld(const T *p)
-{
-    return *(const __attribute__((address_space(4))) T *)uni(p);
-}
-
-// Largest s with offs[s] <= g for a wave-uniform g (offs non-decreasing).
-__device__ inline int find_scene_u(const int64_t *offs, int nscenes, int64_t g)
-{
-    int lo = 0, hi = nscenes - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cld(&offs[mid]) <= g)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
 
 // The reorder state of one scene, in scalar registers.
 struct SortView {
@@ -1993,9 +1999,9 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S) || (!WITH_FORCE && S.ctl[CTL_HAVE_P2G]))
             continue;
-        const Item item = uni_struct(S.items[r.it]);
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
-        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Item item = cld_struct(&S.items[r.it]);
+        const int cur = (int)cld(&S.ctl[CTL_CUR]);
+        const int buf = (int)cld(&S.ctl[CTL_NBUF]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         Tile t;
@@ -2172,9 +2178,9 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = uni_struct(S.items[r.it]);
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
-        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Item item = cld_struct(&S.items[r.it]);
+        const int cur = (int)cld(&S.ctl[CTL_CUR]);
+        const int buf = (int)cld(&S.ctl[CTL_NBUF]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         uint32_t pcell[KP];
@@ -2195,8 +2201,8 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
         // the node box: recorded by the kernel that filled this node buffer
         // when the items are unchanged since, else reduced here
         Tile t;
-        if (uni(S.ctl[CTL_BOX_OK])) {
-            t = uni_struct(pick(S.tiles, buf)[r.it]);
+        if (cld(&S.ctl[CTL_BOX_OK])) {
+            t = cld_struct(&pick(S.tiles, buf)[r.it]);
         } else {
             int blo[3], bhi[3];
             item_box<T>(mn, mx, red, blo, bhi);
@@ -2615,12 +2621,12 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = uni_struct(S.items[r.it]);
-        const Tile t = uni_struct(S.tstep[r.it]);
+        const Item item = cld_struct(&S.items[r.it]);
+        const Tile t = cld_struct(&S.tstep[r.it]);
         if (!t.fits)
             continue;
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
-        const int buf = (int)uni(S.ctl[CTL_NBUF]), nbuf = buf ^ 1;
+        const int cur = (int)cld(&S.ctl[CTL_CUR]);
+        const int buf = (int)cld(&S.ctl[CTL_NBUF]), nbuf = buf ^ 1;
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         const NodeBuf<R> nn = node_buf<R>(S, nbuf);
@@ -2982,12 +2988,12 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = uni_struct(S.items[r.it]);
-        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Item item = cld_struct(&S.items[r.it]);
+        const int buf = (int)cld(&S.ctl[CTL_NBUF]);
         const Tile t = pick(S.tiles, buf)[r.it];
         if (!t.fits)
             continue;
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const int cur = (int)cld(&S.ctl[CTL_CUR]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         int o[3];
@@ -3111,12 +3117,12 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = uni_struct(S.items[r.it]);
-        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Item item = cld_struct(&S.items[r.it]);
+        const int buf = (int)cld(&S.ctl[CTL_NBUF]);
         const Tile t = pick(S.tiles, buf)[r.it];
         if (!t.fits)
             continue;
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const int cur = (int)cld(&S.ctl[CTL_CUR]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
@@ -3213,12 +3219,12 @@ __global__ void __launch_bounds__(T) k_musl_stress(BatchDev B)
         const SceneDev S = load_scene(r.S);
         if (!scene_active(S))
             continue;
-        const Item item = uni_struct(S.items[r.it]);
-        const int buf = (int)uni(S.ctl[CTL_NBUF]);
+        const Item item = cld_struct(&S.items[r.it]);
+        const int buf = (int)cld(&S.ctl[CTL_NBUF]);
         const Tile t = pick(S.tiles, buf)[r.it];
         if (!t.fits)
             continue;
-        const int cur = (int)uni(S.ctl[CTL_CUR]);
+        const int cur = (int)cld(&S.ctl[CTL_CUR]);
         const Parts<R> P = parts<R>(S, cur);
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         int o[3];
