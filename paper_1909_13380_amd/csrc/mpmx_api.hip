@@ -669,9 +669,9 @@ uint64_t layout_key(const Batch &b)
 // fastest repeat), and each kernel keeps its own fastest pair.  Pairs within
 // kTuneBand plus kTuneSlackMs of the fastest count as ties (the slack covers
 // the timing jitter of short kernels), and ties go to the first pair in a
-// fixed preference order (the default shape, then densities nearer the
-// default and larger workgroups), so that timing noise between nearly equal
-// shapes does not change the choice from one run to the next.
+// fixed preference order (16 workgroups per CU, then 32, 8 and 64; larger
+// workgroups first), so that timing noise between nearly equal shapes does
+// not change the choice from one run to the next.
 constexpr int kTuneReps = 3;
 constexpr int kTuneDensity[] = {8, 16, 32, 64};
 constexpr int kNumTuneDensity = 4;
