@@ -1977,6 +1977,216 @@ __device__ inline Parts<R> parts(const SceneDev &S, int cur)
     return P;
 }
 
+// GIMP P2G of one work item (k_p2g): the item's particles' mass and momentum
+// into the node box t, flushed to node buffer nb; with force, a second pass
+// of the nodal force (internal from the current stress and volume, and
+// gravity) through the same LDS accumulators.  When the box fits the
+// anchored layout (kAnchPX), each particle adds to the 4 x 4 x 4 anchored
+// slots of its cell, and a thread's two particles in one cell (successive
+// particles of the cell in level-major order) share one set of adds;
+// otherwise each particle adds to its 27-node support at the box's pitches.
+template <typename R, bool WITH_FORCE, int T>
+__device__ __attribute__((always_inline)) inline void p2g_gimp_item(const SceneDev &S, const Parts<R> &P, const NodeBuf<R> &nb, const Item &item,
+                                     const Tile &t, double (*acc)[kAnchCap], R gx, R gy, R gz)
+{
+    constexpr int KP = kChunk / T;
+    const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+    const bool anch = t.dim[0] <= kAnchPX && t.dim[1] <= 9 && t.dim[2] <= 9;
+    const int px = anch ? kAnchPX : t.dim[0], pxy = anch ? kAnchPXY : t.dim[0] * t.dim[1];
+    auto entry = [&](int i, int j, int k) { return (i - t.lo[0]) + px * (j - t.lo[1]) + pxy * (k - t.lo[2]); };
+    uint32_t pc[KP];
+#pragma unroll
+    for (int rr = 0; rr < KP; ++rr) {
+        const uint32_t q = threadIdx.x + rr * T;
+        pc[rr] = q < item.count ? ldg(P.cell, item.start + q) : 0xffffffffu;
+    }
+    for (int q = threadIdx.x; q < tv; q += T) {
+        int i, j, k;
+        tile_node_small(t, q, i, j, k);
+        const int e = entry(i, j, k);
+        acc[0][e] = acc[1][e] = acc[2][e] = acc[3][e] = 0.0;
+    }
+    __syncthreads();
+    // support of the thread's particle rr (cell c), anchored weights
+    auto support = [&](int rr, const int c[3], R w4[3][4], R dw4[3][4], Support<R, 1> &sq) {
+        const uint32_t p = item.start + threadIdx.x + rr * T;
+        const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+        make_support<R, 1>(S, xp, c, sq);
+        for (int a = 0; a < 3; ++a)
+            anchor4<R>(sq.w[a], sq.dw[a], sq.base[a] == c[a] ? 1 : 0, w4[a], dw4[a]);
+    };
+    // pass 1: mass and momentum of particle ra, and of rb (>= 0) in its cell
+    auto mass_momentum = [&](int ra, int rb) {
+        int c[3];
+        unpack_cell(pc[ra], c);
+        const int np_ = rb >= 0 ? 2 : 1;
+        R w4[2][3][4], dw4[3][4], m[2], mv[2][3];
+        Support<R, 1> sq[2];
+        for (int u = 0; u < np_; ++u) {
+            const int rq = u ? rb : ra;
+            const uint32_t p = item.start + threadIdx.x + rq * T;
+            support(rq, c, w4[u], dw4, sq[u]);
+            m[u] = ldg(P.mass, p);
+            for (int a = 0; a < 3; ++a)
+                mv[u][a] = m[u] * ldg(P.v[a], p);
+        }
+        if (anch) {
+            const int a0 = entry(c[0] - 1, c[1] - 1, c[2] - 1);
+            for (int k = 0; k < 4; ++k)
+                for (int j = 0; j < 4; ++j) {
+                    R y[2];
+                    for (int u = 0; u < np_; ++u)
+                        y[u] = w4[u][1][j] * w4[u][2][k];
+                    for (int i = 0; i < 4; ++i) {
+                        R sm = (R)0, s0 = (R)0, s1 = (R)0, s2 = (R)0;
+                        for (int u = 0; u < np_; ++u) {
+                            const R N = w4[u][0][i] * y[u];
+                            sm += N * m[u];
+                            s0 += N * mv[u][0];
+                            s1 += N * mv[u][1];
+                            s2 += N * mv[u][2];
+                        }
+                        const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
+                        atomicAdd(&acc[0][li], (double)sm);
+                        atomicAdd(&acc[1][li], (double)s0);
+                        atomicAdd(&acc[2][li], (double)s1);
+                        atomicAdd(&acc[3][li], (double)s2);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                }
+        } else {
+            const Support<R, 1> &sp = sq[0];
+            const int b0 = entry(sp.base[0], sp.base[1], sp.base[2]);
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 3; ++j)
+                    for (int i = 0; i < 3; ++i) {
+                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                        const int li = b0 + i + px * j + pxy * k;
+                        atomicAdd(&acc[0][li], (double)(N * m[0]));
+                        atomicAdd(&acc[1][li], (double)(N * mv[0][0]));
+                        atomicAdd(&acc[2][li], (double)(N * mv[0][1]));
+                        atomicAdd(&acc[3][li], (double)(N * mv[0][2]));
+                    }
+        }
+    };
+    // pass 2: internal and external force of particle ra, and of rb (>= 0)
+    // in its cell: f_a = A_a0 dN/dx + A_a1 dN/dy + A_a2 dN/dz + N m g_a with
+    // A = -V sigma; on a support row (j, k), dN/dx = dw_i P1, dN/dy = w_i P2,
+    // dN/dz = w_i P3 and N = w_i P1
+    auto forces = [&](int ra, int rb) {
+        int c[3];
+        unpack_cell(pc[ra], c);
+        const int np_ = rb >= 0 ? 2 : 1;
+        R w4[2][3][4], dw4[2][3][4], A[2][6], mg[2][3];
+        Support<R, 1> sq[2];
+        for (int u = 0; u < np_; ++u) {
+            const int rq = u ? rb : ra;
+            const uint32_t p = item.start + threadIdx.x + rq * T;
+            support(rq, c, w4[u], dw4[u], sq[u]);
+            const R mq = ldg(P.mass, p), vq = ldg(P.vol, p);
+            for (int k = 0; k < 6; ++k)
+                A[u][k] = -vq * ldg(P.sig[k], p);
+            mg[u][0] = mq * gx;
+            mg[u][1] = mq * gy;
+            mg[u][2] = mq * gz;
+        }
+        if (anch) {
+            const int a0 = entry(c[0] - 1, c[1] - 1, c[2] - 1);
+            for (int k = 0; k < 4; ++k)
+                for (int j = 0; j < 4; ++j) {
+                    R f[4][3];
+                    for (int i = 0; i < 4; ++i)
+                        f[i][0] = f[i][1] = f[i][2] = (R)0;
+                    for (int u = 0; u < np_; ++u) {
+                        const R P1 = w4[u][1][j] * w4[u][2][k], P2 = dw4[u][1][j] * w4[u][2][k],
+                                P3 = w4[u][1][j] * dw4[u][2][k];
+                        const R X[3] = {A[u][0] * P1, A[u][3] * P1, A[u][5] * P1};
+                        const R Y[3] = {A[u][3] * P2 + A[u][5] * P3 + mg[u][0] * P1,
+                                        A[u][1] * P2 + A[u][4] * P3 + mg[u][1] * P1,
+                                        A[u][4] * P2 + A[u][2] * P3 + mg[u][2] * P1};
+                        for (int i = 0; i < 4; ++i)
+                            for (int a = 0; a < 3; ++a) {
+                                f[i][a] += dw4[u][0][i] * X[a];
+                                f[i][a] += w4[u][0][i] * Y[a];
+                            }
+                    }
+                    for (int i = 0; i < 4; ++i) {
+                        const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
+                        atomicAdd(&acc[0][li], (double)f[i][0]);
+                        atomicAdd(&acc[1][li], (double)f[i][1]);
+                        atomicAdd(&acc[2][li], (double)f[i][2]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                }
+        } else {
+            const Support<R, 1> &sp = sq[0];
+            const int b0 = entry(sp.base[0], sp.base[1], sp.base[2]);
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 3; ++j)
+                    for (int i = 0; i < 3; ++i) {
+                        const R P1 = sp.w[1][j] * sp.w[2][k], P2 = sp.dw[1][j] * sp.w[2][k],
+                                P3 = sp.w[1][j] * sp.dw[2][k];
+                        const R dx = sp.dw[0][i] * P1, dy = sp.w[0][i] * P2, dz = sp.w[0][i] * P3,
+                                N = sp.w[0][i] * P1;
+                        const int li = b0 + i + px * j + pxy * k;
+                        atomicAdd(&acc[0][li], (double)(A[0][0] * dx + A[0][3] * dy + A[0][5] * dz + N * mg[0][0]));
+                        atomicAdd(&acc[1][li], (double)(A[0][3] * dx + A[0][1] * dy + A[0][4] * dz + N * mg[0][1]));
+                        atomicAdd(&acc[2][li], (double)(A[0][5] * dx + A[0][4] * dy + A[0][2] * dz + N * mg[0][2]));
+                    }
+        }
+    };
+    // a pair: successive particles rr, rr + 1 of the thread in one cell
+    auto each = [&](auto &&fn) {
+#pragma unroll
+        for (int rr = 0; rr < KP; rr += 2) {
+            if (threadIdx.x + rr * T >= item.count)
+                break;
+            const bool has1 = rr + 1 < KP && threadIdx.x + (rr + 1) * T < item.count;
+            if (anch && has1 && pc[rr] == pc[rr + 1]) {
+                fn(rr, rr + 1);
+                continue;
+            }
+            fn(rr, -1);
+            if (has1)
+                fn(rr + 1, -1);
+        }
+    };
+    each(mass_momentum);
+    __syncthreads();
+    for (int q = threadIdx.x; q < tv; q += T) {
+        int i, j, k;
+        tile_node_small(t, q, i, j, k);
+        const int e = entry(i, j, k);
+        const double m = acc[0][e];
+        if (m != 0.0) {
+            const uint32_t I = node_id(S, i, j, k);
+            addg(nb.m, I, m);
+            for (int a = 0; a < 3; ++a)
+                addg(nb.p[a], I, (R)acc[1 + a][e]);
+        }
+        if constexpr (WITH_FORCE)
+            acc[0][e] = acc[1][e] = acc[2][e] = 0.0;
+    }
+    __syncthreads();
+    if constexpr (WITH_FORCE) {
+        each(forces);
+        __syncthreads();
+        for (int q = threadIdx.x; q < tv; q += T) {
+            int i, j, k;
+            tile_node_small(t, q, i, j, k);
+            const int e = entry(i, j, k);
+            const R f0 = (R)acc[0][e], f1 = (R)acc[1][e], f2 = (R)acc[2][e];
+            if (f0 == (R)0 && f1 == (R)0 && f2 == (R)0)
+                continue;
+            const uint32_t I = node_id(S, i, j, k);
+            addg(nb.f[0], I, f0);
+            addg(nb.f[1], I, f1);
+            addg(nb.f[2], I, f2);
+        }
+        __syncthreads();
+    }
+}
+
 // Nodal mass and momentum into the step's node buffer (first step of a call;
 // USF scenes whose buffer is already filled skip it); with WITH_FORCE also
 // the nodal force from the current stress and volume (USL and MUSL, every
@@ -1987,7 +2197,12 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
     constexpr int NACC = WITH_FORCE ? 7 : 4;
-    __shared__ double acc[NACC][CAP];
+    // GIMP: mass and momentum, then (with force) the force, in two passes
+    // over one set of four accumulators, laid out at the anchored pitches
+    // when the item's box fits them
+    constexpr int ACC_N = SH == 1 ? 4 : NACC;
+    constexpr int ACC_CAP = SH == 1 ? kAnchCap : CAP;
+    __shared__ double acc[ACC_N][ACC_CAP];
     __shared__ int red[6 * (T / 64)];
     clear_reorder_flags(B);
     if constexpr (REMAP)
@@ -2030,11 +2245,15 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
             continue;
         }
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+        const R gx = cst<R>(S.g[0], S.f_g[0]), gy = cst<R>(S.g[1], S.f_g[1]), gz = cst<R>(S.g[2], S.f_g[2]);
+        if constexpr (SH == 1) {
+            p2g_gimp_item<R, WITH_FORCE, T>(S, P, nb, item, t, acc, gx, gy, gz);
+            continue;
+        } else {
         for (int q = threadIdx.x; q < tv; q += blockDim.x)
             for (int c = 0; c < NACC; ++c)
                 acc[c][q] = 0.0;
         __syncthreads();
-        const R gx = cst<R>(S.g[0], S.f_g[0]), gy = cst<R>(S.g[1], S.f_g[1]), gz = cst<R>(S.g[2], S.f_g[2]);
         // a work item holds at most kChunk particles: a fixed trip count the
         // compiler unrolls, keeping the next particle's loads in flight
 #pragma unroll
@@ -2097,6 +2316,7 @@ __global__ void __launch_bounds__(T) k_p2g(BatchDev B)
                     addg(nb.f[a], I, (R)acc[4 + a][q]);
         }
         __syncthreads();
+        }
     }
 }
 
