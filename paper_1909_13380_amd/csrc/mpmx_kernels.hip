@@ -3317,6 +3317,165 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
     }
 }
 
+// GIMP k_musl_g2p for one work item (the gather tile loaded, the block
+// synchronized): each particle's velocity from the tile; then, over the same
+// LDS, the remap of the updated momenta with the start-of-step weights into
+// the anchored slots of each particle's cell, a thread's two particles in
+// one cell sharing one set of adds (the 27-slot form at the box's pitches
+// when the box does not fit the anchored layout); flushed to the remap array.
+template <typename R, int T>
+__device__ __attribute__((always_inline)) inline void musl_g2p_gimp_item(const SceneDev &S, const Parts<R> &P,
+                                                                         const Item &item, const Tile &t,
+                                                                         const R4<R> *la, const R4<R> *lvn,
+                                                                         double (*acc)[kAnchCap])
+{
+    constexpr int NS = ShapeTraits<1>::NS;
+    constexpr int KP = kChunk / T;
+    const int tv = t.dim[0] * t.dim[1] * t.dim[2];
+    const R dt = cst<R>(S.dt, S.f_dt);
+    const int pic = S.vel_update == 1;
+    uint32_t err = 0;
+    R mvs[KP][3];
+    uint32_t pcl[KP];
+    bool ok[KP];
+#pragma unroll
+    for (int rr = 0; rr < KP; ++rr) {
+        ok[rr] = false;
+        pcl[rr] = 0xffffffffu;
+        const uint32_t q = threadIdx.x + rr * T;
+        if (q >= item.count)
+            continue;
+        const uint32_t p = item.start + q;
+        const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+        pcl[rr] = ldg(P.cell, p);
+        int c[3];
+        unpack_cell(pcl[rr], c);
+        Support<R, 1> sp;
+        make_support<R, 1>(S, xp, c, sp);
+        const Corners cn = corners(S, t, sp.base);
+        R dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+        for (int k = 0; k < NS; ++k)
+            for (int j = 0; j < NS; ++j)
+                for (int i = 0; i < NS; ++i) {
+                    const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                    const int li = cn.t0 + i + j * cn.ty + k * cn.tz;
+                    const R4<R> a = la[li];
+                    const R4<R> u = lvn[li];
+                    dv[0] += N * a.x;
+                    dv[1] += N * a.y;
+                    dv[2] += N * a.z;
+                    vp[0] += N * u.x;
+                    vp[1] += N * u.y;
+                    vp[2] += N * u.z;
+                    if (i == NS - 1)
+                        __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
+                }
+        pin_sums<R>(dv, vp);
+        const R mp = ldg(P.mass, p);
+        for (int a = 0; a < 3; ++a) {
+            const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
+            stg(P.v[a], p, nva);
+            mvs[rr][a] = mp * nva;
+            if (!isfinite(nva))
+                err |= ERR_NONFINITE;
+        }
+        ok[rr] = true;
+    }
+    if (err)
+        atomicOr(&S.ctl[CTL_ERR], err);
+    // every gather from the tile is done: the same LDS now accumulates
+    __syncthreads();
+    const bool anch = t.dim[0] <= kAnchPX && t.dim[1] <= 9 && t.dim[2] <= 9;
+    const int px = anch ? kAnchPX : t.dim[0], pxy = anch ? kAnchPXY : t.dim[0] * t.dim[1];
+    auto entry = [&](int i, int j, int k) { return (i - t.lo[0]) + px * (j - t.lo[1]) + pxy * (k - t.lo[2]); };
+    for (int q = threadIdx.x; q < tv; q += T) {
+        int i, j, k;
+        tile_node_small(t, q, i, j, k);
+        const int e = entry(i, j, k);
+        acc[0][e] = acc[1][e] = acc[2][e] = 0.0;
+    }
+    __syncthreads();
+    // the updated momenta of particle ra, and of rb (>= 0) in its cell
+    auto remap = [&](int ra, int rb) {
+        int c[3];
+        unpack_cell(pcl[ra], c);
+        const int np_ = rb >= 0 ? 2 : 1;
+        R w4[2][3][4], unused[4];
+        Support<R, 1> sq[2];
+        for (int u = 0; u < np_; ++u) {
+            const uint32_t p = item.start + threadIdx.x + (u ? rb : ra) * T;
+            const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            make_support<R, 1>(S, xp, c, sq[u]);
+            for (int a = 0; a < 3; ++a)
+                anchor4<R>(sq[u].w[a], sq[u].dw[a], sq[u].base[a] == c[a] ? 1 : 0, w4[u][a], unused);
+        }
+        if (anch) {
+            const int a0 = entry(c[0] - 1, c[1] - 1, c[2] - 1);
+            for (int k = 0; k < 4; ++k)
+                for (int j = 0; j < 4; ++j) {
+                    R y[2];
+                    for (int u = 0; u < np_; ++u)
+                        y[u] = w4[u][1][j] * w4[u][2][k];
+                    for (int i = 0; i < 4; ++i) {
+                        R s0 = (R)0, s1 = (R)0, s2 = (R)0;
+                        for (int u = 0; u < np_; ++u) {
+                            const R N = w4[u][0][i] * y[u];
+                            const int ru = u ? rb : ra;
+                            s0 += N * mvs[ru][0];
+                            s1 += N * mvs[ru][1];
+                            s2 += N * mvs[ru][2];
+                        }
+                        const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
+                        atomicAdd(&acc[0][li], (double)s0);
+                        atomicAdd(&acc[1][li], (double)s1);
+                        atomicAdd(&acc[2][li], (double)s2);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                }
+        } else {
+            const Support<R, 1> &sp = sq[0];
+            const int b0 = entry(sp.base[0], sp.base[1], sp.base[2]);
+            for (int k = 0; k < NS; ++k)
+                for (int j = 0; j < NS; ++j)
+                    for (int i = 0; i < NS; ++i) {
+                        const R N = sp.w[0][i] * sp.w[1][j] * sp.w[2][k];
+                        const int li = b0 + i + px * j + pxy * k;
+                        atomicAdd(&acc[0][li], (double)(N * mvs[ra][0]));
+                        atomicAdd(&acc[1][li], (double)(N * mvs[ra][1]));
+                        atomicAdd(&acc[2][li], (double)(N * mvs[ra][2]));
+                    }
+        }
+    };
+#pragma unroll
+    for (int rr = 0; rr < KP; rr += 2) {
+        const bool has1 = rr + 1 < KP && ok[rr + 1];
+        if (anch && ok[rr] && has1 && pcl[rr] == pcl[rr + 1]) {
+            remap(rr, rr + 1);
+            continue;
+        }
+        if (ok[rr])
+            remap(rr, -1);
+        if (has1)
+            remap(rr + 1, -1);
+    }
+    __syncthreads();
+    GLOBAL R *NR = gp((R *)S.nr);
+    const uint32_t nn = (uint32_t)S.nn;
+    for (int q = threadIdx.x; q < tv; q += T) {
+        int i, j, k;
+        tile_node_small(t, q, i, j, k);
+        const int e = entry(i, j, k);
+        const double r0 = acc[0][e], r1 = acc[1][e], r2 = acc[2][e];
+        if (r0 == 0.0 && r1 == 0.0 && r2 == 0.0)
+            continue;
+        const uint32_t I = node_id(S, i, j, k);
+        addg(NR, I, (R)r0);
+        addg(NR, nn + I, (R)r1);
+        addg(NR, 2 * nn + I, (R)r2);
+    }
+    __syncthreads();
+}
+
 // MUSL, after p2g_usl: particle velocity (FLIP or PIC) from the nodal
 // acceleration and updated velocity, then the updated particle momenta back
 // to the nodes through the same start-of-step shape functions, summed in the
@@ -3327,9 +3486,16 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
-    __shared__ R4<R> la[CAP];
-    __shared__ R4<R> lvn[CAP];
-    __shared__ double acc[3][CAP];
+    // GIMP: the remap's accumulators, in the anchored layout, overlay the
+    // gather tile (every particle is gathered before the remap starts)
+    constexpr bool OV = SH == 1;
+    constexpr int ACC_CAP = OV ? kAnchCap : CAP;
+    constexpr int TILE_BYTES = 2 * CAP * (int)sizeof(R4<R>), ACC_BYTES = 3 * ACC_CAP * (int)sizeof(double);
+    __shared__ __attribute__((aligned(16))) char lds[OV ? (TILE_BYTES > ACC_BYTES ? TILE_BYTES : ACC_BYTES)
+                                                        : TILE_BYTES + ACC_BYTES];
+    R4<R> *la = (R4<R> *)lds;
+    R4<R> *lvn = la + CAP;
+    double (*acc)[ACC_CAP] = (double (*)[ACC_CAP])(lds + (OV ? 0 : TILE_BYTES));
     const int64_t total = B.ioffs[B.nscenes];
     const ItemRange ir = item_range(total);
     for (int64_t g = ir.first; g < ir.end; g += ir.step) {
@@ -3347,6 +3513,11 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
         const NodeBuf<R> nb = node_buf<R>(S, buf);
         const int tv = t.dim[0] * t.dim[1] * t.dim[2];
         load_update_tile<R>(S, nb, t, la, lvn);
+        if constexpr (OV) {
+            __syncthreads();
+            musl_g2p_gimp_item<R, T>(S, P, item, t, la, lvn, acc);
+            continue;
+        } else {
         for (int q = threadIdx.x; q < tv; q += blockDim.x)
             acc[0][q] = acc[1][q] = acc[2][q] = 0.0;
         __syncthreads();
@@ -3416,6 +3587,7 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
             addg(NR, 2 * nn + I, (R)r2);
         }
         __syncthreads();
+        }
     }
 }
 
