@@ -249,7 +249,7 @@ const char *mpmx_last_error(const mpmx_ctx *ctx);
  *                          the item kernels at every pair of workgroup size
  *                          and grid density (3 steps each), then keep, for
  *                          each of the two kernels, its fastest pair for
- *                          that layout; pairs at most 2 % plus 2 us
+ *                          that layout; pairs at most 1 % plus 2 us
  *                          slower than the fastest count as ties, settled
  *                          by a fixed preference order (16 workgroups per
  *                          CU and 256 threads first), so that the choice is

@@ -676,7 +676,7 @@ constexpr int kTuneReps = 3;
 constexpr int kTuneDensity[] = {8, 16, 32, 64};
 constexpr int kNumTuneDensity = 4;
 constexpr int kTuneSteps = kTuneReps * kNumItemThreadChoices * kNumTuneDensity;
-constexpr float kTuneBand = 0.02f;
+constexpr float kTuneBand = 0.01f;
 constexpr float kTuneSlackMs = 0.002f;
 static_assert(kTuneSteps + 1 <= MPMX_TUNE_MIN_STEPS, "tuning must fit in the calls it runs on");
 
