@@ -2354,6 +2354,15 @@ __device__ inline void pin_grad(R (&L)[3][3])
                  "+v"(L[2][0]), "+v"(L[2][1]), "+v"(L[2][2]));
 }
 
+// Keep loaded particle values at their loads: a value that one branch alone
+// uses (FLIP's old velocity) is otherwise loaded inside that branch, one more
+// memory round trip per particle.  An empty statement, no code.
+template <typename R>
+__device__ inline void pin_loaded(const R (&v)[3])
+{
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]));
+}
+
 __device__ inline bool same_base(const int a[3], const int b[3])
 {
     return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
@@ -2537,6 +2546,17 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                 break;
             const uint32_t p = item.start + q;
             const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            // every input of the particle in one round trip, except on
+            // isoparametric cells, whose inverse Jacobian leaves no registers
+            // for them (one wavefront per SIMD fewer, measured slower)
+            R vol0 = 0, sg[6] = {0, 0, 0, 0, 0, 0}, mp = 0;
+            if constexpr (SH != 2) {
+                vol0 = ldg(P.vol, p);
+                for (int k = 0; k < 6; ++k)
+                    sg[k] = ldg(P.sig[k], p);
+                mp = ldg(P.mass, p);
+            }
+            __builtin_amdgcn_sched_barrier(0);   // the particle's loads in one round trip
             int c[3];
             unpack_cell(pcell[rr], c);
             Support<R, SH> sp;
@@ -2638,10 +2658,12 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-            const R vol = ldg(P.vol, p) * ((R)1 + de[0] + de[1] + de[2]);
-            R sg[6];
-            for (int k = 0; k < 6; ++k)
-                sg[k] = ldg(P.sig[k], p);
+            if constexpr (SH == 2) {
+                vol0 = ldg(P.vol, p);
+                for (int k = 0; k < 6; ++k)
+                    sg[k] = ldg(P.sig[k], p);
+            }
+            const R vol = vol0 * ((R)1 + de[0] + de[1] + de[2]);
             constitutive<R>(S, de, sg);
             for (int k = 0; k < 6; ++k) {
                 stg(P.sig[k], p, sg[k]);
@@ -2649,7 +2671,8 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                     bad = ERR_NONFINITE;
             }
             stg(P.vol, p, vol);
-            const R mp = ldg(P.mass, p);
+            if constexpr (SH == 2)
+                mp = ldg(P.mass, p);
             auto deposit = [&](int i, int j, int k, R f0, R f1, R f2) {
                 if constexpr (SC) {
                     const int n = i + 2 * j + 4 * k;
@@ -2971,10 +2994,13 @@ __global__ void __launch_bounds__(T) k_g2p_p2g(BatchDev B)
             double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
             const R pv[3] = {ldg(P.v[0], p), ldg(P.v[1], p), ldg(P.v[2], p)};
             const R mp = ldg(P.mass, p);
+            const uint32_t pc = ldg(P.cell, p);
+            __builtin_amdgcn_sched_barrier(0);   // the particle's loads in one round trip
             int c[3];
-            unpack_cell(ldg(P.cell, p), c);
+            unpack_cell(pc, c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
+            pin_loaded(pv);
             const Corners cn = corners(S, t, sp.base);
             if constexpr (GC) {
                 if (!same_base(sp.base, gb)) {
@@ -3226,10 +3252,23 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
             double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            const R pv[3] = {ldg(P.v[0], p), ldg(P.v[1], p), ldg(P.v[2], p)};
+            // volume and stress with the position, except under GIMP, whose
+            // support sums leave no registers for them (one wavefront per
+            // SIMD fewer, measured slower)
+            R vol0 = 0, sg[6] = {0, 0, 0, 0, 0, 0};
+            if constexpr (SH != 1) {
+                vol0 = ldg(P.vol, p);
+                for (int k = 0; k < 6; ++k)
+                    sg[k] = ldg(P.sig[k], p);
+            }
+            const uint32_t pc = ldg(P.cell, p);
+            __builtin_amdgcn_sched_barrier(0);   // the particle's loads in one round trip
             int c[3];
-            unpack_cell(ldg(P.cell, p), c);
+            unpack_cell(pc, c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
+            pin_loaded(pv);
             const Corners cn = corners(S, t, sp.base);
             R dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
             R L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -3267,7 +3306,7 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
             pin_sums<R>(dv, vp);
             pin_grad<R>(L);
             for (int a = 0; a < 3; ++a) {
-                const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
+                const R nva = pic ? vp[a] : pv[a] + dt * dv[a];
                 stg(P.v[a], p, nva);
                 xp[a] += S.dt * (double)vp[a];
                 stg(P.x[a], p, xp[a]);
@@ -3276,10 +3315,12 @@ __global__ void __launch_bounds__(T) k_g2p_usl(BatchDev B)
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-            stg(P.vol, p, ldg(P.vol, p) * ((R)1 + de[0] + de[1] + de[2]));
-            R sg[6];
-            for (int k = 0; k < 6; ++k)
-                sg[k] = ldg(P.sig[k], p);
+            if constexpr (SH == 1) {
+                vol0 = ldg(P.vol, p);
+                for (int k = 0; k < 6; ++k)
+                    sg[k] = ldg(P.sig[k], p);
+            }
+            stg(P.vol, p, vol0 * ((R)1 + de[0] + de[1] + de[2]));
             constitutive<R>(S, de, sg);
             for (int k = 0; k < 6; ++k) {
                 stg(P.sig[k], p, sg[k]);
@@ -3527,10 +3568,15 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
             const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            const R pv[3] = {ldg(P.v[0], p), ldg(P.v[1], p), ldg(P.v[2], p)};
+            const R mp = ldg(P.mass, p);
+            const uint32_t pc = ldg(P.cell, p);
+            __builtin_amdgcn_sched_barrier(0);   // the particle's loads in one round trip
             int c[3];
-            unpack_cell(ldg(P.cell, p), c);
+            unpack_cell(pc, c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
+            pin_loaded(pv);
             const Corners cn = corners(S, t, sp.base);
             R dv[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
             for (int k = 0; k < NS; ++k)
@@ -3551,10 +3597,9 @@ __global__ void __launch_bounds__(T) k_musl_g2p(BatchDev B)
                                 __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
             pin_sums<R>(dv, vp);
-            const R mp = ldg(P.mass, p);
             R mv[3];
             for (int a = 0; a < 3; ++a) {
-                const R nva = pic ? vp[a] : ldg(P.v[a], p) + dt * dv[a];
+                const R nva = pic ? vp[a] : pv[a] + dt * dv[a];
                 stg(P.v[a], p, nva);
                 mv[a] = mp * nva;
                 if (!isfinite(nva))
@@ -3643,8 +3688,14 @@ __global__ void __launch_bounds__(T) k_musl_stress(BatchDev B)
         for (uint32_t q = threadIdx.x; q < item.count; q += blockDim.x) {
             const uint32_t p = item.start + q;
             double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+            const R vol0 = ldg(P.vol, p);
+            R sg[6];
+            for (int k = 0; k < 6; ++k)
+                sg[k] = ldg(P.sig[k], p);
+            const uint32_t pc = ldg(P.cell, p);
+            __builtin_amdgcn_sched_barrier(0);   // the particle's loads in one round trip
             int c[3];
-            unpack_cell(ldg(P.cell, p), c);
+            unpack_cell(pc, c);
             Support<R, SH> sp;
             make_support<R, SH>(S, xp, c, sp);
             const Corners cn = corners(S, t, sp.base);
@@ -3685,10 +3736,7 @@ __global__ void __launch_bounds__(T) k_musl_stress(BatchDev B)
             }
             const R de[6] = {dt * L[0][0], dt * L[1][1], dt * L[2][2], dt * (L[0][1] + L[1][0]),
                              dt * (L[1][2] + L[2][1]), dt * (L[0][2] + L[2][0])};
-            stg(P.vol, p, ldg(P.vol, p) * ((R)1 + de[0] + de[1] + de[2]));
-            R sg[6];
-            for (int k = 0; k < 6; ++k)
-                sg[k] = ldg(P.sig[k], p);
+            stg(P.vol, p, vol0 * ((R)1 + de[0] + de[1] + de[2]));
             constitutive<R>(S, de, sg);
             for (int k = 0; k < 6; ++k) {
                 stg(P.sig[k], p, sg[k]);
