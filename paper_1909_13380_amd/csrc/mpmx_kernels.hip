@@ -564,6 +564,13 @@ __device__ inline uint32_t iso_locate(const SceneDev &S, const double x[3], int 
 // conflicts.  Measured on a probe of this pattern: 8.3 cycles per
 // wavefront-wide FP64 LDS add (2121 per 64 particles) against 31.5 (3407)
 // for the 27-slot form.
+// The rotated form keeps 27 slots and takes them in an order that mostly
+// avoids the collisions: on each axis slots 0 and 1 are the nodes c and
+// c + 1 for every lane, and slot 2 is c + 2 or c - 1 as the support
+// requires.  Only slots 2 mix two translates: 16.7 cycles per add on the
+// same layout (1806 per 64 particles), with 27/64 of the anchored form's
+// arithmetic.  It suits the force scatter, whose anchored form is
+// VALU-bound; two particles of one cell cannot share its adds.
 constexpr int kAnchPX = 12, kAnchPXY = 108, kAnchCap = 972;   // 12 x 9 x 9 entries
 
 // The 4 anchored weights (and their derivatives) of one axis from a 3-node
@@ -2368,15 +2375,16 @@ __device__ inline bool same_base(const int a[3], const int b[3])
     return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
 }
 
-// Register caps of k_stress, as wavefronts per SIMD (1: none), where
-// measurement showed more waves in flight to pay: FP32 GIMP at 256 threads
-// (4: 128 VGPRs, 28 bytes of spills; 1874 -> 1618 us on the 25.2M-particle
-// column) and FP32 linear at 128 threads (6: 79 VGPRs, no spills; 344 ->
-// 324 us on the 256-scene batch).
+// Register cap of k_stress, as wavefronts per SIMD (1: none), where
+// measurement showed more waves in flight to pay: FP32 linear at 128
+// threads (6: 79-80 VGPRs, at most 16 bytes of spills; 344 -> 324 us on the
+// 256-scene batch).  The FP32 GIMP kernel at 256 threads needed a cap of 4
+// with its paired anchored force scatter; with the rotated one it takes 88
+// VGPRs and its LDS sets the occupancy.
 template <typename R, int SH, int T>
 constexpr int stress_waves()
 {
-    return sizeof(R) != 4 ? 1 : (SH == 1 && T == 256) ? 4 : (SH == 0 && T == 128) ? 6 : 1;
+    return sizeof(R) != 4 ? 1 : (SH == 0 && T == 128) ? 6 : 1;
 }
 
 // USF: zero the previous step's node buffer; nodal velocity, strain
@@ -2471,67 +2479,6 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
         int fb[3] = {-(1 << 30), 0, 0};   // support base of the force accumulators
         Corners kc{};
         R cv[GN][3], fa[SN][3];
-        // anchored GIMP: the updated stress and volume of each of the
-        // thread's particles, for the paired force scatter after the loop
-        R dsg[SH == 1 ? KP : 1][6], dvol[SH == 1 ? KP : 1];
-        bool dok[SH == 1 ? KP : 1];
-        for (int rr = 0; rr < (SH == 1 ? KP : 1); ++rr)
-            dok[rr] = false;
-        // internal and external force of particle ra, and of particle rb (>= 0)
-        // in the same cell, into the anchored slots of that cell
-        auto anchored_forces = [&](int ra, int rb) {
-            if constexpr (SH == 1) {
-                R w4[2][3][4], dw4[2][3][4], A[2][6], mg[2][3];
-                int c[3];
-                unpack_cell(pcell[ra], c);
-                const int np_ = rb >= 0 ? 2 : 1;
-                for (int u = 0; u < np_; ++u) {
-                    const int rq = u ? rb : ra;
-                    const uint32_t p = item.start + threadIdx.x + rq * T;
-                    const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
-                    Support<R, SH> sq;
-                    make_support<R, SH>(S, xp, c, sq);
-                    for (int a = 0; a < 3; ++a)
-                        anchor4<R>(sq.w[a], sq.dw[a], sq.base[a] == c[a] ? 1 : 0, w4[u][a], dw4[u][a]);
-                    const R mq = ldg(P.mass, p);
-                    for (int k = 0; k < 6; ++k)
-                        A[u][k] = -dvol[rq] * dsg[rq][k];
-                    mg[u][0] = mq * gx;
-                    mg[u][1] = mq * gy;
-                    mg[u][2] = mq * gz;
-                }
-                const int a0 = (c[0] - 1 - t.lo[0]) + kAnchPX * (c[1] - 1 - t.lo[1]) + kAnchPXY * (c[2] - 1 - t.lo[2]);
-                for (int k = 0; k < 4; ++k)
-                    for (int j = 0; j < 4; ++j) {
-                        R f[4][3];
-                        for (int i = 0; i < 4; ++i)
-                            f[i][0] = f[i][1] = f[i][2] = (R)0;
-                        for (int u = 0; u < np_; ++u) {
-                            // f_a = A_a0 dN/dx + A_a1 dN/dy + A_a2 dN/dz + N m g_a with
-                            // dN/dx = dw_i P1, dN/dy = w_i P2, dN/dz = w_i P3, N = w_i P1:
-                            // the row's (j, k) factors once, then two terms per slot
-                            const R P1 = w4[u][1][j] * w4[u][2][k], P2 = dw4[u][1][j] * w4[u][2][k],
-                                    P3 = w4[u][1][j] * dw4[u][2][k];
-                            const R X[3] = {A[u][0] * P1, A[u][3] * P1, A[u][5] * P1};
-                            const R Y[3] = {A[u][3] * P2 + A[u][5] * P3 + mg[u][0] * P1,
-                                            A[u][1] * P2 + A[u][4] * P3 + mg[u][1] * P1,
-                                            A[u][4] * P2 + A[u][2] * P3 + mg[u][2] * P1};
-                            for (int i = 0; i < 4; ++i)
-                                for (int a = 0; a < 3; ++a) {   // two fused multiply-adds
-                                    f[i][a] += dw4[u][0][i] * X[a];
-                                    f[i][a] += w4[u][0][i] * Y[a];
-                                }
-                        }
-                        for (int i = 0; i < 4; ++i) {
-                            const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
-                            atomicAdd(&lf[0][li], (double)f[i][0]);
-                            atomicAdd(&lf[1][li], (double)f[i][1]);
-                            atomicAdd(&lf[2][li], (double)f[i][2]);
-                        }
-                        __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
-                    }
-            }
-        };
         auto flush = [&]() {
             for (int n = 0; n < SN; ++n) {
                 const int li = kc.t0 + (n & 1) + ((n >> 1) & 1) * kc.ty + (n >> 2) * kc.tz;
@@ -2719,11 +2666,48 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                                     N * mg2 + B[2][0] * ax + B[2][1] * ay + B[2][2] * az);
                         }
             } else if (anch) {
-                // after the particle loop, in pairs (anchored_forces)
+                // the 27 support nodes in rotated order (see kAnchPX): on each
+                // axis slots 0 and 1 are the nodes c and c + 1, slot 2 the
+                // node c + 2 (support from c) or c - 1 (support from c - 1), so
+                // a wavefront's lanes mostly add to one translate of their
+                // cells.  f_a = A_a0 dN/dx + A_a1 dN/dy + A_a2 dN/dz + N m g_a
+                // with A = -V sigma, dN/dx = dw_i P1, dN/dy = w_i P2,
+                // dN/dz = w_i P3, N = w_i P1: the row's (j, k) factors once,
+                // then two terms per slot
+                R wr[3][3], dr[3][3];
+                int e[3];
+                for (int a = 0; a < 3; ++a) {
+                    const bool up = sp.base[a] == c[a];
+                    wr[a][0] = up ? sp.w[a][0] : sp.w[a][1];
+                    wr[a][1] = up ? sp.w[a][1] : sp.w[a][2];
+                    wr[a][2] = up ? sp.w[a][2] : sp.w[a][0];
+                    dr[a][0] = up ? sp.dw[a][0] : sp.dw[a][1];
+                    dr[a][1] = up ? sp.dw[a][1] : sp.dw[a][2];
+                    dr[a][2] = up ? sp.dw[a][2] : sp.dw[a][0];
+                    e[a] = up ? 3 : 0;
+                }
+                R A[6];
                 for (int k = 0; k < 6; ++k)
-                    dsg[rr][k] = sg[k];
-                dvol[rr] = vol;
-                dok[rr] = true;
+                    A[k] = -vol * sg[k];
+                const R mg[3] = {mp * gx, mp * gy, mp * gz};
+                const int a0 = (c[0] - 1 - t.lo[0]) + kAnchPX * (c[1] - 1 - t.lo[1]) + kAnchPXY * (c[2] - 1 - t.lo[2]);
+                const int ox[3] = {1, 2, e[0]}, oy[3] = {kAnchPX, 2 * kAnchPX, kAnchPX * e[1]},
+                          oz[3] = {kAnchPXY, 2 * kAnchPXY, kAnchPXY * e[2]};
+                for (int k = 0; k < 3; ++k)
+                    for (int j = 0; j < 3; ++j) {
+                        const R P1 = wr[1][j] * wr[2][k], P2 = dr[1][j] * wr[2][k], P3 = wr[1][j] * dr[2][k];
+                        const R X[3] = {A[0] * P1, A[3] * P1, A[5] * P1};
+                        const R Y[3] = {A[3] * P2 + A[5] * P3 + mg[0] * P1, A[1] * P2 + A[4] * P3 + mg[1] * P1,
+                                        A[4] * P2 + A[2] * P3 + mg[2] * P1};
+                        const int rb = a0 + oy[j] + oz[k];
+                        for (int i = 0; i < 3; ++i) {
+                            const int li = rb + ox[i];
+                            atomicAdd(&lf[0][li], (double)(dr[0][i] * X[0] + wr[0][i] * Y[0]));
+                            atomicAdd(&lf[1][li], (double)(dr[0][i] * X[1] + wr[0][i] * Y[1]));
+                            atomicAdd(&lf[2][li], (double)(dr[0][i] * X[2] + wr[0][i] * Y[2]));
+                        }
+                        __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
+                    }
             } else {
             for (int k = 0; k < NS; ++k)
                 for (int j = 0; j < NS; ++j)
@@ -2741,26 +2725,6 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                             if (i == NS - 1)
                                 __builtin_amdgcn_sched_barrier(0);   // one support layer of LDS reads in flight
                     }
-            }
-        }
-        if constexpr (SH == 1) {
-            if (anch) {
-                // particles rr and rr + 1 of a thread are successive particles
-                // of one cell in level-major order: such a pair shares one set
-                // of anchored adds (half the LDS atomics); positions and masses
-                // are loaded again (cache hits), the stress and volume kept
-#pragma unroll
-                for (int rr = 0; rr < KP; rr += 2) {
-                    const bool two = rr + 1 < KP && dok[rr] && dok[rr + 1] && pcell[rr] == pcell[rr + 1];
-                    if (two) {
-                        anchored_forces(rr, rr + 1);
-                        continue;
-                    }
-#pragma unroll
-                    for (int r2 = rr; r2 < rr + 2 && r2 < KP; ++r2)
-                        if (dok[r2])
-                            anchored_forces(r2, -1);
-                }
             }
         }
         if constexpr (SC)
