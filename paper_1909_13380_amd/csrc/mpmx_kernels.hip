@@ -588,6 +588,22 @@ __device__ inline void anchor4(const R w[3], const R dw[3], int d, R w4[4], R dw
     dw4[3] = d ? dw[2] : (R)0;
 }
 
+// The rotated slot order of one axis (see kAnchPX) from a 3-node support
+// that starts at cell c (up) or c - 1: weights and derivatives of the nodes
+// c, c + 1, then c + 2 (up) or c - 1; returns the last slot's offset from
+// node c - 1.
+template <typename R>
+__device__ inline int rotate3(const R w[3], const R dw[3], bool up, R wr[3], R dr[3])
+{
+    wr[0] = up ? w[0] : w[1];
+    wr[1] = up ? w[1] : w[2];
+    wr[2] = up ? w[2] : w[0];
+    dr[0] = up ? dw[0] : dw[1];
+    dr[1] = up ? dw[1] : dw[2];
+    dr[2] = up ? dw[2] : dw[0];
+    return up ? 3 : 0;
+}
+
 // Cells a per-step location walk may visit: a particle moves less than a
 // cell per step (CFL), so it ends in its cell or a neighbour of it.
 constexpr int kIsoWalk = 8;
@@ -1988,10 +2004,11 @@ __device__ inline Parts<R> parts(const SceneDev &S, int cur)
 // into the node box t, flushed to node buffer nb; with force, a second pass
 // of the nodal force (internal from the current stress and volume, and
 // gravity) through the same LDS accumulators.  When the box fits the
-// anchored layout (kAnchPX), each particle adds to the 4 x 4 x 4 anchored
-// slots of its cell, and a thread's two particles in one cell (successive
-// particles of the cell in level-major order) share one set of adds;
-// otherwise each particle adds to its 27-node support at the box's pitches.
+// anchored layout (kAnchPX), each particle adds its mass and momentum to the
+// 4 x 4 x 4 anchored slots of its cell, a thread's two particles in one cell
+// (successive particles of the cell in level-major order) sharing one set of
+// adds, and its force to its 27 support nodes in rotated order; otherwise
+// each particle adds to its 27-node support at the box's pitches.
 template <typename R, bool WITH_FORCE, int T>
 __device__ __attribute__((always_inline)) inline void p2g_gimp_item(const SceneDev &S, const Parts<R> &P, const NodeBuf<R> &nb, const Item &item,
                                      const Tile &t, double (*acc)[kAnchCap], R gx, R gy, R gz)
@@ -2076,57 +2093,48 @@ __device__ __attribute__((always_inline)) inline void p2g_gimp_item(const SceneD
                     }
         }
     };
-    // pass 2: internal and external force of particle ra, and of rb (>= 0)
-    // in its cell: f_a = A_a0 dN/dx + A_a1 dN/dy + A_a2 dN/dz + N m g_a with
-    // A = -V sigma; on a support row (j, k), dN/dx = dw_i P1, dN/dy = w_i P2,
-    // dN/dz = w_i P3 and N = w_i P1
-    auto forces = [&](int ra, int rb) {
+    // pass 2: internal and external force of particle rr: f_a = A_a0 dN/dx +
+    // A_a1 dN/dy + A_a2 dN/dz + N m g_a with A = -V sigma; on a support row
+    // (j, k), dN/dx = dw_i P1, dN/dy = w_i P2, dN/dz = w_i P3 and N = w_i P1.
+    // In the anchored layout the 27 slots go in rotated order (see kAnchPX):
+    // the pass is VALU-bound, and a pair's 64 shared slots cost more
+    // arithmetic than they save in LDS adds
+    auto forces = [&](int rr, int) {
         int c[3];
-        unpack_cell(pc[ra], c);
-        const int np_ = rb >= 0 ? 2 : 1;
-        R w4[2][3][4], dw4[2][3][4], A[2][6], mg[2][3];
-        Support<R, 1> sq[2];
-        for (int u = 0; u < np_; ++u) {
-            const int rq = u ? rb : ra;
-            const uint32_t p = item.start + threadIdx.x + rq * T;
-            support(rq, c, w4[u], dw4[u], sq[u]);
-            const R mq = ldg(P.mass, p), vq = ldg(P.vol, p);
-            for (int k = 0; k < 6; ++k)
-                A[u][k] = -vq * ldg(P.sig[k], p);
-            mg[u][0] = mq * gx;
-            mg[u][1] = mq * gy;
-            mg[u][2] = mq * gz;
-        }
+        unpack_cell(pc[rr], c);
+        const uint32_t p = item.start + threadIdx.x + rr * T;
+        const double xp[3] = {ldg(P.x[0], p), ldg(P.x[1], p), ldg(P.x[2], p)};
+        Support<R, 1> sp;
+        make_support<R, 1>(S, xp, c, sp);
+        const R mq = ldg(P.mass, p), vq = ldg(P.vol, p);
+        R A[6];
+        for (int k = 0; k < 6; ++k)
+            A[k] = -vq * ldg(P.sig[k], p);
+        const R mg[3] = {mq * gx, mq * gy, mq * gz};
         if (anch) {
+            R wr[3][3], dr[3][3];
+            int e[3];
+            for (int a = 0; a < 3; ++a)
+                e[a] = rotate3<R>(sp.w[a], sp.dw[a], sp.base[a] == c[a], wr[a], dr[a]);
             const int a0 = entry(c[0] - 1, c[1] - 1, c[2] - 1);
-            for (int k = 0; k < 4; ++k)
-                for (int j = 0; j < 4; ++j) {
-                    R f[4][3];
-                    for (int i = 0; i < 4; ++i)
-                        f[i][0] = f[i][1] = f[i][2] = (R)0;
-                    for (int u = 0; u < np_; ++u) {
-                        const R P1 = w4[u][1][j] * w4[u][2][k], P2 = dw4[u][1][j] * w4[u][2][k],
-                                P3 = w4[u][1][j] * dw4[u][2][k];
-                        const R X[3] = {A[u][0] * P1, A[u][3] * P1, A[u][5] * P1};
-                        const R Y[3] = {A[u][3] * P2 + A[u][5] * P3 + mg[u][0] * P1,
-                                        A[u][1] * P2 + A[u][4] * P3 + mg[u][1] * P1,
-                                        A[u][4] * P2 + A[u][2] * P3 + mg[u][2] * P1};
-                        for (int i = 0; i < 4; ++i)
-                            for (int a = 0; a < 3; ++a) {
-                                f[i][a] += dw4[u][0][i] * X[a];
-                                f[i][a] += w4[u][0][i] * Y[a];
-                            }
-                    }
-                    for (int i = 0; i < 4; ++i) {
-                        const int li = a0 + i + kAnchPX * j + kAnchPXY * k;
-                        atomicAdd(&acc[0][li], (double)f[i][0]);
-                        atomicAdd(&acc[1][li], (double)f[i][1]);
-                        atomicAdd(&acc[2][li], (double)f[i][2]);
+            const int ox[3] = {1, 2, e[0]}, oy[3] = {kAnchPX, 2 * kAnchPX, kAnchPX * e[1]},
+                      oz[3] = {kAnchPXY, 2 * kAnchPXY, kAnchPXY * e[2]};
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 3; ++j) {
+                    const R P1 = wr[1][j] * wr[2][k], P2 = dr[1][j] * wr[2][k], P3 = wr[1][j] * dr[2][k];
+                    const R X[3] = {A[0] * P1, A[3] * P1, A[5] * P1};
+                    const R Y[3] = {A[3] * P2 + A[5] * P3 + mg[0] * P1, A[1] * P2 + A[4] * P3 + mg[1] * P1,
+                                    A[4] * P2 + A[2] * P3 + mg[2] * P1};
+                    const int rb = a0 + oy[j] + oz[k];
+                    for (int i = 0; i < 3; ++i) {
+                        const int li = rb + ox[i];
+                        atomicAdd(&acc[0][li], (double)(dr[0][i] * X[0] + wr[0][i] * Y[0]));
+                        atomicAdd(&acc[1][li], (double)(dr[0][i] * X[1] + wr[0][i] * Y[1]));
+                        atomicAdd(&acc[2][li], (double)(dr[0][i] * X[2] + wr[0][i] * Y[2]));
                     }
                     __builtin_amdgcn_sched_barrier(0);   // one row of LDS adds in flight
                 }
         } else {
-            const Support<R, 1> &sp = sq[0];
             const int b0 = entry(sp.base[0], sp.base[1], sp.base[2]);
             for (int k = 0; k < 3; ++k)
                 for (int j = 0; j < 3; ++j)
@@ -2136,20 +2144,21 @@ __device__ __attribute__((always_inline)) inline void p2g_gimp_item(const SceneD
                         const R dx = sp.dw[0][i] * P1, dy = sp.w[0][i] * P2, dz = sp.w[0][i] * P3,
                                 N = sp.w[0][i] * P1;
                         const int li = b0 + i + px * j + pxy * k;
-                        atomicAdd(&acc[0][li], (double)(A[0][0] * dx + A[0][3] * dy + A[0][5] * dz + N * mg[0][0]));
-                        atomicAdd(&acc[1][li], (double)(A[0][3] * dx + A[0][1] * dy + A[0][4] * dz + N * mg[0][1]));
-                        atomicAdd(&acc[2][li], (double)(A[0][5] * dx + A[0][4] * dy + A[0][2] * dz + N * mg[0][2]));
+                        atomicAdd(&acc[0][li], (double)(A[0] * dx + A[3] * dy + A[5] * dz + N * mg[0]));
+                        atomicAdd(&acc[1][li], (double)(A[3] * dx + A[1] * dy + A[4] * dz + N * mg[1]));
+                        atomicAdd(&acc[2][li], (double)(A[5] * dx + A[4] * dy + A[2] * dz + N * mg[2]));
                     }
         }
     };
-    // a pair: successive particles rr, rr + 1 of the thread in one cell
-    auto each = [&](auto &&fn) {
+    // each particle of the thread; with pairs, successive particles rr,
+    // rr + 1 of one cell together
+    auto each = [&](auto &&fn, bool pairs) {
 #pragma unroll
         for (int rr = 0; rr < KP; rr += 2) {
             if (threadIdx.x + rr * T >= item.count)
                 break;
             const bool has1 = rr + 1 < KP && threadIdx.x + (rr + 1) * T < item.count;
-            if (anch && has1 && pc[rr] == pc[rr + 1]) {
+            if (pairs && anch && has1 && pc[rr] == pc[rr + 1]) {
                 fn(rr, rr + 1);
                 continue;
             }
@@ -2158,7 +2167,7 @@ __device__ __attribute__((always_inline)) inline void p2g_gimp_item(const SceneD
                 fn(rr + 1, -1);
         }
     };
-    each(mass_momentum);
+    each(mass_momentum, true);
     __syncthreads();
     for (int q = threadIdx.x; q < tv; q += T) {
         int i, j, k;
@@ -2176,7 +2185,7 @@ __device__ __attribute__((always_inline)) inline void p2g_gimp_item(const SceneD
     }
     __syncthreads();
     if constexpr (WITH_FORCE) {
-        each(forces);
+        each(forces, false);
         __syncthreads();
         for (int q = threadIdx.x; q < tv; q += T) {
             int i, j, k;
@@ -2676,16 +2685,8 @@ __global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchD
                 // then two terms per slot
                 R wr[3][3], dr[3][3];
                 int e[3];
-                for (int a = 0; a < 3; ++a) {
-                    const bool up = sp.base[a] == c[a];
-                    wr[a][0] = up ? sp.w[a][0] : sp.w[a][1];
-                    wr[a][1] = up ? sp.w[a][1] : sp.w[a][2];
-                    wr[a][2] = up ? sp.w[a][2] : sp.w[a][0];
-                    dr[a][0] = up ? sp.dw[a][0] : sp.dw[a][1];
-                    dr[a][1] = up ? sp.dw[a][1] : sp.dw[a][2];
-                    dr[a][2] = up ? sp.dw[a][2] : sp.dw[a][0];
-                    e[a] = up ? 3 : 0;
-                }
+                for (int a = 0; a < 3; ++a)
+                    e[a] = rotate3<R>(sp.w[a], sp.dw[a], sp.base[a] == c[a], wr[a], dr[a]);
                 R A[6];
                 for (int k = 0; k < 6; ++k)
                     A[k] = -vol * sg[k];
