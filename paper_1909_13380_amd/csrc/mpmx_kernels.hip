@@ -2384,22 +2384,10 @@ __device__ inline bool same_base(const int a[3], const int b[3])
     return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
 }
 
-// Register cap of k_stress, as wavefronts per SIMD (1: none), where
-// measurement showed more waves in flight to pay: FP32 linear at 128
-// threads (6: 79-80 VGPRs, at most 16 bytes of spills; 344 -> 324 us on the
-// 256-scene batch).  The FP32 GIMP kernel at 256 threads needed a cap of 4
-// with its paired anchored force scatter; with the rotated one it takes 88
-// VGPRs and its LDS sets the occupancy.
-template <typename R, int SH, int T>
-constexpr int stress_waves()
-{
-    return sizeof(R) != 4 ? 1 : (SH == 0 && T == 128) ? 6 : 1;
-}
-
 // USF: zero the previous step's node buffer; nodal velocity, strain
 // increment, volume and stress update, nodal internal + external force.
 template <typename R, int SH, int T>
-__global__ void __launch_bounds__(T, (stress_waves<R, SH, T>())) k_stress(BatchDev B)
+__global__ void __launch_bounds__(T) k_stress(BatchDev B)
 {
     constexpr int NS = ShapeTraits<SH>::NS;
     constexpr int CAP = ShapeTraits<SH>::cap;
