@@ -817,6 +817,30 @@ def test_usl_many_steps_with_reorders(ctx, mp, shape, algo):
         s.destroy()
 
 
+@pytest.mark.parametrize("algo", [0, 1, 2])
+def test_gimp_particles_anywhere_in_their_cells(ctx, mp, algo):
+    """GIMP with every position drawn uniformly inside its cell (not at
+    jittered sub-cell centres), so the supports of one wavefront's particles
+    start at c - 1 or c at random: the force and mass scatters, whose slot
+    order depends on that start, against the oracle over 8 steps, FP64 and
+    FP32."""
+    sc = block(shape=1, material=MATERIALS["dp"], algo=algo, seed=43, vel=2.0)
+    h = sc["mesh"]["h"]
+    o = np.asarray(sc["mesh"]["origin"], dtype=np.float64)
+    x = np.asarray(sc["x"], dtype=np.float64)
+    rng = np.random.default_rng(43)
+    sc["x"] = o + (np.floor((x - o) / h) + rng.uniform(0.02, 0.98, size=x.shape)) * h
+    ref = oracle.run(sc, 8)
+    for prec, tol in ((mp.FP64, (1e-9, 1e-9)), (mp.FP32, (U_TOL, S_TOL))):
+        s = ctx.create_scene(sc, precision=prec)
+        s.step(8)
+        st = s.stats()
+        assert st["error_bits"] == 0 and st["steps_done"] == 8, st
+        check_state(f"gimp-anywhere/{ALGO_NAMES[algo]}/{'fp64' if prec == mp.FP64 else 'fp32'}", s.read(), ref,
+                    sc["x"], tol[0], tol[1])
+        s.destroy()
+
+
 def test_batch_of_more_scenes_than_a_workgroup_has_threads(ctx, mp):
     """1,300 tiny scenes in one batch (the step control takes scenes 1,024 at
     a time and carries its scans across the rounds; the reorder's brick scan
